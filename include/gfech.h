@@ -1,0 +1,155 @@
+/*
+ * gfech: blocked Gaussian elimination over a prime field GF(p), p <= 251, on
+ * an MI355X (gfx950) GPU.  C ABI of libgfech.so.
+ *
+ * The method is that of Linton, Nebe, Niemeyer, Parker and Thackray, "A
+ * parallel algorithm for Gaussian elimination over finite fields" (arXiv
+ * 1806.04211).  For A in GF(p)^{m x n} of rank r the library computes, as in
+ * Eq. (2) of Section 3.1 (the whole-matrix form of Remark 2.3, Eq. (1)),
+ *
+ *     [[M, 0], [K, 1]] * [rho; rho_bar] * A * [gamma^tr  gamma_bar^tr]
+ *         = [[-1, R], [0, 0]]
+ *
+ * with rho the selected rows (r of them), gamma the pivot columns, M (r x r),
+ * K ((m - r) x r) and R (r x (n - r)): the *negative* reduced echelon form the
+ * paper uses.  Pivot rule (Section 1): a row's pivot is its first non-zero
+ * entry and rows are taken in their original order, so row i is selected
+ * exactly when it is outside the span of rows 0..i-1; with that rule every
+ * output is unique.  The standard forms are available too: the RREF
+ * E = [1 | -R] * P_gamma^-1 (pivots +1) and T = [[-M, 0], [K, 1]] * P_rho with
+ * T * A = [E; 0] (T = A^-1 when A is invertible).
+ *
+ * Conventions of every call:
+ *   - sizes and leading dimensions are int64_t counts of elements;
+ *   - matrices are row-major with an explicit leading dimension (>= columns);
+ *   - field elements are canonical residues in [0, p), one per uint8_t;
+ *   - index lists are 0-based and ascending;
+ *   - rows of M and R are ordered by pivot column, columns of M and K by
+ *     selected row, rows of K by non-selected row, columns of R ascending.
+ * Every call returns a status; nothing aborts or throws across the ABI.
+ * Calls are serialised inside the library (one device per process).
+ */
+#ifndef GFECH_H
+#define GFECH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gfech_status {
+    GFECH_OK = 0,
+    GFECH_E_ARG = 1,        /* null pointer, negative size, leading dimension too small */
+    GFECH_E_FIELD = 2,      /* p is not a prime <= 251 */
+    GFECH_E_RANGE = 3,      /* an input entry is >= p (inputs are never reduced silently) */
+    GFECH_E_NOMEM = 4,      /* device or host allocation failed */
+    GFECH_E_TOO_BIG = 5,    /* a size exceeds what the kernels index (2^31 - 1 per dimension) */
+    GFECH_E_DEVICE = 6,     /* HIP runtime error or no usable gfx950 device */
+    GFECH_E_CANCELLED = 7,
+    GFECH_E_STATE = 8       /* call not valid for this object */
+} gfech_status;
+
+/* Options.  Zero-initialised options (or NULL) select the defaults. */
+typedef struct gfech_opts {
+    int64_t block_rows;     /* a_i target (Section 3.1); 0 = automatic */
+    int64_t block_cols;     /* b_j target; 0 = automatic */
+    int32_t skip_range_check; /* 1: the caller guarantees entries < p (no validation pass) */
+    int32_t reserved[7];
+} gfech_opts;
+
+/* Opaque, library-owned result; immutable once returned.  Its matrices stay
+ * in device memory (HBM) until copied out by the getters below. */
+typedef struct gfech_result gfech_result;
+
+/* Echelonise A (host memory, m x n, leading dimension lda) over GF(p).
+ * m = 0 or n = 0 is valid (rank 0).  A is only read during the call.
+ * On success *out owns a new result; on failure *out is NULL. */
+gfech_status gfech_echelonise_u8(const uint8_t* A, int64_t m, int64_t n, int64_t lda, uint32_t p,
+                                 const gfech_opts* opts, gfech_result** out);
+
+/* Same with A in device memory (a HIP device pointer).  `stream` is a
+ * hipStream_t (NULL = the default stream); the call returns after the work on
+ * that stream has completed.  The result stays in device memory. */
+gfech_status gfech_echelonise_u8_dev(const uint8_t* A_dev, int64_t m, int64_t n, int64_t lda, uint32_t p,
+                                     const gfech_opts* opts, void* stream, gfech_result** out);
+
+/* One independent problem of a batch. */
+typedef struct gfech_problem {
+    const uint8_t* A;       /* host or device pointer, as the batch call says */
+    int64_t m, n, lda;
+    uint32_t p;
+    uint32_t reserved;
+} gfech_problem;
+
+/* Echelonise `count` independent matrices together: every job of every
+ * problem runs in shared grouped launches.  inputs_on_device selects whether
+ * probs[t].A are device (1) or host (0) pointers.  outs[t] receives a result
+ * or NULL; per_problem[t] (optional) its status.  Returns GFECH_OK when every
+ * problem succeeded, else the first failing status. */
+gfech_status gfech_echelonise_batch(int64_t count, const gfech_problem* probs, int32_t inputs_on_device,
+                                    const gfech_opts* opts, void* stream, gfech_result** outs,
+                                    gfech_status* per_problem);
+
+/* Queries. */
+int64_t gfech_rank(const gfech_result* res);                  /* r, or -1 for NULL */
+gfech_status gfech_shape(const gfech_result* res, int64_t* m, int64_t* n, uint32_t* p);
+
+/* gamma[r] pivot columns and rho[r] selected rows (host buffers, ascending). */
+gfech_status gfech_pivots(const gfech_result* res, int64_t* gamma, int64_t* rho);
+/* gamma_bar[n - r] non-pivot columns and rho_bar[m - r] non-selected rows. */
+gfech_status gfech_nonpivots(const gfech_result* res, int64_t* gamma_bar, int64_t* rho_bar);
+
+/* Copy the paper-form matrices into host buffers (row-major, given ld):
+ * R is r x (n - r), M is r x r, K is (m - r) x r. */
+gfech_status gfech_get_R(const gfech_result* res, uint8_t* R, int64_t ldr);
+gfech_status gfech_get_M(const gfech_result* res, uint8_t* M, int64_t ldm);
+gfech_status gfech_get_K(const gfech_result* res, uint8_t* K, int64_t ldk);
+
+/* Standard forms into host buffers: E is r x n (the RREF, pivots +1);
+ * T is m x m with T * A = [E; 0], rows: pivot rows by pivot column, then the
+ * non-selected rows ascending. */
+gfech_status gfech_expand_rref(const gfech_result* res, uint8_t* E, int64_t lde);
+gfech_status gfech_expand_transform(const gfech_result* res, uint8_t* T, int64_t ldt);
+/* Same into device buffers (work ordered on `stream`, complete on return). */
+gfech_status gfech_expand_rref_dev(const gfech_result* res, uint8_t* E_dev, int64_t lde, void* stream);
+gfech_status gfech_expand_transform_dev(const gfech_result* res, uint8_t* T_dev, int64_t ldt, void* stream);
+
+/* Device pointers to the result's matrices (valid until gfech_result_free). */
+typedef struct gfech_view {
+    const uint8_t* R; int64_t ldr;     /* r x (n - r) */
+    const uint8_t* M; int64_t ldm;     /* r x r */
+    const uint8_t* K; int64_t ldk;     /* (m - r) x r */
+    const int32_t* gamma;              /* r   */
+    const int32_t* gamma_bar;          /* n - r */
+    const int32_t* rho;                /* r   */
+    const int32_t* rho_bar;            /* m - r */
+} gfech_view;
+gfech_status gfech_device_view(const gfech_result* res, gfech_view* view);
+
+/* Work counters of the run (cost model of Section 5: a product (x by y)(y by z)
+ * counts xyz multiply-adds, echelonising x by y of rank r counts xyr). */
+typedef struct gfech_stats {
+    double mac_cleardown;   /* ClearDown's MADs */
+    double mac_ech;         /* ECH jobs */
+    double mac_updaterow;   /* UpdateRow on the data blocks */
+    double mac_trafo;       /* UpdateRowTrafo on the transformation blocks */
+    double mac_clearup;     /* ClearUp (Step 3) */
+    double gather_bytes;    /* bytes read + written by extracts, riffles and copies */
+    int64_t layers, echs, gemms, launches, syncs;
+    int64_t block_rows, block_cols;   /* a and b */
+} gfech_stats;
+gfech_status gfech_get_stats(const gfech_result* res, gfech_stats* stats);
+
+void gfech_result_free(gfech_result* res);
+
+const char* gfech_strerror(gfech_status s);
+/* Detail of the last failure on this thread ("" if none). */
+const char* gfech_last_error(void);
+/* Name of the compute backend this library was built with ("hip-gfx950"). */
+const char* gfech_backend_name(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GFECH_H */

@@ -1,0 +1,212 @@
+"""Thin Python binding over the C ABI (argument marshalling only).
+
+Every call goes straight to the same-named ``gfech_*`` entry point of a
+loaded library; numpy arrays are host buffers, torch tensors on the GPU are
+device buffers (their data pointers are passed through).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _abi
+
+
+class GfechError(RuntimeError):
+    def __init__(self, status: int, detail: str = ""):
+        self.status = status
+        super().__init__(f"{_abi.STATUS_NAMES.get(status, status)}: {detail}")
+
+
+@dataclass
+class Outputs:
+    """Everything a result holds, copied to host numpy arrays."""
+    p: int
+    m: int
+    n: int
+    rank: int
+    gamma: np.ndarray
+    rho: np.ndarray
+    gamma_bar: np.ndarray
+    rho_bar: np.ndarray
+    R: np.ndarray
+    M: np.ndarray
+    K: np.ndarray
+    E: np.ndarray | None = None
+    T: np.ndarray | None = None
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data) if a.size else ctypes.c_void_p(0)
+
+
+class Result:
+    """Owns one gfech_result*."""
+
+    def __init__(self, lib, handle: int):
+        self._lib = lib
+        self._h = ctypes.c_void_p(handle)
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.gfech_result_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def _check(self, st):
+        if st != _abi.GFECH_OK:
+            raise GfechError(st, self._lib.gfech_last_error().decode())
+
+    @property
+    def rank(self) -> int:
+        return int(self._lib.gfech_rank(self._h))
+
+    def shape(self):
+        m, n, p = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint32()
+        self._check(self._lib.gfech_shape(self._h, ctypes.byref(m), ctypes.byref(n), ctypes.byref(p)))
+        return m.value, n.value, p.value
+
+    def stats(self) -> dict:
+        s = _abi.Stats()
+        self._check(self._lib.gfech_get_stats(self._h, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in _abi.Stats._fields_}
+
+    def view(self) -> _abi.View:
+        v = _abi.View()
+        self._check(self._lib.gfech_device_view(self._h, ctypes.byref(v)))
+        return v
+
+    def pivots(self):
+        r = self.rank
+        g = np.zeros(r, np.int64)
+        rho = np.zeros(r, np.int64)
+        self._check(self._lib.gfech_pivots(self._h, _ptr(g), _ptr(rho)))
+        return g, rho
+
+    def nonpivots(self):
+        m, n, _ = self.shape()
+        r = self.rank
+        gb = np.zeros(n - r, np.int64)
+        rb = np.zeros(m - r, np.int64)
+        self._check(self._lib.gfech_nonpivots(self._h, _ptr(gb), _ptr(rb)))
+        return gb, rb
+
+    def get_R(self):
+        m, n, _ = self.shape()
+        r = self.rank
+        out = np.zeros((r, n - r), np.uint8)
+        self._check(self._lib.gfech_get_R(self._h, _ptr(out), max(n - r, 1)))
+        return out
+
+    def get_M(self):
+        r = self.rank
+        out = np.zeros((r, r), np.uint8)
+        self._check(self._lib.gfech_get_M(self._h, _ptr(out), max(r, 1)))
+        return out
+
+    def get_K(self):
+        m, n, _ = self.shape()
+        r = self.rank
+        out = np.zeros((m - r, r), np.uint8)
+        self._check(self._lib.gfech_get_K(self._h, _ptr(out), max(r, 1)))
+        return out
+
+    def expand_rref(self):
+        m, n, _ = self.shape()
+        out = np.zeros((self.rank, n), np.uint8)
+        self._check(self._lib.gfech_expand_rref(self._h, _ptr(out), max(n, 1)))
+        return out
+
+    def expand_transform(self):
+        m, n, _ = self.shape()
+        out = np.zeros((m, m), np.uint8)
+        self._check(self._lib.gfech_expand_transform(self._h, _ptr(out), max(m, 1)))
+        return out
+
+    def expand_rref_dev(self, out_ptr: int, lde: int, stream: int = 0):
+        self._check(self._lib.gfech_expand_rref_dev(self._h, ctypes.c_void_p(out_ptr), lde, ctypes.c_void_p(stream)))
+
+    def expand_transform_dev(self, out_ptr: int, ldt: int, stream: int = 0):
+        self._check(self._lib.gfech_expand_transform_dev(self._h, ctypes.c_void_p(out_ptr), ldt,
+                                                         ctypes.c_void_p(stream)))
+
+    def outputs(self, expand: bool = True) -> Outputs:
+        m, n, p = self.shape()
+        g, rho = self.pivots()
+        gb, rb = self.nonpivots()
+        o = Outputs(p=p, m=m, n=n, rank=self.rank, gamma=g, rho=rho, gamma_bar=gb, rho_bar=rb,
+                    R=self.get_R(), M=self.get_M(), K=self.get_K())
+        if expand:
+            o.E = self.expand_rref()
+            o.T = self.expand_transform()
+        return o
+
+
+def _opts(block_rows=0, block_cols=0, skip_range_check=False):
+    o = _abi.Opts()
+    o.block_rows = int(block_rows)
+    o.block_cols = int(block_cols)
+    o.skip_range_check = 1 if skip_range_check else 0
+    return o
+
+
+class Library:
+    """Calls into one loaded gfech library."""
+
+    def __init__(self, lib):
+        self.lib = _abi.declare(lib)
+
+    def backend_name(self) -> str:
+        return self.lib.gfech_backend_name().decode()
+
+    def _check(self, st):
+        if st != _abi.GFECH_OK:
+            raise GfechError(st, self.lib.gfech_last_error().decode())
+
+    def echelonise(self, A, p: int, block_rows=0, block_cols=0) -> Result:
+        """A: host numpy (m x n, uint8)."""
+        A = np.ascontiguousarray(np.asarray(A, dtype=np.uint8))
+        m, n = A.shape
+        out = ctypes.c_void_p()
+        o = _opts(block_rows, block_cols)
+        self._check(self.lib.gfech_echelonise_u8(_ptr(A), m, n, max(n, 1), p, ctypes.byref(o), ctypes.byref(out)))
+        return Result(self.lib, out.value)
+
+    def echelonise_dev(self, ptr: int, m: int, n: int, lda: int, p: int, stream: int = 0, block_rows=0,
+                       block_cols=0, skip_range_check=False) -> Result:
+        """ptr: device address of an m x n uint8 matrix with leading dimension lda."""
+        out = ctypes.c_void_p()
+        o = _opts(block_rows, block_cols, skip_range_check)
+        self._check(self.lib.gfech_echelonise_u8_dev(ctypes.c_void_p(ptr), m, n, lda, p, ctypes.byref(o),
+                                                     ctypes.c_void_p(stream), ctypes.byref(out)))
+        return Result(self.lib, out.value)
+
+    def echelonise_batch(self, problems, on_device: bool = False, stream: int = 0, block_rows=0, block_cols=0):
+        """problems: list of (A, p) with A a host numpy array (on_device=False) or
+        (ptr, m, n, lda, p) tuples (on_device=True).  Returns (results, statuses)."""
+        cnt = len(problems)
+        arr = (_abi.Problem * max(cnt, 1))()
+        keep = []
+        for t, pr in enumerate(problems):
+            if on_device:
+                ptr, m, n, lda, p = pr
+                arr[t].A = ptr
+            else:
+                A, p = pr
+                A = np.ascontiguousarray(np.asarray(A, np.uint8))
+                keep.append(A)
+                m, n = A.shape
+                lda = max(n, 1)
+                arr[t].A = A.ctypes.data if A.size else 0
+            arr[t].m, arr[t].n, arr[t].lda, arr[t].p = m, n, lda, p
+        outs = (ctypes.c_void_p * max(cnt, 1))()
+        sts = (ctypes.c_int * max(cnt, 1))()
+        o = _opts(block_rows, block_cols)
+        self.lib.gfech_echelonise_batch(cnt, arr, 1 if on_device else 0, ctypes.byref(o), ctypes.c_void_p(stream),
+                                        outs, sts)
+        res = [Result(self.lib, outs[t]) if outs[t] else None for t in range(cnt)]
+        return res, [int(sts[t]) for t in range(cnt)]

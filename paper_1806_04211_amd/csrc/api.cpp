@@ -1,0 +1,454 @@
+// C ABI of libgfech (declared in include/gfech.h): argument checks, host /
+// device staging, block-size choice and the result getters.  All arithmetic
+// runs in the backend's kernels through the Chief.
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gfech.h"
+#include "backend.h"
+#include "chief.h"
+
+namespace gfech {
+// Provided by the backend translation unit linked into the library.
+Backend* backend_instance(std::string* err);
+}  // namespace gfech
+
+struct gfech_result {
+    std::unique_ptr<gfech::Result> r;
+};
+
+namespace {
+
+std::mutex g_mu;
+thread_local std::string g_last_error;
+
+gfech_status fail(gfech_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+bool is_prime(uint32_t p) {
+    if (p < 2) return false;
+    for (uint32_t d = 2; d * d <= p; ++d)
+        if (p % d == 0) return false;
+    return true;
+}
+
+// Block sizes (Section 3.1: roughly square blocks).  Matrices up to the
+// single-block limit are one block: one ECH then does the whole job.
+void choose_blocks(int64_t m, int64_t n, const gfech_opts* o, std::vector<int32_t>& a, std::vector<int32_t>& b) {
+    const int64_t single = 1024;
+    const int64_t target = 512;
+    int64_t br = (o && o->block_rows > 0) ? o->block_rows : 0;
+    int64_t bc = (o && o->block_cols > 0) ? o->block_cols : 0;
+    if (!br && !bc) {
+        if (m <= single && n <= single) {
+            br = m;
+            bc = n;
+        } else {
+            br = target;
+            bc = target;
+        }
+    } else if (!br) {
+        br = bc;
+    } else if (!bc) {
+        bc = br;
+    }
+    a = gfech::even_blocks(m, br);
+    b = gfech::even_blocks(n, bc);
+}
+
+gfech_status check_common(int64_t m, int64_t n, int64_t lda, uint32_t p, const void* A) {
+    if (m < 0 || n < 0) return fail(GFECH_E_ARG, "negative size");
+    if (m > INT32_MAX || n > INT32_MAX || m + n > INT32_MAX) return fail(GFECH_E_TOO_BIG, "dimension too large");
+    if (m > 0 && n > 0 && (!A || lda < n)) return fail(GFECH_E_ARG, "null input or lda < n");
+    if (p > 251 || !is_prime(p)) return fail(GFECH_E_FIELD, "p must be a prime <= 251");
+    return GFECH_OK;
+}
+
+gfech::Backend* get_backend(gfech_status* st) {
+    std::string err;
+    gfech::Backend* be = gfech::backend_instance(&err);
+    if (!be) *st = fail(GFECH_E_DEVICE, err.empty() ? "no device backend" : err);
+    return be;
+}
+
+// run a set of problems whose inputs are already in backend memory
+gfech_status run(gfech::Backend* be, std::vector<gfech::Problem>& probs, gfech_result** outs) {
+    std::vector<std::unique_ptr<gfech::Result>> res;
+    std::string err;
+    int rc = gfech::run_chief(*be, probs, res, &err);
+    if (rc) return fail(rc == 4 ? GFECH_E_NOMEM : GFECH_E_DEVICE, err);
+    for (size_t q = 0; q < res.size(); ++q) {
+        outs[q] = new gfech_result();
+        outs[q]->r = std::move(res[q]);
+    }
+    return GFECH_OK;
+}
+
+gfech_status echelonise_impl(const uint8_t* A, bool on_device, int64_t m, int64_t n, int64_t lda, uint32_t p,
+                             const gfech_opts* opts, void* stream, gfech_result** out) {
+    if (!out) return fail(GFECH_E_ARG, "out is NULL");
+    *out = nullptr;
+    gfech_status st = check_common(m, n, lda, p, A);
+    if (st) return st;
+    bool check = !(opts && opts->skip_range_check);
+    if (!on_device && check) {
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t j = 0; j < n; ++j)
+                if (A[i * lda + j] >= p) return fail(GFECH_E_RANGE, "entry >= p");
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    gfech::Backend* be = get_backend(&st);
+    if (!be) return st;
+    be->set_stream(stream);
+    const uint8_t* dA = A;
+    void* staged = nullptr;
+    int64_t ld = lda;
+    if (!on_device && m > 0 && n > 0) {
+        staged = be->alloc((size_t)(m * n));
+        if (!staged) return fail(GFECH_E_NOMEM, "device allocation of the input failed");
+        if (lda == n) {
+            be->upload(staged, A, (size_t)(m * n));
+        } else {
+            std::vector<uint8_t> tmp((size_t)(m * n));
+            for (int64_t i = 0; i < m; ++i) memcpy(tmp.data() + i * n, A + i * lda, (size_t)n);
+            be->upload(staged, tmp.data(), (size_t)(m * n));
+        }
+        dA = (const uint8_t*)staged;
+        ld = n;
+    } else if (on_device && check && m > 0 && n > 0) {
+        int64_t bad = be->count_out_of_range(A, m, n, lda, (int32_t)p);
+        if (bad != 0) {
+            be->set_stream(nullptr);
+            return fail(bad > 0 ? GFECH_E_RANGE : GFECH_E_DEVICE, bad > 0 ? "entry >= p" : "device error");
+        }
+    }
+    std::vector<gfech::Problem> probs(1);
+    probs[0].A = dA;
+    probs[0].m = m;
+    probs[0].n = n;
+    probs[0].lda = ld;
+    probs[0].p = (int32_t)p;
+    choose_blocks(m, n, opts, probs[0].row_blocks, probs[0].col_blocks);
+    st = run(be, probs, out);
+    if (staged) be->release(staged);
+    be->set_stream(nullptr);
+    return st;
+}
+
+template <typename T>
+gfech_status download_list(gfech::Backend* be, const int32_t* src, int64_t count, T* dst) {
+    if (count == 0) return GFECH_OK;
+    std::vector<int32_t> tmp((size_t)count);
+    be->download(tmp.data(), src, sizeof(int32_t) * (size_t)count);
+    for (int64_t i = 0; i < count; ++i) dst[i] = (T)tmp[(size_t)i];
+    return GFECH_OK;
+}
+
+gfech_status download_matrix(gfech::Backend* be, const uint8_t* src, int64_t lds, int64_t rows, int64_t cols,
+                             uint8_t* dst, int64_t ldd) {
+    if (rows == 0 || cols == 0) return GFECH_OK;
+    if (lds == cols && ldd == cols) {
+        be->download(dst, src, (size_t)(rows * cols));
+        return GFECH_OK;
+    }
+    std::vector<uint8_t> tmp((size_t)(rows * lds));
+    be->download(tmp.data(), src, (size_t)((rows - 1) * lds + cols));
+    for (int64_t i = 0; i < rows; ++i) memcpy(dst + i * ldd, tmp.data() + i * lds, (size_t)cols);
+    return GFECH_OK;
+}
+
+void expand_rref_ops(const gfech::Result& R, uint8_t* E, int64_t lde, gfech::Backend* be) {
+    int64_t r = R.r, n = R.n;
+    if (r == 0 || n == 0) return;
+    std::vector<gfech::FillDesc> f(2);
+    f[0].rows = (int32_t)r; f[0].cols = (int32_t)n; f[0].dst = E; f[0].ldd = lde; f[0].value = 0;
+    be->fill({f[0]});
+    f[1].rows = (int32_t)r; f[1].dst = E; f[1].ldd = lde; f[1].diag_value = 1; f[1].dcol = R.upsilon;
+    be->fill({f[1]});
+    if (n - r > 0) {
+        gfech::GatherDesc g;
+        g.rows = (int32_t)r; g.cols = (int32_t)(n - r); g.neg_p = R.p;
+        g.src = R.Pfinal + r; g.lds = R.ldP;
+        g.dst = E; g.ldd = lde; g.dcol = R.upsilon_bar;
+        be->gather({g});
+    }
+}
+
+void expand_transform_ops(const gfech::Result& R, uint8_t* T, int64_t ldt, gfech::Backend* be) {
+    int64_t r = R.r, m = R.m;
+    if (m == 0) return;
+    gfech::FillDesc z;
+    z.rows = (int32_t)m; z.cols = (int32_t)m; z.dst = T; z.ldd = ldt; z.value = 0;
+    be->fill({z});
+    if (r > 0) {
+        gfech::GatherDesc g;
+        g.rows = (int32_t)r; g.cols = (int32_t)r; g.neg_p = R.p;
+        g.src = R.Pfinal + R.n; g.lds = R.ldP;
+        g.dst = T; g.ldd = ldt; g.dcol = R.varrho;
+        be->gather({g});
+        if (m - r > 0) {
+            gfech::GatherDesc k;
+            k.rows = (int32_t)(m - r); k.cols = (int32_t)r;
+            k.src = R.Kfinal; k.lds = R.ldK;
+            k.dst = T + r * ldt; k.ldd = ldt; k.dcol = R.varrho;
+            be->gather({k});
+        }
+    }
+    if (m - r > 0) {
+        gfech::FillDesc id;
+        id.rows = (int32_t)(m - r); id.dst = T + r * ldt; id.ldd = ldt; id.diag_value = 1; id.dcol = R.varrho_bar;
+        be->fill({id});
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+gfech_status gfech_echelonise_u8(const uint8_t* A, int64_t m, int64_t n, int64_t lda, uint32_t p,
+                                 const gfech_opts* opts, gfech_result** out) {
+    return echelonise_impl(A, false, m, n, lda, p, opts, nullptr, out);
+}
+
+gfech_status gfech_echelonise_u8_dev(const uint8_t* A_dev, int64_t m, int64_t n, int64_t lda, uint32_t p,
+                                     const gfech_opts* opts, void* stream, gfech_result** out) {
+    return echelonise_impl(A_dev, true, m, n, lda, p, opts, stream, out);
+}
+
+gfech_status gfech_echelonise_batch(int64_t count, const gfech_problem* probs, int32_t inputs_on_device,
+                                    const gfech_opts* opts, void* stream, gfech_result** outs,
+                                    gfech_status* per_problem) {
+    if (count < 0 || (count > 0 && (!probs || !outs))) return fail(GFECH_E_ARG, "bad batch arguments");
+    gfech_status first = GFECH_OK;
+    std::vector<int64_t> ok;
+    for (int64_t t = 0; t < count; ++t) {
+        outs[t] = nullptr;
+        const gfech_problem& q = probs[t];
+        gfech_status st = check_common(q.m, q.n, q.lda, q.p, q.A);
+        if (!st && !inputs_on_device && !(opts && opts->skip_range_check)) {
+            for (int64_t i = 0; i < q.m && !st; ++i)
+                for (int64_t j = 0; j < q.n; ++j)
+                    if (q.A[i * q.lda + j] >= q.p) { st = fail(GFECH_E_RANGE, "entry >= p"); break; }
+        }
+        if (per_problem) per_problem[t] = st;
+        if (st) { if (!first) first = st; continue; }
+        ok.push_back(t);
+    }
+    if (ok.empty()) return first;
+    std::lock_guard<std::mutex> lk(g_mu);
+    gfech_status st = GFECH_OK;
+    gfech::Backend* be = get_backend(&st);
+    if (!be) return st;
+    be->set_stream(stream);
+    std::vector<gfech::Problem> pv;
+    std::vector<int64_t> run_idx;
+    std::vector<void*> staged;
+    for (int64_t t : ok) {
+        const gfech_problem& q = probs[t];
+        gfech::Problem pr;
+        pr.m = q.m; pr.n = q.n; pr.lda = q.lda; pr.p = (int32_t)q.p; pr.A = q.A;
+        if (inputs_on_device && !(opts && opts->skip_range_check) && q.m > 0 && q.n > 0) {
+            int64_t bad = be->count_out_of_range(q.A, q.m, q.n, q.lda, (int32_t)q.p);
+            if (bad) {
+                if (per_problem) per_problem[t] = GFECH_E_RANGE;
+                if (!first) first = fail(GFECH_E_RANGE, "entry >= p");
+                continue;
+            }
+        }
+        if (!inputs_on_device && q.m > 0 && q.n > 0) {
+            void* d = be->alloc((size_t)(q.m * q.n));
+            if (!d) { st = fail(GFECH_E_NOMEM, "staging allocation failed"); break; }
+            std::vector<uint8_t> tmp((size_t)(q.m * q.n));
+            for (int64_t i = 0; i < q.m; ++i) memcpy(tmp.data() + i * q.n, q.A + i * q.lda, (size_t)q.n);
+            be->upload(d, tmp.data(), tmp.size());
+            staged.push_back(d);
+            pr.A = (const uint8_t*)d;
+            pr.lda = q.n;
+        }
+        choose_blocks(pr.m, pr.n, opts, pr.row_blocks, pr.col_blocks);
+        pv.push_back(pr);
+        run_idx.push_back(t);
+    }
+    std::vector<gfech_result*> tmp_out(pv.size(), nullptr);
+    if (!st && !pv.empty()) st = run(be, pv, tmp_out.data());
+    for (void* d : staged) be->release(d);
+    be->set_stream(nullptr);
+    // map results back (problems that failed validation keep NULL)
+    for (size_t k = 0; k < run_idx.size(); ++k) {
+        outs[run_idx[k]] = tmp_out[k];
+        if (per_problem) per_problem[run_idx[k]] = st;
+    }
+    if (st && !first) first = st;
+    return first;
+}
+
+int64_t gfech_rank(const gfech_result* res) { return res ? res->r->r : -1; }
+
+gfech_status gfech_shape(const gfech_result* res, int64_t* m, int64_t* n, uint32_t* p) {
+    if (!res) return fail(GFECH_E_ARG, "NULL result");
+    if (m) *m = res->r->m;
+    if (n) *n = res->r->n;
+    if (p) *p = (uint32_t)res->r->p;
+    return GFECH_OK;
+}
+
+gfech_status gfech_pivots(const gfech_result* res, int64_t* gamma, int64_t* rho) {
+    if (!res) return fail(GFECH_E_ARG, "NULL result");
+    std::lock_guard<std::mutex> lk(g_mu);
+    const gfech::Result& R = *res->r;
+    if (gamma) download_list(R.be, R.upsilon, R.r, gamma);
+    if (rho) download_list(R.be, R.varrho, R.r, rho);
+    return GFECH_OK;
+}
+
+gfech_status gfech_nonpivots(const gfech_result* res, int64_t* gamma_bar, int64_t* rho_bar) {
+    if (!res) return fail(GFECH_E_ARG, "NULL result");
+    std::lock_guard<std::mutex> lk(g_mu);
+    const gfech::Result& R = *res->r;
+    if (gamma_bar) download_list(R.be, R.upsilon_bar, R.n - R.r, gamma_bar);
+    if (rho_bar) download_list(R.be, R.varrho_bar, R.m - R.r, rho_bar);
+    return GFECH_OK;
+}
+
+gfech_status gfech_get_R(const gfech_result* res, uint8_t* R_, int64_t ldr) {
+    if (!res) return fail(GFECH_E_ARG, "NULL result");
+    const gfech::Result& R = *res->r;
+    if (R.r > 0 && R.n - R.r > 0 && (!R_ || ldr < R.n - R.r)) return fail(GFECH_E_ARG, "bad R buffer");
+    std::lock_guard<std::mutex> lk(g_mu);
+    return download_matrix(R.be, R.Pfinal + R.r, R.ldP, R.r, R.n - R.r, R_, ldr);
+}
+
+gfech_status gfech_get_M(const gfech_result* res, uint8_t* M, int64_t ldm) {
+    if (!res) return fail(GFECH_E_ARG, "NULL result");
+    const gfech::Result& R = *res->r;
+    if (R.r > 0 && (!M || ldm < R.r)) return fail(GFECH_E_ARG, "bad M buffer");
+    std::lock_guard<std::mutex> lk(g_mu);
+    return download_matrix(R.be, R.Pfinal + R.n, R.ldP, R.r, R.r, M, ldm);
+}
+
+gfech_status gfech_get_K(const gfech_result* res, uint8_t* K, int64_t ldk) {
+    if (!res) return fail(GFECH_E_ARG, "NULL result");
+    const gfech::Result& R = *res->r;
+    if (R.r > 0 && R.m - R.r > 0 && (!K || ldk < R.r)) return fail(GFECH_E_ARG, "bad K buffer");
+    std::lock_guard<std::mutex> lk(g_mu);
+    return download_matrix(R.be, R.Kfinal, R.ldK, R.m - R.r, R.r, K, ldk);
+}
+
+gfech_status gfech_expand_rref_dev(const gfech_result* res, uint8_t* E, int64_t lde, void* stream) {
+    if (!res) return fail(GFECH_E_ARG, "NULL result");
+    const gfech::Result& R = *res->r;
+    if (R.r > 0 && R.n > 0 && (!E || lde < R.n)) return fail(GFECH_E_ARG, "bad E buffer");
+    std::lock_guard<std::mutex> lk(g_mu);
+    R.be->set_stream(stream);
+    expand_rref_ops(R, E, lde, R.be);
+    R.be->sync();
+    R.be->set_stream(nullptr);
+    return R.be->error() ? fail(GFECH_E_DEVICE, "device error") : GFECH_OK;
+}
+
+gfech_status gfech_expand_transform_dev(const gfech_result* res, uint8_t* T, int64_t ldt, void* stream) {
+    if (!res) return fail(GFECH_E_ARG, "NULL result");
+    const gfech::Result& R = *res->r;
+    if (R.m > 0 && (!T || ldt < R.m)) return fail(GFECH_E_ARG, "bad T buffer");
+    std::lock_guard<std::mutex> lk(g_mu);
+    R.be->set_stream(stream);
+    expand_transform_ops(R, T, ldt, R.be);
+    R.be->sync();
+    R.be->set_stream(nullptr);
+    return R.be->error() ? fail(GFECH_E_DEVICE, "device error") : GFECH_OK;
+}
+
+gfech_status gfech_expand_rref(const gfech_result* res, uint8_t* E, int64_t lde) {
+    if (!res) return fail(GFECH_E_ARG, "NULL result");
+    const gfech::Result& R = *res->r;
+    if (R.r == 0 || R.n == 0) return GFECH_OK;
+    if (!E || lde < R.n) return fail(GFECH_E_ARG, "bad E buffer");
+    std::lock_guard<std::mutex> lk(g_mu);
+    uint8_t* d = (uint8_t*)R.be->alloc((size_t)(R.r * R.n));
+    if (!d) return fail(GFECH_E_NOMEM, "device allocation failed");
+    expand_rref_ops(R, d, R.n, R.be);
+    download_matrix(R.be, d, R.n, R.r, R.n, E, lde);
+    R.be->release(d);
+    return R.be->error() ? fail(GFECH_E_DEVICE, "device error") : GFECH_OK;
+}
+
+gfech_status gfech_expand_transform(const gfech_result* res, uint8_t* T, int64_t ldt) {
+    if (!res) return fail(GFECH_E_ARG, "NULL result");
+    const gfech::Result& R = *res->r;
+    if (R.m == 0) return GFECH_OK;
+    if (!T || ldt < R.m) return fail(GFECH_E_ARG, "bad T buffer");
+    std::lock_guard<std::mutex> lk(g_mu);
+    uint8_t* d = (uint8_t*)R.be->alloc((size_t)(R.m * R.m));
+    if (!d) return fail(GFECH_E_NOMEM, "device allocation failed");
+    expand_transform_ops(R, d, R.m, R.be);
+    download_matrix(R.be, d, R.m, R.m, R.m, T, ldt);
+    R.be->release(d);
+    return R.be->error() ? fail(GFECH_E_DEVICE, "device error") : GFECH_OK;
+}
+
+gfech_status gfech_device_view(const gfech_result* res, gfech_view* v) {
+    if (!res || !v) return fail(GFECH_E_ARG, "NULL argument");
+    const gfech::Result& R = *res->r;
+    v->R = R.Pfinal + R.r; v->ldr = R.ldP;
+    v->M = R.Pfinal + R.n; v->ldm = R.ldP;
+    v->K = R.Kfinal; v->ldk = R.ldK;
+    v->gamma = R.upsilon; v->gamma_bar = R.upsilon_bar;
+    v->rho = R.varrho; v->rho_bar = R.varrho_bar;
+    return GFECH_OK;
+}
+
+gfech_status gfech_get_stats(const gfech_result* res, gfech_stats* s) {
+    if (!res || !s) return fail(GFECH_E_ARG, "NULL argument");
+    const gfech::Stats& t = res->r->stats;
+    s->mac_cleardown = t.cd_mad;
+    s->mac_ech = t.ech;
+    s->mac_updaterow = t.ur_mad;
+    s->mac_trafo = t.urt_mad;
+    s->mac_clearup = t.cu_mad;
+    s->gather_bytes = t.gather_bytes;
+    s->layers = t.layers;
+    s->echs = t.echs;
+    s->gemms = t.gemms;
+    s->launches = t.launches;
+    s->syncs = t.syncs;
+    s->block_rows = (int64_t)res->r->row_blocks.size();
+    s->block_cols = (int64_t)res->r->col_blocks.size();
+    return GFECH_OK;
+}
+
+void gfech_result_free(gfech_result* res) {
+    if (!res) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    delete res;
+}
+
+const char* gfech_strerror(gfech_status s) {
+    switch (s) {
+        case GFECH_OK: return "ok";
+        case GFECH_E_ARG: return "invalid argument";
+        case GFECH_E_FIELD: return "p is not a prime <= 251";
+        case GFECH_E_RANGE: return "input entry >= p";
+        case GFECH_E_NOMEM: return "out of memory";
+        case GFECH_E_TOO_BIG: return "problem too large";
+        case GFECH_E_DEVICE: return "device error";
+        case GFECH_E_CANCELLED: return "cancelled";
+        case GFECH_E_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char* gfech_last_error(void) { return g_last_error.c_str(); }
+
+const char* gfech_backend_name(void) {
+    gfech_status st = GFECH_OK;
+    gfech::Backend* be = get_backend(&st);
+    return be ? be->name() : "unavailable";
+}
+
+}  // extern "C"

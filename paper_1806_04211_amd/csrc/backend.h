@@ -1,0 +1,123 @@
+// Job-level interface between the host planner (the Chief) and the device.
+//
+// Every operation is *grouped*: the planner hands over all independent jobs of
+// one phase at once and the backend runs them in a single launch.  Pointers in
+// the descriptors are addresses in the backend's memory (HBM for the HIP
+// backend).  Shapes are exact; the planner never asks a backend to touch
+// bytes outside the extents a descriptor states.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace gfech {
+
+// MAD / MUL job (Section 4.1): D = (Cin + A * B) mod p.
+//   A   : M x K, row-major, leading dimension lda
+//   B   : K x N; row t of B is row brow[t] of the base when brow != nullptr
+//   Cin : M x N; nullptr means zero; row x is row crow[x] of the base when crow != nullptr
+//   D   : M x N output.  D may equal Cin when crow == nullptr and ldc == ldd
+//         (element-wise in place); D never overlaps A or B.
+// Entries are canonical residues in [0, p); K may be 0 (then D = Cin).
+struct GemmDesc {
+    int32_t M = 0, N = 0, K = 0, p = 0;
+    const uint8_t* A = nullptr; int64_t lda = 0;
+    const uint8_t* B = nullptr; int64_t ldb = 0; const int32_t* brow = nullptr;
+    const uint8_t* C = nullptr; int64_t ldc = 0; const int32_t* crow = nullptr;
+    uint8_t* D = nullptr; int64_t ldd = 0;
+};
+
+// Permuted copy (the extract / riffle jobs CEX, REX, RRF of Section 4.1):
+//   dst[drow[x]][dcol[y]] = f(src[srow[x]][scol[y]])   for x < rows, y < cols
+// with each map optional (identity when nullptr) and f(v) = v, or
+// f(v) = (neg_p - v) mod neg_p when neg_p != 0 (negation in GF(neg_p)).
+struct GatherDesc {
+    int32_t rows = 0, cols = 0, neg_p = 0;
+    const uint8_t* src = nullptr; int64_t lds = 0;
+    const int32_t* srow = nullptr; const int32_t* scol = nullptr;
+    uint8_t* dst = nullptr; int64_t ldd = 0;
+    const int32_t* drow = nullptr; const int32_t* dcol = nullptr;
+};
+
+// Fill dst (rows x cols) with `value`; when diag_value >= 0 the entries
+// (t, t) are set to diag_value instead (identity-like fills).  When dcol is
+// given only the entries (t, dcol[t]), t < rows, are written, with diag_value
+// (a scattered identity); `cols` is then unused.
+struct FillDesc {
+    int32_t rows = 0, cols = 0;
+    uint8_t* dst = nullptr; int64_t ldd = 0;
+    int32_t value = 0, diag_value = -1;
+    const int32_t* dcol = nullptr;
+};
+
+// ECH job (Remark 2.3) on H (rows x cols).  With r = rank(H), outputs
+//   rcount[0] = r
+//   prow[t]   (t < r)        : row of the t-th pivot, pivots ordered by column
+//   qrow[s]   (s < rows-r)   : non-pivot rows, ascending
+//   pcol[t]   (t < r)        : pivot columns, ascending
+//   qcol[s]   (s < cols-r)   : non-pivot columns, ascending
+//   Mo (r x r), Ko ((rows-r) x r), Ro (r x (cols-r)) with
+//   [[Mo,0],[Ko,1]] [H[prow]; H[qrow]] [H cols pcol | qcol] = [[-1, Ro],[0,0]].
+// Pivot rule of the paper: a column's pivot is the first not-yet-selected row
+// (in H's row order) that is non-zero there after elimination.  `work` is
+// scratch of rows x (cols + min(rows, cols)) bytes with leading dimension ldw.
+struct EchDesc {
+    int32_t rows = 0, cols = 0, p = 0;
+    const uint8_t* H = nullptr; int64_t ldh = 0;
+    uint8_t* work = nullptr; int64_t ldw = 0;
+    int32_t* rcount = nullptr;
+    int32_t* prow = nullptr; int32_t* qrow = nullptr;
+    int32_t* pcol = nullptr; int32_t* qcol = nullptr;
+    uint8_t* Mo = nullptr; int64_t ldm = 0;
+    uint8_t* Ko = nullptr; int64_t ldk = 0;
+    uint8_t* Ro = nullptr; int64_t ldr = 0;
+};
+
+// Index-list update used by Extend / UNH (Section 4.2) and ClearDown's UNH:
+//   append[t]  = add + map[pick[t]]   for t < npick   (new elements, in pick order)
+//   keep_out[s] = map[keep[s]]        for s < nkeep   (the remaining complement)
+// keep_out must not alias map.
+struct ListDesc {
+    int32_t npick = 0, nkeep = 0, add = 0;
+    const int32_t* map = nullptr;
+    const int32_t* pick = nullptr; int32_t* append = nullptr;
+    const int32_t* keep = nullptr; int32_t* keep_out = nullptr;
+};
+
+// Sorting of small distinct-valued lists (for the final row and column orders):
+//   mode 0: out[k] = add + (k-th smallest value)
+//   mode 1: out[k] = add + (index of the k-th smallest value)
+struct SortDesc {
+    int32_t n = 0, mode = 0, add = 0;
+    const int32_t* vals = nullptr;
+    int32_t* out = nullptr;
+};
+
+class Backend {
+public:
+    virtual ~Backend() = default;
+    virtual const char* name() const = 0;
+    // memory (alloc returns zeroed memory, nullptr on failure)
+    virtual void* alloc(size_t bytes) = 0;
+    virtual void release(void* ptr) = 0;
+    virtual void zero(void* ptr, size_t bytes) = 0;
+    virtual void upload(void* dst, const void* host_src, size_t bytes) = 0;
+    virtual void download(void* host_dst, const void* src, size_t bytes) = 0;   // waits for prior work
+    virtual void copy(void* dst, const void* src, size_t bytes) = 0;            // device to device
+    // grouped jobs, executed in submission order
+    virtual void gemm(const std::vector<GemmDesc>& d) = 0;
+    virtual void gather(const std::vector<GatherDesc>& d) = 0;
+    virtual void fill(const std::vector<FillDesc>& d) = 0;
+    virtual void ech(const std::vector<EchDesc>& d) = 0;
+    virtual void lists(const std::vector<ListDesc>& d) = 0;
+    virtual void sort(const std::vector<SortDesc>& d) = 0;
+    virtual void sync() = 0;
+    // number of entries >= p in an m x n matrix (waits for the answer)
+    virtual int64_t count_out_of_range(const uint8_t* A, int64_t m, int64_t n, int64_t lda, int32_t p) = 0;
+    // stream for subsequent work (a hipStream_t for the HIP backend)
+    virtual void set_stream(void* stream) { (void)stream; }
+    // non-zero after a device error; the planner stops and reports it
+    virtual int error() const { return 0; }
+};
+
+}  // namespace gfech

@@ -1,0 +1,883 @@
+// The Chief (Section 3, "The Chief"): Step 1 (ClearDown, Extend, UpdateRow,
+// UpdateRowTrafo), Step 2 (RowLengthen) and Step 3 (PreClearUp, Copy,
+// ClearUp), executed layer by layer (layer i + j, Section 5) as grouped jobs.
+//
+// Storage differs from the paper's in one respect, chosen for the GPU: the
+// pivot rows of a block column, the pivot columns of D.gamma and the selected
+// rows of a block row are kept in the order they were found ("append order")
+// instead of sorted order.  The riffles then become appends: RRF with
+// lambda = (0..0 1..1), CRZ = extend with zero columns at the end, ADI =
+// identity columns at the end, RowLengthen = nothing to do.  One permutation
+// when the result is assembled restores the sorted orders of Eq. (2).  Every
+// product the paper computes is computed on the same operands, merely with
+// rows / columns stored in another order.
+//
+// Block-row data are held as panels: block row i's blocks C_i,k for k > j are
+// one a_i x n panel (so UpdateRow(i, j, k) for all k > j is one MAD), and its
+// transformation blocks K_i,h (h <= i) sit side by side in one panel, each in
+// a column range reserved for block row h.  The pivot rows B_j,k and M_j,h of
+// block column j live in rows of one pivot matrix P.
+#include "chief.h"
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+namespace gfech {
+
+Result::~Result() {
+    if (!be) return;
+    be->release(Pfinal);
+    be->release(Kfinal);
+    be->release(upsilon);
+    be->release(upsilon_bar);
+    be->release(varrho);
+    be->release(varrho_bar);
+}
+
+std::vector<int32_t> even_blocks(int64_t total, int64_t target) {
+    std::vector<int32_t> v;
+    if (total <= 0) return v;
+    if (target <= 0 || target >= total) {
+        v.push_back((int32_t)total);
+        return v;
+    }
+    int64_t k = (total + target - 1) / target;
+    for (int64_t i = 0; i < k; ++i) v.push_back((int32_t)(total / k + (i < total % k ? 1 : 0)));
+    return v;
+}
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct Arena {
+    size_t size = 0;
+    size_t take(size_t bytes) {
+        size_t off = size;
+        size += (bytes + kAlign - 1) / kAlign * kAlign;
+        return off;
+    }
+};
+
+struct Ops {
+    std::vector<GemmDesc> gemm;
+    std::vector<GatherDesc> gather;
+    std::vector<ListDesc> lists;
+    std::vector<EchDesc> ech;
+    std::vector<SortDesc> sort;
+    std::vector<FillDesc> fill;
+};
+
+struct TaskState {      // one (i, j) of the current layer
+    int i = 0, j = 0;
+    bool active = false, did_ech = false;
+    int32_t alpha = 0;  // rows of block row i when the layer started
+    int32_t r = 0;      // pivots of block column j before ClearDown
+    int32_t rp = 0;     // new pivots r'
+};
+
+class Plan {
+public:
+    Plan(Backend& be, const Problem& pr, Stats& st) : be_(be), pr_(pr), st_(st) {
+        a_ = (int)pr.row_blocks.size();
+        b_ = (int)pr.col_blocks.size();
+        m_ = pr.m;
+        n_ = pr.n;
+        p_ = pr.p;
+        R0_.assign(a_ + 1, 0);
+        C0_.assign(b_ + 1, 0);
+        for (int i = 0; i < a_; ++i) R0_[i + 1] = R0_[i] + pr.row_blocks[i];
+        for (int j = 0; j < b_; ++j) C0_[j + 1] = C0_[j] + pr.col_blocks[j];
+        alpha_.assign(pr.row_blocks.begin(), pr.row_blocks.end());
+        rankc_.assign(b_, 0);
+        sel_.assign(a_, std::vector<int32_t>(b_, 0));
+        amax_ = a_ ? *std::max_element(pr.row_blocks.begin(), pr.row_blocks.end()) : 0;
+    }
+
+    int layers() const { return (a_ && b_) ? a_ + b_ - 1 : 0; }
+    int blockcols() const { return b_; }
+
+    // ------------------------------------------------------------ memory
+    size_t plan_memory() {
+        Arena ar;
+        rows_.resize(a_);
+        cols_.resize(b_);
+        for (int i = 0; i < a_; ++i) {
+            BR& br = rows_[i];
+            int64_t ai = pr_.row_blocks[i];
+            br.ldC = std::max<int64_t>(n_, 1);
+            br.ldK = R0_[i] + ai;
+            for (int s = 0; s < 2; ++s) {
+                br.oC[s] = ar.take(ai * br.ldC);
+                br.oK[s] = ar.take(ai * br.ldK);
+                br.oU[s] = ar.take(sizeof(int32_t) * ai);
+            }
+            br.oE = ar.take(sizeof(int32_t) * ai);
+        }
+        int64_t prow = 0;
+        for (int j = 0; j < b_; ++j) {
+            BC& bc = cols_[j];
+            int64_t bj = pr_.col_blocks[j];
+            bc.cap = std::min<int64_t>(bj, m_);
+            bc.ld = bj;
+            bc.prow0 = prow;
+            prow += bc.cap;
+            for (int s = 0; s < 2; ++s) {
+                bc.oDR[s] = ar.take(bc.cap * bj);
+                bc.oGbar[s] = ar.take(sizeof(int32_t) * bj);
+            }
+            bc.oGam = ar.take(sizeof(int32_t) * bj);
+            bc.oAA = ar.take(amax_ * bj);
+            bc.oH = ar.take(amax_ * bj);
+            bc.ldW = 2 * bj;
+            bc.oW = ar.take(amax_ * bc.ldW);
+            bc.oAM = ar.take(bj * bj);
+            bc.oAK = ar.take(amax_ * bj);
+            bc.oAE = ar.take(bc.cap * bj);
+            bc.oProw = ar.take(sizeof(int32_t) * std::max<int64_t>(amax_, 1));
+            bc.oQrow = ar.take(sizeof(int32_t) * std::max<int64_t>(amax_, 1));
+            bc.oPcol = ar.take(sizeof(int32_t) * bj);
+            bc.oQcol = ar.take(sizeof(int32_t) * bj);
+        }
+        prow_total_ = prow;
+        ldP_ = n_ + m_;
+        oP_ = ar.take(prow_total_ * ldP_);
+        arena_bytes_ = ar.size;
+        return ar.size;
+    }
+
+    void bind(uint8_t* base, int32_t* counts) {
+        base_ = base;
+        counts_ = counts;
+        for (auto& br : rows_) {
+            for (int s = 0; s < 2; ++s) {
+                br.C[s] = base + br.oC[s];
+                br.K[s] = base + br.oK[s];
+                br.U[s] = (int32_t*)(base + br.oU[s]);
+            }
+            br.E = (int32_t*)(base + br.oE);
+        }
+        for (auto& bc : cols_) {
+            for (int s = 0; s < 2; ++s) {
+                bc.DR[s] = base + bc.oDR[s];
+                bc.Gbar[s] = (int32_t*)(base + bc.oGbar[s]);
+            }
+            bc.Gam = (int32_t*)(base + bc.oGam);
+            bc.AA = base + bc.oAA;
+            bc.H = base + bc.oH;
+            bc.W = base + bc.oW;
+            bc.AM = base + bc.oAM;
+            bc.AK = base + bc.oAK;
+            bc.AE = base + bc.oAE;
+            bc.Prow = (int32_t*)(base + bc.oProw);
+            bc.Qrow = (int32_t*)(base + bc.oQrow);
+            bc.Pcol = (int32_t*)(base + bc.oPcol);
+            bc.Qcol = (int32_t*)(base + bc.oQcol);
+        }
+        P_ = base + oP_;
+    }
+
+    // zero what must start at zero, load the input, initialise the index lists
+    void init(Ops& ops) {
+        be_.zero(P_, (size_t)(prow_total_ * ldP_));
+        for (int i = 0; i < a_; ++i) {
+            BR& br = rows_[i];
+            int64_t ai = pr_.row_blocks[i];
+            be_.zero(br.K[0], (size_t)(ai * br.ldK));
+            be_.zero(br.K[1], (size_t)(ai * br.ldK));
+            if (n_ > 0) {
+                GatherDesc g;
+                g.rows = (int32_t)ai;
+                g.cols = (int32_t)n_;
+                g.src = pr_.A + R0_[i] * pr_.lda;
+                g.lds = pr_.lda;
+                g.dst = br.C[0];
+                g.ldd = br.ldC;
+                ops.gather.push_back(g);
+            }
+            std::vector<int32_t> io(ai);
+            std::iota(io.begin(), io.end(), 0);
+            if (ai) be_.upload(br.U[0], io.data(), sizeof(int32_t) * ai);
+        }
+        for (int j = 0; j < b_; ++j) {
+            int64_t bj = pr_.col_blocks[j];
+            std::vector<int32_t> io(bj);
+            std::iota(io.begin(), io.end(), 0);
+            be_.upload(cols_[j].Gbar[0], io.data(), sizeof(int32_t) * bj);
+        }
+    }
+
+    // ------------------------------------------------------------ Step 1, one layer
+    void begin_layer(int L) {
+        tasks_.clear();
+        int ilo = std::max(0, L - b_ + 1), ihi = std::min(a_ - 1, L);
+        for (int i = ilo; i <= ihi; ++i) {
+            TaskState t;
+            t.i = i;
+            t.j = L - i;
+            t.alpha = alpha_[i];
+            t.r = rankc_[t.j];
+            t.active = t.alpha > 0;
+            tasks_.push_back(t);
+        }
+    }
+
+    // ClearDown: CEX of C by D.gamma (A.A and A')
+    void cd_extract(Ops& ops) {
+        for (auto& t : tasks_) {
+            if (!t.active) continue;
+            BR& br = rows_[t.i];
+            BC& bc = cols_[t.j];
+            int32_t bj = pr_.col_blocks[t.j];
+            const uint8_t* Cij = br.C[br.cur] + C0_[t.j];
+            if (t.r > 0) {
+                GatherDesc g;
+                g.rows = t.alpha; g.cols = t.r;
+                g.src = Cij; g.lds = br.ldC; g.scol = bc.Gam;
+                g.dst = bc.AA; g.ldd = bj;
+                ops.gather.push_back(g);
+                st_.gather_bytes += 2.0 * t.alpha * t.r;
+                if (bj - t.r > 0) {
+                    GatherDesc h = g;
+                    h.cols = bj - t.r; h.scol = bc.Gbar[bc.gcur];
+                    h.dst = bc.H;
+                    ops.gather.push_back(h);
+                    st_.gather_bytes += 2.0 * t.alpha * (bj - t.r);
+                }
+            }
+        }
+    }
+
+    // ClearDown's first MAD (H = A' + A.A * D.R) and UpdateRow / UpdateRowTrafo step (1)
+    void cd_mad_ur1(Ops& ops) {
+        for (auto& t : tasks_) {
+            if (!t.active || t.r == 0) continue;
+            BR& br = rows_[t.i];
+            BC& bc = cols_[t.j];
+            int32_t bj = pr_.col_blocks[t.j];
+            if (bj - t.r > 0) {
+                GemmDesc g;
+                g.M = t.alpha; g.N = bj - t.r; g.K = t.r; g.p = p_;
+                g.A = bc.AA; g.lda = bj;
+                g.B = bc.DR[bc.dcur]; g.ldb = bc.ld;
+                g.C = bc.H; g.ldc = bj; g.D = bc.H; g.ldd = bj;
+                push_gemm(ops, g, st_.cd_mad);
+            }
+            // (1) Z := C + A.A * B over all blocks k > j of the panel
+            int64_t c0 = C0_[t.j + 1];
+            if (n_ - c0 > 0) {
+                GemmDesc g;
+                g.M = t.alpha; g.N = (int32_t)(n_ - c0); g.K = t.r; g.p = p_;
+                g.A = bc.AA; g.lda = bj;
+                g.B = P_ + bc.prow0 * ldP_ + c0; g.ldb = ldP_;
+                g.C = br.C[br.cur] + c0; g.ldc = br.ldC;
+                g.D = br.C[br.cur] + c0; g.ldd = br.ldC;
+                push_gemm(ops, g, st_.ur_mad);
+            }
+            // URT (1), h != i: Z := K + A.A * M   (K's new columns are the zero columns CRZ adds)
+            for (int h = 0; h < t.i; ++h) {
+                int32_t w = sel_[h][t.j];
+                if (w == 0) continue;
+                GemmDesc g;
+                g.M = t.alpha; g.N = w; g.K = t.r; g.p = p_;
+                g.A = bc.AA; g.lda = bj;
+                g.B = P_ + bc.prow0 * ldP_ + n_ + R0_[h]; g.ldb = ldP_;
+                g.C = br.K[br.cur] + R0_[h]; g.ldc = br.ldK;
+                g.D = br.K[br.cur] + R0_[h]; g.ldd = br.ldK;
+                push_gemm(ops, g, st_.urt_mad);
+            }
+        }
+    }
+
+    // ClearDown's ECH
+    void cd_ech(Ops& ops) {
+        for (auto& t : tasks_) {
+            if (!t.active) continue;
+            BR& br = rows_[t.i];
+            BC& bc = cols_[t.j];
+            int32_t bj = pr_.col_blocks[t.j];
+            if (bj - t.r == 0) continue;
+            EchDesc e;
+            e.rows = t.alpha; e.cols = bj - t.r; e.p = p_;
+            if (t.r > 0) { e.H = bc.H; e.ldh = bj; }
+            else { e.H = br.C[br.cur] + C0_[t.j]; e.ldh = br.ldC; }
+            e.work = bc.W; e.ldw = bc.ldW;
+            e.rcount = counts_ + t.j;
+            e.prow = bc.Prow; e.qrow = bc.Qrow; e.pcol = bc.Pcol; e.qcol = bc.Qcol;
+            e.Mo = bc.AM; e.ldm = bj;
+            e.Ko = bc.AK; e.ldk = bj;
+            e.Ro = bc.DR[1 - bc.dcur] + (int64_t)t.r * bc.ld; e.ldr = bc.ld;
+            ops.ech.push_back(e);
+            t.did_ech = true;
+        }
+    }
+
+    bool any_ech() const {
+        for (auto& t : tasks_) if (t.did_ech) return true;
+        return false;
+    }
+
+    void absorb_counts(const int32_t* host_counts) {
+        for (auto& t : tasks_) {
+            t.rp = t.did_ech ? host_counts[t.j] : 0;
+            if (t.did_ech) {
+                int32_t bj = pr_.col_blocks[t.j];
+                st_.ech += (double)t.alpha * (bj - t.r) * t.rp;
+                st_.echs += 1;
+            }
+        }
+    }
+
+    // ClearDown after ECH: CEX of D.R by gamma' (A.E and R'), UNH on D.gamma, Extend on E.rho
+    void cd_post(Ops& ops) {
+        for (auto& t : tasks_) {
+            if (!t.active || t.rp == 0) continue;
+            BR& br = rows_[t.i];
+            BC& bc = cols_[t.j];
+            int32_t bj = pr_.col_blocks[t.j];
+            int32_t rest = bj - t.r - t.rp;
+            if (t.r > 0) {
+                GatherDesc g;
+                g.rows = t.r; g.cols = t.rp;
+                g.src = bc.DR[bc.dcur]; g.lds = bc.ld; g.scol = bc.Pcol;
+                g.dst = bc.AE; g.ldd = bj;
+                ops.gather.push_back(g);
+                st_.gather_bytes += 2.0 * t.r * t.rp;
+                if (rest > 0) {
+                    GatherDesc h = g;
+                    h.cols = rest; h.scol = bc.Qcol;
+                    h.dst = bc.DR[1 - bc.dcur]; h.ldd = bc.ld;
+                    ops.gather.push_back(h);
+                    st_.gather_bytes += 2.0 * t.r * rest;
+                }
+            }
+            // UNH(D.gamma, gamma'): new pivots appended, complement filtered
+            ListDesc lg;
+            lg.npick = t.rp; lg.nkeep = rest; lg.map = bc.Gbar[bc.gcur];
+            lg.pick = bc.Pcol; lg.append = bc.Gam + t.r;
+            lg.keep = bc.Qcol; lg.keep_out = bc.Gbar[1 - bc.gcur];
+            ops.lists.push_back(lg);
+            // Extend: UNH(E.rho, A.rho') in original local row numbers
+            int32_t prev = t.j ? sel_[t.i][t.j - 1] : 0;
+            ListDesc le;
+            le.npick = t.rp; le.nkeep = t.alpha - t.rp; le.map = br.U[br.ucur];
+            le.pick = bc.Prow; le.append = br.E + prev;
+            le.keep = bc.Qrow; le.keep_out = br.U[1 - br.ucur];
+            ops.lists.push_back(le);
+        }
+    }
+
+    // ClearDown's second MAD: R' := R' + A.E * R   (RRF = [R'; R] in append order)
+    void cd_mad2(Ops& ops) {
+        for (auto& t : tasks_) {
+            if (!t.active || t.rp == 0 || t.r == 0) continue;
+            BC& bc = cols_[t.j];
+            int32_t bj = pr_.col_blocks[t.j];
+            int32_t rest = bj - t.r - t.rp;
+            if (rest == 0) continue;
+            GemmDesc g;
+            g.M = t.r; g.N = rest; g.K = t.rp; g.p = p_;
+            g.A = bc.AE; g.lda = bj;
+            g.B = bc.DR[1 - bc.dcur] + (int64_t)t.r * bc.ld; g.ldb = bc.ld;
+            g.C = bc.DR[1 - bc.dcur]; g.ldc = bc.ld;
+            g.D = bc.DR[1 - bc.dcur]; g.ldd = bc.ld;
+            push_gemm(ops, g, st_.cd_mad);
+        }
+    }
+
+    // host bookkeeping once the layer's ClearDowns are complete
+    void cd_commit() {
+        for (auto& t : tasks_) {
+            int32_t prev = t.j ? sel_[t.i][t.j - 1] : 0;
+            sel_[t.i][t.j] = prev + t.rp;
+            if (!t.active || t.rp == 0) continue;
+            BR& br = rows_[t.i];
+            BC& bc = cols_[t.j];
+            rankc_[t.j] += t.rp;
+            alpha_[t.i] -= t.rp;
+            bc.dcur ^= 1;
+            bc.gcur ^= 1;
+            br.ucur ^= 1;
+        }
+    }
+
+    // UpdateRow / UpdateRowTrafo step (3): X := A.M * V with V = rho' Z (and ADI for h = i)
+    void ur3(Ops& ops) {
+        for (auto& t : tasks_) {
+            if (!t.active || t.rp == 0) continue;
+            BR& br = rows_[t.i];
+            BC& bc = cols_[t.j];
+            int32_t bj = pr_.col_blocks[t.j];
+            uint8_t* X = P_ + (bc.prow0 + t.r) * ldP_;
+            int64_t c0 = C0_[t.j + 1];
+            if (n_ - c0 > 0) {
+                GemmDesc g;
+                g.M = t.rp; g.N = (int32_t)(n_ - c0); g.K = t.rp; g.p = p_;
+                g.A = bc.AM; g.lda = bj;
+                g.B = br.C[br.cur] + c0; g.ldb = br.ldC; g.brow = bc.Prow;
+                g.D = X + c0; g.ldd = ldP_;
+                push_gemm(ops, g, st_.ur_mad);
+            }
+            for (int h = 0; h <= t.i; ++h) {
+                int32_t w = (h < t.i) ? sel_[h][t.j] : (t.j ? sel_[t.i][t.j - 1] : 0);
+                if (w > 0) {
+                    GemmDesc g;
+                    g.M = t.rp; g.N = w; g.K = t.rp; g.p = p_;
+                    g.A = bc.AM; g.lda = bj;
+                    g.B = br.K[br.cur] + R0_[h]; g.ldb = br.ldK; g.brow = bc.Prow;
+                    g.D = X + n_ + R0_[h]; g.ldd = ldP_;
+                    push_gemm(ops, g, st_.urt_mad);
+                }
+                if (h == t.i) {
+                    // V's identity columns (ADI) make X := A.M there
+                    GatherDesc c;
+                    c.rows = t.rp; c.cols = t.rp;
+                    c.src = bc.AM; c.lds = bj;
+                    c.dst = X + n_ + R0_[h] + w; c.ldd = ldP_;
+                    ops.gather.push_back(c);
+                    st_.gather_bytes += 2.0 * t.rp * t.rp;
+                }
+            }
+        }
+    }
+
+    // step (4): S := B + A.E * X  (for h = i the stored M block is zero), RRF = append
+    void ur4(Ops& ops) {
+        for (auto& t : tasks_) {
+            if (!t.active || t.rp == 0 || t.r == 0) continue;
+            BC& bc = cols_[t.j];
+            int32_t bj = pr_.col_blocks[t.j];
+            uint8_t* Brow = P_ + bc.prow0 * ldP_;
+            uint8_t* X = P_ + (bc.prow0 + t.r) * ldP_;
+            int64_t c0 = C0_[t.j + 1];
+            if (n_ - c0 > 0) {
+                GemmDesc g;
+                g.M = t.r; g.N = (int32_t)(n_ - c0); g.K = t.rp; g.p = p_;
+                g.A = bc.AE; g.lda = bj;
+                g.B = X + c0; g.ldb = ldP_;
+                g.C = Brow + c0; g.ldc = ldP_; g.D = Brow + c0; g.ldd = ldP_;
+                push_gemm(ops, g, st_.ur_mad);
+            }
+            for (int h = 0; h <= t.i; ++h) {
+                int32_t w = sel_[h][t.j];
+                if (w == 0) continue;
+                GemmDesc g;
+                g.M = t.r; g.N = w; g.K = t.rp; g.p = p_;
+                g.A = bc.AE; g.lda = bj;
+                g.B = X + n_ + R0_[h]; g.ldb = ldP_;
+                g.C = Brow + n_ + R0_[h]; g.ldc = ldP_; g.D = Brow + n_ + R0_[h]; g.ldd = ldP_;
+                push_gemm(ops, g, st_.urt_mad);
+            }
+        }
+    }
+
+    // step (6): C := W + A.K * V with W = rho'-bar Z, written compacted to the other panel
+    void ur6(Ops& ops) {
+        for (auto& t : tasks_) {
+            if (!t.active || t.rp == 0) continue;
+            BR& br = rows_[t.i];
+            BC& bc = cols_[t.j];
+            int32_t bj = pr_.col_blocks[t.j];
+            int32_t left = t.alpha - t.rp;
+            if (left == 0) continue;
+            int64_t c0 = C0_[t.j + 1];
+            if (n_ - c0 > 0) {
+                GemmDesc g;
+                g.M = left; g.N = (int32_t)(n_ - c0); g.K = t.rp; g.p = p_;
+                g.A = bc.AK; g.lda = bj;
+                g.B = br.C[br.cur] + c0; g.ldb = br.ldC; g.brow = bc.Prow;
+                g.C = br.C[br.cur] + c0; g.ldc = br.ldC; g.crow = bc.Qrow;
+                g.D = br.C[1 - br.cur] + c0; g.ldd = br.ldC;
+                push_gemm(ops, g, st_.ur_mad);
+            }
+            for (int h = 0; h <= t.i; ++h) {
+                int32_t w = (h < t.i) ? sel_[h][t.j] : (t.j ? sel_[t.i][t.j - 1] : 0);
+                if (w > 0) {
+                    GemmDesc g;
+                    g.M = left; g.N = w; g.K = t.rp; g.p = p_;
+                    g.A = bc.AK; g.lda = bj;
+                    g.B = br.K[br.cur] + R0_[h]; g.ldb = br.ldK; g.brow = bc.Prow;
+                    g.C = br.K[br.cur] + R0_[h]; g.ldc = br.ldK; g.crow = bc.Qrow;
+                    g.D = br.K[1 - br.cur] + R0_[h]; g.ldd = br.ldK;
+                    push_gemm(ops, g, st_.urt_mad);
+                }
+                if (h == t.i) {
+                    // V is the identity on the new columns and W is zero there: K := A.K
+                    GatherDesc c;
+                    c.rows = left; c.cols = t.rp;
+                    c.src = bc.AK; c.lds = bj;
+                    c.dst = br.K[1 - br.cur] + R0_[h] + w; c.ldd = br.ldK;
+                    ops.gather.push_back(c);
+                    st_.gather_bytes += 2.0 * left * t.rp;
+                }
+            }
+        }
+    }
+
+    void ur_commit() {
+        for (auto& t : tasks_) {
+            if (!t.active || t.rp == 0) continue;
+            rows_[t.i].cur ^= 1;   // the compacted panels are now current
+        }
+    }
+
+    // ------------------------------------------------------------ assembly, Step 2, Step 3
+    int64_t rank() const {
+        int64_t r = 0;
+        for (int32_t x : rankc_) r += x;
+        return r;
+    }
+
+    // allocate the result and emit the index sorts of the final orders
+    bool assemble_lists(Result& res, Ops& ops) {
+        r_ = rank();
+        res.m = m_; res.n = n_; res.r = r_; res.p = p_;
+        res.row_blocks = pr_.row_blocks;
+        res.col_blocks = pr_.col_blocks;
+        res.ldP = n_ + r_;
+        res.ldK = r_;
+        auto ialloc = [&](int64_t cnt) { return (int32_t*)be_.alloc(sizeof(int32_t) * std::max<int64_t>(cnt, 1)); };
+        res.Pfinal = (uint8_t*)be_.alloc((size_t)std::max<int64_t>(r_ * res.ldP, 1));
+        res.Kfinal = (uint8_t*)be_.alloc((size_t)std::max<int64_t>((m_ - r_) * r_, 1));
+        res.upsilon = ialloc(r_);
+        res.upsilon_bar = ialloc(n_ - r_);
+        res.varrho = ialloc(r_);
+        res.varrho_bar = ialloc(m_ - r_);
+        rowmap_ = ialloc(r_);
+        colmap_ = ialloc(n_ + r_);
+        kmap_ = ialloc(r_);
+        ordj_ = ialloc(r_);
+        if (!res.Pfinal || !res.Kfinal || !res.upsilon || !res.upsilon_bar || !res.varrho || !res.varrho_bar ||
+            !rowmap_ || !colmap_ || !kmap_ || !ordj_)
+            return false;
+        // block column offsets in the final orders
+        rowoff_.assign(b_ + 1, 0);
+        noff_.assign(b_ + 1, 0);
+        for (int j = 0; j < b_; ++j) {
+            rowoff_[j + 1] = rowoff_[j] + rankc_[j];
+            noff_[j + 1] = noff_[j] + (pr_.col_blocks[j] - rankc_[j]);
+        }
+        soff_.assign(a_ + 1, 0);
+        uoff_.assign(a_ + 1, 0);
+        for (int h = 0; h < a_; ++h) {
+            soff_[h + 1] = soff_[h] + (b_ ? sel_[h][b_ - 1] : 0);
+            uoff_[h + 1] = uoff_[h] + alpha_[h];
+        }
+        for (int j = 0; j < b_; ++j) {
+            BC& bc = cols_[j];
+            int32_t rj = rankc_[j], nj = pr_.col_blocks[j] - rj;
+            if (rj > 0) {
+                SortDesc s;
+                s.n = rj; s.vals = bc.Gam;
+                s.mode = 1; s.add = 0; s.out = ordj_ + rowoff_[j];
+                ops.sort.push_back(s);
+                s.mode = 1; s.add = (int32_t)bc.prow0; s.out = rowmap_ + rowoff_[j];
+                ops.sort.push_back(s);
+                s.mode = 0; s.add = (int32_t)C0_[j]; s.out = colmap_ + rowoff_[j];
+                ops.sort.push_back(s);
+                s.out = res.upsilon + rowoff_[j];
+                ops.sort.push_back(s);
+            }
+            if (nj > 0) {
+                ListDesc l;
+                l.npick = nj; l.add = (int32_t)C0_[j]; l.map = bc.Gbar[bc.gcur];
+                l.append = colmap_ + r_ + noff_[j];
+                ops.lists.push_back(l);
+                l.append = res.upsilon_bar + noff_[j];
+                ops.lists.push_back(l);
+            }
+        }
+        for (int h = 0; h < a_; ++h) {
+            BR& br = rows_[h];
+            int32_t sh = soff_[h + 1] - soff_[h];
+            if (sh > 0) {
+                SortDesc s;
+                s.n = sh; s.vals = br.E;
+                s.mode = 1; s.add = (int32_t)(n_ + R0_[h]); s.out = colmap_ + n_ + soff_[h];
+                ops.sort.push_back(s);
+                s.mode = 1; s.add = (int32_t)R0_[h]; s.out = kmap_ + soff_[h];
+                ops.sort.push_back(s);
+                s.mode = 0; s.add = (int32_t)R0_[h]; s.out = res.varrho + soff_[h];
+                ops.sort.push_back(s);
+            }
+            if (alpha_[h] > 0) {
+                ListDesc l;
+                l.npick = alpha_[h]; l.add = (int32_t)R0_[h]; l.map = br.U[br.ucur];
+                l.append = res.varrho_bar + uoff_[h];
+                ops.lists.push_back(l);
+            }
+        }
+        if (a_ == 0 || b_ == 0) {
+            // degenerate shapes: every row non-selected / every column non-pivot
+            std::vector<int32_t> io(std::max<int64_t>(m_, n_));
+            std::iota(io.begin(), io.end(), 0);
+            if (m_) be_.upload(res.varrho_bar, io.data(), sizeof(int32_t) * m_);
+            if (n_) be_.upload(res.upsilon_bar, io.data(), sizeof(int32_t) * n_);
+        }
+        return true;
+    }
+
+    // PreClearUp + Copy for every block at once: gather the pivot matrix into
+    // the final [X | R | M] layout (rows ordered by pivot column), then place
+    // the diagonal remnants D_k.R.  RowLengthen (Step 2) is already done:
+    // columns of rows selected later were never written and are zero.
+    void repack(Result& res, Ops& ops) {
+        if (r_ == 0) return;
+        GatherDesc g;
+        g.rows = (int32_t)r_; g.cols = (int32_t)(n_ + r_);
+        g.src = P_; g.lds = ldP_; g.srow = rowmap_; g.scol = colmap_;
+        g.dst = res.Pfinal; g.ldd = res.ldP;
+        ops.gather.push_back(g);
+        st_.gather_bytes += 2.0 * r_ * (n_ + r_);
+    }
+
+    void repack_diag(Result& res, Ops& ops) {
+        for (int j = 0; j < b_; ++j) {
+            BC& bc = cols_[j];
+            int32_t rj = rankc_[j], nj = pr_.col_blocks[j] - rj;
+            if (rj == 0 || nj == 0) continue;
+            GatherDesc g;
+            g.rows = rj; g.cols = nj;
+            g.src = bc.DR[bc.dcur]; g.lds = bc.ld; g.srow = ordj_ + rowoff_[j];
+            g.dst = res.Pfinal + rowoff_[j] * res.ldP + r_ + noff_[j]; g.ldd = res.ldP;
+            ops.gather.push_back(g);
+        }
+        // K: (m - r) x r, rows = the final non-selected rows of each block row,
+        // columns = selected rows in ascending order (zero for block rows h > i)
+        if (m_ - r_ > 0 && r_ > 0) {
+            FillDesc f;
+            f.rows = (int32_t)(m_ - r_); f.cols = (int32_t)r_;
+            f.dst = res.Kfinal; f.ldd = res.ldK;
+            ops.fill.push_back(f);
+        }
+    }
+
+    void k_assemble(Result& res, Ops& ops) {
+        if (m_ - r_ == 0 || r_ == 0) return;
+        for (int i = 0; i < a_; ++i) {
+            BR& br = rows_[i];
+            int32_t cols = soff_[i + 1];
+            if (alpha_[i] == 0 || cols == 0) continue;
+            GatherDesc g;
+            g.rows = alpha_[i]; g.cols = cols;
+            g.src = br.K[br.cur]; g.lds = br.ldK; g.scol = kmap_;
+            g.dst = res.Kfinal + uoff_[i] * res.ldK; g.ldd = res.ldK;
+            ops.gather.push_back(g);
+            st_.gather_bytes += 2.0 * alpha_[i] * cols;
+        }
+    }
+
+    // Step 3, layer k (block columns from b down to 2): for all j < k at once,
+    // [R_{j,l>=k} | M_j] += X_jk * [R_{k,l>=k} | M_k]
+    void clearup(Result& res, int k, Ops& ops) {
+        if (k <= 0 || k >= b_) return;
+        int64_t above = rowoff_[k];
+        int32_t rk = rankc_[k];
+        if (above == 0 || rk == 0) return;
+        int64_t c0 = r_ + noff_[k];
+        int64_t width = n_ + r_ - c0;
+        if (width <= 0) return;
+        GemmDesc g;
+        g.M = (int32_t)above; g.N = (int32_t)width; g.K = rk; g.p = p_;
+        g.A = res.Pfinal + rowoff_[k]; g.lda = res.ldP;
+        g.B = res.Pfinal + rowoff_[k] * res.ldP + c0; g.ldb = res.ldP;
+        g.C = res.Pfinal + c0; g.ldc = res.ldP;
+        g.D = res.Pfinal + c0; g.ldd = res.ldP;
+        push_gemm(ops, g, st_.cu_mad);
+    }
+
+    void release_maps() {
+        be_.release(rowmap_);
+        be_.release(colmap_);
+        be_.release(kmap_);
+        be_.release(ordj_);
+        rowmap_ = colmap_ = kmap_ = ordj_ = nullptr;
+    }
+
+    size_t arena_bytes() const { return arena_bytes_; }
+
+private:
+    struct BR {
+        size_t oC[2] = {0, 0}, oK[2] = {0, 0}, oU[2] = {0, 0}, oE = 0;
+        uint8_t* C[2] = {nullptr, nullptr};
+        uint8_t* K[2] = {nullptr, nullptr};
+        int32_t* U[2] = {nullptr, nullptr};
+        int32_t* E = nullptr;
+        int64_t ldC = 0, ldK = 0;
+        int cur = 0, ucur = 0;
+    };
+    struct BC {
+        size_t oDR[2] = {0, 0}, oGbar[2] = {0, 0}, oGam = 0, oAA = 0, oH = 0, oW = 0, oAM = 0, oAK = 0, oAE = 0;
+        size_t oProw = 0, oQrow = 0, oPcol = 0, oQcol = 0;
+        uint8_t* DR[2] = {nullptr, nullptr};
+        int32_t* Gbar[2] = {nullptr, nullptr};
+        int32_t* Gam = nullptr;
+        uint8_t *AA = nullptr, *H = nullptr, *W = nullptr, *AM = nullptr, *AK = nullptr, *AE = nullptr;
+        int32_t *Prow = nullptr, *Qrow = nullptr, *Pcol = nullptr, *Qcol = nullptr;
+        int64_t cap = 0, ld = 0, ldW = 0, prow0 = 0;
+        int dcur = 0, gcur = 0;
+    };
+
+    void push_gemm(Ops& ops, const GemmDesc& g, double& counter) {
+        if (g.M <= 0 || g.N <= 0) return;
+        ops.gemm.push_back(g);
+        counter += (double)g.M * g.N * g.K;
+    }
+
+    Backend& be_;
+    const Problem& pr_;
+    Stats& st_;
+    int a_ = 0, b_ = 0;
+    int64_t m_ = 0, n_ = 0;
+    int32_t p_ = 0;
+    int32_t amax_ = 0;
+    std::vector<int64_t> R0_, C0_;
+    std::vector<int32_t> alpha_, rankc_;
+    std::vector<std::vector<int32_t>> sel_;   // sel_[h][j] = |E_{h,j}.rho|
+    std::vector<BR> rows_;
+    std::vector<BC> cols_;
+    std::vector<TaskState> tasks_;
+    uint8_t* base_ = nullptr;
+    uint8_t* P_ = nullptr;
+    int32_t* counts_ = nullptr;
+    size_t oP_ = 0, arena_bytes_ = 0;
+    int64_t prow_total_ = 0, ldP_ = 0, r_ = 0;
+    int32_t *rowmap_ = nullptr, *colmap_ = nullptr, *kmap_ = nullptr, *ordj_ = nullptr;
+    std::vector<int64_t> rowoff_, noff_, soff_, uoff_;
+};
+
+void flush(Backend& be, Ops& ops, Stats& st) {
+    if (!ops.gather.empty()) { be.gather(ops.gather); st.launches++; }
+    if (!ops.fill.empty()) { be.fill(ops.fill); st.launches++; }
+    if (!ops.lists.empty()) { be.lists(ops.lists); st.launches++; }
+    if (!ops.sort.empty()) { be.sort(ops.sort); st.launches++; }
+    if (!ops.gemm.empty()) { be.gemm(ops.gemm); st.launches++; st.gemms += (int64_t)ops.gemm.size(); }
+    if (!ops.ech.empty()) { be.ech(ops.ech); st.launches++; }
+    ops = Ops();
+}
+
+}  // namespace
+
+int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::unique_ptr<Result>>& out,
+              std::string* err) {
+    Stats shared;
+    std::vector<Stats> st(probs.size());
+    std::vector<std::unique_ptr<Plan>> plans;
+    plans.reserve(probs.size());
+    size_t total = 0;
+    std::vector<size_t> base_off;
+    int64_t ncounts = 0;
+    std::vector<int64_t> count_off;
+    int maxL = 0;
+    for (size_t q = 0; q < probs.size(); ++q) {
+        plans.emplace_back(new Plan(be, probs[q], st[q]));
+        size_t sz = plans.back()->plan_memory();
+        base_off.push_back(total);
+        total += (sz + kAlign - 1) / kAlign * kAlign;
+        count_off.push_back(ncounts);
+        ncounts += plans.back()->blockcols();
+        maxL = std::max(maxL, plans.back()->layers());
+    }
+    uint8_t* arena = (uint8_t*)be.alloc(std::max<size_t>(total, 1));
+    int32_t* counts = (int32_t*)be.alloc(sizeof(int32_t) * std::max<int64_t>(ncounts, 1));
+    if (!arena || !counts) {
+        be.release(arena);
+        be.release(counts);
+        if (err) *err = "device allocation of the block arena failed";
+        return 4;
+    }
+    std::vector<int32_t> hcounts(std::max<int64_t>(ncounts, 1));
+    Ops ops;
+    for (size_t q = 0; q < plans.size(); ++q) {
+        plans[q]->bind(arena + base_off[q], counts + count_off[q]);
+        plans[q]->init(ops);
+    }
+    flush(be, ops, shared);
+
+    // Step 1, layer by layer
+    for (int L = 0; L < maxL; ++L) {
+        for (auto& pl : plans) pl->begin_layer(L);
+        for (auto& pl : plans) pl->cd_extract(ops);
+        flush(be, ops, shared);
+        for (auto& pl : plans) pl->cd_mad_ur1(ops);
+        flush(be, ops, shared);
+        bool any = false;
+        for (auto& pl : plans) { pl->cd_ech(ops); any = any || pl->any_ech(); }
+        flush(be, ops, shared);
+        if (any) {
+            be.download(hcounts.data(), counts, sizeof(int32_t) * ncounts);
+            shared.syncs++;
+            if (be.error()) break;
+        }
+        for (size_t q = 0; q < plans.size(); ++q) plans[q]->absorb_counts(hcounts.data() + count_off[q]);
+        for (auto& pl : plans) pl->cd_post(ops);
+        flush(be, ops, shared);
+        for (auto& pl : plans) pl->cd_mad2(ops);
+        for (auto& pl : plans) pl->ur3(ops);
+        flush(be, ops, shared);
+        for (auto& pl : plans) pl->cd_commit();
+        for (auto& pl : plans) pl->ur4(ops);
+        flush(be, ops, shared);
+        for (auto& pl : plans) pl->ur6(ops);
+        flush(be, ops, shared);
+        for (auto& pl : plans) pl->ur_commit();
+        shared.layers++;
+    }
+    int rc = be.error();
+    if (rc) {
+        be.release(arena);
+        be.release(counts);
+        if (err) *err = "device error during Step 1";
+        return rc;
+    }
+    // Step 2 is implicit (see the header comment); assembly and Step 3
+    std::vector<std::unique_ptr<Result>> res(plans.size());
+    for (size_t q = 0; q < plans.size(); ++q) {
+        res[q].reset(new Result());
+        res[q]->be = &be;
+        if (!plans[q]->assemble_lists(*res[q], ops)) {
+            flush(be, ops, shared);
+            be.sync();
+            for (auto& pl : plans) pl->release_maps();
+            be.release(arena);
+            be.release(counts);
+            if (err) *err = "device allocation of the result failed";
+            return 4;
+        }
+    }
+    flush(be, ops, shared);
+    for (size_t q = 0; q < plans.size(); ++q) plans[q]->repack(*res[q], ops);
+    flush(be, ops, shared);
+    for (size_t q = 0; q < plans.size(); ++q) plans[q]->repack_diag(*res[q], ops);
+    flush(be, ops, shared);
+    for (size_t q = 0; q < plans.size(); ++q) plans[q]->k_assemble(*res[q], ops);
+    flush(be, ops, shared);
+    int maxb = 0;
+    for (auto& pr : probs) maxb = std::max(maxb, (int)pr.col_blocks.size());
+    for (int k = maxb - 1; k >= 1; --k) {
+        for (size_t q = 0; q < plans.size(); ++q) plans[q]->clearup(*res[q], k, ops);
+        flush(be, ops, shared);
+    }
+    be.sync();
+    rc = be.error();
+    for (auto& pl : plans) pl->release_maps();
+    be.release(arena);
+    be.release(counts);
+    if (rc) {
+        if (err) *err = "device error during assembly / Step 3";
+        return rc;
+    }
+    for (size_t q = 0; q < plans.size(); ++q) {
+        Stats s = st[q];
+        s.layers = shared.layers;
+        s.launches = shared.launches;
+        s.gemms = shared.gemms;
+        s.syncs = shared.syncs;
+        res[q]->stats = s;
+        out.push_back(std::move(res[q]));
+    }
+    return 0;
+}
+
+}  // namespace gfech

@@ -1,0 +1,65 @@
+// The Chief (Section 3): the plan of ClearDown / Extend / UpdateRow /
+// UpdateRowTrafo tasks (Step 1), RowLengthen (Step 2) and PreClearUp / Copy /
+// ClearUp (Step 3) over a block grid, executed layer by layer (layer = i + j,
+// Section 5) as grouped launches on a Backend.
+#pragma once
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "backend.h"
+
+namespace gfech {
+
+// Algorithmic multiply-adds per task kind, using the cost model of Section 5
+// (a product (x by y)(y by z) costs xyz, echelonising x by y of rank r costs xyr).
+struct Stats {
+    double cd_mad = 0;     // ClearDown's two MADs
+    double ech = 0;        // ECH jobs
+    double ur_mad = 0;     // UpdateRow MADs / MULs on the data blocks
+    double urt_mad = 0;    // UpdateRowTrafo MADs / MULs on the transformation blocks
+    double cu_mad = 0;     // ClearUp MADs (Step 3)
+    double gather_bytes = 0;   // bytes moved by extracts / riffles / copies
+    int64_t layers = 0, echs = 0, gemms = 0, launches = 0, syncs = 0;
+    double total_mac() const { return cd_mad + ech + ur_mad + urt_mad + cu_mad; }
+};
+
+// Device-resident result (library-owned).
+struct Result {
+    Backend* be = nullptr;
+    int64_t m = 0, n = 0, r = 0;
+    int32_t p = 0;
+    // Pfinal: r x (n + r), leading dimension ldP.  Columns [0, r) are scratch
+    // (the cleared X blocks), [r, n) hold the remnant R (Eq. (3), rows ordered by
+    // pivot column, columns = non-pivot columns ascending), [n, n + r) hold M
+    // (columns ordered by selected row).
+    uint8_t* Pfinal = nullptr; int64_t ldP = 0;
+    uint8_t* Kfinal = nullptr; int64_t ldK = 0;   // (m - r) x r
+    int32_t* upsilon = nullptr;      // r pivot columns, ascending
+    int32_t* upsilon_bar = nullptr;  // n - r
+    int32_t* varrho = nullptr;       // r selected rows, ascending
+    int32_t* varrho_bar = nullptr;   // m - r
+    Stats stats;
+    std::vector<int32_t> row_blocks, col_blocks;
+    ~Result();
+};
+
+struct Problem {
+    const uint8_t* A = nullptr;   // backend address of the m x n input
+    int64_t m = 0, n = 0, lda = 0;
+    int32_t p = 0;
+    std::vector<int32_t> row_blocks, col_blocks;   // a_i and b_j (sums m and n)
+};
+
+// Choose block sizes: blocks of `target` rows / columns, the last one taking
+// the remainder (Section 3.1).  target <= 0 means a single block.
+std::vector<int32_t> even_blocks(int64_t total, int64_t target);
+
+// Run the whole method on a set of independent problems in lockstep (their
+// jobs share launches).  Returns 0 or a backend error code; results are
+// appended to `out` in problem order.
+int run_chief(Backend& be, const std::vector<Problem>& probs,
+              std::vector<std::unique_ptr<Result>>& out, std::string* err);
+
+}  // namespace gfech

@@ -1,0 +1,174 @@
+"""The Chief's bookkeeping (Steps 1-3, append orders, the UpdateRowTrafo case
+table) through the C ABI, run on the test-only CPU emulator backend and
+compared with the oracle bit for bit, for every kind of blocking."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import emu
+from tests import _pins as P
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return emu.library()
+
+
+def compare(o, e, where=""):
+    assert o.rank == e.rank, where
+    assert np.array_equal(o.gamma, e.gamma), where
+    assert np.array_equal(o.rho, e.rho), where
+    assert np.array_equal(o.R, e.R), where
+    assert np.array_equal(o.M, e.M), where
+    assert np.array_equal(o.K, e.K), where
+    assert np.array_equal(o.E, e.E), where
+    assert np.array_equal(o.T, e.T), where
+    assert np.array_equal(o.gamma_bar, e.gamma_bar), where
+    assert np.array_equal(o.rho_bar, e.rho_bar), where
+
+
+def test_backend_is_emulator(lib):
+    assert lib.backend_name() == "cpu-emulator"
+
+
+@pytest.mark.parametrize("p", [2, 3, 5, 7, 251])
+def test_random_blockings(lib, p):
+    rng = np.random.default_rng(p)
+    for trial in range(60):
+        m = int(rng.integers(1, 17))
+        n = int(rng.integers(1, 17))
+        A = rng.integers(0, p, (m, n)).astype(np.uint8)
+        if trial % 3 == 0 and m > 2:
+            k = int(rng.integers(1, m))
+            rows = rng.choice(m, size=k, replace=False)
+            others = np.setdiff1d(np.arange(m), rows)
+            A[rows] = P.matmul_mod(rng.integers(0, p, (k, len(others))), A[others], p)
+        br = int(rng.integers(1, 7))
+        bc = int(rng.integers(1, 7))
+        o = lib.echelonise(A, p, block_rows=br, block_cols=bc).outputs()
+        compare(o, oracle.echelonize(A, p), f"p={p} {m}x{n} blocks {br}x{bc}")
+
+
+def test_every_blocking_of_one_matrix(lib):
+    """Outputs are identical for every blocking, from 1x1 blocks to one block."""
+    p = 3
+    A = synth.deficient(0, 7, 9, 11, p)
+    e = oracle.echelonize(A, p)
+    for br in range(1, 10):
+        for bc in range(1, 12):
+            compare(lib.echelonise(A, p, block_rows=br, block_cols=bc).outputs(), e, f"{br}x{bc}")
+
+
+@pytest.mark.parametrize("shape", [(40, 40), (24, 60), (60, 24), (33, 47)])
+@pytest.mark.parametrize("p", [2, 7, 251])
+def test_larger_shapes(lib, shape, p):
+    m, n = shape
+    A = synth.uniform(1, 0, m, n, p)
+    A[m // 2] = A[1]                       # a duplicate row
+    A[:, n // 3] = 0                       # a zero column
+    e = oracle.echelonize(A, p)
+    for bs in (5, 8, 13):
+        compare(lib.echelonise(A, p, block_rows=bs, block_cols=bs + 2).outputs(), e, f"bs={bs}")
+
+
+def test_low_rank_product(lib):
+    p = 7
+    A = synth.low_rank_product(0, 48, 48, 30, p)
+    e = oracle.echelonize(A, p)
+    assert e.rank <= 30
+    compare(lib.echelonise(A, p, block_rows=8, block_cols=8).outputs(), e)
+
+
+@pytest.mark.parametrize("p", [2, 3, 251])
+def test_special_matrices(lib, p):
+    for A in (np.zeros((7, 9), np.uint8), np.eye(8, dtype=np.uint8), np.eye(6, 9, 2, dtype=np.uint8),
+              np.ones((5, 5), np.uint8), np.eye(9, 4, -3, dtype=np.uint8)):
+        e = oracle.echelonize(A, p)
+        for bs in (1, 2, 3, 100):
+            compare(lib.echelonise(A, p, block_rows=bs, block_cols=bs).outputs(), e, f"bs={bs}")
+
+
+def test_empty(lib):
+    for shape in ((0, 4), (4, 0), (0, 0)):
+        o = lib.echelonise(np.zeros(shape, np.uint8), 5).outputs()
+        assert o.rank == 0
+        assert o.rho_bar.tolist() == list(range(shape[0]))
+        assert o.gamma_bar.tolist() == list(range(shape[1]))
+
+
+def test_range_and_field_errors(lib):
+    from paper_1806_04211_amd.api import GfechError
+    with pytest.raises(GfechError) as ex:
+        lib.echelonise(np.full((3, 3), 5, np.uint8), 5)
+    assert ex.value.status == 3
+    with pytest.raises(GfechError) as ex:
+        lib.echelonise(np.zeros((3, 3), np.uint8), 9)
+    assert ex.value.status == 2
+
+
+def test_batch_mixed(lib):
+    mix = synth.batch_mix(3, 12, nmin=4, nmax=30)
+    res, sts = lib.echelonise_batch(mix, block_rows=7, block_cols=7)
+    assert all(s == 0 for s in sts)
+    for (A, p), r in zip(mix, res):
+        compare(r.outputs(), oracle.echelonize(A, p))
+
+
+def test_batch_reports_bad_problem(lib):
+    good = (synth.uniform(0, 0, 6, 6, 5), 5)
+    bad = (np.full((3, 3), 9, np.uint8), 7)
+    res, sts = lib.echelonise_batch([good, bad, good])
+    assert sts == [0, 3, 0]
+    assert res[1] is None
+    compare(res[2].outputs(), oracle.echelonize(good[0], 5))
+
+
+# ------------------------------------------------ structure the analysis of Section 5 predicts
+
+def test_full_rank_transform_is_inverse(lib):
+    p = 251
+    A = synth.uniform(5, 0, 30, 30, p)
+    o = lib.echelonise(A, p, block_rows=6, block_cols=6).outputs()
+    assert o.rank == 30
+    assert np.array_equal(P.matmul_mod(o.T, A, p), np.eye(30))
+    assert np.array_equal(P.matmul_mod(A, o.T, p), np.eye(30))
+
+
+def test_well_conditioned_work_counts(lib):
+    """Theorem 5.4's setting: leading block minors of full rank.  Then only
+    the diagonal ClearDowns echelonise (a ECHs of alpha^3) and UpdateRow
+    never selects rows (r' = 0 off the diagonal)."""
+    p = 251
+    alpha, a = 6, 4
+    n = alpha * a
+    A = synth.uniform(2, 0, n, n, p)
+    for j in range(1, a + 1):          # check the assumption with the oracle
+        assert oracle.echelonize(A[: j * alpha, : j * alpha], p).rank == j * alpha
+    r = lib.echelonise(A, p, block_rows=alpha, block_cols=alpha)
+    st = r.stats()
+    assert st["echs"] == a
+    assert st["mac_ech"] == a * alpha ** 3
+    assert r.rank == n
+
+
+def test_stats_accounting_matches_cost_model_total(lib):
+    """For an invertible matrix with transformation, the work is about n^3
+    multiply-adds (Section 5, proof of Proposition 5.3): between 0.5 n^3 and
+    1.25 n^3 for every blocking."""
+    p = 251
+    n = 36
+    A = synth.uniform(4, 0, n, n, p)
+    assert oracle.echelonize(A, p).rank == n
+    for bs in (4, 6, 9, 12):
+        st = lib.echelonise(A, p, block_rows=bs, block_cols=bs).stats()
+        total = sum(st[k] for k in ("mac_cleardown", "mac_ech", "mac_updaterow", "mac_trafo", "mac_clearup"))
+        assert 0.5 * n ** 3 <= total <= 1.25 * n ** 3, (bs, total / n ** 3)
+
+
+def test_layers(lib):
+    """Step 1 has a + b - 1 layers (Section 5)."""
+    A = synth.uniform(0, 0, 20, 30, 5)
+    st = lib.echelonise(A, 5, block_rows=4, block_cols=6).stats()
+    assert st["layers"] == 5 + 5 - 1
+    assert st["block_rows"] == 5 and st["block_cols"] == 5
