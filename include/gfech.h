@@ -143,6 +143,49 @@ gfech_status gfech_get_stats(const gfech_result* res, gfech_stats* stats);
 
 void gfech_result_free(gfech_result* res);
 
+/* ---------------------------------------------------------------- single jobs
+ * The paper's jobs (Section 4.1) on caller-owned device buffers, for callers
+ * that build their own task graphs and for per-kernel checks.  Inputs must
+ * hold canonical residues < p (not checked: results are unspecified
+ * otherwise); shapes, pointers and p are checked.  Work is ordered on
+ * `stream` (a hipStream_t, NULL = default) and complete on return. */
+
+/* MAD: D = (C + A * B) mod p.  A: M x K (lda); B: K x N (ldb), row t of B is
+ * row brow[t] of the B buffer when brow != NULL (a device int32 array); C:
+ * M x N (ldc) or NULL for zero, row x of C is row crow[x] when crow != NULL;
+ * D: M x N (ldd).  D may equal C when crow == NULL and ldc == ldd; D must not
+ * overlap A or B.  K <= 65536. */
+gfech_status gfech_mad_dev(int64_t M, int64_t N, int64_t K, uint32_t p,
+                           const uint8_t* A, int64_t lda,
+                           const uint8_t* B, int64_t ldb, const int32_t* brow,
+                           const uint8_t* C, int64_t ldc, const int32_t* crow,
+                           uint8_t* D, int64_t ldd, void* stream);
+
+/* Several independent MADs in one launch (same rules per entry). */
+typedef struct gfech_mad_desc {
+    int64_t M, N, K;
+    uint32_t p, reserved;
+    const uint8_t* A; int64_t lda;
+    const uint8_t* B; int64_t ldb; const int32_t* brow;
+    const uint8_t* C; int64_t ldc; const int32_t* crow;
+    uint8_t* D; int64_t ldd;
+} gfech_mad_desc;
+gfech_status gfech_mad_batch_dev(int64_t count, const gfech_mad_desc* descs, void* stream);
+
+/* ECH (Remark 2.3) of one block H (rows x cols, ldh) in device memory.  With
+ * r = rank(H) (returned in *rank, host memory) the device outputs are
+ *   prow[r]        row of the t-th pivot, pivots by increasing column
+ *   qrow[rows - r] non-pivot rows ascending;  pcol[r] pivot columns ascending;
+ *   qcol[cols - r] non-pivot columns ascending
+ *   M (r x r, ldm), K ((rows - r) x r, ldk), R (r x (cols - r), ldr) with
+ *   [[M,0],[K,1]] [H[prow]; H[qrow]] [H[:, pcol] | H[:, qcol]] = [[-1, R],[0,0]]
+ * (columns of M and K follow prow).  Buffers must be sized for r = min(rows, cols).
+ * rows + cols <= 8192. */
+gfech_status gfech_ech_dev(const uint8_t* H, int64_t rows, int64_t cols, int64_t ldh, uint32_t p,
+                           int32_t* prow, int32_t* qrow, int32_t* pcol, int32_t* qcol,
+                           uint8_t* M, int64_t ldm, uint8_t* K, int64_t ldk, uint8_t* R, int64_t ldr,
+                           int64_t* rank, void* stream);
+
 const char* gfech_strerror(gfech_status s);
 /* Detail of the last failure on this thread ("" if none). */
 const char* gfech_last_error(void);

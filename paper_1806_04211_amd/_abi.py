@@ -37,6 +37,12 @@ class Stats(ctypes.Structure):
                 ("block_rows", c_i64), ("block_cols", c_i64)]
 
 
+class MadDesc(ctypes.Structure):
+    _fields_ = [("M", c_i64), ("N", c_i64), ("K", c_i64), ("p", c_u32), ("reserved", c_u32),
+                ("A", vp), ("lda", c_i64), ("B", vp), ("ldb", c_i64), ("brow", vp),
+                ("C", vp), ("ldc", c_i64), ("crow", vp), ("D", vp), ("ldd", c_i64)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "gfech_echelonise_u8": (ctypes.c_int, [vp, c_i64, c_i64, c_i64, c_u32, vp, ctypes.POINTER(vp)]),
@@ -59,6 +65,11 @@ SIGNATURES = {
     "gfech_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "gfech_last_error": (ctypes.c_char_p, []),
     "gfech_backend_name": (ctypes.c_char_p, []),
+    "gfech_mad_dev": (ctypes.c_int, [c_i64, c_i64, c_i64, c_u32, vp, c_i64, vp, c_i64, vp, vp, c_i64, vp, vp,
+                                     c_i64, vp]),
+    "gfech_mad_batch_dev": (ctypes.c_int, [c_i64, vp, vp]),
+    "gfech_ech_dev": (ctypes.c_int, [vp, c_i64, c_i64, c_i64, c_u32, vp, vp, vp, vp, vp, c_i64, vp, c_i64, vp,
+                                     c_i64, i64p, vp]),
 }
 
 

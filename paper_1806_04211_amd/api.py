@@ -185,6 +185,28 @@ class Library:
                                                      ctypes.c_void_p(stream), ctypes.byref(out)))
         return Result(self.lib, out.value)
 
+    def mad_dev(self, M, N, K, p, A, lda, B, ldb, D, ldd, C=0, ldc=0, brow=0, crow=0, stream=0):
+        """MAD job on device addresses: D = (C + A B) mod p (C = 0 means none)."""
+        self._check(self.lib.gfech_mad_dev(M, N, K, p, ctypes.c_void_p(A), lda, ctypes.c_void_p(B), ldb,
+                                           ctypes.c_void_p(brow), ctypes.c_void_p(C), ldc, ctypes.c_void_p(crow),
+                                           ctypes.c_void_p(D), ldd, ctypes.c_void_p(stream)))
+
+    def mad_batch_dev(self, descs, stream=0):
+        """descs: list of dicts with the gfech_mad_desc fields (device addresses)."""
+        arr = (_abi.MadDesc * max(len(descs), 1))()
+        for t, d in enumerate(descs):
+            for k, v in d.items():
+                setattr(arr[t], k, v)
+        self._check(self.lib.gfech_mad_batch_dev(len(descs), arr, ctypes.c_void_p(stream)))
+
+    def ech_dev(self, H, rows, cols, ldh, p, prow, qrow, pcol, qcol, M, ldm, K, ldk, R, ldr, stream=0) -> int:
+        """ECH job on device addresses; returns the rank."""
+        r = ctypes.c_int64()
+        vp = ctypes.c_void_p
+        self._check(self.lib.gfech_ech_dev(vp(H), rows, cols, ldh, p, vp(prow), vp(qrow), vp(pcol), vp(qcol),
+                                           vp(M), ldm, vp(K), ldk, vp(R), ldr, ctypes.byref(r), vp(stream)))
+        return r.value
+
     def echelonise_batch(self, problems, on_device: bool = False, stream: int = 0, block_rows=0, block_cols=0):
         """problems: list of (A, p) with A a host numpy array (on_device=False) or
         (ptr, m, n, lda, p) tuples (on_device=True).  Returns (results, statuses)."""

@@ -428,6 +428,97 @@ void gfech_result_free(gfech_result* res) {
     delete res;
 }
 
+static gfech_status mad_check(const gfech_mad_desc& d) {
+    if (d.M < 0 || d.N < 0 || d.K < 0) return fail(GFECH_E_ARG, "negative MAD size");
+    if (d.M > INT32_MAX || d.N > INT32_MAX || d.K > 65536) return fail(GFECH_E_TOO_BIG, "MAD size too large");
+    if (d.p > 251 || !is_prime(d.p)) return fail(GFECH_E_FIELD, "p must be a prime <= 251");
+    if (d.M == 0 || d.N == 0) return GFECH_OK;
+    if (!d.D || d.ldd < d.N) return fail(GFECH_E_ARG, "bad D");
+    if (d.K > 0 && (!d.A || !d.B || d.lda < d.K || d.ldb < d.N)) return fail(GFECH_E_ARG, "bad A or B");
+    if (d.C && d.ldc < d.N) return fail(GFECH_E_ARG, "bad C");
+    return GFECH_OK;
+}
+
+static gfech::GemmDesc to_gemm(const gfech_mad_desc& d) {
+    gfech::GemmDesc g;
+    g.M = (int32_t)d.M; g.N = (int32_t)d.N; g.K = (int32_t)d.K; g.p = (int32_t)d.p;
+    g.A = d.A; g.lda = d.lda; g.B = d.B; g.ldb = d.ldb; g.brow = d.brow;
+    g.C = d.C; g.ldc = d.ldc; g.crow = d.crow; g.D = d.D; g.ldd = d.ldd;
+    return g;
+}
+
+gfech_status gfech_mad_batch_dev(int64_t count, const gfech_mad_desc* descs, void* stream) {
+    if (count < 0 || (count > 0 && !descs)) return fail(GFECH_E_ARG, "bad MAD batch");
+    std::vector<gfech::GemmDesc> gs;
+    for (int64_t t = 0; t < count; ++t) {
+        gfech_status st = mad_check(descs[t]);
+        if (st) return st;
+        if (descs[t].M && descs[t].N) gs.push_back(to_gemm(descs[t]));
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    gfech_status st = GFECH_OK;
+    gfech::Backend* be = get_backend(&st);
+    if (!be) return st;
+    be->set_stream(stream);
+    if (!gs.empty()) be->gemm(gs);
+    be->sync();
+    be->set_stream(nullptr);
+    return be->error() ? fail(GFECH_E_DEVICE, "device error") : GFECH_OK;
+}
+
+gfech_status gfech_mad_dev(int64_t M, int64_t N, int64_t K, uint32_t p, const uint8_t* A, int64_t lda,
+                           const uint8_t* B, int64_t ldb, const int32_t* brow, const uint8_t* C, int64_t ldc,
+                           const int32_t* crow, uint8_t* D, int64_t ldd, void* stream) {
+    gfech_mad_desc d;
+    memset(&d, 0, sizeof(d));
+    d.M = M; d.N = N; d.K = K; d.p = p;
+    d.A = A; d.lda = lda; d.B = B; d.ldb = ldb; d.brow = brow;
+    d.C = C; d.ldc = ldc; d.crow = crow; d.D = D; d.ldd = ldd;
+    return gfech_mad_batch_dev(1, &d, stream);
+}
+
+gfech_status gfech_ech_dev(const uint8_t* H, int64_t rows, int64_t cols, int64_t ldh, uint32_t p, int32_t* prow,
+                           int32_t* qrow, int32_t* pcol, int32_t* qcol, uint8_t* M, int64_t ldm, uint8_t* K,
+                           int64_t ldk, uint8_t* R, int64_t ldr, int64_t* rank, void* stream) {
+    if (!rank) return fail(GFECH_E_ARG, "rank is NULL");
+    *rank = 0;
+    if (rows < 0 || cols < 0) return fail(GFECH_E_ARG, "negative size");
+    if (rows + cols > 8192) return fail(GFECH_E_TOO_BIG, "block too large for one ECH");
+    if (p > 251 || !is_prime(p)) return fail(GFECH_E_FIELD, "p must be a prime <= 251");
+    if (rows == 0 || cols == 0) return GFECH_OK;
+    int64_t mr = rows < cols ? rows : cols;
+    if (!H || ldh < cols || !prow || !qrow || !pcol || !qcol || !M || !K || !R || ldm < mr || ldk < mr ||
+        ldr < cols)
+        return fail(GFECH_E_ARG, "bad ECH buffers");
+    std::lock_guard<std::mutex> lk(g_mu);
+    gfech_status st = GFECH_OK;
+    gfech::Backend* be = get_backend(&st);
+    if (!be) return st;
+    be->set_stream(stream);
+    int64_t ldw = cols + mr;
+    uint8_t* work = (uint8_t*)be->alloc((size_t)(rows * ldw));
+    int32_t* cnt = (int32_t*)be->alloc(sizeof(int32_t));
+    if (!work || !cnt) {
+        be->release(work);
+        be->release(cnt);
+        be->set_stream(nullptr);
+        return fail(GFECH_E_NOMEM, "ECH workspace");
+    }
+    gfech::EchDesc e;
+    e.rows = (int32_t)rows; e.cols = (int32_t)cols; e.p = (int32_t)p;
+    e.H = H; e.ldh = ldh; e.work = work; e.ldw = ldw; e.rcount = cnt;
+    e.prow = prow; e.qrow = qrow; e.pcol = pcol; e.qcol = qcol;
+    e.Mo = M; e.ldm = ldm; e.Ko = K; e.ldk = ldk; e.Ro = R; e.ldr = ldr;
+    be->ech({e});
+    int32_t r = 0;
+    be->download(&r, cnt, sizeof(int32_t));
+    be->release(work);
+    be->release(cnt);
+    be->set_stream(nullptr);
+    *rank = r;
+    return be->error() ? fail(GFECH_E_DEVICE, "device error") : GFECH_OK;
+}
+
 const char* gfech_strerror(gfech_status s) {
     switch (s) {
         case GFECH_OK: return "ok";

@@ -97,7 +97,7 @@ class Backend {
 public:
     virtual ~Backend() = default;
     virtual const char* name() const = 0;
-    // memory (alloc returns zeroed memory, nullptr on failure)
+    // memory (alloc does not initialise; nullptr on failure)
     virtual void* alloc(size_t bytes) = 0;
     virtual void release(void* ptr) = 0;
     virtual void zero(void* ptr, size_t bytes) = 0;

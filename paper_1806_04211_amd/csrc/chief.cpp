@@ -20,7 +20,9 @@
 #include "chief.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <numeric>
 
 namespace gfech {
@@ -53,8 +55,10 @@ constexpr size_t kAlign = 256;
 
 struct Arena {
     size_t size = 0;
+    std::vector<std::pair<size_t, size_t>> slots;   // (offset, bytes) of every sub-buffer
     size_t take(size_t bytes) {
         size_t off = size;
+        slots.push_back({off, bytes});
         size += (bytes + kAlign - 1) / kAlign * kAlign;
         return off;
     }
@@ -144,38 +148,42 @@ public:
         ldP_ = n_ + m_;
         oP_ = ar.take(prow_total_ * ldP_);
         arena_bytes_ = ar.size;
+        slots_ = ar.slots;
         return ar.size;
     }
 
-    void bind(uint8_t* base, int32_t* counts) {
-        base_ = base;
+    const std::vector<std::pair<size_t, size_t>>& slots() const { return slots_; }
+
+    // at(offset) gives the address of the sub-buffer planned at that offset
+    template <typename At>
+    void bind(At at, int32_t* counts) {
         counts_ = counts;
         for (auto& br : rows_) {
             for (int s = 0; s < 2; ++s) {
-                br.C[s] = base + br.oC[s];
-                br.K[s] = base + br.oK[s];
-                br.U[s] = (int32_t*)(base + br.oU[s]);
+                br.C[s] = at(br.oC[s]);
+                br.K[s] = at(br.oK[s]);
+                br.U[s] = (int32_t*)at(br.oU[s]);
             }
-            br.E = (int32_t*)(base + br.oE);
+            br.E = (int32_t*)at(br.oE);
         }
         for (auto& bc : cols_) {
             for (int s = 0; s < 2; ++s) {
-                bc.DR[s] = base + bc.oDR[s];
-                bc.Gbar[s] = (int32_t*)(base + bc.oGbar[s]);
+                bc.DR[s] = at(bc.oDR[s]);
+                bc.Gbar[s] = (int32_t*)at(bc.oGbar[s]);
             }
-            bc.Gam = (int32_t*)(base + bc.oGam);
-            bc.AA = base + bc.oAA;
-            bc.H = base + bc.oH;
-            bc.W = base + bc.oW;
-            bc.AM = base + bc.oAM;
-            bc.AK = base + bc.oAK;
-            bc.AE = base + bc.oAE;
-            bc.Prow = (int32_t*)(base + bc.oProw);
-            bc.Qrow = (int32_t*)(base + bc.oQrow);
-            bc.Pcol = (int32_t*)(base + bc.oPcol);
-            bc.Qcol = (int32_t*)(base + bc.oQcol);
+            bc.Gam = (int32_t*)at(bc.oGam);
+            bc.AA = at(bc.oAA);
+            bc.H = at(bc.oH);
+            bc.W = at(bc.oW);
+            bc.AM = at(bc.oAM);
+            bc.AK = at(bc.oAK);
+            bc.AE = at(bc.oAE);
+            bc.Prow = (int32_t*)at(bc.oProw);
+            bc.Qrow = (int32_t*)at(bc.oQrow);
+            bc.Pcol = (int32_t*)at(bc.oPcol);
+            bc.Qcol = (int32_t*)at(bc.oQcol);
         }
-        P_ = base + oP_;
+        P_ = at(oP_);
     }
 
     // zero what must start at zero, load the input, initialise the index lists
@@ -738,7 +746,7 @@ private:
     std::vector<BR> rows_;
     std::vector<BC> cols_;
     std::vector<TaskState> tasks_;
-    uint8_t* base_ = nullptr;
+    std::vector<std::pair<size_t, size_t>> slots_;
     uint8_t* P_ = nullptr;
     int32_t* counts_ = nullptr;
     size_t oP_ = 0, arena_bytes_ = 0;
@@ -779,9 +787,14 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
         ncounts += plans.back()->blockcols();
         maxL = std::max(maxL, plans.back()->layers());
     }
-    uint8_t* arena = (uint8_t*)be.alloc(std::max<size_t>(total, 1));
+    // GFECH_SEPARATE_BUFFERS=1: every sub-buffer is its own allocation, so a
+    // bounds-checking backend can tell any overrun of one buffer into the next
+    const char* sep_env = getenv("GFECH_SEPARATE_BUFFERS");
+    const bool separate = sep_env && sep_env[0] == '1';
+    std::vector<void*> pieces;
+    uint8_t* arena = separate ? nullptr : (uint8_t*)be.alloc(std::max<size_t>(total, 1));
     int32_t* counts = (int32_t*)be.alloc(sizeof(int32_t) * std::max<int64_t>(ncounts, 1));
-    if (!arena || !counts) {
+    if ((!separate && !arena) || !counts) {
         be.release(arena);
         be.release(counts);
         if (err) *err = "device allocation of the block arena failed";
@@ -790,7 +803,24 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
     std::vector<int32_t> hcounts(std::max<int64_t>(ncounts, 1));
     Ops ops;
     for (size_t q = 0; q < plans.size(); ++q) {
-        plans[q]->bind(arena + base_off[q], counts + count_off[q]);
+        if (separate) {
+            std::map<size_t, uint8_t*> where;
+            for (auto& sl : plans[q]->slots()) {
+                uint8_t* ptr = (uint8_t*)be.alloc(std::max<size_t>(sl.second, 1));
+                if (!ptr) {
+                    for (void* v : pieces) be.release(v);
+                    be.release(counts);
+                    if (err) *err = "device allocation of a sub-buffer failed";
+                    return 4;
+                }
+                pieces.push_back(ptr);
+                where[sl.first] = ptr;
+            }
+            plans[q]->bind([&](size_t off) { return where.at(off); }, counts + count_off[q]);
+        } else {
+            uint8_t* base = arena + base_off[q];
+            plans[q]->bind([base](size_t off) { return base + off; }, counts + count_off[q]);
+        }
         plans[q]->init(ops);
     }
     flush(be, ops, shared);
@@ -827,6 +857,7 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
     int rc = be.error();
     if (rc) {
         be.release(arena);
+        for (void* v : pieces) be.release(v);
         be.release(counts);
         if (err) *err = "device error during Step 1";
         return rc;
@@ -841,6 +872,7 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
             be.sync();
             for (auto& pl : plans) pl->release_maps();
             be.release(arena);
+            for (void* v : pieces) be.release(v);
             be.release(counts);
             if (err) *err = "device allocation of the result failed";
             return 4;
@@ -863,6 +895,7 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
     rc = be.error();
     for (auto& pl : plans) pl->release_maps();
     be.release(arena);
+    for (void* v : pieces) be.release(v);
     be.release(counts);
     if (rc) {
         if (err) *err = "device error during assembly / Step 3";

@@ -8,8 +8,10 @@
 // uses (first not-yet-selected non-zero row of each column becomes its pivot,
 // rows kept reduced in the negative form, transformation columns kept only
 // for selected rows), so it checks that algorithm as well.
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -21,16 +23,63 @@ namespace {
 class CpuBackend final : public Backend {
 public:
     const char* name() const override { return "cpu-emulator"; }
-    void* alloc(size_t bytes) override { return calloc(bytes ? bytes : 1, 1); }
-    void release(void* p) override { free(p); }
-    void zero(void* p, size_t bytes) override { if (bytes) memset(p, 0, bytes); }
-    void upload(void* dst, const void* src, size_t bytes) override { if (bytes) memcpy(dst, src, bytes); }
-    void download(void* dst, const void* src, size_t bytes) override { if (bytes) memcpy(dst, src, bytes); }
-    void copy(void* dst, const void* src, size_t bytes) override { if (bytes) memmove(dst, src, bytes); }
+    // fresh memory holds garbage, as device memory does: the planner must zero what it relies on
+    void* alloc(size_t bytes) override {
+        void* p = malloc(bytes ? bytes : 1);
+        if (p) {
+            memset(p, 0xA5, bytes ? bytes : 1);
+            allocs_[(uintptr_t)p] = bytes;
+        }
+        return p;
+    }
+    void release(void* p) override {
+        if (!p) return;
+        allocs_.erase((uintptr_t)p);
+        free(p);
+    }
+    void zero(void* p, size_t bytes) override { if (bytes && chk(p, bytes, "zero")) memset(p, 0, bytes); }
+    void upload(void* dst, const void* src, size_t bytes) override {
+        if (bytes && chk(dst, bytes, "upload")) memcpy(dst, src, bytes);
+    }
+    void download(void* dst, const void* src, size_t bytes) override {
+        if (bytes && chk(src, bytes, "download")) memcpy(dst, src, bytes);
+    }
+    void copy(void* dst, const void* src, size_t bytes) override {
+        if (bytes && chk(dst, bytes, "copy") && chk(src, bytes, "copy")) memmove(dst, src, bytes);
+    }
     void sync() override {}
+    int error() const override { return err_; }
+
+    // every byte a job touches must lie inside one live allocation
+    bool chk(const void* p, size_t bytes, const char* what) {
+        if (bytes == 0) return true;
+        uintptr_t a = (uintptr_t)p;
+        auto it = allocs_.upper_bound(a);
+        if (it != allocs_.begin()) {
+            --it;
+            if (a >= it->first && a + bytes <= it->first + it->second) return true;
+        }
+        if (!err_) fprintf(stderr, "emulator: out-of-bounds access in %s (%zu bytes at %p)\n", what, bytes, p);
+        err_ = 6;
+        return false;
+    }
+    bool gemm_ok(const GemmDesc& g) {
+        bool ok = chk(g.D, 1, "gemm D");
+        if (g.brow) ok &= chk(g.brow, sizeof(int32_t) * g.K, "gemm brow");
+        if (g.crow) ok &= chk(g.crow, sizeof(int32_t) * g.M, "gemm crow");
+        if (!ok) return false;
+        for (int x = 0; x < g.M; ++x) {
+            ok &= chk(g.D + (int64_t)x * g.ldd, g.N, "gemm D row");
+            if (g.K) ok &= chk(g.A + (int64_t)x * g.lda, g.K, "gemm A row");
+            if (g.C) ok &= chk(g.C + (int64_t)(g.crow ? g.crow[x] : x) * g.ldc, g.N, "gemm C row");
+        }
+        for (int k = 0; k < g.K; ++k) ok &= chk(g.B + (int64_t)(g.brow ? g.brow[k] : k) * g.ldb, g.N, "gemm B row");
+        return ok;
+    }
 
     void gemm(const std::vector<GemmDesc>& ds) override {
         for (const GemmDesc& g : ds) {
+            if (g.M <= 0 || g.N <= 0 || !gemm_ok(g)) continue;
             std::vector<uint8_t> out((size_t)g.M * g.N);
             for (int x = 0; x < g.M; ++x)
                 for (int y = 0; y < g.N; ++y) {
@@ -51,6 +100,18 @@ public:
 
     void gather(const std::vector<GatherDesc>& ds) override {
         for (const GatherDesc& g : ds) {
+            bool ok = true;
+            if (g.srow) ok &= chk(g.srow, sizeof(int32_t) * g.rows, "gather srow");
+            if (g.scol) ok &= chk(g.scol, sizeof(int32_t) * g.cols, "gather scol");
+            if (g.drow) ok &= chk(g.drow, sizeof(int32_t) * g.rows, "gather drow");
+            if (g.dcol) ok &= chk(g.dcol, sizeof(int32_t) * g.cols, "gather dcol");
+            for (int x = 0; ok && x < g.rows; ++x)
+                for (int y = 0; ok && y < g.cols; ++y) {
+                    int64_t sr = g.srow ? g.srow[x] : x, sc = g.scol ? g.scol[y] : y;
+                    int64_t dr = g.drow ? g.drow[x] : x, dc = g.dcol ? g.dcol[y] : y;
+                    ok &= chk(g.src + sr * g.lds + sc, 1, "gather src") && chk(g.dst + dr * g.ldd + dc, 1, "gather dst");
+                }
+            if (!ok) continue;
             std::vector<uint8_t> tmp((size_t)g.rows * g.cols);
             for (int x = 0; x < g.rows; ++x)
                 for (int y = 0; y < g.cols; ++y) {
@@ -69,6 +130,14 @@ public:
 
     void fill(const std::vector<FillDesc>& ds) override {
         for (const FillDesc& f : ds) {
+            bool ok = true;
+            if (f.dcol) {
+                ok &= chk(f.dcol, sizeof(int32_t) * f.rows, "fill dcol");
+                for (int t = 0; ok && t < f.rows; ++t) ok &= chk(f.dst + (int64_t)t * f.ldd + f.dcol[t], 1, "fill");
+            } else {
+                for (int x = 0; ok && x < f.rows; ++x) ok &= chk(f.dst + (int64_t)x * f.ldd, f.cols, "fill row");
+            }
+            if (!ok) continue;
             if (f.dcol) {
                 for (int t = 0; t < f.rows; ++t) f.dst[(int64_t)t * f.ldd + f.dcol[t]] = (uint8_t)f.diag_value;
                 continue;
@@ -81,6 +150,18 @@ public:
 
     void lists(const std::vector<ListDesc>& ds) override {
         for (const ListDesc& l : ds) {
+            bool ok = true;
+            if (l.npick) {
+                ok &= chk(l.append, sizeof(int32_t) * l.npick, "list append");
+                if (l.pick) ok &= chk(l.pick, sizeof(int32_t) * l.npick, "list pick");
+                for (int t = 0; ok && t < l.npick; ++t) ok &= chk(l.map + (l.pick ? l.pick[t] : t), 4, "list map");
+            }
+            if (l.nkeep) {
+                ok &= chk(l.keep_out, sizeof(int32_t) * l.nkeep, "list keep_out");
+                if (l.keep) ok &= chk(l.keep, sizeof(int32_t) * l.nkeep, "list keep");
+                for (int t = 0; ok && t < l.nkeep; ++t) ok &= chk(l.map + (l.keep ? l.keep[t] : t), 4, "list map");
+            }
+            if (!ok) continue;
             for (int t = 0; t < l.npick; ++t) l.append[t] = l.add + l.map[l.pick ? l.pick[t] : t];
             for (int s = 0; s < l.nkeep; ++s) l.keep_out[s] = l.map[l.keep ? l.keep[s] : s];
         }
@@ -88,6 +169,8 @@ public:
 
     void sort(const std::vector<SortDesc>& ds) override {
         for (const SortDesc& s : ds) {
+            if (!chk(s.vals, sizeof(int32_t) * s.n, "sort vals") || !chk(s.out, sizeof(int32_t) * s.n, "sort out"))
+                continue;
             for (int t = 0; t < s.n; ++t) {
                 int rank = 0;
                 for (int u = 0; u < s.n; ++u) rank += s.vals[u] < s.vals[t];
@@ -104,10 +187,29 @@ public:
     }
 
     void ech(const std::vector<EchDesc>& ds) override {
-        for (const EchDesc& e : ds) ech_one(e);
+        for (const EchDesc& e : ds) {
+            const int maxr = e.rows < e.cols ? e.rows : e.cols;
+            bool ok = chk(e.rcount, 4, "ech rcount") && chk(e.prow, 4 * maxr, "ech prow") &&
+                      chk(e.pcol, 4 * maxr, "ech pcol") && chk(e.qrow, 4 * e.rows, "ech qrow") &&
+                      chk(e.qcol, 4 * e.cols, "ech qcol");
+            for (int x = 0; ok && x < e.rows; ++x)
+                ok &= chk(e.H + (int64_t)x * e.ldh, e.cols, "ech H") &&
+                      chk(e.work + (int64_t)x * e.ldw, e.cols + maxr, "ech work");
+            // outputs sized for the largest possible rank (what the kernel may write)
+            for (int t = 0; ok && t < maxr; ++t) ok &= chk(e.Mo + (int64_t)t * e.ldm, maxr, "ech M");
+            if (ok) {
+                ech_one(e);
+                int r = *e.rcount;
+                for (int t = 0; ok && t < r; ++t) ok &= chk(e.Ro + (int64_t)t * e.ldr, e.cols - r, "ech R");
+                for (int t = 0; ok && t < e.rows - r; ++t) ok &= chk(e.Ko + (int64_t)t * e.ldk, r, "ech K");
+            }
+        }
     }
 
 private:
+    std::map<uintptr_t, size_t> allocs_;
+    int err_ = 0;
+
     static uint32_t inv(uint32_t a, uint32_t p) {   // a^(p-2)
         uint32_t r = 1, b = a % p, x = p - 2;
         while (x) { if (x & 1) r = r * b % p; b = b * b % p; x >>= 1; }

@@ -172,3 +172,19 @@ def test_layers(lib):
     st = lib.echelonise(A, 5, block_rows=4, block_cols=6).stats()
     assert st["layers"] == 5 + 5 - 1
     assert st["block_rows"] == 5 and st["block_cols"] == 5
+
+
+def test_every_access_in_bounds_with_separate_buffers(lib, monkeypatch):
+    """With every planner sub-buffer allocated on its own, the emulator checks
+    that each byte any job touches lies inside the buffer it belongs to."""
+    monkeypatch.setenv("GFECH_SEPARATE_BUFFERS", "1")
+    rng = np.random.default_rng(11)
+    for trial in range(40):
+        p = int(rng.choice([2, 3, 251]))
+        m, n = (int(x) for x in rng.integers(1, 40, 2))
+        A = synth.deficient(trial, 3, m, n, p) if trial % 2 else synth.uniform(trial, 3, m, n, p)
+        br, bc = (int(x) for x in rng.integers(1, 12, 2))
+        compare(lib.echelonise(A, p, block_rows=br, block_cols=bc).outputs(), oracle.echelonize(A, p))
+    mix = synth.batch_mix(9, 10, nmin=3, nmax=40)
+    res, sts = lib.echelonise_batch(mix, block_rows=9, block_cols=9)
+    assert all(s == 0 for s in sts)

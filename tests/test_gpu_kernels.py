@@ -1,0 +1,128 @@
+"""Per-kernel parity on the GPU through the C ABI: the MAD job (int8 MFMA,
+mod p) and the ECH job, against the oracle's plain definitions."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import jobs
+import synth
+from tests.gpu_util import dev, gpu_library, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+MAD_SHAPES = [(1, 1, 1), (17, 33, 5), (128, 128, 64), (130, 257, 65), (300, 129, 200), (64, 1000, 3),
+              (513, 70, 130), (7, 9, 300), (256, 384, 1024)]
+PRIMES = [2, 3, 7, 127, 131, 251]
+
+
+@pytest.mark.parametrize("p", PRIMES)
+@pytest.mark.parametrize("shape", MAD_SHAPES)
+def test_mad_plain(shape, p):
+    torch = torch_cuda()
+    lib = gpu_library()
+    M, N, K = shape
+    say(f"mad {shape} p={p}")
+    rng = np.random.default_rng(M * 7 + N * 13 + K + p)
+    A = rng.integers(0, p, (M, K)).astype(np.uint8)
+    B = rng.integers(0, p, (K, N)).astype(np.uint8)
+    C = rng.integers(0, p, (M, N)).astype(np.uint8)
+    dA, dB, dC = dev(torch, A), dev(torch, B), dev(torch, C)
+    dD = torch.zeros(M * N, dtype=torch.uint8, device="cuda:0")
+    lib.mad_dev(M, N, K, p, dA.data_ptr(), K, dB.data_ptr(), N, dD.data_ptr(), N, C=dC.data_ptr(), ldc=N)
+    torch.cuda.synchronize()
+    assert np.array_equal(dD.cpu().numpy().reshape(M, N), jobs.mad(C, A, B, p))
+    # without C, in place and adversarial all-(p-1) operands
+    A[:] = p - 1
+    B[:] = p - 1
+    dA, dB = dev(torch, A), dev(torch, B)
+    lib.mad_dev(M, N, K, p, dA.data_ptr(), K, dB.data_ptr(), N, dC.data_ptr(), N, C=dC.data_ptr(), ldc=N)
+    torch.cuda.synchronize()
+    assert np.array_equal(dC.cpu().numpy().reshape(M, N), jobs.mad(C, A, B, p))
+
+
+@pytest.mark.parametrize("p", [3, 251])
+def test_mad_unaligned_strided_and_gathered(p):
+    """Operands at odd byte offsets with odd leading dimensions, B and C rows gathered."""
+    torch = torch_cuda()
+    lib = gpu_library()
+    rng = np.random.default_rng(p)
+    M, N, K = 203, 157, 91
+    lda, ldb, ldc, ldd = K + 5, N + 3, N + 7, N + 1
+    say(f"mad unaligned p={p}")
+    Abuf = rng.integers(0, p, (M, lda)).astype(np.uint8)
+    Bbuf = rng.integers(0, p, (2 * K, ldb)).astype(np.uint8)
+    Cbuf = rng.integers(0, p, (2 * M, ldc)).astype(np.uint8)
+    brow = rng.choice(2 * K, size=K, replace=False).astype(np.int32)
+    crow = rng.choice(2 * M, size=M, replace=False).astype(np.int32)
+    offA, offB, offC, offD = 3, 1, 2, 5
+    dA = dev(torch, np.concatenate([np.zeros(offA, np.uint8), Abuf.ravel()]))
+    dB = dev(torch, np.concatenate([np.zeros(offB, np.uint8), Bbuf.ravel()]))
+    dC = dev(torch, np.concatenate([np.zeros(offC, np.uint8), Cbuf.ravel()]))
+    dD = torch.zeros(offD + M * ldd, dtype=torch.uint8, device="cuda:0")
+    db, dc = dev(torch, brow), dev(torch, crow)
+    lib.mad_dev(M, N, K, p, dA.data_ptr() + offA, lda, dB.data_ptr() + offB, ldb, dD.data_ptr() + offD, ldd,
+                C=dC.data_ptr() + offC, ldc=ldc, brow=db.data_ptr(), crow=dc.data_ptr())
+    torch.cuda.synchronize()
+    got = dD.cpu().numpy()[offD:].reshape(M, ldd)[:, :N]
+    exp = jobs.mad(Cbuf[crow, :N], Abuf[:, :K], Bbuf[brow, :N], p)
+    assert np.array_equal(got, exp)
+
+
+def test_mad_batch_grouped():
+    torch = torch_cuda()
+    lib = gpu_library()
+    rng = np.random.default_rng(1)
+    descs, keep, exps = [], [], []
+    for t in range(40):
+        M, N, K = (int(x) for x in rng.integers(1, 260, 3))
+        p = int(rng.choice(PRIMES))
+        A = rng.integers(0, p, (M, K)).astype(np.uint8)
+        B = rng.integers(0, p, (K, N)).astype(np.uint8)
+        dA, dB = dev(torch, A), dev(torch, B)
+        dD = torch.zeros(M * N, dtype=torch.uint8, device="cuda:0")
+        keep += [dA, dB, dD]
+        descs.append(dict(M=M, N=N, K=K, p=p, A=dA.data_ptr(), lda=K, B=dB.data_ptr(), ldb=N, D=dD.data_ptr(),
+                          ldd=N))
+        exps.append((dD, jobs.mul(A, B, p), M, N))
+    say("mad batch of 40")
+    lib.mad_batch_dev(descs)
+    torch.cuda.synchronize()
+    for dD, exp, M, N in exps:
+        assert np.array_equal(dD.cpu().numpy().reshape(M, N), exp)
+
+
+ECH_SHAPES = [(1, 1), (5, 9), (9, 5), (64, 64), (100, 37), (37, 100), (300, 300), (513, 200), (200, 700)]
+
+
+@pytest.mark.parametrize("p", [2, 3, 5, 251])
+@pytest.mark.parametrize("shape", ECH_SHAPES)
+def test_ech_block(shape, p):
+    torch = torch_cuda()
+    lib = gpu_library()
+    rows, cols = shape
+    say(f"ech {shape} p={p}")
+    H = synth.deficient(p, rows * 1000 + cols, rows, cols, p) if rows > 3 else synth.uniform(p, 9, rows, cols, p)
+    mr = min(rows, cols)
+    dH = dev(torch, H)
+    i32 = lambda k: torch.zeros(max(k, 1), dtype=torch.int32, device="cuda:0")
+    u8 = lambda k: torch.zeros(max(k, 1), dtype=torch.uint8, device="cuda:0")
+    prow, qrow, pcol, qcol = i32(mr), i32(rows), i32(mr), i32(cols)
+    dM, dK, dR = u8(mr * mr), u8(rows * mr), u8(mr * cols)
+    r = lib.ech_dev(dH.data_ptr(), rows, cols, cols, p, prow.data_ptr(), qrow.data_ptr(), pcol.data_ptr(),
+                    qcol.data_ptr(), dM.data_ptr(), mr, dK.data_ptr(), mr, dR.data_ptr(), cols)
+    torch.cuda.synchronize()
+    M, K, R, rho, gamma = jobs.ech(H, p)
+    assert r == len(rho)
+    P = prow.cpu().numpy()[:r]
+    # pivot rows in pivot (column) order; the oracle lists them ascending
+    assert sorted(P.tolist()) == rho.tolist()
+    assert pcol.cpu().numpy()[:r].tolist() == gamma.tolist()
+    assert qrow.cpu().numpy()[: rows - r].tolist() == jobs.complement(rho, rows).tolist()
+    assert qcol.cpu().numpy()[: cols - r].tolist() == jobs.complement(gamma, cols).tolist()
+    perm = np.searchsorted(rho, P)            # our column u is the oracle's column perm[u]
+    gM = dM.cpu().numpy()[: mr * mr].reshape(mr, mr)[:r, :r]
+    gK = dK.cpu().numpy()[: rows * mr].reshape(rows, mr)[: rows - r, :r]
+    gR = dR.cpu().numpy()[: mr * cols].reshape(mr, cols)[:r, : cols - r]
+    assert np.array_equal(gM, M[:, perm])
+    assert np.array_equal(gK, K[:, perm])
+    assert np.array_equal(gR, R)
