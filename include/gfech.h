@@ -55,7 +55,8 @@ typedef struct gfech_opts {
     int64_t block_rows;     /* a_i target (Section 3.1); 0 = automatic */
     int64_t block_cols;     /* b_j target; 0 = automatic */
     int32_t skip_range_check; /* 1: the caller guarantees entries < p (no validation pass) */
-    int32_t reserved[7];
+    int32_t profile;        /* 1: time every kernel launch with device events (see gfech_stats) */
+    int32_t reserved[6];
 } gfech_opts;
 
 /* Opaque, library-owned result; immutable once returned.  Its matrices stay
@@ -138,6 +139,10 @@ typedef struct gfech_stats {
     double gather_bytes;    /* bytes read + written by extracts, riffles and copies */
     int64_t layers, echs, gemms, launches, syncs;
     int64_t block_rows, block_cols;   /* a and b */
+    /* with opts.profile: summed device time and launch count of the MAD
+     * kernel, the ECH kernel and the extract / riffle / list kernels */
+    double ms_mad, ms_ech, ms_small;
+    int64_t launches_mad, launches_ech, launches_small;
 } gfech_stats;
 gfech_status gfech_get_stats(const gfech_result* res, gfech_stats* stats);
 

@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "GFECH_OK", 1: "GFECH_E_ARG", 2: "GFECH_E_FIELD", 3: "GFECH_E
 
 class Opts(ctypes.Structure):
     _fields_ = [("block_rows", c_i64), ("block_cols", c_i64), ("skip_range_check", c_i32),
-                ("reserved", c_i32 * 7)]
+                ("profile", c_i32), ("reserved", c_i32 * 6)]
 
 
 class Problem(ctypes.Structure):
@@ -34,7 +34,9 @@ class Stats(ctypes.Structure):
                 ("mac_updaterow", ctypes.c_double), ("mac_trafo", ctypes.c_double),
                 ("mac_clearup", ctypes.c_double), ("gather_bytes", ctypes.c_double),
                 ("layers", c_i64), ("echs", c_i64), ("gemms", c_i64), ("launches", c_i64), ("syncs", c_i64),
-                ("block_rows", c_i64), ("block_cols", c_i64)]
+                ("block_rows", c_i64), ("block_cols", c_i64),
+                ("ms_mad", ctypes.c_double), ("ms_ech", ctypes.c_double), ("ms_small", ctypes.c_double),
+                ("launches_mad", c_i64), ("launches_ech", c_i64), ("launches_small", c_i64)]
 
 
 class MadDesc(ctypes.Structure):

@@ -146,11 +146,12 @@ class Result:
         return o
 
 
-def _opts(block_rows=0, block_cols=0, skip_range_check=False):
+def _opts(block_rows=0, block_cols=0, skip_range_check=False, profile=False):
     o = _abi.Opts()
     o.block_rows = int(block_rows)
     o.block_cols = int(block_cols)
     o.skip_range_check = 1 if skip_range_check else 0
+    o.profile = 1 if profile else 0
     return o
 
 
@@ -177,10 +178,10 @@ class Library:
         return Result(self.lib, out.value)
 
     def echelonise_dev(self, ptr: int, m: int, n: int, lda: int, p: int, stream: int = 0, block_rows=0,
-                       block_cols=0, skip_range_check=False) -> Result:
+                       block_cols=0, skip_range_check=False, profile=False) -> Result:
         """ptr: device address of an m x n uint8 matrix with leading dimension lda."""
         out = ctypes.c_void_p()
-        o = _opts(block_rows, block_cols, skip_range_check)
+        o = _opts(block_rows, block_cols, skip_range_check, profile)
         self._check(self.lib.gfech_echelonise_u8_dev(ctypes.c_void_p(ptr), m, n, lda, p, ctypes.byref(o),
                                                      ctypes.c_void_p(stream), ctypes.byref(out)))
         return Result(self.lib, out.value)
@@ -207,7 +208,8 @@ class Library:
                                            vp(M), ldm, vp(K), ldk, vp(R), ldr, ctypes.byref(r), vp(stream)))
         return r.value
 
-    def echelonise_batch(self, problems, on_device: bool = False, stream: int = 0, block_rows=0, block_cols=0):
+    def echelonise_batch(self, problems, on_device: bool = False, stream: int = 0, block_rows=0, block_cols=0,
+                         profile=False):
         """problems: list of (A, p) with A a host numpy array (on_device=False) or
         (ptr, m, n, lda, p) tuples (on_device=True).  Returns (results, statuses)."""
         cnt = len(problems)
@@ -227,7 +229,7 @@ class Library:
             arr[t].m, arr[t].n, arr[t].lda, arr[t].p = m, n, lda, p
         outs = (ctypes.c_void_p * max(cnt, 1))()
         sts = (ctypes.c_int * max(cnt, 1))()
-        o = _opts(block_rows, block_cols)
+        o = _opts(block_rows, block_cols, profile=profile)
         self.lib.gfech_echelonise_batch(cnt, arr, 1 if on_device else 0, ctypes.byref(o), ctypes.c_void_p(stream),
                                         outs, sts)
         res = [Result(self.lib, outs[t]) if outs[t] else None for t in range(cnt)]

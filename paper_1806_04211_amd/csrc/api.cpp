@@ -39,9 +39,10 @@ bool is_prime(uint32_t p) {
 }
 
 // Block sizes (Section 3.1: roughly square blocks).  Matrices up to the
-// single-block limit are one block: one ECH then does the whole job.
+// single-block limit are one block: one ECH then does the whole job.  Blocks
+// of at most 512 rows keep every ECH on the register-panel kernel.
 void choose_blocks(int64_t m, int64_t n, const gfech_opts* o, std::vector<int32_t>& a, std::vector<int32_t>& b) {
-    const int64_t single = 1024;
+    const int64_t single = 512;
     const int64_t target = 512;
     int64_t br = (o && o->block_rows > 0) ? o->block_rows : 0;
     int64_t bc = (o && o->block_cols > 0) ? o->block_cols : 0;
@@ -78,10 +79,11 @@ gfech::Backend* get_backend(gfech_status* st) {
 }
 
 // run a set of problems whose inputs are already in backend memory
-gfech_status run(gfech::Backend* be, std::vector<gfech::Problem>& probs, gfech_result** outs) {
+gfech_status run(gfech::Backend* be, std::vector<gfech::Problem>& probs, gfech_result** outs,
+                 const gfech_opts* opts) {
     std::vector<std::unique_ptr<gfech::Result>> res;
     std::string err;
-    int rc = gfech::run_chief(*be, probs, res, &err);
+    int rc = gfech::run_chief(*be, probs, res, &err, opts && opts->profile);
     if (rc) return fail(rc == 4 ? GFECH_E_NOMEM : GFECH_E_DEVICE, err);
     for (size_t q = 0; q < res.size(); ++q) {
         outs[q] = new gfech_result();
@@ -135,7 +137,7 @@ gfech_status echelonise_impl(const uint8_t* A, bool on_device, int64_t m, int64_
     probs[0].lda = ld;
     probs[0].p = (int32_t)p;
     choose_blocks(m, n, opts, probs[0].row_blocks, probs[0].col_blocks);
-    st = run(be, probs, out);
+    st = run(be, probs, out, opts);
     if (staged) be->release(staged);
     be->set_stream(nullptr);
     return st;
@@ -276,7 +278,7 @@ gfech_status gfech_echelonise_batch(int64_t count, const gfech_problem* probs, i
         run_idx.push_back(t);
     }
     std::vector<gfech_result*> tmp_out(pv.size(), nullptr);
-    if (!st && !pv.empty()) st = run(be, pv, tmp_out.data());
+    if (!st && !pv.empty()) st = run(be, pv, tmp_out.data(), opts);
     for (void* d : staged) be->release(d);
     be->set_stream(nullptr);
     // map results back (problems that failed validation keep NULL)
@@ -419,6 +421,12 @@ gfech_status gfech_get_stats(const gfech_result* res, gfech_stats* s) {
     s->syncs = t.syncs;
     s->block_rows = (int64_t)res->r->row_blocks.size();
     s->block_cols = (int64_t)res->r->col_blocks.size();
+    s->ms_mad = t.kernel_ms[0];
+    s->ms_ech = t.kernel_ms[1];
+    s->ms_small = t.kernel_ms[2];
+    s->launches_mad = t.kernel_launches[0];
+    s->launches_ech = t.kernel_launches[1];
+    s->launches_small = t.kernel_launches[2];
     return GFECH_OK;
 }
 

@@ -118,6 +118,13 @@ public:
     virtual void set_stream(void* stream) { (void)stream; }
     // non-zero after a device error; the planner stops and reports it
     virtual int error() const { return 0; }
+    // per-launch timing of the grouped jobs (device events on the work stream)
+    struct Profile {
+        double ms[4] = {0, 0, 0, 0};        // gemm, ech, gather/fill/lists/sort, range check
+        int64_t launches[4] = {0, 0, 0, 0};
+    };
+    virtual void set_profile(bool on) { (void)on; }
+    virtual Profile take_profile() { return Profile(); }
 };
 
 }  // namespace gfech

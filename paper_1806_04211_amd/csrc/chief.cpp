@@ -768,7 +768,11 @@ void flush(Backend& be, Ops& ops, Stats& st) {
 }  // namespace
 
 int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::unique_ptr<Result>>& out,
-              std::string* err) {
+              std::string* err, bool profile) {
+    if (profile) {
+        be.take_profile();
+        be.set_profile(true);
+    }
     Stats shared;
     std::vector<Stats> st(probs.size());
     std::vector<std::unique_ptr<Plan>> plans;
@@ -893,6 +897,11 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
     }
     be.sync();
     rc = be.error();
+    Backend::Profile prof;
+    if (profile) {
+        prof = be.take_profile();
+        be.set_profile(false);
+    }
     for (auto& pl : plans) pl->release_maps();
     be.release(arena);
     for (void* v : pieces) be.release(v);
@@ -907,6 +916,10 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
         s.launches = shared.launches;
         s.gemms = shared.gemms;
         s.syncs = shared.syncs;
+        for (int k = 0; k < 3; ++k) {
+            s.kernel_ms[k] = prof.ms[k];
+            s.kernel_launches[k] = prof.launches[k];
+        }
         res[q]->stats = s;
         out.push_back(std::move(res[q]));
     }

@@ -22,6 +22,9 @@ struct Stats {
     double cu_mad = 0;     // ClearUp MADs (Step 3)
     double gather_bytes = 0;   // bytes moved by extracts / riffles / copies
     int64_t layers = 0, echs = 0, gemms = 0, launches = 0, syncs = 0;
+    // kernel time by kind when profiling was requested (device events): gemm, ech, small jobs
+    double kernel_ms[3] = {0, 0, 0};
+    int64_t kernel_launches[3] = {0, 0, 0};
     double total_mac() const { return cd_mad + ech + ur_mad + urt_mad + cu_mad; }
 };
 
@@ -60,6 +63,6 @@ std::vector<int32_t> even_blocks(int64_t total, int64_t target);
 // jobs share launches).  Returns 0 or a backend error code; results are
 // appended to `out` in problem order.
 int run_chief(Backend& be, const std::vector<Problem>& probs,
-              std::vector<std::unique_ptr<Result>>& out, std::string* err);
+              std::vector<std::unique_ptr<Result>>& out, std::string* err, bool profile = false);
 
 }  // namespace gfech

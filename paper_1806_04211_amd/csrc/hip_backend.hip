@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -32,6 +33,19 @@ __device__ __forceinline__ uint32_t mod_small(uint32_t x, uint32_t p, uint32_t m
     uint32_t r = x - q * p;
     return r >= p ? r - p : r;
 }
+
+// v mod p for any int32 v with |v| < 2^31 - 256: shift by a multiple of p into
+// [0, 2^32), then q = mulhi(u, floor(2^32 / p)) is floor(u / p) or one less.
+struct ModP {
+    uint32_t p, m, bias;
+    __device__ __forceinline__ explicit ModP(uint32_t pp)
+        : p(pp), m((uint32_t)(0x100000000ull / pp)), bias((uint32_t)((0x80000000u / pp) * pp)) {}
+    __device__ __forceinline__ uint32_t operator()(int v) const {
+        uint32_t u = (uint32_t)v + bias;
+        uint32_t r = u - __umulhi(u, m) * p;
+        return r >= p ? r - p : r;
+    }
+};
 
 // ============================================================================ GEMM mod p
 
@@ -185,7 +199,8 @@ k_gemm_modp(const GemmDesc* __restrict__ descs, const GemmTileMap* __restrict__ 
 
     // ---- epilogue: D = (Cin + acc) mod p
     // acc[i][j] element e sits at row 4 * (lane / 16) + e, column lane % 16 of block (i, j);
-    // |acc| <= K * 127^2 < 2^31 for K <= 2^16
+    // |acc| <= K * 127^2 < 2^30 for K <= 2^16
+    const ModP mod(p);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -200,9 +215,7 @@ k_gemm_modp(const GemmDesc* __restrict__ descs, const GemmTileMap* __restrict__ 
                         int64_t cr = g.crow ? g.crow[row] : row;
                         v += g.C[cr * g.ldc + col];
                     }
-                    int rr = v % (int)p;
-                    if (rr < 0) rr += (int)p;
-                    g.D[(int64_t)row * g.ldd + col] = (uint8_t)rr;
+                    g.D[(int64_t)row * g.ldd + col] = (uint8_t)mod(v);
                 }
             }
 }
@@ -333,6 +346,242 @@ __global__ void __launch_bounds__(ECH_THREADS) k_ech(const EchDesc* __restrict__
     }
 }
 
+// ---------------------------------------------------------------------------- ECH, panel form
+//
+// One workgroup per block, one thread per row (rows <= 512).  Columns are
+// processed in panels of PW: the thread holds its row's panel entries and its
+// row of the panel transform F in registers as unreduced 32-bit sums (each
+// elimination is one multiply-add; values stay below 2^24 for PW <= 32 and
+// p <= 251).  A pivot is the first not-yet-selected row with a non-zero in
+// the column (the paper's rule); each wave proposes its first candidate and
+// parks that row in LDS, and the winning row is reduced by its wave and read
+// by all.  After a panel, every other column of the block and every
+// transformation column of earlier pivots gets
+//     W[x] := (x a pivot of this panel ? 0 : W[x]) + F[x] * W_old[pivot rows]
+// on int8 MFMA; the transformation columns of the new pivots are F itself.
+constexpr int PW = 32;          // panel width
+constexpr int FL_ROW = 80;      // LDS bytes per row of F (64 used by the MFMA, zero beyond the panel)
+constexpr int VCH = 64;         // columns per trailing-update chunk
+constexpr int ECHP_MAX_ROWS = 512;
+
+__host__ __device__ constexpr size_t echp_fixed_lds() {
+    return 128 + 2 * 16 * 64 * 4 + 2 * ECHP_MAX_ROWS * 4 + 256 * 4 + 2 * ECHP_MAX_ROWS + VCH * FL_ROW;
+}
+__host__ __device__ inline size_t echp_lds_bytes(int rows) { return echp_fixed_lds() + (size_t)((rows + 15) & ~15) * FL_ROW; }
+
+__global__ void __launch_bounds__(512) k_ech_panel(const EchDesc* __restrict__ descs) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const EchDesc e = descs[blockIdx.x];
+    const int rows = e.rows, cols = e.cols;
+    const int maxr = rows < cols ? rows : cols;
+    const int width = cols + maxr;
+    const uint32_t p = (uint32_t)e.p;
+    const uint32_t minv = (1u << 24) / p;
+    const uint32_t adj = p > 127 ? 256u - p : 0u;
+    const ModP mod(p);
+    const int x = threadIdx.x;
+    const int nthr = blockDim.x, lane = x & 63, wave = x >> 6, nwaves = nthr >> 6;
+    const int rows16 = (rows + 15) & ~15;
+
+    int* cand = (int*)smem;                                        // [2][16]
+    uint32_t* slot = (uint32_t*)(smem + 128);                      // [2][16][64]
+    int* prl = (int*)(smem + 128 + 2 * 16 * 64 * 4);               // pivot rows, pivot order
+    int* pcl = prl + ECHP_MAX_ROWS;                                // pivot columns
+    uint32_t* invt = (uint32_t*)(pcl + ECHP_MAX_ROWS);             // inverses mod p
+    uint8_t* sel = (uint8_t*)(invt + 256);                         // row selected
+    uint8_t* inpanel = sel + ECHP_MAX_ROWS;                        // row selected in the current panel
+    uint8_t* Vt = inpanel + ECHP_MAX_ROWS;                         // [VCH][FL_ROW] pivot rows, transposed
+    uint8_t* Fl = Vt + VCH * FL_ROW;                               // [rows16][FL_ROW]
+
+    for (int i = x; i < 256; i += nthr) invt[i] = (i > 0 && (uint32_t)i < p) ? pow_mod_dev((uint32_t)i, p - 2, p) : 0u;
+    for (int i = x; i < ECHP_MAX_ROWS; i += nthr) sel[i] = 0;
+    for (int64_t idx = x; idx < (int64_t)rows * width; idx += nthr) {
+        int rr = (int)(idx / width), y = (int)(idx % width);
+        e.work[(int64_t)rr * e.ldw + y] = y < cols ? e.H[(int64_t)rr * e.ldh + y] : 0;
+    }
+    __syncthreads();
+    uint8_t* Wx = e.work + (int64_t)x * e.ldw;
+
+    int r = 0;
+    for (int c0 = 0; c0 < cols && r < maxr; c0 += PW) {
+        const int wc = min(PW, cols - c0);
+        uint32_t reg[PW], F[PW];
+#pragma unroll
+        for (int j = 0; j < PW; ++j) {
+            reg[j] = (x < rows && j < wc) ? Wx[c0 + j] : 0u;
+            F[j] = 0;
+        }
+        bool mysel = x < rows && sel[x];
+        bool mine = false;
+        uint32_t myscale = 0;
+        int rp = 0;
+#pragma unroll
+        for (int k = 0; k < PW; ++k) {
+            if (k < wc && r + rp < maxr) {
+                const uint32_t v = mod_small(reg[k], p, minv);
+                reg[k] = v;
+                const bool isc = x < rows && !mysel && v != 0;
+                const unsigned long long bal = __ballot(isc);
+                const int par = k & 1;
+                if (bal) {
+                    const int first = __ffsll((long long)bal) - 1;
+                    if (lane == first) {
+                        cand[par * 16 + wave] = x;
+                        uint32_t* my = slot + (par * 16 + wave) * 64;
+#pragma unroll
+                        for (int j = 0; j < PW; ++j) my[j] = reg[j];
+#pragma unroll
+                        for (int t = 0; t < PW; ++t) my[PW + t] = (t == rp) ? 1u : F[t];
+                    }
+                } else if (lane == 0) {
+                    cand[par * 16 + wave] = 0x7fffffff;
+                }
+                __syncthreads();
+                int best = 0x7fffffff;
+                for (int w = 0; w < nwaves; ++w) best = min(best, cand[par * 16 + w]);
+                if (best != 0x7fffffff) {
+                    uint32_t* ps = slot + (par * 16 + (best >> 6)) * 64;
+                    if (wave == (best >> 6)) ps[lane] = mod_small(ps[lane], p, minv);
+                    __syncthreads();
+                    const uint32_t s = (p - invt[ps[k]]) % p;        // -1 / pivot
+                    if (x == best) {
+                        mysel = true;
+                        mine = true;
+                        myscale = s;
+#pragma unroll
+                        for (int t = 0; t < PW; ++t)
+                            if (t == rp) F[t] = 1;
+                        sel[x] = 1;
+                        prl[r + rp] = x;
+                        pcl[r + rp] = c0 + k;
+                    } else if (x < rows) {
+                        const uint32_t f = mod_small(v * s, p, minv);
+                        if (f) {
+#pragma unroll
+                            for (int j = k + 1; j < PW; ++j) reg[j] += f * ps[j];
+                            reg[k] = 0;
+#pragma unroll
+                            for (int t = 0; t < PW; ++t) F[t] += f * ps[PW + t];
+                        }
+                    }
+                    ++rp;
+                }
+            }
+        }
+        // normalise this panel's pivot rows (pivot -> -1) and reduce everything
+#pragma unroll
+        for (int j = 0; j < PW; ++j) {
+            uint32_t a = mod_small(reg[j], p, minv), b = mod_small(F[j], p, minv);
+            if (mine) {
+                a = mod_small(a * myscale, p, minv);
+                b = mod_small(b * myscale, p, minv);
+            }
+            reg[j] = a;
+            F[j] = b;
+        }
+        if (x < rows) {
+#pragma unroll
+            for (int j = 0; j < PW; ++j)
+                if (j < wc) Wx[c0 + j] = (uint8_t)reg[j];
+#pragma unroll
+            for (int t = 0; t < PW; ++t)
+                if (t < rp) Wx[cols + r + t] = (uint8_t)F[t];
+            inpanel[x] = mine ? 1 : 0;
+        }
+        if (x < rows16) {
+            uint32_t* fr = (uint32_t*)(Fl + x * FL_ROW);
+#pragma unroll
+            for (int w4 = 0; w4 < 16; ++w4) {
+                uint32_t word = 0;
+                if (x < rows) {
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int t = w4 * 4 + b;
+                        if (t < PW && t < rp) word |= F[t < PW ? t : 0] << (8 * b);
+                    }
+                }
+                fr[w4] = adj ? centre(word, adj) : word;
+            }
+        }
+        __syncthreads();
+        if (rp > 0) {
+            const int nd = cols - (c0 + wc);     // data columns right of the panel
+            const int total = nd + r;            // plus transformation columns of earlier pivots
+            for (int ch = 0; ch < total; ch += VCH) {
+                for (int i = x; i < VCH * 16; i += nthr) {
+                    const int cl = i >> 4, tw = (i & 15) * 4, q = ch + cl;
+                    uint32_t word = 0;
+                    if (q < total) {
+                        const int y = q < nd ? c0 + wc + q : cols + (q - nd);
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) {
+                            const int t = tw + b;
+                            if (t < rp) word |= (uint32_t)e.work[(int64_t)prl[r + t] * e.ldw + y] << (8 * b);
+                        }
+                    }
+                    *(uint32_t*)(Vt + cl * FL_ROW + tw) = adj ? centre(word, adj) : word;
+                }
+                __syncthreads();
+                const int nb = (rows16 >> 4) * (VCH / 16);
+                for (int b = wave; b < nb; b += nwaves) {
+                    const int rb = b / (VCH / 16), cb = b % (VCH / 16);
+                    const v4i av = *(const v4i*)(Fl + (rb * 16 + (lane & 15)) * FL_ROW + (lane >> 4) * 16);
+                    const v4i bv = *(const v4i*)(Vt + (cb * 16 + (lane & 15)) * FL_ROW + (lane >> 4) * 16);
+                    const v4i acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, bv, v4i{0, 0, 0, 0}, 0, 0, 0);
+                    const int cl = cb * 16 + (lane & 15), q = ch + cl;
+                    if (q < total) {
+                        const int y = q < nd ? c0 + wc + q : cols + (q - nd);
+#pragma unroll
+                        for (int ee = 0; ee < 4; ++ee) {
+                            const int row = rb * 16 + (lane >> 4) * 4 + ee;
+                            if (row < rows) {
+                                uint8_t* w = e.work + (int64_t)row * e.ldw + y;
+                                const int old = inpanel[row] ? 0 : (int)*w;
+                                *w = (uint8_t)mod(acc[ee] + old);
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        r += rp;
+    }
+    __syncthreads();
+    // ---- outputs
+    if (x == 0) *e.rcount = r;
+    for (int t = x; t < r; t += nthr) {
+        e.prow[t] = prl[t];
+        e.pcol[t] = pcl[t];
+    }
+    if (x == 0) {
+        int q = 0;
+        for (int rr = 0; rr < rows; ++rr)
+            if (!sel[rr]) e.qrow[q++] = rr;
+        q = 0;
+        int t = 0;
+        for (int y = 0; y < cols; ++y) {
+            if (t < r && pcl[t] == y) { ++t; continue; }
+            e.qcol[q++] = y;
+        }
+    }
+    __syncthreads();
+    for (int64_t idx = x; idx < (int64_t)r * r; idx += nthr) {
+        int t = (int)(idx / r), u = (int)(idx % r);
+        e.Mo[(int64_t)t * e.ldm + u] = e.work[(int64_t)prl[t] * e.ldw + cols + u];
+    }
+    const int nr = cols - r;
+    for (int64_t idx = x; idx < (int64_t)r * nr; idx += nthr) {
+        int t = (int)(idx / nr), k2 = (int)(idx % nr);
+        e.Ro[(int64_t)t * e.ldr + k2] = e.work[(int64_t)prl[t] * e.ldw + e.qcol[k2]];
+    }
+    const int nq = rows - r;
+    for (int64_t idx = x; idx < (int64_t)nq * r; idx += nthr) {
+        int s2 = (int)(idx / r), u = (int)(idx % r);
+        e.Ko[(int64_t)s2 * e.ldk + u] = e.work[(int64_t)e.qrow[s2] * e.ldw + cols + u];
+    }
+}
+
 // ============================================================================ small jobs
 
 constexpr int SMALL_THREADS = 256;
@@ -435,6 +684,11 @@ public:
             if (err) *err = "counter allocation failed";
             return false;
         }
+        if (hipFuncSetAttribute((const void*)k_ech_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)echp_lds_bytes(ECHP_MAX_ROWS)) != hipSuccess) {
+            if (err) *err = "cannot reserve LDS for the ECH kernel";
+            return false;
+        }
         return true;
     }
 
@@ -516,12 +770,26 @@ public:
         if (tiles > INT32_MAX) { note_error(hipErrorInvalidValue, "too many gemm tiles"); return; }
         const GemmDesc* dd = (const GemmDesc*)put(d.data(), d.size() * sizeof(GemmDesc));
         const GemmTileMap* dm = (const GemmTileMap*)put(maps.data(), maps.size() * sizeof(GemmTileMap));
+        hipEvent_t e0 = prof_begin();
         hipLaunchKernelGGL(k_gemm_modp, dim3((unsigned)tiles), dim3(GEMM_THREADS), 0, stream_, dd, dm, (int)d.size());
         HIP_OK(hipGetLastError());
+        prof_end(0, e0);
     }
 
     void ech(const std::vector<EchDesc>& ds) override {
         if (ds.empty()) return;
+        int maxrows_all = 0;
+        for (const EchDesc& e : ds) maxrows_all = std::max(maxrows_all, e.rows);
+        if (maxrows_all <= ECHP_MAX_ROWS && !getenv("GFECH_ECH_SIMPLE")) {
+            int threads = std::max(64, (maxrows_all + 63) / 64 * 64);
+            size_t shm = echp_lds_bytes(maxrows_all);
+            const EchDesc* dd = (const EchDesc*)put(ds.data(), ds.size() * sizeof(EchDesc));
+            hipEvent_t e0 = prof_begin();
+            hipLaunchKernelGGL(k_ech_panel, dim3((unsigned)ds.size()), dim3(threads), shm, stream_, dd);
+            HIP_OK(hipGetLastError());
+            prof_end(1, e0);
+            return;
+        }
         int maxrows = 0, maxw = 0;
         for (const EchDesc& e : ds) {
             int maxr = std::min(e.rows, e.cols);
@@ -533,8 +801,10 @@ public:
         size_t shm = ((size_t)(2 * maxrows + maxw + 15) & ~(size_t)15) + 2 * sizeof(int) * (size_t)maxr_all;
         if (shm > 64 * 1024) { note_error(hipErrorInvalidValue, "ech block too large for LDS"); return; }
         const EchDesc* dd = (const EchDesc*)put(ds.data(), ds.size() * sizeof(EchDesc));
+        hipEvent_t e0 = prof_begin();
         hipLaunchKernelGGL(k_ech, dim3((unsigned)ds.size()), dim3(ECH_THREADS), shm, stream_, dd);
         HIP_OK(hipGetLastError());
+        prof_end(1, e0);
     }
 
     template <typename D, typename F>
@@ -546,8 +816,10 @@ public:
         for (size_t off = 0; off < ds.size(); off += 65535) {
             size_t cnt = std::min<size_t>(65535, ds.size() - off);
             const D* dd = (const D*)put(ds.data() + off, cnt * sizeof(D));
+            hipEvent_t e0 = prof_begin();
             hipLaunchKernelGGL(kernel, dim3((unsigned)bx, (unsigned)cnt), dim3(SMALL_THREADS), 0, stream_, dd);
             HIP_OK(hipGetLastError());
+            prof_end(2, e0);
         }
     }
 
@@ -578,7 +850,48 @@ public:
         return err_ ? -1 : (int64_t)bad;
     }
 
+    void set_profile(bool on) override { prof_ = on; }
+    Profile take_profile() override {
+        Profile pr;
+        HIP_OK(hipStreamSynchronize(stream_));
+        for (auto& ev : evs_) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, ev.a, ev.b) == hipSuccess) {
+                pr.ms[ev.kind] += ms;
+                pr.launches[ev.kind] += 1;
+            }
+            pool_.push_back(ev.a);
+            pool_.push_back(ev.b);
+        }
+        evs_.clear();
+        return pr;
+    }
+
 private:
+    struct Ev { hipEvent_t a, b; int kind; };
+    hipEvent_t new_event() {
+        if (!pool_.empty()) {
+            hipEvent_t e = pool_.back();
+            pool_.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        HIP_OK(hipEventCreate(&e));
+        return e;
+    }
+    hipEvent_t prof_begin() {
+        if (!prof_) return nullptr;
+        hipEvent_t e = new_event();
+        HIP_OK(hipEventRecord(e, stream_));
+        return e;
+    }
+    void prof_end(int kind, hipEvent_t a) {
+        if (!prof_ || !a) return;
+        hipEvent_t b = new_event();
+        HIP_OK(hipEventRecord(b, stream_));
+        evs_.push_back({a, b, kind});
+    }
+
     void note_error(hipError_t e, const char* what) {
         if (!err_) {
             err_ = 6;
@@ -614,6 +927,9 @@ private:
     void* counter_ = nullptr;
     int err_ = 0;
     int num_cu_ = 0;
+    bool prof_ = false;
+    std::vector<Ev> evs_;
+    std::vector<hipEvent_t> pool_;
     std::map<void*, size_t> sizes_;
     std::multimap<size_t, void*> free_;
 };

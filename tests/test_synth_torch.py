@@ -1,0 +1,19 @@
+"""The torch generator reproduces the numpy one bit for bit (CPU torch here)."""
+import numpy as np
+import torch
+
+import synth
+from synth import torch_gen
+
+
+def test_uniform_matches_numpy():
+    for p in (2, 7, 251):
+        a = synth.uniform(3, 4, 37, 53, p)
+        b = torch_gen.uniform(3, 4, 37, 53, p, device="cpu", chunk_rows=10).numpy()
+        assert np.array_equal(a, b)
+
+
+def test_low_rank_product_matches_numpy():
+    a = synth.low_rank_product(0, 30, 40, 20, 7)
+    b = torch_gen.low_rank_product(0, 30, 40, 20, 7, device="cpu", chunk_rows=7).numpy()
+    assert np.array_equal(a, b)
