@@ -44,6 +44,13 @@ std::vector<int32_t> even_blocks(int64_t total, int64_t target) {
         v.push_back((int32_t)total);
         return v;
     }
+    // targets that are multiples of 64 give blocks of exactly `target` (aligned
+    // panels for the vector loads) and a smaller last block; other targets are
+    // split evenly
+    if (target % 64 == 0) {
+        for (int64_t off = 0; off < total; off += target) v.push_back((int32_t)std::min<int64_t>(target, total - off));
+        return v;
+    }
     int64_t k = (total + target - 1) / target;
     for (int64_t i = 0; i < k; ++i) v.push_back((int32_t)(total / k + (i < total % k ? 1 : 0)));
     return v;

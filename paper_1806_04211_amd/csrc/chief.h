@@ -55,8 +55,10 @@ struct Problem {
     std::vector<int32_t> row_blocks, col_blocks;   // a_i and b_j (sums m and n)
 };
 
-// Choose block sizes: blocks of `target` rows / columns, the last one taking
-// the remainder (Section 3.1).  target <= 0 means a single block.
+// Choose block sizes (Section 3.1).  A target that is a multiple of 64 gives
+// blocks of exactly that size and a smaller last block (the paper notes the
+// first and last blocks may be smaller); other targets split evenly.
+// target <= 0 means a single block.
 std::vector<int32_t> even_blocks(int64_t total, int64_t target);
 
 // Run the whole method on a set of independent problems in lockstep (their

@@ -24,15 +24,44 @@
 namespace gfech {
 namespace {
 
+// ============================================================================ memory helpers
+
+// Accesses through pointers taken from descriptors in memory would otherwise
+// compile to flat instructions, whose completion also gates LDS waits; these
+// make them global (address space 1) loads and stores.
+#define GPTR(T, p) ((const __attribute__((address_space(1))) T*)(p))
+#define GPTRW(T, p) ((__attribute__((address_space(1))) T*)(p))
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ T gload(const void* p) { return *GPTR(T, p); }
+template <>
+__device__ __forceinline__ uint4 gload<uint4>(const void* p) {
+    const u32x4 v = *GPTR(u32x4, p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+template <>
+__device__ __forceinline__ uint2 gload<uint2>(const void* p) {
+    const u32x2 v = *GPTR(u32x2, p);
+    return make_uint2(v.x, v.y);
+}
+template <typename T>
+__device__ __forceinline__ void gstore(void* p, T v) { *GPTRW(T, p) = v; }
+template <>
+__device__ __forceinline__ void gstore<uint4>(void* p, uint4 v) { *GPTRW(u32x4, p) = u32x4{v.x, v.y, v.z, v.w}; }
+
 // ============================================================================ field helpers
 
 // x mod p for 0 <= x < 2^24, p <= 251: q = floor(x * floor(2^24 / p) / 2^24) is
 // floor(x / p) or one less, so one conditional subtraction finishes.
 __device__ __forceinline__ uint32_t mod_small(uint32_t x, uint32_t p, uint32_t minv) {
     uint32_t q = __umulhi(x << 8, minv);
-    uint32_t r = x - q * p;
+    uint32_t r = x - __umul24(q, p);
     return r >= p ? r - p : r;
 }
+
+// a + b * c for b, c < 2^24 (one full-rate v_mad_u32_u24)
+__device__ __forceinline__ uint32_t mad24(uint32_t b, uint32_t c, uint32_t a) { return __umul24(b, c) + a; }
 
 // v mod p for any int32 v with |v| < 2^31 - 256: shift by a multiple of p into
 // [0, 2^32), then q = mulhi(u, floor(2^32 / p)) is floor(u / p) or one less.
@@ -48,8 +77,17 @@ struct ModP {
 };
 
 // ============================================================================ GEMM mod p
+//
+// Workgroup tile TM x TN of D, 4 waves in 2 x 2, each wave 128 x 64 as
+// 8 x 4 blocks of v_mfma_i32_16x16x64_i8.  The MFMA is issued with the
+// operands swapped (the B tile as the first operand) so that each lane's
+// four results are four consecutive columns of one row of D: the epilogue
+// reduces, packs and stores them as one dword.  K advances in steps of TK
+// through two LDS stages; the next step's global loads are in registers while
+// the current step computes.  A is kept [m][k] in LDS and B transposed
+// [n][k], so both MFMA operands read 16 consecutive k bytes per lane.
 
-constexpr int TM = 128;          // rows of D per workgroup tile
+constexpr int TM = 256;          // rows of D per workgroup tile
 constexpr int TN = 128;          // columns of D per workgroup tile
 constexpr int TK = 64;           // reduction depth per LDS stage
 constexpr int LDS_ROW = 80;      // bytes per LDS row (64 data + 16 pad)
@@ -71,15 +109,16 @@ __device__ __forceinline__ uint4 load16_lim(const uint8_t* p, int rem) {
         uintptr_t a = (uintptr_t)p;
         const uint32_t* q = (const uint32_t*)(a & ~(uintptr_t)3);
         uint32_t sh = (uint32_t)(a & 3);
-        uint32_t w0 = q[0], w1 = q[1], w2 = q[2], w3 = q[3];
+        uint32_t w0 = gload<uint32_t>(q), w1 = gload<uint32_t>(q + 1), w2 = gload<uint32_t>(q + 2),
+                 w3 = gload<uint32_t>(q + 3);
         if (sh == 0) return make_uint4(w0, w1, w2, w3);
-        uint32_t w4 = q[4];
+        uint32_t w4 = gload<uint32_t>(q + 4);
         return make_uint4(__builtin_amdgcn_alignbyte(w1, w0, sh), __builtin_amdgcn_alignbyte(w2, w1, sh),
                           __builtin_amdgcn_alignbyte(w3, w2, sh), __builtin_amdgcn_alignbyte(w4, w3, sh));
     }
     uint32_t w[4] = {0, 0, 0, 0};
     int n = rem < 16 ? rem : 16;
-    for (int b = 0; b < n; ++b) w[b >> 2] |= (uint32_t)p[b] << (8 * (b & 3));
+    for (int b = 0; b < n; ++b) w[b >> 2] |= (uint32_t)gload<uint8_t>(p + b) << (8 * (b & 3));
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
@@ -89,15 +128,25 @@ __device__ __forceinline__ uint2 load8_lim(const uint8_t* p, int rem) {
         uintptr_t a = (uintptr_t)p;
         const uint32_t* q = (const uint32_t*)(a & ~(uintptr_t)3);
         uint32_t sh = (uint32_t)(a & 3);
-        uint32_t w0 = q[0], w1 = q[1];
+        uint32_t w0 = gload<uint32_t>(q), w1 = gload<uint32_t>(q + 1);
         if (sh == 0) return make_uint2(w0, w1);
-        uint32_t w2 = q[2];
+        uint32_t w2 = gload<uint32_t>(q + 2);
         return make_uint2(__builtin_amdgcn_alignbyte(w1, w0, sh), __builtin_amdgcn_alignbyte(w2, w1, sh));
     }
     uint32_t w[2] = {0, 0};
     int n = rem < 8 ? rem : 8;
-    for (int b = 0; b < n; ++b) w[b >> 2] |= (uint32_t)p[b] << (8 * (b & 3));
+    for (int b = 0; b < n; ++b) w[b >> 2] |= (uint32_t)gload<uint8_t>(p + b) << (8 * (b & 3));
     return make_uint2(w[0], w[1]);
+}
+
+// 4 bytes starting at p, `rem` (>= 1) valid
+__device__ __forceinline__ uint32_t load4_lim(const uint8_t* p, int rem) {
+    uintptr_t a = (uintptr_t)p;
+    if ((a & 3) == 0 && rem >= 4) return gload<uint32_t>(p);
+    uint32_t w = 0;
+    int n = rem < 4 ? rem : 4;
+    for (int b = 0; b < n; ++b) w |= (uint32_t)gload<uint8_t>(p + b) << (8 * b);
+    return w;
 }
 
 // residues of p > 127 become signed int8 values x - p for x >= 128: add 256 - p to those bytes
@@ -106,10 +155,103 @@ __device__ __forceinline__ uint32_t centre(uint32_t w, uint32_t adj) {
     return w + hi * adj;
 }
 
-__global__ void __launch_bounds__(GEMM_THREADS)
+// transpose a 4 x 4 block of bytes: in r[i] byte j is element (i, j); out c[j] byte i is element (i, j)
+__device__ __forceinline__ void transpose4x4(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t r3, uint32_t& c0,
+                                             uint32_t& c1, uint32_t& c2, uint32_t& c3) {
+    const uint32_t t0 = __builtin_amdgcn_perm(r1, r0, 0x05010400u);   // r0.b0 r1.b0 r0.b1 r1.b1
+    const uint32_t t1 = __builtin_amdgcn_perm(r3, r2, 0x05010400u);   // r2.b0 r3.b0 r2.b1 r3.b1
+    const uint32_t t2 = __builtin_amdgcn_perm(r1, r0, 0x07030602u);   // r0.b2 r1.b2 r0.b3 r1.b3
+    const uint32_t t3 = __builtin_amdgcn_perm(r3, r2, 0x07030602u);   // r2.b2 r3.b2 r2.b3 r3.b3
+    c0 = __builtin_amdgcn_perm(t1, t0, 0x05040100u);
+    c1 = __builtin_amdgcn_perm(t1, t0, 0x07060302u);
+    c2 = __builtin_amdgcn_perm(t3, t2, 0x05040100u);
+    c3 = __builtin_amdgcn_perm(t3, t2, 0x07060302u);
+}
+
+struct GemmRegs {
+    uint4 a[4];     // A: four 16-byte chunks (rows of the A tile)
+    uint2 b[4];     // B: four k-rows x 8 columns
+};
+
+// Interior tiles of aligned operands (FAST): plain 16- and 8-byte vector loads
+// with no branches, so they stay in flight while the MFMAs of the current step
+// run.  Otherwise every chunk is bounds-checked and realigned.
+template <bool FAST>
+__device__ __forceinline__ void gemm_load(const GemmDesc& g, int m0, int n0, int k0, int tid, uint32_t adj,
+                                          GemmRegs& R) {
+    const int kg = tid >> 4, ng = tid & 15;
+    if (FAST) {
+        int64_t br[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) br[t] = g.brow ? gload<int32_t>(g.brow + k0 + kg * 4 + t) : k0 + kg * 4 + t;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int c = tid + s * GEMM_THREADS;
+            R.a[s] = gload<uint4>(g.A + (int64_t)(m0 + (c >> 2)) * g.lda + k0 + (c & 3) * 16);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) R.b[t] = gload<uint2>(g.B + br[t] * g.ldb + n0 + ng * 8);
+        if (adj) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                R.a[s].x = centre(R.a[s].x, adj); R.a[s].y = centre(R.a[s].y, adj);
+                R.a[s].z = centre(R.a[s].z, adj); R.a[s].w = centre(R.a[s].w, adj);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) { R.b[t].x = centre(R.b[t].x, adj); R.b[t].y = centre(R.b[t].y, adj); }
+        }
+        return;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int c = tid + s * GEMM_THREADS;
+        const int row = c >> 2, kc = (c & 3) * 16;
+        const int gr = m0 + row, gk = k0 + kc;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (gr < g.M && gk < g.K) {
+            v = load16_lim(g.A + (int64_t)gr * g.lda + gk, g.K - gk);
+            if (adj) { v.x = centre(v.x, adj); v.y = centre(v.y, adj); v.z = centre(v.z, adj); v.w = centre(v.w, adj); }
+        }
+        R.a[s] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int gk = k0 + kg * 4 + t, gn = n0 + ng * 8;
+        uint2 v = make_uint2(0, 0);
+        if (gk < g.K && gn < g.N) {
+            const int64_t br = g.brow ? gload<int32_t>(g.brow + gk) : gk;
+            v = load8_lim(g.B + br * g.ldb + gn, g.N - gn);
+            if (adj) { v.x = centre(v.x, adj); v.y = centre(v.y, adj); }
+        }
+        R.b[t] = v;
+    }
+}
+
+__device__ __forceinline__ void gemm_store_lds(const GemmRegs& R, uint8_t* As, uint8_t* Bs, int tid) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int c = tid + s * GEMM_THREADS;
+        *(uint4*)(As + (c >> 2) * LDS_ROW + (c & 3) * 16) = R.a[s];
+    }
+    const int kg = tid >> 4, ng = tid & 15;
+    uint32_t c0, c1, c2, c3;
+    transpose4x4(R.b[0].x, R.b[1].x, R.b[2].x, R.b[3].x, c0, c1, c2, c3);
+    uint8_t* base = Bs + (ng * 8) * LDS_ROW + kg * 4;
+    *(uint32_t*)(base + 0 * LDS_ROW) = c0;
+    *(uint32_t*)(base + 1 * LDS_ROW) = c1;
+    *(uint32_t*)(base + 2 * LDS_ROW) = c2;
+    *(uint32_t*)(base + 3 * LDS_ROW) = c3;
+    transpose4x4(R.b[0].y, R.b[1].y, R.b[2].y, R.b[3].y, c0, c1, c2, c3);
+    *(uint32_t*)(base + 4 * LDS_ROW) = c0;
+    *(uint32_t*)(base + 5 * LDS_ROW) = c1;
+    *(uint32_t*)(base + 6 * LDS_ROW) = c2;
+    *(uint32_t*)(base + 7 * LDS_ROW) = c3;
+}
+
+__global__ void __launch_bounds__(GEMM_THREADS, 2)
 k_gemm_modp(const GemmDesc* __restrict__ descs, const GemmTileMap* __restrict__ maps, int ndesc) {
-    __shared__ __attribute__((aligned(16))) uint8_t As[TM * LDS_ROW];
-    __shared__ __attribute__((aligned(16))) uint8_t Bs[TN * LDS_ROW];   // transposed: [n][k]
+    __shared__ __attribute__((aligned(16))) uint8_t As[2][TM * LDS_ROW];
+    __shared__ __attribute__((aligned(16))) uint8_t Bs[2][TN * LDS_ROW];   // transposed: [n][k]
 
     // which descriptor owns this tile (binary search over the prefix sums)
     const int tile = blockIdx.x;
@@ -126,98 +268,77 @@ k_gemm_modp(const GemmDesc* __restrict__ descs, const GemmTileMap* __restrict__ 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm = (wave >> 1) * 64;      // wave's 64 x 64 sub-tile
+    const int wm = (wave >> 1) * 128;     // wave's 128 x 64 sub-tile
     const int wn = (wave & 1) * 64;
     const uint32_t p = (uint32_t)g.p;
     const uint32_t adj = p > 127 ? 256u - p : 0u;
 
-    v4i acc[4][4];
+    v4i acc[8][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = v4i{0, 0, 0, 0};
 
-    for (int k0 = 0; k0 < g.K; k0 += TK) {
-        // ---- A tile: 128 rows x 64 bytes, two 16-byte chunks per thread
+    const int nk = (g.K + TK - 1) / TK;
+    // steps that may use the branch-free loads: whole tile inside D, 16-byte
+    // aligned A rows, 8-byte aligned B rows, and a full TK of K
+    const bool fast = m0 + TM <= g.M && n0 + TN <= g.N && ((uintptr_t)g.A & 15) == 0 && (g.lda & 15) == 0 &&
+                      ((uintptr_t)g.B & 7) == 0 && (g.ldb & 7) == 0;
+    const int nk_fast = fast ? g.K / TK : 0;
+    GemmRegs R;
+    if (nk > 0) {
+        if (nk_fast > 0) gemm_load<true>(g, m0, n0, 0, tid, adj, R);
+        else gemm_load<false>(g, m0, n0, 0, tid, adj, R);
+        gemm_store_lds(R, As[0], Bs[0], tid);
+    }
+    __syncthreads();
+    const int r16 = lane & 15;
+    const int kq = (lane >> 4) * 16;
+    for (int ks = 0; ks < nk; ++ks) {
+        const int st = ks & 1;
+        if (ks + 1 < nk_fast) gemm_load<true>(g, m0, n0, (ks + 1) * TK, tid, adj, R);
+        else if (ks + 1 < nk) gemm_load<false>(g, m0, n0, (ks + 1) * TK, tid, adj, R);
+        v4i bf[4];
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            int c = tid + s * GEMM_THREADS;
-            int row = c >> 2;
-            int kc = (c & 3) * 16;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            int gr = m0 + row, gk = k0 + kc;
-            if (gr < g.M && gk < g.K) {
-                v = load16_lim(g.A + (int64_t)gr * g.lda + gk, g.K - gk);
-                if (adj) { v.x = centre(v.x, adj); v.y = centre(v.y, adj); v.z = centre(v.z, adj); v.w = centre(v.w, adj); }
-            }
-            *(uint4*)(As + row * LDS_ROW + kc) = v;
+        for (int j = 0; j < 4; ++j) bf[j] = *(const v4i*)(Bs[st] + (wn + j * 16 + r16) * LDS_ROW + kq);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const v4i af = *(const v4i*)(As[st] + (wm + i * 16 + r16) * LDS_ROW + kq);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(bf[j], af, acc[i][j], 0, 0, 0);
         }
-        // ---- B tile: 64 k-rows x 128 columns, stored transposed; each thread 4 k x 8 n
-        {
-            int kg = tid >> 4;           // 0..15 -> k rows 4kg..4kg+3
-            int ng = tid & 15;           // 0..15 -> columns 8ng..8ng+7
-            uint32_t lo4[4], hi4[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                int gk = k0 + kg * 4 + t;
-                int gn = n0 + ng * 8;
-                uint2 v = make_uint2(0, 0);
-                if (gk < g.K && gn < g.N) {
-                    int64_t br = g.brow ? g.brow[gk] : gk;
-                    v = load8_lim(g.B + br * g.ldb + gn, g.N - gn);
-                    if (adj) { v.x = centre(v.x, adj); v.y = centre(v.y, adj); }
-                }
-                lo4[t] = v.x;
-                hi4[t] = v.y;
-            }
-            // transpose 4 (k) x 8 (n) bytes: column j gathers byte j of each k-row
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                uint32_t sh = (j & 3) * 8;
-                const uint32_t* src = j < 4 ? lo4 : hi4;
-                uint32_t col = ((src[0] >> sh) & 0xffu) | (((src[1] >> sh) & 0xffu) << 8) |
-                               (((src[2] >> sh) & 0xffu) << 16) | (((src[3] >> sh) & 0xffu) << 24);
-                *(uint32_t*)(Bs + (ng * 8 + j) * LDS_ROW + kg * 4) = col;
-            }
-        }
-        __syncthreads();
-        // ---- MFMA: each wave 4 x 4 blocks of 16 x 16, k = 64
-        const int r16 = lane & 15;
-        const int kq = (lane >> 4) * 16;
-        v4i af[4], bf[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) af[i] = *(const v4i*)(As + (wm + i * 16 + r16) * LDS_ROW + kq);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bf[j] = *(const v4i*)(Bs + (wn + j * 16 + r16) * LDS_ROW + kq);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[i], bf[j], acc[i][j], 0, 0, 0);
+        if (ks + 1 < nk) gemm_store_lds(R, As[st ^ 1], Bs[st ^ 1], tid);
         __syncthreads();
     }
 
-    // ---- epilogue: D = (Cin + acc) mod p
-    // acc[i][j] element e sits at row 4 * (lane / 16) + e, column lane % 16 of block (i, j);
-    // |acc| <= K * 127^2 < 2^30 for K <= 2^16
+    // ---- epilogue: D = (Cin + acc) mod p.  Lane holds, for block (i, j), row
+    // wm + 16 i + lane % 16 and the four columns wn + 16 j + 4 (lane / 16) + e.
+    // |acc| <= K * 127^2 < 2^30 for K <= 2^16.
     const ModP mod(p);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 8; ++i) {
+        const int row = m0 + wm + i * 16 + r16;
+        if (row >= g.M) continue;
+        const uint8_t* crow_ptr = g.C ? g.C + (int64_t)(g.crow ? gload<int32_t>(g.crow + row) : row) * g.ldc : nullptr;
+        uint8_t* drow_ptr = g.D + (int64_t)row * g.ldd;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 4; ++j) {
+            const int col = n0 + wn + j * 16 + (lane >> 4) * 4;
+            if (col >= g.N) continue;
+            const int rem = g.N - col;
+            const uint32_t cw = crow_ptr ? load4_lim(crow_ptr + col, rem) : 0u;
+            uint32_t out = 0;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                int row = m0 + wm + i * 16 + (lane >> 4) * 4 + e;
-                int col = n0 + wn + j * 16 + (lane & 15);
-                if (row < g.M && col < g.N) {
-                    int v = acc[i][j][e];
-                    if (g.C) {
-                        int64_t cr = g.crow ? g.crow[row] : row;
-                        v += g.C[cr * g.ldc + col];
-                    }
-                    g.D[(int64_t)row * g.ldd + col] = (uint8_t)mod(v);
-                }
+            for (int e = 0; e < 4; ++e) out |= mod(acc[i][j][e] + (int)((cw >> (8 * e)) & 0xffu)) << (8 * e);
+            uint8_t* dp = drow_ptr + col;
+            if (rem >= 4 && (((uintptr_t)dp) & 3) == 0) {
+                gstore<uint32_t>(dp, out);
+            } else {
+                const int n = rem < 4 ? rem : 4;
+                for (int e = 0; e < n; ++e) gstore<uint8_t>(dp + e, (uint8_t)(out >> (8 * e)));
             }
+        }
+    }
 }
 
 // ============================================================================ ECH
@@ -253,10 +374,9 @@ __global__ void __launch_bounds__(ECH_THREADS) k_ech(const EchDesc* __restrict__
     int* piv_cols = piv_rows + maxr;
 
     for (int x = tid; x < rows; x += ECH_THREADS) sel[x] = 0;
-    for (int64_t idx = tid; idx < (int64_t)rows * width; idx += ECH_THREADS) {
-        int x = (int)(idx / width), y = (int)(idx % width);
-        e.work[(int64_t)x * e.ldw + y] = y < cols ? e.H[(int64_t)x * e.ldh + y] : 0;
-    }
+    for (int x = wave; x < rows; x += ECH_THREADS / 64)
+        for (int y = lane; y < width; y += 64)
+            e.work[(int64_t)x * e.ldw + y] = y < cols ? e.H[(int64_t)x * e.ldh + y] : 0;
     __syncthreads();
 
     int r = 0;
@@ -330,20 +450,13 @@ __global__ void __launch_bounds__(ECH_THREADS) k_ech(const EchDesc* __restrict__
     }
     __syncthreads();
     // Mo[t][u] = T[prow[t]][u];  Ro[t][k] = W[prow[t]][qcol[k]];  Ko[s][u] = T[qrow[s]][u]
-    for (int64_t idx = tid; idx < (int64_t)r * r; idx += ECH_THREADS) {
-        int t = (int)(idx / r), u = (int)(idx % r);
-        e.Mo[(int64_t)t * e.ldm + u] = e.work[(int64_t)piv_rows[t] * e.ldw + cols + u];
+    for (int t = wave; t < r; t += ECH_THREADS / 64) {
+        for (int u = lane; u < r; u += 64) e.Mo[(int64_t)t * e.ldm + u] = e.work[(int64_t)piv_rows[t] * e.ldw + cols + u];
+        for (int k = lane; k < cols - r; k += 64)
+            e.Ro[(int64_t)t * e.ldr + k] = e.work[(int64_t)piv_rows[t] * e.ldw + e.qcol[k]];
     }
-    const int nr = cols - r;
-    for (int64_t idx = tid; idx < (int64_t)r * nr; idx += ECH_THREADS) {
-        int t = (int)(idx / nr), k = (int)(idx % nr);
-        e.Ro[(int64_t)t * e.ldr + k] = e.work[(int64_t)piv_rows[t] * e.ldw + e.qcol[k]];
-    }
-    const int nq = rows - r;
-    for (int64_t idx = tid; idx < (int64_t)nq * r; idx += ECH_THREADS) {
-        int s2 = (int)(idx / r), u = (int)(idx % r);
-        e.Ko[(int64_t)s2 * e.ldk + u] = e.work[(int64_t)e.qrow[s2] * e.ldw + cols + u];
-    }
+    for (int s2 = wave; s2 < rows - r; s2 += ECH_THREADS / 64)
+        for (int u = lane; u < r; u += 64) e.Ko[(int64_t)s2 * e.ldk + u] = e.work[(int64_t)e.qrow[s2] * e.ldw + cols + u];
 }
 
 // ---------------------------------------------------------------------------- ECH, panel form
@@ -367,7 +480,20 @@ constexpr int ECHP_MAX_ROWS = 512;
 __host__ __device__ constexpr size_t echp_fixed_lds() {
     return 128 + 2 * 16 * 64 * 4 + 2 * ECHP_MAX_ROWS * 4 + 256 * 4 + 2 * ECHP_MAX_ROWS + VCH * FL_ROW;
 }
-__host__ __device__ inline size_t echp_lds_bytes(int rows) { return echp_fixed_lds() + (size_t)((rows + 15) & ~15) * FL_ROW; }
+__host__ __device__ inline size_t echp_lds_bytes(int rows) {
+    return echp_fixed_lds() + (size_t)((rows + 15) & ~15) * (FL_ROW + VCH);
+}
+
+// (a + b) mod p on four packed residues (both < p <= 251), in 16-bit lanes
+__device__ __forceinline__ uint32_t addmod4(uint32_t a, uint32_t b, uint32_t p) {
+    const uint32_t k = (0x8000u - p) * 0x00010001u, pp = p * 0x00010001u;
+    uint32_t lo = (a & 0x00ff00ffu) + (b & 0x00ff00ffu);
+    uint32_t hi = ((a >> 8) & 0x00ff00ffu) + ((b >> 8) & 0x00ff00ffu);
+    lo -= ((lo + k) >> 15 & 0x00010001u) * p;
+    hi -= ((hi + k) >> 15 & 0x00010001u) * p;
+    (void)pp;
+    return lo | (hi << 8);
+}
 
 __global__ void __launch_bounds__(512) k_ech_panel(const EchDesc* __restrict__ descs) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
@@ -392,12 +518,35 @@ __global__ void __launch_bounds__(512) k_ech_panel(const EchDesc* __restrict__ d
     uint8_t* inpanel = sel + ECHP_MAX_ROWS;                        // row selected in the current panel
     uint8_t* Vt = inpanel + ECHP_MAX_ROWS;                         // [VCH][FL_ROW] pivot rows, transposed
     uint8_t* Fl = Vt + VCH * FL_ROW;                               // [rows16][FL_ROW]
+    uint8_t* St = Fl + rows16 * FL_ROW;                            // [rows16][VCH] staged products
 
-    for (int i = x; i < 256; i += nthr) invt[i] = (i > 0 && (uint32_t)i < p) ? pow_mod_dev((uint32_t)i, p - 2, p) : 0u;
+    // invt[v] = -1/v mod p: the multiplier that turns a pivot v into -1
+    for (int i = x; i < 256; i += nthr) invt[i] = (i > 0 && (uint32_t)i < p) ? (p - pow_mod_dev((uint32_t)i, p - 2, p)) % p : 0u;
     for (int i = x; i < ECHP_MAX_ROWS; i += nthr) sel[i] = 0;
-    for (int64_t idx = x; idx < (int64_t)rows * width; idx += nthr) {
-        int rr = (int)(idx / width), y = (int)(idx % width);
-        e.work[(int64_t)rr * e.ldw + y] = y < cols ? e.H[(int64_t)rr * e.ldh + y] : 0;
+    for (int i = x; i < 32; i += nthr) cand[i] = 0x7fffffff;
+    // W = [H | 0]: 16 bytes per lane where the rows are aligned, bytes otherwise
+    {
+        const bool vec = ((((uintptr_t)e.H) | ((uintptr_t)e.work) | (uintptr_t)e.ldh | (uintptr_t)e.ldw) & 15) == 0;
+        for (int rr = wave; rr < rows; rr += nwaves) {
+            const uint8_t* src = e.H + (int64_t)rr * e.ldh;
+            uint8_t* dst = e.work + (int64_t)rr * e.ldw;
+            if (vec) {
+                for (int y = lane * 16; y < width; y += 64 * 16) {
+                    uint4 v = make_uint4(0, 0, 0, 0);
+                    if (y + 16 <= cols) v = gload<uint4>(src + y);
+                    else if (y < cols) v = load16_lim(src + y, cols - y);
+                    if (y + 16 <= width) gstore<uint4>(dst + y, v);
+                    else {
+                        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                        for (int bb = 0; bb < 16; ++bb)
+                            if (y + bb < width) gstore<uint8_t>(dst + y + bb, (uint8_t)(w4[bb >> 2] >> (8 * (bb & 3))));
+                    }
+                }
+            } else {
+                for (int y = lane; y < width; y += 64) gstore<uint8_t>(dst + y, y < cols ? gload<uint8_t>(src + y) : 0);
+            }
+        }
     }
     __syncthreads();
     uint8_t* Wx = e.work + (int64_t)x * e.ldw;
@@ -408,42 +557,65 @@ __global__ void __launch_bounds__(512) k_ech_panel(const EchDesc* __restrict__ d
         uint32_t reg[PW], F[PW];
 #pragma unroll
         for (int j = 0; j < PW; ++j) {
-            reg[j] = (x < rows && j < wc) ? Wx[c0 + j] : 0u;
+            reg[j] = (x < rows && j < wc) ? gload<uint8_t>(Wx + c0 + j) : 0u;
             F[j] = 0;
         }
         bool mysel = x < rows && sel[x];
         bool mine = false;
         uint32_t myscale = 0;
         int rp = 0;
-#pragma unroll
+        // The window reg[0..PW) is a shift register: at step k, reg[0] holds column
+        // c0 + k.  A column is final once its step is done (later pivots are zero
+        // there), so it rotates to the back; after PW steps reg[j] is column c0 + j
+        // again.  Every register index is static, so the loop stays rolled.
+#pragma clang loop unroll(disable)
         for (int k = 0; k < PW; ++k) {
             if (k < wc && r + rp < maxr) {
-                const uint32_t v = mod_small(reg[k], p, minv);
-                reg[k] = v;
+                const uint32_t v = mod_small(reg[0], p, minv);
+                reg[0] = v;
                 const bool isc = x < rows && !mysel && v != 0;
                 const unsigned long long bal = __ballot(isc);
                 const int par = k & 1;
                 if (bal) {
+                    // this wave's first candidate parks its window and transform row
+                    // (with a 1 for itself); the wave reduces them
                     const int first = __ffsll((long long)bal) - 1;
+                    uint32_t* my = slot + (par * 16 + wave) * 64;
                     if (lane == first) {
                         cand[par * 16 + wave] = x;
-                        uint32_t* my = slot + (par * 16 + wave) * 64;
+                        uint4* my4 = (uint4*)my;
 #pragma unroll
-                        for (int j = 0; j < PW; ++j) my[j] = reg[j];
+                        for (int q = 0; q < PW / 4; ++q)
+                            my4[q] = make_uint4(reg[4 * q], reg[4 * q + 1], reg[4 * q + 2], reg[4 * q + 3]);
 #pragma unroll
-                        for (int t = 0; t < PW; ++t) my[PW + t] = (t == rp) ? 1u : F[t];
+                        for (int q = 0; q < PW / 4; ++q)
+                            my4[PW / 4 + q] = make_uint4(4 * q == rp ? 1u : F[4 * q], 4 * q + 1 == rp ? 1u : F[4 * q + 1],
+                                                         4 * q + 2 == rp ? 1u : F[4 * q + 2],
+                                                         4 * q + 3 == rp ? 1u : F[4 * q + 3]);
                     }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    my[lane] = mod_small(my[lane], p, minv);
                 } else if (lane == 0) {
                     cand[par * 16 + wave] = 0x7fffffff;
                 }
                 __syncthreads();
                 int best = 0x7fffffff;
-                for (int w = 0; w < nwaves; ++w) best = min(best, cand[par * 16 + w]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int4 c4 = ((const int4*)(cand + par * 16))[q];
+                    best = min(best, min(min(c4.x, c4.y), min(c4.z, c4.w)));
+                }
                 if (best != 0x7fffffff) {
-                    uint32_t* ps = slot + (par * 16 + (best >> 6)) * 64;
-                    if (wave == (best >> 6)) ps[lane] = mod_small(ps[lane], p, minv);
-                    __syncthreads();
-                    const uint32_t s = (p - invt[ps[k]]) % p;        // -1 / pivot
+                    const uint32_t* ps = slot + (par * 16 + (best >> 6)) * 64;
+                    uint32_t pv[2 * PW];
+#pragma unroll
+                    for (int q = 0; q < PW / 2; ++q) {
+                        const uint4 w4 = ((const uint4*)ps)[q];
+                        pv[4 * q] = w4.x; pv[4 * q + 1] = w4.y; pv[4 * q + 2] = w4.z; pv[4 * q + 3] = w4.w;
+                    }
+                    const uint32_t s = invt[pv[0]];                   // -1 / pivot
                     if (x == best) {
                         mysel = true;
                         mine = true;
@@ -455,37 +627,53 @@ __global__ void __launch_bounds__(512) k_ech_panel(const EchDesc* __restrict__ d
                         prl[r + rp] = x;
                         pcl[r + rp] = c0 + k;
                     } else if (x < rows) {
-                        const uint32_t f = mod_small(v * s, p, minv);
-                        if (f) {
+                        const uint32_t f = mod_small(__umul24(v, s), p, minv);
 #pragma unroll
-                            for (int j = k + 1; j < PW; ++j) reg[j] += f * ps[j];
-                            reg[k] = 0;
+                        for (int j = 1; j < PW; ++j) reg[j] = mad24(f, pv[j], reg[j]);
+                        reg[0] = 0;
 #pragma unroll
-                            for (int t = 0; t < PW; ++t) F[t] += f * ps[PW + t];
-                        }
+                        for (int t = 0; t < PW; ++t) F[t] = mad24(f, pv[PW + t], F[t]);
                     }
                     ++rp;
                 }
             }
+            const uint32_t done = reg[0];
+#pragma unroll
+            for (int j = 0; j + 1 < PW; ++j) reg[j] = reg[j + 1];
+            reg[PW - 1] = done;
         }
         // normalise this panel's pivot rows (pivot -> -1) and reduce everything
 #pragma unroll
         for (int j = 0; j < PW; ++j) {
             uint32_t a = mod_small(reg[j], p, minv), b = mod_small(F[j], p, minv);
             if (mine) {
-                a = mod_small(a * myscale, p, minv);
-                b = mod_small(b * myscale, p, minv);
+                a = mod_small(__umul24(a, myscale), p, minv);
+                b = mod_small(__umul24(b, myscale), p, minv);
             }
             reg[j] = a;
             F[j] = b;
         }
         if (x < rows) {
+            uint32_t pw[PW / 4], fw[PW / 4];
 #pragma unroll
-            for (int j = 0; j < PW; ++j)
-                if (j < wc) Wx[c0 + j] = (uint8_t)reg[j];
+            for (int q = 0; q < PW / 4; ++q) {
+                pw[q] = reg[4 * q] | (reg[4 * q + 1] << 8) | (reg[4 * q + 2] << 16) | (reg[4 * q + 3] << 24);
+                fw[q] = F[4 * q] | (F[4 * q + 1] << 8) | (F[4 * q + 2] << 16) | (F[4 * q + 3] << 24);
+            }
+            uint8_t* dp = Wx + c0;
+            if (wc == PW && (((uintptr_t)dp) & 15) == 0) {
+#pragma unroll
+                for (int q = 0; q < PW / 16; ++q)
+                    gstore<uint4>(dp + 16 * q, make_uint4(pw[4 * q], pw[4 * q + 1], pw[4 * q + 2], pw[4 * q + 3]));
+            } else {
+#pragma unroll
+                for (int j = 0; j < PW; ++j)
+                    if (j < wc) gstore<uint8_t>(dp + j, (uint8_t)(pw[j >> 2] >> (8 * (j & 3))));
+            }
+            uint8_t* tp = Wx + cols + r;
 #pragma unroll
             for (int t = 0; t < PW; ++t)
-                if (t < rp) Wx[cols + r + t] = (uint8_t)F[t];
+                if (t < rp) gstore<uint8_t>(tp + t, (uint8_t)(fw[t >> 2] >> (8 * (t & 3))));
             inpanel[x] = mine ? 1 : 0;
         }
         if (x < rows16) {
@@ -505,45 +693,70 @@ __global__ void __launch_bounds__(512) k_ech_panel(const EchDesc* __restrict__ d
         }
         __syncthreads();
         if (rp > 0) {
-            const int nd = cols - (c0 + wc);     // data columns right of the panel
-            const int total = nd + r;            // plus transformation columns of earlier pivots
-            for (int ch = 0; ch < total; ch += VCH) {
-                for (int i = x; i < VCH * 16; i += nthr) {
-                    const int cl = i >> 4, tw = (i & 15) * 4, q = ch + cl;
-                    uint32_t word = 0;
-                    if (q < total) {
-                        const int y = q < nd ? c0 + wc + q : cols + (q - nd);
+            // segment 0: data columns right of the panel; segment 1: transformation
+            // columns of the pivots of earlier panels
+            for (int seg = 0; seg < 2; ++seg) {
+                const int ybase = seg == 0 ? c0 + wc : cols;
+                const int ny = seg == 0 ? cols - (c0 + wc) : r;
+                for (int ch = 0; ch < ny; ch += VCH) {
+                    const int nc = min(VCH, ny - ch);
+                    // pivot rows of this chunk, transposed into Vt[column][pivot]
+                    for (int i = x; i < rp * (VCH / 16); i += nthr) {
+                        const int t = i / (VCH / 16), cb = (i % (VCH / 16)) * 16;
+                        if (cb < nc) {
+                            const uint8_t* src = e.work + (int64_t)prl[r + t] * e.ldw + ybase + ch + cb;
+                            const uint4 v = load16_lim(src, ny - ch - cb);
 #pragma unroll
-                        for (int b = 0; b < 4; ++b) {
-                            const int t = tw + b;
-                            if (t < rp) word |= (uint32_t)e.work[(int64_t)prl[r + t] * e.ldw + y] << (8 * b);
+                            for (int bb = 0; bb < 16; ++bb) {
+                                const uint32_t wv = bb < 4 ? v.x : bb < 8 ? v.y : bb < 12 ? v.z : v.w;
+                                uint32_t byte = (wv >> (8 * (bb & 3))) & 0xffu;
+                                if (adj && byte >= 128) byte += adj;
+                                Vt[(cb + bb) * FL_ROW + t] = (uint8_t)byte;
+                            }
                         }
                     }
-                    *(uint32_t*)(Vt + cl * FL_ROW + tw) = adj ? centre(word, adj) : word;
-                }
-                __syncthreads();
-                const int nb = (rows16 >> 4) * (VCH / 16);
-                for (int b = wave; b < nb; b += nwaves) {
-                    const int rb = b / (VCH / 16), cb = b % (VCH / 16);
-                    const v4i av = *(const v4i*)(Fl + (rb * 16 + (lane & 15)) * FL_ROW + (lane >> 4) * 16);
-                    const v4i bv = *(const v4i*)(Vt + (cb * 16 + (lane & 15)) * FL_ROW + (lane >> 4) * 16);
-                    const v4i acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(av, bv, v4i{0, 0, 0, 0}, 0, 0, 0);
-                    const int cl = cb * 16 + (lane & 15), q = ch + cl;
-                    if (q < total) {
-                        const int y = q < nd ? c0 + wc + q : cols + (q - nd);
+                    __syncthreads();
+                    // products F * V, reduced mod p, staged as bytes: lane holds row
+                    // rb*16 + lane%16 and columns cb*16 + 4*(lane/16) .. +3
+                    const int nb = (rows16 >> 4) * (VCH / 16);
+                    for (int b = wave; b < nb; b += nwaves) {
+                        const int rb = b / (VCH / 16), cb = b % (VCH / 16);
+                        const v4i av = *(const v4i*)(Fl + (rb * 16 + (lane & 15)) * FL_ROW + (lane >> 4) * 16);
+                        const v4i bv = *(const v4i*)(Vt + (cb * 16 + (lane & 15)) * FL_ROW + (lane >> 4) * 16);
+                        const v4i acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(bv, av, v4i{0, 0, 0, 0}, 0, 0, 0);
+                        uint32_t word = 0;
 #pragma unroll
-                        for (int ee = 0; ee < 4; ++ee) {
-                            const int row = rb * 16 + (lane >> 4) * 4 + ee;
-                            if (row < rows) {
-                                uint8_t* w = e.work + (int64_t)row * e.ldw + y;
-                                const int old = inpanel[row] ? 0 : (int)*w;
-                                *w = (uint8_t)mod(acc[ee] + old);
+                        for (int ee = 0; ee < 4; ++ee) word |= mod(acc[ee]) << (8 * ee);
+                        *(uint32_t*)(St + (rb * 16 + (lane & 15)) * VCH + cb * 16 + (lane >> 4) * 4) = word;
+                    }
+                    __syncthreads();
+                    // row x: W := (pivot of this panel ? 0 : W) + staged, 16 bytes at a time
+                    if (x < rows) {
+                        uint8_t* dst = e.work + (int64_t)x * e.ldw + ybase + ch;
+                        const bool keep_old = !inpanel[x];
+                        for (int cb = 0; cb < nc; cb += 16) {
+                            const uint4 st = *(const uint4*)(St + x * VCH + cb);
+                            uint4 nv = st;
+                            if (keep_old) {
+                                const uint4 old = load16_lim(dst + cb, ny - ch - cb);
+                                nv = make_uint4(addmod4(old.x, st.x, p), addmod4(old.y, st.y, p),
+                                                addmod4(old.z, st.z, p), addmod4(old.w, st.w, p));
+                            }
+                            const int n = min(16, nc - cb);
+                            if (n == 16 && (((uintptr_t)(dst + cb)) & 15) == 0) {
+                                gstore<uint4>(dst + cb, nv);
+                            } else {
+#pragma unroll
+                                for (int bb = 0; bb < 16; ++bb) {
+                                    const uint32_t wv = bb < 4 ? nv.x : bb < 8 ? nv.y : bb < 12 ? nv.z : nv.w;
+                                    if (bb < n) gstore<uint8_t>(dst + cb + bb, (uint8_t)(wv >> (8 * (bb & 3))));
+                                }
                             }
                         }
                     }
                 }
-                __syncthreads();
             }
+            __syncthreads();
         }
         r += rp;
     }
@@ -566,19 +779,15 @@ __global__ void __launch_bounds__(512) k_ech_panel(const EchDesc* __restrict__ d
         }
     }
     __syncthreads();
-    for (int64_t idx = x; idx < (int64_t)r * r; idx += nthr) {
-        int t = (int)(idx / r), u = (int)(idx % r);
-        e.Mo[(int64_t)t * e.ldm + u] = e.work[(int64_t)prl[t] * e.ldw + cols + u];
+    for (int t = wave; t < r; t += nwaves) {
+        const uint8_t* src = e.work + (int64_t)prl[t] * e.ldw;
+        for (int u = lane; u < r; u += 64) gstore<uint8_t>(e.Mo + (int64_t)t * e.ldm + u, gload<uint8_t>(src + cols + u));
+        for (int k2 = lane; k2 < cols - r; k2 += 64)
+            gstore<uint8_t>(e.Ro + (int64_t)t * e.ldr + k2, gload<uint8_t>(src + gload<int32_t>(e.qcol + k2)));
     }
-    const int nr = cols - r;
-    for (int64_t idx = x; idx < (int64_t)r * nr; idx += nthr) {
-        int t = (int)(idx / nr), k2 = (int)(idx % nr);
-        e.Ro[(int64_t)t * e.ldr + k2] = e.work[(int64_t)prl[t] * e.ldw + e.qcol[k2]];
-    }
-    const int nq = rows - r;
-    for (int64_t idx = x; idx < (int64_t)nq * r; idx += nthr) {
-        int s2 = (int)(idx / r), u = (int)(idx % r);
-        e.Ko[(int64_t)s2 * e.ldk + u] = e.work[(int64_t)e.qrow[s2] * e.ldw + cols + u];
+    for (int s2 = wave; s2 < rows - r; s2 += nwaves) {
+        const uint8_t* src = e.work + (int64_t)gload<int32_t>(e.qrow + s2) * e.ldw + cols;
+        for (int u = lane; u < r; u += 64) gstore<uint8_t>(e.Ko + (int64_t)s2 * e.ldk + u, gload<uint8_t>(src + u));
     }
 }
 
@@ -587,18 +796,21 @@ __global__ void __launch_bounds__(512) k_ech_panel(const EchDesc* __restrict__ d
 constexpr int SMALL_THREADS = 256;
 
 // grid: (x blocks striding over elements, y = descriptor)
+// grid: (x blocks striding over rows, y = descriptor); threads stride over columns
 __global__ void __launch_bounds__(SMALL_THREADS) k_gather(const GatherDesc* __restrict__ descs) {
     const GatherDesc g = descs[blockIdx.y];
-    const int64_t total = (int64_t)g.rows * g.cols;
-    if (total == 0) return;
-    for (int64_t idx = (int64_t)blockIdx.x * SMALL_THREADS + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * SMALL_THREADS) {
-        int x = (int)(idx / g.cols), y = (int)(idx % g.cols);
-        int64_t sr = g.srow ? g.srow[x] : x, sc = g.scol ? g.scol[y] : y;
-        uint32_t v = g.src[sr * g.lds + sc];
-        if (g.neg_p) v = (uint32_t)((g.neg_p - (int)v) % g.neg_p);
-        int64_t dr = g.drow ? g.drow[x] : x, dc = g.dcol ? g.dcol[y] : y;
-        g.dst[dr * g.ldd + dc] = (uint8_t)v;
+    for (int x = blockIdx.x; x < g.rows; x += gridDim.x) {
+        const int64_t sr = g.srow ? gload<int32_t>(g.srow + x) : x;
+        const int64_t dr = g.drow ? gload<int32_t>(g.drow + x) : x;
+        const uint8_t* src = g.src + sr * g.lds;
+        uint8_t* dst = g.dst + dr * g.ldd;
+        for (int y = threadIdx.x; y < g.cols; y += SMALL_THREADS) {
+            const int64_t sc = g.scol ? gload<int32_t>(g.scol + y) : y;
+            uint32_t v = gload<uint8_t>(src + sc);
+            if (g.neg_p) v = (uint32_t)((g.neg_p - (int)v) % g.neg_p);
+            const int64_t dc = g.dcol ? gload<int32_t>(g.dcol + y) : y;
+            gstore<uint8_t>(dst + dc, (uint8_t)v);
+        }
     }
 }
 
@@ -609,12 +821,10 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_fill(const FillDesc* __restri
             f.dst[(int64_t)t * f.ldd + f.dcol[t]] = (uint8_t)f.diag_value;
         return;
     }
-    const int64_t total = (int64_t)f.rows * f.cols;
-    for (int64_t idx = (int64_t)blockIdx.x * SMALL_THREADS + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * SMALL_THREADS) {
-        int x = (int)(idx / f.cols), y = (int)(idx % f.cols);
-        f.dst[(int64_t)x * f.ldd + y] = (uint8_t)((x == y && f.diag_value >= 0) ? f.diag_value : f.value);
-    }
+    for (int x = blockIdx.x; x < f.rows; x += gridDim.x)
+        for (int y = threadIdx.x; y < f.cols; y += SMALL_THREADS)
+            gstore<uint8_t>(f.dst + (int64_t)x * f.ldd + y,
+                            (uint8_t)((x == y && f.diag_value >= 0) ? f.diag_value : f.value));
 }
 
 __global__ void __launch_bounds__(SMALL_THREADS) k_lists(const ListDesc* __restrict__ descs) {
@@ -638,12 +848,8 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_sort(const SortDesc* __restri
 __global__ void __launch_bounds__(SMALL_THREADS)
 k_range(const uint8_t* __restrict__ A, int64_t m, int64_t n, int64_t lda, int p, unsigned long long* bad) {
     unsigned long long cnt = 0;
-    const int64_t total = m * n;
-    for (int64_t idx = (int64_t)blockIdx.x * SMALL_THREADS + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * SMALL_THREADS) {
-        int64_t x = idx / n, y = idx % n;
-        cnt += A[x * lda + y] >= p;
-    }
+    for (int64_t x = blockIdx.x; x < m; x += gridDim.x)
+        for (int64_t y = threadIdx.x; y < n; y += SMALL_THREADS) cnt += gload<uint8_t>(A + x * lda + y) >= p;
     if (cnt) atomicAdd(bad, cnt);
 }
 
@@ -824,11 +1030,12 @@ public:
     }
 
     void gather(const std::vector<GatherDesc>& ds) override {
-        small<GatherDesc>(ds, k_gather, [](const GatherDesc& g) -> int64_t { return (int64_t)g.rows * g.cols; });
+        // one block per row (up to the cap); the work function counts rows x threads
+        small<GatherDesc>(ds, k_gather, [](const GatherDesc& g) -> int64_t { return (int64_t)g.rows * SMALL_THREADS; });
     }
     void fill(const std::vector<FillDesc>& ds) override {
         small<FillDesc>(ds, k_fill, [](const FillDesc& f) -> int64_t {
-            return f.dcol ? (int64_t)f.rows : (int64_t)f.rows * f.cols;
+            return f.dcol ? (int64_t)f.rows : (int64_t)f.rows * SMALL_THREADS;
         });
     }
     void lists(const std::vector<ListDesc>& ds) override {
@@ -840,8 +1047,7 @@ public:
 
     int64_t count_out_of_range(const uint8_t* A, int64_t m, int64_t n, int64_t lda, int32_t p) override {
         HIP_OK(hipMemsetAsync(counter_, 0, 8, stream_));
-        int64_t total = m * n;
-        int64_t bx = std::min<int64_t>((total + SMALL_THREADS - 1) / SMALL_THREADS, 8192);
+        int64_t bx = std::min<int64_t>(m, 8192);
         hipLaunchKernelGGL(k_range, dim3((unsigned)std::max<int64_t>(bx, 1)), dim3(SMALL_THREADS), 0, stream_, A, m,
                            n, lda, p, (unsigned long long*)counter_);
         HIP_OK(hipGetLastError());
