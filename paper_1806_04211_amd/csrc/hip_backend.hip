@@ -236,7 +236,8 @@ __device__ __forceinline__ void gemm_store_lds(const GemmRegs& R, uint8_t* As, u
     const int kg = tid >> 4, ng = tid & 15;
     uint32_t c0, c1, c2, c3;
     transpose4x4(R.b[0].x, R.b[1].x, R.b[2].x, R.b[3].x, c0, c1, c2, c3);
-    uint8_t* base = Bs + (ng * 8) * LDS_ROW + kg * 4;
+    // the 16-byte chunk (kg >> 2) of columns 8 ng .. 8 ng + 7 sits at chunk (kg >> 2) ^ (ng & 3)
+    uint8_t* base = Bs + (ng * 8) * LDS_ROW + ((((kg >> 2) ^ (ng & 3)) << 4) | ((kg & 3) << 2));
     *(uint32_t*)(base + 0 * LDS_ROW) = c0;
     *(uint32_t*)(base + 1 * LDS_ROW) = c1;
     *(uint32_t*)(base + 2 * LDS_ROW) = c2;
@@ -300,7 +301,10 @@ k_gemm_modp(const GemmDesc* __restrict__ descs, const GemmTileMap* __restrict__ 
         else if (ks + 1 < nk) gemm_load<false>(g, m0, n0, (ks + 1) * TK, tid, adj, R);
         v4i bf[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bf[j] = *(const v4i*)(Bs[st] + (wn + j * 16 + r16) * LDS_ROW + kq);
+        for (int j = 0; j < 4; ++j) {
+            const int n = wn + j * 16 + r16;
+            bf[j] = *(const v4i*)(Bs[st] + n * LDS_ROW + ((kq >> 4) ^ ((n >> 3) & 3)) * 16);
+        }
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const v4i af = *(const v4i*)(As[st] + (wm + i * 16 + r16) * LDS_ROW + kq);
