@@ -49,6 +49,21 @@ def cpu_baseline(n: int, k: int, p: int):
             "seconds": dt}
 
 
+def copy_calibration(torch, mib: int):
+    """A streaming kernel of known traffic, three times: an elementwise negation
+    that reads ``mib`` MiB and writes ``mib`` MiB (torch's elementwise kernel,
+    not a DMA copy, so that per-dispatch counters see it).  The reading of an
+    HBM byte counter for one dispatch, divided by the bytes it moved, is that
+    counter's scale factor."""
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +74,8 @@ def main():
     ap.add_argument("--p", type=int, default=7)
     ap.add_argument("--block", type=int, default=0, help="block size (0 = the library's choice)")
     ap.add_argument("--cpu-sample", type=int, default=1600, help="oracle sample size (0 = skip)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the method here runs on a "
@@ -66,6 +83,10 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_mib > 0:
+        copy_calibration(torch, args.copy_mib)
+        return
 
     import paper_1806_04211_amd as gf
     from synth import torch_gen
