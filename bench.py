@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--inner", type=int, default=39000)
     ap.add_argument("--p", type=int, default=7)
     ap.add_argument("--block", type=int, default=0, help="block size (0 = the library's choice)")
+    ap.add_argument("--block-rows", type=int, default=0, help="block rows a_i (overrides --block)")
+    ap.add_argument("--block-cols", type=int, default=0, help="block columns b_j (overrides --block)")
     ap.add_argument("--cpu-sample", type=int, default=1600, help="oracle sample size (0 = skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates HBM byte counters)")
@@ -102,7 +104,7 @@ def main():
 
     lib = gf.library()
     stream = torch.cuda.current_stream(dev)
-    kw = dict(block_rows=args.block, block_cols=args.block)
+    kw = dict(block_rows=args.block_rows or args.block, block_cols=args.block_cols or args.block)
 
     def solve(profile):
         return lib.echelonise_dev(A.data_ptr(), n, n, n, p, stream=stream.cuda_stream, profile=profile, **kw)

@@ -116,6 +116,13 @@ public:
     virtual int64_t count_out_of_range(const uint8_t* A, int64_t m, int64_t n, int64_t lda, int32_t p) = 0;
     // stream for subsequent work (a hipStream_t for the HIP backend)
     virtual void set_stream(void* stream) { (void)stream; }
+    // Two lanes of work: lane 0 is the caller's stream, lane 1 a second stream
+    // whose work may overlap lane 0's.  mark() records the point reached by a
+    // lane's queued work; wait_mark() makes a lane wait for such a point.
+    // Memory transfers (upload, download, zero, copy) always run on lane 0.
+    virtual void set_lane(int lane) { (void)lane; }
+    virtual int mark(int lane) { (void)lane; return 0; }
+    virtual void wait_mark(int lane, int mark) { (void)lane; (void)mark; }
     // non-zero after a device error; the planner stops and reports it
     virtual int error() const { return 0; }
     // per-launch timing of the grouped jobs (device events on the work stream)

@@ -17,6 +17,20 @@
 // transformation blocks K_i,h (h <= i) sit side by side in one panel, each in
 // a column range reserved for block row h.  The pivot rows B_j,k and M_j,h of
 // block column j live in rows of one pivot matrix P.
+//
+// Lookahead on two lanes (streams).  Every UpdateRow / UpdateRowTrafo
+// product is column-separable: output column c depends only on column c of
+// its inputs.  So the products of task (i, j) are split by output columns
+// into a priority part, block column j + 1 (the one the next ClearDown of
+// block row i reads), which runs on lane 0 with the ClearDowns, and a bulk
+// part (block columns j + 2.. and every transformation column), which runs
+// on lane 1.  Lane 0 runs layer L + 1's ClearDowns (extract, MADs, ECH) while
+// lane 1 runs layer L's bulk part (started after layer L + 1's ClearDown
+// MADs, and issued after its ECHs so that they reach the device first); lane 0 waits for that bulk
+// part only before layer L + 1's own UpdateRow products, which read columns
+// it wrote.  The job scratch the bulk part reads (A.A, A.M, A.K, the row
+// lists of the ECH) is kept twice, by layer parity, so layer L + 1's
+// ClearDowns cannot overwrite what layer L's bulk part still reads.
 #include "chief.h"
 
 #include <algorithm>
@@ -78,10 +92,14 @@ struct Ops {
     std::vector<EchDesc> ech;
     std::vector<SortDesc> sort;
     std::vector<FillDesc> fill;
+    bool empty() const {
+        return gemm.empty() && gather.empty() && lists.empty() && ech.empty() && sort.empty() && fill.empty();
+    }
 };
 
 struct TaskState {      // one (i, j) of the current layer
     int i = 0, j = 0;
+    int par = 0;        // layer parity: which copy of the job scratch this layer uses
     bool active = false, did_ech = false;
     int32_t alpha = 0;  // rows of block row i when the layer started
     int32_t r = 0;      // pivots of block column j before ClearDown
@@ -139,15 +157,17 @@ public:
                 bc.oGbar[s] = ar.take(sizeof(int32_t) * bj);
             }
             bc.oGam = ar.take(sizeof(int32_t) * bj);
-            bc.oAA = ar.take(amax_ * bj);
+            for (int s = 0; s < 2; ++s) {
+                bc.oAA[s] = ar.take(amax_ * bj);
+                bc.oAM[s] = ar.take(bj * bj);
+                bc.oAK[s] = ar.take(amax_ * bj);
+                bc.oProw[s] = ar.take(sizeof(int32_t) * std::max<int64_t>(amax_, 1));
+                bc.oQrow[s] = ar.take(sizeof(int32_t) * std::max<int64_t>(amax_, 1));
+            }
             bc.oH = ar.take(amax_ * bj);
             bc.ldW = 2 * bj;
             bc.oW = ar.take(amax_ * bc.ldW);
-            bc.oAM = ar.take(bj * bj);
-            bc.oAK = ar.take(amax_ * bj);
             bc.oAE = ar.take(bc.cap * bj);
-            bc.oProw = ar.take(sizeof(int32_t) * std::max<int64_t>(amax_, 1));
-            bc.oQrow = ar.take(sizeof(int32_t) * std::max<int64_t>(amax_, 1));
             bc.oPcol = ar.take(sizeof(int32_t) * bj);
             bc.oQcol = ar.take(sizeof(int32_t) * bj);
         }
@@ -177,16 +197,16 @@ public:
             for (int s = 0; s < 2; ++s) {
                 bc.DR[s] = at(bc.oDR[s]);
                 bc.Gbar[s] = (int32_t*)at(bc.oGbar[s]);
+                bc.AA[s] = at(bc.oAA[s]);
+                bc.AM[s] = at(bc.oAM[s]);
+                bc.AK[s] = at(bc.oAK[s]);
+                bc.Prow[s] = (int32_t*)at(bc.oProw[s]);
+                bc.Qrow[s] = (int32_t*)at(bc.oQrow[s]);
             }
             bc.Gam = (int32_t*)at(bc.oGam);
-            bc.AA = at(bc.oAA);
             bc.H = at(bc.oH);
             bc.W = at(bc.oW);
-            bc.AM = at(bc.oAM);
-            bc.AK = at(bc.oAK);
             bc.AE = at(bc.oAE);
-            bc.Prow = (int32_t*)at(bc.oProw);
-            bc.Qrow = (int32_t*)at(bc.oQrow);
             bc.Pcol = (int32_t*)at(bc.oPcol);
             bc.Qcol = (int32_t*)at(bc.oQcol);
         }
@@ -233,6 +253,7 @@ public:
             t.j = L - i;
             t.alpha = alpha_[i];
             t.r = rankc_[t.j];
+            t.par = L & 1;
             t.active = t.alpha > 0;
             tasks_.push_back(t);
         }
@@ -250,7 +271,7 @@ public:
                 GatherDesc g;
                 g.rows = t.alpha; g.cols = t.r;
                 g.src = Cij; g.lds = br.ldC; g.scol = bc.Gam;
-                g.dst = bc.AA; g.ldd = bj;
+                g.dst = bc.AA[t.par]; g.ldd = bj;
                 ops.gather.push_back(g);
                 st_.gather_bytes += 2.0 * t.alpha * t.r;
                 if (bj - t.r > 0) {
@@ -264,43 +285,51 @@ public:
         }
     }
 
-    // ClearDown's first MAD (H = A' + A.A * D.R) and UpdateRow / UpdateRowTrafo step (1)
-    void cd_mad_ur1(Ops& ops) {
+    // ClearDown's first MAD: H = A' + A.A * D.R
+    void cd_mad(Ops& ops) {
+        for (auto& t : tasks_) {
+            if (!t.active || t.r == 0) continue;
+            BC& bc = cols_[t.j];
+            int32_t bj = pr_.col_blocks[t.j];
+            if (bj - t.r == 0) continue;
+            GemmDesc g;
+            g.M = t.alpha; g.N = bj - t.r; g.K = t.r; g.p = p_;
+            g.A = bc.AA[t.par]; g.lda = bj;
+            g.B = bc.DR[bc.dcur]; g.ldb = bc.ld;
+            g.C = bc.H; g.ldc = bj; g.D = bc.H; g.ldd = bj;
+            push_gemm(ops, g, st_.cd_mad);
+        }
+    }
+
+    // UpdateRow / UpdateRowTrafo step (1): Z := C + A.A * B over all blocks
+    // k > j of the panel, and Z := K + A.A * M for h != i (K's new columns are
+    // the zero columns CRZ adds)
+    void ur1(Ops& pri, Ops& bulk) {
         for (auto& t : tasks_) {
             if (!t.active || t.r == 0) continue;
             BR& br = rows_[t.i];
             BC& bc = cols_[t.j];
             int32_t bj = pr_.col_blocks[t.j];
-            if (bj - t.r > 0) {
-                GemmDesc g;
-                g.M = t.alpha; g.N = bj - t.r; g.K = t.r; g.p = p_;
-                g.A = bc.AA; g.lda = bj;
-                g.B = bc.DR[bc.dcur]; g.ldb = bc.ld;
-                g.C = bc.H; g.ldc = bj; g.D = bc.H; g.ldd = bj;
-                push_gemm(ops, g, st_.cd_mad);
-            }
-            // (1) Z := C + A.A * B over all blocks k > j of the panel
             int64_t c0 = C0_[t.j + 1];
             if (n_ - c0 > 0) {
                 GemmDesc g;
                 g.M = t.alpha; g.N = (int32_t)(n_ - c0); g.K = t.r; g.p = p_;
-                g.A = bc.AA; g.lda = bj;
+                g.A = bc.AA[t.par]; g.lda = bj;
                 g.B = P_ + bc.prow0 * ldP_ + c0; g.ldb = ldP_;
                 g.C = br.C[br.cur] + c0; g.ldc = br.ldC;
                 g.D = br.C[br.cur] + c0; g.ldd = br.ldC;
-                push_gemm(ops, g, st_.ur_mad);
+                push_split(pri, bulk, g, t.j, st_.ur_mad);
             }
-            // URT (1), h != i: Z := K + A.A * M   (K's new columns are the zero columns CRZ adds)
             for (int h = 0; h < t.i; ++h) {
                 int32_t w = sel_[h][t.j];
                 if (w == 0) continue;
                 GemmDesc g;
                 g.M = t.alpha; g.N = w; g.K = t.r; g.p = p_;
-                g.A = bc.AA; g.lda = bj;
+                g.A = bc.AA[t.par]; g.lda = bj;
                 g.B = P_ + bc.prow0 * ldP_ + n_ + R0_[h]; g.ldb = ldP_;
                 g.C = br.K[br.cur] + R0_[h]; g.ldc = br.ldK;
                 g.D = br.K[br.cur] + R0_[h]; g.ldd = br.ldK;
-                push_gemm(ops, g, st_.urt_mad);
+                push_gemm(bulk, g, st_.urt_mad);
             }
         }
     }
@@ -319,9 +348,9 @@ public:
             else { e.H = br.C[br.cur] + C0_[t.j]; e.ldh = br.ldC; }
             e.work = bc.W; e.ldw = bc.ldW;
             e.rcount = counts_ + t.j;
-            e.prow = bc.Prow; e.qrow = bc.Qrow; e.pcol = bc.Pcol; e.qcol = bc.Qcol;
-            e.Mo = bc.AM; e.ldm = bj;
-            e.Ko = bc.AK; e.ldk = bj;
+            e.prow = bc.Prow[t.par]; e.qrow = bc.Qrow[t.par]; e.pcol = bc.Pcol; e.qcol = bc.Qcol;
+            e.Mo = bc.AM[t.par]; e.ldm = bj;
+            e.Ko = bc.AK[t.par]; e.ldk = bj;
             e.Ro = bc.DR[1 - bc.dcur] + (int64_t)t.r * bc.ld; e.ldr = bc.ld;
             ops.ech.push_back(e);
             t.did_ech = true;
@@ -377,8 +406,8 @@ public:
             int32_t prev = t.j ? sel_[t.i][t.j - 1] : 0;
             ListDesc le;
             le.npick = t.rp; le.nkeep = t.alpha - t.rp; le.map = br.U[br.ucur];
-            le.pick = bc.Prow; le.append = br.E + prev;
-            le.keep = bc.Qrow; le.keep_out = br.U[1 - br.ucur];
+            le.pick = bc.Prow[t.par]; le.append = br.E + prev;
+            le.keep = bc.Qrow[t.par]; le.keep_out = br.U[1 - br.ucur];
             ops.lists.push_back(le);
         }
     }
@@ -418,7 +447,7 @@ public:
     }
 
     // UpdateRow / UpdateRowTrafo step (3): X := A.M * V with V = rho' Z (and ADI for h = i)
-    void ur3(Ops& ops) {
+    void ur3(Ops& pri, Ops& bulk) {
         for (auto& t : tasks_) {
             if (!t.active || t.rp == 0) continue;
             BR& br = rows_[t.i];
@@ -429,28 +458,28 @@ public:
             if (n_ - c0 > 0) {
                 GemmDesc g;
                 g.M = t.rp; g.N = (int32_t)(n_ - c0); g.K = t.rp; g.p = p_;
-                g.A = bc.AM; g.lda = bj;
-                g.B = br.C[br.cur] + c0; g.ldb = br.ldC; g.brow = bc.Prow;
+                g.A = bc.AM[t.par]; g.lda = bj;
+                g.B = br.C[br.cur] + c0; g.ldb = br.ldC; g.brow = bc.Prow[t.par];
                 g.D = X + c0; g.ldd = ldP_;
-                push_gemm(ops, g, st_.ur_mad);
+                push_split(pri, bulk, g, t.j, st_.ur_mad);
             }
             for (int h = 0; h <= t.i; ++h) {
                 int32_t w = (h < t.i) ? sel_[h][t.j] : (t.j ? sel_[t.i][t.j - 1] : 0);
                 if (w > 0) {
                     GemmDesc g;
                     g.M = t.rp; g.N = w; g.K = t.rp; g.p = p_;
-                    g.A = bc.AM; g.lda = bj;
-                    g.B = br.K[br.cur] + R0_[h]; g.ldb = br.ldK; g.brow = bc.Prow;
+                    g.A = bc.AM[t.par]; g.lda = bj;
+                    g.B = br.K[br.cur] + R0_[h]; g.ldb = br.ldK; g.brow = bc.Prow[t.par];
                     g.D = X + n_ + R0_[h]; g.ldd = ldP_;
-                    push_gemm(ops, g, st_.urt_mad);
+                    push_gemm(bulk, g, st_.urt_mad);
                 }
                 if (h == t.i) {
                     // V's identity columns (ADI) make X := A.M there
                     GatherDesc c;
                     c.rows = t.rp; c.cols = t.rp;
-                    c.src = bc.AM; c.lds = bj;
+                    c.src = bc.AM[t.par]; c.lds = bj;
                     c.dst = X + n_ + R0_[h] + w; c.ldd = ldP_;
-                    ops.gather.push_back(c);
+                    bulk.gather.push_back(c);
                     st_.gather_bytes += 2.0 * t.rp * t.rp;
                 }
             }
@@ -458,7 +487,7 @@ public:
     }
 
     // step (4): S := B + A.E * X  (for h = i the stored M block is zero), RRF = append
-    void ur4(Ops& ops) {
+    void ur4(Ops& pri, Ops& bulk) {
         for (auto& t : tasks_) {
             if (!t.active || t.rp == 0 || t.r == 0) continue;
             BC& bc = cols_[t.j];
@@ -472,7 +501,7 @@ public:
                 g.A = bc.AE; g.lda = bj;
                 g.B = X + c0; g.ldb = ldP_;
                 g.C = Brow + c0; g.ldc = ldP_; g.D = Brow + c0; g.ldd = ldP_;
-                push_gemm(ops, g, st_.ur_mad);
+                push_split(pri, bulk, g, t.j, st_.ur_mad);
             }
             for (int h = 0; h <= t.i; ++h) {
                 int32_t w = sel_[h][t.j];
@@ -482,13 +511,13 @@ public:
                 g.A = bc.AE; g.lda = bj;
                 g.B = X + n_ + R0_[h]; g.ldb = ldP_;
                 g.C = Brow + n_ + R0_[h]; g.ldc = ldP_; g.D = Brow + n_ + R0_[h]; g.ldd = ldP_;
-                push_gemm(ops, g, st_.urt_mad);
+                push_gemm(bulk, g, st_.urt_mad);
             }
         }
     }
 
     // step (6): C := W + A.K * V with W = rho'-bar Z, written compacted to the other panel
-    void ur6(Ops& ops) {
+    void ur6(Ops& pri, Ops& bulk) {
         for (auto& t : tasks_) {
             if (!t.active || t.rp == 0) continue;
             BR& br = rows_[t.i];
@@ -500,30 +529,30 @@ public:
             if (n_ - c0 > 0) {
                 GemmDesc g;
                 g.M = left; g.N = (int32_t)(n_ - c0); g.K = t.rp; g.p = p_;
-                g.A = bc.AK; g.lda = bj;
-                g.B = br.C[br.cur] + c0; g.ldb = br.ldC; g.brow = bc.Prow;
-                g.C = br.C[br.cur] + c0; g.ldc = br.ldC; g.crow = bc.Qrow;
+                g.A = bc.AK[t.par]; g.lda = bj;
+                g.B = br.C[br.cur] + c0; g.ldb = br.ldC; g.brow = bc.Prow[t.par];
+                g.C = br.C[br.cur] + c0; g.ldc = br.ldC; g.crow = bc.Qrow[t.par];
                 g.D = br.C[1 - br.cur] + c0; g.ldd = br.ldC;
-                push_gemm(ops, g, st_.ur_mad);
+                push_split(pri, bulk, g, t.j, st_.ur_mad);
             }
             for (int h = 0; h <= t.i; ++h) {
                 int32_t w = (h < t.i) ? sel_[h][t.j] : (t.j ? sel_[t.i][t.j - 1] : 0);
                 if (w > 0) {
                     GemmDesc g;
                     g.M = left; g.N = w; g.K = t.rp; g.p = p_;
-                    g.A = bc.AK; g.lda = bj;
-                    g.B = br.K[br.cur] + R0_[h]; g.ldb = br.ldK; g.brow = bc.Prow;
-                    g.C = br.K[br.cur] + R0_[h]; g.ldc = br.ldK; g.crow = bc.Qrow;
+                    g.A = bc.AK[t.par]; g.lda = bj;
+                    g.B = br.K[br.cur] + R0_[h]; g.ldb = br.ldK; g.brow = bc.Prow[t.par];
+                    g.C = br.K[br.cur] + R0_[h]; g.ldc = br.ldK; g.crow = bc.Qrow[t.par];
                     g.D = br.K[1 - br.cur] + R0_[h]; g.ldd = br.ldK;
-                    push_gemm(ops, g, st_.urt_mad);
+                    push_gemm(bulk, g, st_.urt_mad);
                 }
                 if (h == t.i) {
                     // V is the identity on the new columns and W is zero there: K := A.K
                     GatherDesc c;
                     c.rows = left; c.cols = t.rp;
-                    c.src = bc.AK; c.lds = bj;
+                    c.src = bc.AK[t.par]; c.lds = bj;
                     c.dst = br.K[1 - br.cur] + R0_[h] + w; c.ldd = br.ldK;
-                    ops.gather.push_back(c);
+                    bulk.gather.push_back(c);
                     st_.gather_bytes += 2.0 * left * t.rp;
                 }
             }
@@ -550,7 +579,7 @@ public:
         res.m = m_; res.n = n_; res.r = r_; res.p = p_;
         res.row_blocks = pr_.row_blocks;
         res.col_blocks = pr_.col_blocks;
-        res.ldP = n_ + r_;
+        res.ldP = (n_ + r_ + 63) / 64 * 64;   // 64-byte aligned rows for the vector loads
         res.ldK = r_;
         auto ialloc = [&](int64_t cnt) { return (int32_t*)be_.alloc(sizeof(int32_t) * std::max<int64_t>(cnt, 1)); };
         res.Pfinal = (uint8_t*)be_.alloc((size_t)std::max<int64_t>(r_ * res.ldP, 1));
@@ -683,23 +712,41 @@ public:
         }
     }
 
-    // Step 3, layer k (block columns from b down to 2): for all j < k at once,
-    // [R_{j,l>=k} | M_j] += X_jk * [R_{k,l>=k} | M_k]
-    void clearup(Result& res, int k, Ops& ops) {
-        if (k <= 0 || k >= b_) return;
-        int64_t above = rowoff_[k];
-        int32_t rk = rankc_[k];
-        if (above == 0 || rk == 0) return;
-        int64_t c0 = r_ + noff_[k];
-        int64_t width = n_ + r_ - c0;
-        if (width <= 0) return;
-        GemmDesc g;
-        g.M = (int32_t)above; g.N = (int32_t)width; g.K = rk; g.p = p_;
-        g.A = res.Pfinal + rowoff_[k]; g.lda = res.ldP;
-        g.B = res.Pfinal + rowoff_[k] * res.ldP + c0; g.ldb = res.ldP;
-        g.C = res.Pfinal + c0; g.ldc = res.ldP;
-        g.D = res.Pfinal + c0; g.ldd = res.ldP;
-        push_gemm(ops, g, st_.cu_mad);
+    // Step 3 (ClearUp), as a list of dependent launches.  Clearing the rows
+    // of block columns j < k with the pivot rows of block column k is
+    //     [R_{j, l>=k} | M_j] += X_jk * [R_{k, l>=k} | M_k]
+    // for k from b down to 2 (Section 3, Step 3).  A pivot row of block column
+    // k is zero in the pivot columns of every block column before k, so using
+    // it never changes X_jk' for k' < k: the updates of a group G of
+    // consecutive block columns can be applied together.  For each group
+    // (taken from the right, about `group_rank` pivots each): first the
+    // sequential clearing inside G, then one product for all rows above G
+    // with inner dimension |pivots of G|:
+    //     [R | M]_{rows above G} += X_{rows above G, G} * [R | M]_{rows of G}
+    // which is the same sum the column-by-column order forms.
+    void plan_clearup(Result& res, int64_t group_rank) {
+        cu_steps_.clear();
+        int k1 = b_;                                    // group = block columns [k0, k1)
+        while (k1 > 1) {
+            int k0 = k1 - 1;
+            while (k0 > 0 && rowoff_[k1] - rowoff_[k0] < group_rank) --k0;
+            if (rowoff_[k1] - rowoff_[k0] > group_rank && k0 < k1 - 1) ++k0;
+            // inside the group, column by column
+            for (int k = k1 - 1; k > k0; --k) {
+                GemmDesc g;
+                if (clearup_desc(res, k, rowoff_[k0], rowoff_[k], rowoff_[k], rowoff_[k + 1], k, g))
+                    cu_steps_.push_back({g});
+            }
+            // every row above the group at once
+            GemmDesc g;
+            if (clearup_desc(res, k0, 0, rowoff_[k0], rowoff_[k0], rowoff_[k1], k0, g)) cu_steps_.push_back({g});
+            k1 = k0;
+        }
+    }
+    size_t clearup_steps() const { return cu_steps_.size(); }
+    void clearup_step(size_t s, Ops& ops) {
+        if (s >= cu_steps_.size()) return;
+        for (const GemmDesc& g : cu_steps_[s]) push_gemm(ops, g, st_.cu_mad);
     }
 
     void release_maps() {
@@ -723,13 +770,20 @@ private:
         int cur = 0, ucur = 0;
     };
     struct BC {
-        size_t oDR[2] = {0, 0}, oGbar[2] = {0, 0}, oGam = 0, oAA = 0, oH = 0, oW = 0, oAM = 0, oAK = 0, oAE = 0;
-        size_t oProw = 0, oQrow = 0, oPcol = 0, oQcol = 0;
+        size_t oDR[2] = {0, 0}, oGbar[2] = {0, 0}, oGam = 0, oH = 0, oW = 0, oAE = 0;
+        size_t oAA[2] = {0, 0}, oAM[2] = {0, 0}, oAK[2] = {0, 0}, oProw[2] = {0, 0}, oQrow[2] = {0, 0};
+        size_t oPcol = 0, oQcol = 0;
         uint8_t* DR[2] = {nullptr, nullptr};
         int32_t* Gbar[2] = {nullptr, nullptr};
         int32_t* Gam = nullptr;
-        uint8_t *AA = nullptr, *H = nullptr, *W = nullptr, *AM = nullptr, *AK = nullptr, *AE = nullptr;
-        int32_t *Prow = nullptr, *Qrow = nullptr, *Pcol = nullptr, *Qcol = nullptr;
+        // by layer parity (read by the bulk lane one layer late)
+        uint8_t* AA[2] = {nullptr, nullptr};
+        uint8_t* AM[2] = {nullptr, nullptr};
+        uint8_t* AK[2] = {nullptr, nullptr};
+        int32_t* Prow[2] = {nullptr, nullptr};
+        int32_t* Qrow[2] = {nullptr, nullptr};
+        uint8_t *H = nullptr, *W = nullptr, *AE = nullptr;
+        int32_t *Pcol = nullptr, *Qcol = nullptr;
         int64_t cap = 0, ld = 0, ldW = 0, prow0 = 0;
         int dcur = 0, gcur = 0;
     };
@@ -738,6 +792,39 @@ private:
         if (g.M <= 0 || g.N <= 0) return;
         ops.gemm.push_back(g);
         counter += (double)g.M * g.N * g.K;
+    }
+
+    // rows [rlo, rhi) of [X | R | M] += X[rows, plo:phi] * rows [plo, phi),
+    // on the columns from block column kc's remnant to the end
+    bool clearup_desc(Result& res, int kc, int64_t rlo, int64_t rhi, int64_t plo, int64_t phi, int, GemmDesc& g) {
+        if (rhi - rlo <= 0 || phi - plo <= 0) return false;
+        int64_t c0 = r_ + noff_[kc];
+        int64_t width = n_ + r_ - c0;
+        if (width <= 0) return false;
+        g = GemmDesc();
+        g.M = (int32_t)(rhi - rlo); g.N = (int32_t)width; g.K = (int32_t)(phi - plo); g.p = p_;
+        g.A = res.Pfinal + rlo * res.ldP + plo; g.lda = res.ldP;
+        g.B = res.Pfinal + plo * res.ldP + c0; g.ldb = res.ldP;
+        g.C = res.Pfinal + rlo * res.ldP + c0; g.ldc = res.ldP;
+        g.D = res.Pfinal + rlo * res.ldP + c0; g.ldd = res.ldP;
+        return true;
+    }
+
+    // g covers the data columns [C0_{j+1}, n) of a product of task (i, j):
+    // block column j + 1 goes to `pri`, the columns after it to `bulk`
+    void push_split(Ops& pri, Ops& bulk, const GemmDesc& g, int j, double& counter) {
+        const int32_t n1 = (int32_t)std::min<int64_t>(g.N, C0_[j + 2] - C0_[j + 1]);
+        GemmDesc a = g;
+        a.N = n1;
+        push_gemm(pri, a, counter);
+        if (g.N > n1) {
+            GemmDesc c = g;
+            c.N = g.N - n1;
+            c.B = g.B + n1;
+            if (g.C) c.C = g.C + n1;
+            c.D = g.D + n1;
+            push_gemm(bulk, c, counter);
+        }
     }
 
     Backend& be_;
@@ -760,6 +847,7 @@ private:
     int64_t prow_total_ = 0, ldP_ = 0, r_ = 0;
     int32_t *rowmap_ = nullptr, *colmap_ = nullptr, *kmap_ = nullptr, *ordj_ = nullptr;
     std::vector<int64_t> rowoff_, noff_, soff_, uoff_;
+    std::vector<std::vector<GemmDesc>> cu_steps_;
 };
 
 void flush(Backend& be, Ops& ops, Stats& st) {
@@ -836,35 +924,60 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
     }
     flush(be, ops, shared);
 
-    // Step 1, layer by layer
+    // Step 1, layer by layer, on two lanes (see the header comment)
+    int bulk_done = -1;      // lane 1's mark after the last bulk part issued
+    Ops b1, b3, b4, b6;      // the bulk part of the previous layer, not issued yet
+    auto issue_bulk = [&](int ready) {
+        if (b1.empty() && b3.empty() && b4.empty() && b6.empty()) return;
+        be.set_lane(1);
+        be.wait_mark(1, ready);
+        flush(be, b1, shared);
+        flush(be, b3, shared);
+        flush(be, b4, shared);
+        flush(be, b6, shared);
+        bulk_done = be.mark(1);
+        be.set_lane(0);
+    };
     for (int L = 0; L < maxL; ++L) {
         for (auto& pl : plans) pl->begin_layer(L);
         for (auto& pl : plans) pl->cd_extract(ops);
         flush(be, ops, shared);
-        for (auto& pl : plans) pl->cd_mad_ur1(ops);
+        for (auto& pl : plans) pl->cd_mad(ops);
         flush(be, ops, shared);
+        // the previous layer's bulk part starts after this layer's ClearDown
+        // MADs and is issued after this layer's ECHs, so the ECHs (one
+        // workgroup each) reach the device first: issued behind a large
+        // product, an ECH would wait for that product's last tiles
+        const int ready = be.mark(0);
         bool any = false;
         for (auto& pl : plans) { pl->cd_ech(ops); any = any || pl->any_ech(); }
         flush(be, ops, shared);
+        issue_bulk(ready);
         if (any) {
             be.download(hcounts.data(), counts, sizeof(int32_t) * ncounts);
             shared.syncs++;
             if (be.error()) break;
         }
         for (size_t q = 0; q < plans.size(); ++q) plans[q]->absorb_counts(hcounts.data() + count_off[q]);
+        // the UpdateRow products below read columns the previous bulk part wrote
+        if (bulk_done >= 0) be.wait_mark(0, bulk_done);
+        for (auto& pl : plans) pl->ur1(ops, b1);
+        flush(be, ops, shared);
         for (auto& pl : plans) pl->cd_post(ops);
         flush(be, ops, shared);
         for (auto& pl : plans) pl->cd_mad2(ops);
-        for (auto& pl : plans) pl->ur3(ops);
+        for (auto& pl : plans) pl->ur3(ops, b3);
         flush(be, ops, shared);
         for (auto& pl : plans) pl->cd_commit();
-        for (auto& pl : plans) pl->ur4(ops);
+        for (auto& pl : plans) pl->ur4(ops, b4);
         flush(be, ops, shared);
-        for (auto& pl : plans) pl->ur6(ops);
+        for (auto& pl : plans) pl->ur6(ops, b6);
         flush(be, ops, shared);
         for (auto& pl : plans) pl->ur_commit();
         shared.layers++;
     }
+    issue_bulk(be.mark(0));
+    if (bulk_done >= 0) be.wait_mark(0, bulk_done);
     int rc = be.error();
     if (rc) {
         be.release(arena);
@@ -896,10 +1009,16 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
     flush(be, ops, shared);
     for (size_t q = 0; q < plans.size(); ++q) plans[q]->k_assemble(*res[q], ops);
     flush(be, ops, shared);
-    int maxb = 0;
-    for (auto& pr : probs) maxb = std::max(maxb, (int)pr.col_blocks.size());
-    for (int k = maxb - 1; k >= 1; --k) {
-        for (size_t q = 0; q < plans.size(); ++q) plans[q]->clearup(*res[q], k, ops);
+    // Step 3: the plans' ClearUp launches in lockstep
+    const char* gr_env = getenv("GFECH_CLEARUP_GROUP");
+    const int64_t group_rank = gr_env ? std::max<int64_t>(1, atoll(gr_env)) : 2048;
+    size_t nsteps = 0;
+    for (size_t q = 0; q < plans.size(); ++q) {
+        plans[q]->plan_clearup(*res[q], group_rank);
+        nsteps = std::max(nsteps, plans[q]->clearup_steps());
+    }
+    for (size_t s = 0; s < nsteps; ++s) {
+        for (auto& pl : plans) pl->clearup_step(s, ops);
         flush(be, ops, shared);
     }
     be.sync();

@@ -894,6 +894,12 @@ public:
             if (err) *err = "counter allocation failed";
             return false;
         }
+        // lane 1: a second stream at the default priority; non-blocking, so it
+        // never synchronises implicitly with the legacy default stream
+        if (hipStreamCreateWithFlags(&lane1_, hipStreamNonBlocking) != hipSuccess) {
+            if (err) *err = "stream creation failed";
+            return false;
+        }
         if (hipFuncSetAttribute((const void*)k_ech_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)echp_lds_bytes(ECHP_MAX_ROWS)) != hipSuccess) {
             if (err) *err = "cannot reserve LDS for the ECH kernel";
@@ -933,13 +939,14 @@ public:
         sizes_.erase(it);
     }
     void trim() {
-        hipStreamSynchronize(stream_);
+        sync_all();
         for (auto& kv : free_) hipFree(kv.second);
         free_.clear();
     }
     void zero(void* p, size_t bytes) override {
         if (bytes) HIP_OK(hipMemsetAsync(p, 0, bytes, stream_));
     }
+    // memory transfers run on lane 0 (stream_); kernels on the current lane (cur_)
     void upload(void* dst, const void* src, size_t bytes) override {
         if (!bytes) return;
         if (bytes <= kRing / 4) {
@@ -958,8 +965,29 @@ public:
     void copy(void* dst, const void* src, size_t bytes) override {
         if (bytes) HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, stream_));
     }
-    void sync() override { HIP_OK(hipStreamSynchronize(stream_)); }
-    void set_stream(void* s) override { stream_ = (hipStream_t)s; }
+    void sync() override { sync_all(); }
+    void set_stream(void* s) override {
+        stream_ = (hipStream_t)s;
+        cur_ = stream_;
+    }
+    void set_lane(int lane) override { cur_ = lane == 1 ? lane1_ : stream_; }
+    int mark(int lane) override {
+        hipEvent_t e = nullptr;
+        if (!mark_pool_.empty()) {
+            e = mark_pool_.back();
+            mark_pool_.pop_back();
+        } else {
+            HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        }
+        HIP_OK(hipEventRecord(e, lane == 1 ? lane1_ : stream_));
+        marks_.push_back(e);
+        return mark_base_ + (int)marks_.size() - 1;
+    }
+    void wait_mark(int lane, int m) override {
+        // marks below mark_base_ were passed by a full synchronisation already
+        if (m < mark_base_ || m - mark_base_ >= (int)marks_.size()) return;
+        HIP_OK(hipStreamWaitEvent(lane == 1 ? lane1_ : stream_, marks_[m - mark_base_], 0));
+    }
     int error() const override { return err_; }
 
     void gemm(const std::vector<GemmDesc>& ds) override {
@@ -981,7 +1009,7 @@ public:
         const GemmDesc* dd = (const GemmDesc*)put(d.data(), d.size() * sizeof(GemmDesc));
         const GemmTileMap* dm = (const GemmTileMap*)put(maps.data(), maps.size() * sizeof(GemmTileMap));
         hipEvent_t e0 = prof_begin();
-        hipLaunchKernelGGL(k_gemm_modp, dim3((unsigned)tiles), dim3(GEMM_THREADS), 0, stream_, dd, dm, (int)d.size());
+        hipLaunchKernelGGL(k_gemm_modp, dim3((unsigned)tiles), dim3(GEMM_THREADS), 0, cur_, dd, dm, (int)d.size());
         HIP_OK(hipGetLastError());
         prof_end(0, e0);
     }
@@ -995,7 +1023,7 @@ public:
             size_t shm = echp_lds_bytes(maxrows_all);
             const EchDesc* dd = (const EchDesc*)put(ds.data(), ds.size() * sizeof(EchDesc));
             hipEvent_t e0 = prof_begin();
-            hipLaunchKernelGGL(k_ech_panel, dim3((unsigned)ds.size()), dim3(threads), shm, stream_, dd);
+            hipLaunchKernelGGL(k_ech_panel, dim3((unsigned)ds.size()), dim3(threads), shm, cur_, dd);
             HIP_OK(hipGetLastError());
             prof_end(1, e0);
             return;
@@ -1012,7 +1040,7 @@ public:
         if (shm > 64 * 1024) { note_error(hipErrorInvalidValue, "ech block too large for LDS"); return; }
         const EchDesc* dd = (const EchDesc*)put(ds.data(), ds.size() * sizeof(EchDesc));
         hipEvent_t e0 = prof_begin();
-        hipLaunchKernelGGL(k_ech, dim3((unsigned)ds.size()), dim3(ECH_THREADS), shm, stream_, dd);
+        hipLaunchKernelGGL(k_ech, dim3((unsigned)ds.size()), dim3(ECH_THREADS), shm, cur_, dd);
         HIP_OK(hipGetLastError());
         prof_end(1, e0);
     }
@@ -1027,7 +1055,7 @@ public:
             size_t cnt = std::min<size_t>(65535, ds.size() - off);
             const D* dd = (const D*)put(ds.data() + off, cnt * sizeof(D));
             hipEvent_t e0 = prof_begin();
-            hipLaunchKernelGGL(kernel, dim3((unsigned)bx, (unsigned)cnt), dim3(SMALL_THREADS), 0, stream_, dd);
+            hipLaunchKernelGGL(kernel, dim3((unsigned)bx, (unsigned)cnt), dim3(SMALL_THREADS), 0, cur_, dd);
             HIP_OK(hipGetLastError());
             prof_end(2, e0);
         }
@@ -1063,7 +1091,7 @@ public:
     void set_profile(bool on) override { prof_ = on; }
     Profile take_profile() override {
         Profile pr;
-        HIP_OK(hipStreamSynchronize(stream_));
+        sync_all();
         for (auto& ev : evs_) {
             float ms = 0;
             if (hipEventElapsedTime(&ms, ev.a, ev.b) == hipSuccess) {
@@ -1092,13 +1120,13 @@ private:
     hipEvent_t prof_begin() {
         if (!prof_) return nullptr;
         hipEvent_t e = new_event();
-        HIP_OK(hipEventRecord(e, stream_));
+        HIP_OK(hipEventRecord(e, cur_));
         return e;
     }
     void prof_end(int kind, hipEvent_t a) {
         if (!prof_ || !a) return;
         hipEvent_t b = new_event();
-        HIP_OK(hipEventRecord(b, stream_));
+        HIP_OK(hipEventRecord(b, cur_));
         evs_.push_back({a, b, kind});
     }
 
@@ -1113,7 +1141,7 @@ private:
     void* stage(const void* src, size_t bytes) {
         size_t need = (bytes + 255) & ~(size_t)255;
         if (ring_off_ + need > kRing) {
-            HIP_OK(hipStreamSynchronize(stream_));   // earlier copies out of the ring are done
+            sync_all();   // earlier copies out of the ring, and the kernels reading them, are done
             ring_off_ = 0;
         }
         void* h = (char*)ring_host_ + ring_off_;
@@ -1126,11 +1154,24 @@ private:
         void* h = stage(src, bytes);
         size_t off = (char*)h - (char*)ring_host_;
         void* d = (char*)ring_dev_ + off;
-        HIP_OK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, stream_));
+        HIP_OK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, cur_));   // ordered before the launch reading it
         return d;
     }
+    // both lanes drained; the marks can be reused
+    void sync_all() {
+        HIP_OK(hipStreamSynchronize(lane1_));
+        HIP_OK(hipStreamSynchronize(stream_));
+        for (hipEvent_t e : marks_) mark_pool_.push_back(e);
+        mark_base_ += (int)marks_.size();
+        if (mark_base_ > (1 << 30)) mark_base_ = 0;
+        marks_.clear();
+    }
 
-    hipStream_t stream_ = nullptr;
+    hipStream_t stream_ = nullptr;   // lane 0: the caller's stream
+    hipStream_t lane1_ = nullptr;    // lane 1
+    hipStream_t cur_ = nullptr;      // the lane kernels go to
+    std::vector<hipEvent_t> marks_, mark_pool_;
+    int mark_base_ = 0;              // id of marks_[0]
     void* ring_host_ = nullptr;
     void* ring_dev_ = nullptr;
     size_t ring_off_ = 0;

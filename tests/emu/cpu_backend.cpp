@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -47,7 +48,24 @@ public:
     void copy(void* dst, const void* src, size_t bytes) override {
         if (bytes && chk(dst, bytes, "copy") && chk(src, bytes, "copy")) memmove(dst, src, bytes);
     }
-    void sync() override {}
+    // Lanes: lane 1's jobs are queued and run as late as the planner's marks
+    // allow (when lane 0 waits for them, or at sync).  Any job the planner
+    // ordered wrongly across the lanes then reads or overwrites data out of
+    // turn, and the results stop matching the oracle.  GFECH_EMU_EAGER=1
+    // runs everything at once instead.
+    void set_lane(int lane) override { lane_ = lane; }
+    int mark(int lane) override { return lane == 1 ? (int)(q1_.size() * 2 + 1) : 0; }
+    void wait_mark(int lane, int m) override {
+        if (lane == 0 && (m & 1)) drain((size_t)(m >> 1));
+    }
+    void drain(size_t upto) {
+        while (done1_ < upto && done1_ < q1_.size()) {
+            auto f = std::move(q1_[done1_]);
+            ++done1_;
+            f();
+        }
+    }
+    void sync() override { drain(q1_.size()); }
     int error() const override { return err_; }
 
     // every byte a job touches must lie inside one live allocation
@@ -78,6 +96,10 @@ public:
     }
 
     void gemm(const std::vector<GemmDesc>& ds) override {
+        if (lane_ == 1 && defer_) { q1_.push_back([this, ds] { gemm_now(ds); }); return; }
+        gemm_now(ds);
+    }
+    void gemm_now(const std::vector<GemmDesc>& ds) {
         for (const GemmDesc& g : ds) {
             if (g.M <= 0 || g.N <= 0 || !gemm_ok(g)) continue;
             std::vector<uint8_t> out((size_t)g.M * g.N);
@@ -99,6 +121,10 @@ public:
     }
 
     void gather(const std::vector<GatherDesc>& ds) override {
+        if (lane_ == 1 && defer_) { q1_.push_back([this, ds] { gather_now(ds); }); return; }
+        gather_now(ds);
+    }
+    void gather_now(const std::vector<GatherDesc>& ds) {
         for (const GatherDesc& g : ds) {
             bool ok = true;
             if (g.srow) ok &= chk(g.srow, sizeof(int32_t) * g.rows, "gather srow");
@@ -129,6 +155,10 @@ public:
     }
 
     void fill(const std::vector<FillDesc>& ds) override {
+        if (lane_ == 1 && defer_) { q1_.push_back([this, ds] { fill_now(ds); }); return; }
+        fill_now(ds);
+    }
+    void fill_now(const std::vector<FillDesc>& ds) {
         for (const FillDesc& f : ds) {
             bool ok = true;
             if (f.dcol) {
@@ -149,6 +179,10 @@ public:
     }
 
     void lists(const std::vector<ListDesc>& ds) override {
+        if (lane_ == 1 && defer_) { q1_.push_back([this, ds] { lists_now(ds); }); return; }
+        lists_now(ds);
+    }
+    void lists_now(const std::vector<ListDesc>& ds) {
         for (const ListDesc& l : ds) {
             bool ok = true;
             if (l.npick) {
@@ -168,6 +202,10 @@ public:
     }
 
     void sort(const std::vector<SortDesc>& ds) override {
+        if (lane_ == 1 && defer_) { q1_.push_back([this, ds] { sort_now(ds); }); return; }
+        sort_now(ds);
+    }
+    void sort_now(const std::vector<SortDesc>& ds) {
         for (const SortDesc& s : ds) {
             if (!chk(s.vals, sizeof(int32_t) * s.n, "sort vals") || !chk(s.out, sizeof(int32_t) * s.n, "sort out"))
                 continue;
@@ -187,6 +225,10 @@ public:
     }
 
     void ech(const std::vector<EchDesc>& ds) override {
+        if (lane_ == 1 && defer_) { q1_.push_back([this, ds] { ech_now(ds); }); return; }
+        ech_now(ds);
+    }
+    void ech_now(const std::vector<EchDesc>& ds) {
         for (const EchDesc& e : ds) {
             const int maxr = e.rows < e.cols ? e.rows : e.cols;
             bool ok = chk(e.rcount, 4, "ech rcount") && chk(e.prow, 4 * maxr, "ech prow") &&
@@ -209,6 +251,10 @@ public:
 private:
     std::map<uintptr_t, size_t> allocs_;
     int err_ = 0;
+    int lane_ = 0;
+    bool defer_ = !(getenv("GFECH_EMU_EAGER") && getenv("GFECH_EMU_EAGER")[0] == '1');
+    std::vector<std::function<void()>> q1_;
+    size_t done1_ = 0;
 
     static uint32_t inv(uint32_t a, uint32_t p) {   // a^(p-2)
         uint32_t r = 1, b = a % p, x = p - 2;
