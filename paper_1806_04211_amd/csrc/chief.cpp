@@ -104,7 +104,16 @@ struct TaskState {      // one (i, j) of the current layer
     int32_t alpha = 0;  // rows of block row i when the layer started
     int32_t r = 0;      // pivots of block column j before ClearDown
     int32_t rp = 0;     // new pivots r'
+    // ECH of the leading columns only (see cd_ech)
+    int32_t w = 0;      // columns the ECH was given
+    bool split = false; // w < all columns of H
+    bool rerun = false; // the leading columns did not select every row: ECH again on all of H
+    const uint8_t* H = nullptr;
+    int64_t ldh = 0;
 };
+
+// Columns beyond the number of rows the leading-columns ECH is given
+constexpr int32_t kSplitSlack = 32;
 
 class Plan {
 public:
@@ -334,18 +343,34 @@ public:
         }
     }
 
-    // ClearDown's ECH
-    void cd_ech(Ops& ops) {
+    // ClearDown's ECH.  When H has more than alpha + kSplitSlack columns, the
+    // ECH first gets only the leading alpha + kSplitSlack of them.  If that
+    // selects every row (the usual case for a block of full row rank), no
+    // later column can hold a pivot, and the remnant of the remaining columns
+    // H2 is R2 = M H2[rho'] (the top rows of the identity of Remark 2.3), one
+    // product on the whole device instead of a trailing update inside the ECH
+    // (cd_post).  Otherwise the ECH runs again on all of H (rerun pass).
+    void cd_ech(Ops& ops, bool rerun_pass) {
         for (auto& t : tasks_) {
             if (!t.active) continue;
             BR& br = rows_[t.i];
             BC& bc = cols_[t.j];
             int32_t bj = pr_.col_blocks[t.j];
-            if (bj - t.r == 0) continue;
+            const int32_t w = bj - t.r;
+            if (w == 0) continue;
+            if (rerun_pass) {
+                if (!t.rerun) continue;
+                t.w = w;
+                t.split = false;
+            } else {
+                t.w = (w > t.alpha + kSplitSlack) ? t.alpha + kSplitSlack : w;
+                t.split = t.w < w;
+            }
+            if (t.r > 0) { t.H = bc.H; t.ldh = bj; }
+            else { t.H = br.C[br.cur] + C0_[t.j]; t.ldh = br.ldC; }
             EchDesc e;
-            e.rows = t.alpha; e.cols = bj - t.r; e.p = p_;
-            if (t.r > 0) { e.H = bc.H; e.ldh = bj; }
-            else { e.H = br.C[br.cur] + C0_[t.j]; e.ldh = br.ldC; }
+            e.rows = t.alpha; e.cols = t.w; e.p = p_;
+            e.H = t.H; e.ldh = t.ldh;
             e.work = bc.W; e.ldw = bc.ldW;
             e.rcount = counts_ + t.j;
             e.prow = bc.Prow[t.par]; e.qrow = bc.Qrow[t.par]; e.pcol = bc.Pcol; e.qcol = bc.Qcol;
@@ -362,15 +387,26 @@ public:
         return false;
     }
 
-    void absorb_counts(const int32_t* host_counts) {
+    // returns true when some task needs the rerun pass
+    bool absorb_counts(const int32_t* host_counts, bool rerun_pass) {
+        bool again = false;
         for (auto& t : tasks_) {
-            t.rp = t.did_ech ? host_counts[t.j] : 0;
-            if (t.did_ech) {
-                int32_t bj = pr_.col_blocks[t.j];
-                st_.ech += (double)t.alpha * (bj - t.r) * t.rp;
+            if (!t.did_ech || (rerun_pass && !t.rerun)) continue;
+            t.rp = host_counts[t.j];
+            st_.ech += (double)t.alpha * t.w * t.rp;
+            if (rerun_pass) {
+                t.rerun = false;
+            } else {
                 st_.echs += 1;
+                t.rerun = t.split && t.rp < t.alpha;
+                again = again || t.rerun;
             }
         }
+        return again;
+    }
+
+    void clear_counts() {
+        for (auto& t : tasks_) t.rp = 0;
     }
 
     // ClearDown after ECH: CEX of D.R by gamma' (A.E and R'), UNH on D.gamma, Extend on E.rho
@@ -381,6 +417,20 @@ public:
             BC& bc = cols_[t.j];
             int32_t bj = pr_.col_blocks[t.j];
             int32_t rest = bj - t.r - t.rp;
+            if (t.split) {
+                // every row was selected in the leading t.w columns: the other
+                // columns are non-pivot columns, and their remnant is M * H2[rho']
+                const int32_t w = bj - t.r;
+                GemmDesc g;
+                g.M = t.rp; g.N = w - t.w; g.K = t.rp; g.p = p_;
+                g.A = bc.AM[t.par]; g.lda = bj;
+                g.B = t.H + t.w; g.ldb = t.ldh; g.brow = bc.Prow[t.par];
+                g.D = bc.DR[1 - bc.dcur] + (int64_t)t.r * bc.ld + (t.w - t.rp); g.ldd = bc.ld;
+                push_gemm(ops, g, st_.cd_mad);
+                std::vector<int32_t> tail(w - t.w);
+                std::iota(tail.begin(), tail.end(), t.w);
+                be_.upload(bc.Qcol + (t.w - t.rp), tail.data(), sizeof(int32_t) * tail.size());
+            }
             if (t.r > 0) {
                 GatherDesc g;
                 g.rows = t.r; g.cols = t.rp;
@@ -950,15 +1000,26 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
         // product, an ECH would wait for that product's last tiles
         const int ready = be.mark(0);
         bool any = false;
-        for (auto& pl : plans) { pl->cd_ech(ops); any = any || pl->any_ech(); }
+        for (auto& pl : plans) { pl->cd_ech(ops, false); any = any || pl->any_ech(); }
         flush(be, ops, shared);
         issue_bulk(ready);
+        for (auto& pl : plans) pl->clear_counts();
         if (any) {
             be.download(hcounts.data(), counts, sizeof(int32_t) * ncounts);
             shared.syncs++;
             if (be.error()) break;
+            bool again = false;
+            for (size_t q = 0; q < plans.size(); ++q)
+                again = plans[q]->absorb_counts(hcounts.data() + count_off[q], false) || again;
+            if (again) {
+                for (auto& pl : plans) pl->cd_ech(ops, true);
+                flush(be, ops, shared);
+                be.download(hcounts.data(), counts, sizeof(int32_t) * ncounts);
+                shared.syncs++;
+                if (be.error()) break;
+                for (size_t q = 0; q < plans.size(); ++q) plans[q]->absorb_counts(hcounts.data() + count_off[q], true);
+            }
         }
-        for (size_t q = 0; q < plans.size(); ++q) plans[q]->absorb_counts(hcounts.data() + count_off[q]);
         // the UpdateRow products below read columns the previous bulk part wrote
         if (bulk_done >= 0) be.wait_mark(0, bulk_done);
         for (auto& pl : plans) pl->ur1(ops, b1);

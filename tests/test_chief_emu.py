@@ -188,3 +188,23 @@ def test_every_access_in_bounds_with_separate_buffers(lib, monkeypatch):
     mix = synth.batch_mix(9, 10, nmin=3, nmax=40)
     res, sts = lib.echelonise_batch(mix, block_rows=9, block_cols=9)
     assert all(s == 0 for s in sts)
+
+
+@pytest.mark.parametrize("p", [2, 3, 251])
+def test_wide_block_columns(lib, p):
+    """Block columns much wider than block rows: ClearDown first echelonises
+    the leading columns only, and either finishes the remnant with one product
+    (every row selected) or runs again on the whole block (some row not
+    selected: a dependent row, or too few pivots among the leading columns)."""
+    rng = np.random.default_rng(100 + p)
+    cases = [synth.uniform(p, 7, 24, 150, p),                     # rows fill quickly
+             synth.deficient(p, 8, 24, 150, p),                   # dependent rows
+             synth.low_rank_product(p, 30, 140, 9, p)]            # rank 9 < block rows
+    Z = synth.uniform(p, 9, 20, 160, p)
+    Z[:, 3:60] = 0                                                # pivots far to the right
+    cases.append(Z)
+    for A in cases:
+        e = oracle.echelonize(A, p)
+        for br, bc in ((4, 80), (5, 120), (3, 45), (8, 160)):
+            compare(lib.echelonise(A, p, block_rows=br, block_cols=bc).outputs(), e, f"{A.shape} {br}x{bc}")
+    del rng
