@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--block-rows", type=int, default=0, help="block rows a_i (overrides --block)")
     ap.add_argument("--block-cols", type=int, default=0, help="block columns b_j (overrides --block)")
     ap.add_argument("--cpu-sample", type=int, default=1600, help="oracle sample size (0 = skip)")
+    ap.add_argument("--no-kernel-events", action="store_true",
+                    help="time the steps without per-launch device events (no roofline / kernel_ms)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -122,7 +124,7 @@ def main():
     for s in range(args.steps):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        r = solve(True)
+        r = solve(not args.no_kernel_events)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         times.append(dt)

@@ -123,6 +123,14 @@ public:
     virtual void set_lane(int lane) { (void)lane; }
     virtual int mark(int lane) { (void)lane; return 0; }
     virtual void wait_mark(int lane, int mark) { (void)lane; (void)mark; }
+    // A small int32 array that jobs write on the device and read_counts()
+    // returns to the host once lane 0's queued work is complete (lane 1 may
+    // still be running).  One array per backend, valid until the next call.
+    virtual int32_t* counts_buffer(size_t n) { return (int32_t*)alloc(sizeof(int32_t) * n); }
+    virtual void read_counts(int32_t* host, const int32_t* counts, size_t n) {
+        download(host, counts, sizeof(int32_t) * n);
+    }
+    virtual void release_counts(int32_t* counts) { release(counts); }
     // non-zero after a device error; the planner stops and reports it
     virtual int error() const { return 0; }
     // per-launch timing of the grouped jobs (device events on the work stream)

@@ -942,10 +942,10 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
     const bool separate = sep_env && sep_env[0] == '1';
     std::vector<void*> pieces;
     uint8_t* arena = separate ? nullptr : (uint8_t*)be.alloc(std::max<size_t>(total, 1));
-    int32_t* counts = (int32_t*)be.alloc(sizeof(int32_t) * std::max<int64_t>(ncounts, 1));
+    int32_t* counts = be.counts_buffer((size_t)std::max<int64_t>(ncounts, 1));
     if ((!separate && !arena) || !counts) {
         be.release(arena);
-        be.release(counts);
+        be.release_counts(counts);
         if (err) *err = "device allocation of the block arena failed";
         return 4;
     }
@@ -958,7 +958,7 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
                 uint8_t* ptr = (uint8_t*)be.alloc(std::max<size_t>(sl.second, 1));
                 if (!ptr) {
                     for (void* v : pieces) be.release(v);
-                    be.release(counts);
+                    be.release_counts(counts);
                     if (err) *err = "device allocation of a sub-buffer failed";
                     return 4;
                 }
@@ -1005,7 +1005,7 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
         issue_bulk(ready);
         for (auto& pl : plans) pl->clear_counts();
         if (any) {
-            be.download(hcounts.data(), counts, sizeof(int32_t) * ncounts);
+            be.read_counts(hcounts.data(), counts, (size_t)ncounts);
             shared.syncs++;
             if (be.error()) break;
             bool again = false;
@@ -1014,7 +1014,7 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
             if (again) {
                 for (auto& pl : plans) pl->cd_ech(ops, true);
                 flush(be, ops, shared);
-                be.download(hcounts.data(), counts, sizeof(int32_t) * ncounts);
+                be.read_counts(hcounts.data(), counts, (size_t)ncounts);
                 shared.syncs++;
                 if (be.error()) break;
                 for (size_t q = 0; q < plans.size(); ++q) plans[q]->absorb_counts(hcounts.data() + count_off[q], true);
@@ -1043,7 +1043,7 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
     if (rc) {
         be.release(arena);
         for (void* v : pieces) be.release(v);
-        be.release(counts);
+        be.release_counts(counts);
         if (err) *err = "device error during Step 1";
         return rc;
     }
@@ -1058,7 +1058,7 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
             for (auto& pl : plans) pl->release_maps();
             be.release(arena);
             for (void* v : pieces) be.release(v);
-            be.release(counts);
+            be.release_counts(counts);
             if (err) *err = "device allocation of the result failed";
             return 4;
         }
@@ -1092,7 +1092,7 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
     for (auto& pl : plans) pl->release_maps();
     be.release(arena);
     for (void* v : pieces) be.release(v);
-    be.release(counts);
+    be.release_counts(counts);
     if (rc) {
         if (err) *err = "device error during assembly / Step 3";
         return rc;

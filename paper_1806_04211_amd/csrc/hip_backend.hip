@@ -76,6 +76,23 @@ struct ModP {
     }
 };
 
+// ============================================================================ descriptor sources
+//
+// Every kernel reads its job descriptors through a source: a few of them
+// travel by value in the kernel arguments (no upload before the launch),
+// larger sets are uploaded and read through a pointer.  Indices are uniform
+// across the workgroup.
+template <typename D, int CAP>
+struct DescArg {
+    D d[CAP];
+    __device__ __forceinline__ D get(int i) const { return d[i]; }
+};
+template <typename D>
+struct DescPtr {
+    const D* p;
+    __device__ __forceinline__ D get(int i) const { return p[i]; }
+};
+
 // ============================================================================ GEMM mod p
 //
 // Workgroup tile TM x TN_ of D (TN_ = 128 or 256), 4 waves in 2 x 2, each
@@ -108,6 +125,26 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 struct GemmTileMap {           // per-descriptor tile grid, device side
     int32_t tiles_n;           // tiles along N
     int32_t first_tile;        // prefix sum of tiles
+};
+
+// MAD descriptors with their tile grids: by value (up to GEMM_ARG_CAP) or
+// through pointers into one uploaded block
+constexpr int GEMM_ARG_CAP = 12;
+struct GemmArgSrc {
+    int n;
+    GemmTileMap m[GEMM_ARG_CAP];
+    GemmDesc d[GEMM_ARG_CAP];
+    __device__ __forceinline__ int count() const { return n; }
+    __device__ __forceinline__ GemmTileMap map(int i) const { return m[i]; }
+    __device__ __forceinline__ GemmDesc get(int i) const { return d[i]; }
+};
+struct GemmPtrSrc {
+    int n;
+    const GemmTileMap* m;
+    const GemmDesc* d;
+    __device__ __forceinline__ int count() const { return n; }
+    __device__ __forceinline__ GemmTileMap map(int i) const { return m[i]; }
+    __device__ __forceinline__ GemmDesc get(int i) const { return d[i]; }
 };
 
 // v mod p for 0 <= v < 2^22.  With inv = fl(1/p), fl(v * inv) differs from
@@ -323,9 +360,8 @@ __device__ __forceinline__ void gemm_store_lds(const GemmRegs<TN_>& R, uint8_t* 
     }
 }
 
-template <int TN_>
-__global__ void __launch_bounds__(GEMM_THREADS, TN_ == 128 ? 2 : 1)
-k_gemm_modp(const GemmDesc* __restrict__ descs, const GemmTileMap* __restrict__ maps, int ndesc) {
+template <int TN_, class Src>
+__global__ void __launch_bounds__(GEMM_THREADS, TN_ == 128 ? 2 : 1) k_gemm_modp(Src src) {
     constexpr int NB = TN_ / 16;
     constexpr int JN = TN_ / 32;          // 16-column MFMA blocks per wave
     extern __shared__ __attribute__((aligned(16))) uint8_t gsm[];
@@ -335,14 +371,15 @@ k_gemm_modp(const GemmDesc* __restrict__ descs, const GemmTileMap* __restrict__ 
 
     // which descriptor owns this tile (binary search over the prefix sums)
     const int tile = blockIdx.x;
-    int lo = 0, hi = ndesc - 1;
+    int lo = 0, hi = src.count() - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (maps[mid].first_tile <= tile) lo = mid; else hi = mid - 1;
+        if (src.map(mid).first_tile <= tile) lo = mid; else hi = mid - 1;
     }
-    const GemmDesc g = descs[lo];
-    const int local = tile - maps[lo].first_tile;
-    const int tn = maps[lo].tiles_n;
+    const GemmDesc g = src.get(lo);
+    const GemmTileMap gm = src.map(lo);
+    const int local = tile - gm.first_tile;
+    const int tn = gm.tiles_n;
     const int m0 = (local / tn) * TM;
     const int n0 = (local % tn) * TN_;
     const int tid = threadIdx.x;
@@ -448,11 +485,12 @@ __device__ __forceinline__ uint32_t pow_mod_dev(uint32_t a, uint32_t e, uint32_t
 }
 
 // dynamic LDS: sel[rows] flags, f[rows] multipliers, prow_lds[cols + maxr] pivot row copy
-__global__ void __launch_bounds__(ECH_THREADS) k_ech(const EchDesc* __restrict__ descs) {
+template <class Src>
+__global__ void __launch_bounds__(ECH_THREADS) k_ech(Src src) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     __shared__ int red[ECH_THREADS / 64];
     __shared__ uint32_t s_scale;
-    const EchDesc e = descs[blockIdx.x];
+    const EchDesc e = src.get(blockIdx.x);
     const int rows = e.rows, cols = e.cols;
     const int maxr = rows < cols ? rows : cols;
     const int width = cols + maxr;
@@ -568,6 +606,7 @@ constexpr int PW = 32;          // panel width
 constexpr int FL_ROW = 80;      // LDS bytes per row of F (64 used by the MFMA, zero beyond the panel)
 constexpr int VCH = 64;         // columns per trailing-update chunk
 constexpr int ECHP_MAX_ROWS = 512;
+constexpr int ECH_ARG_CAP = 8;         // descriptors passed by value (8 x 136 bytes)
 
 __host__ __device__ constexpr size_t echp_fixed_lds() {
     return 128 + 2 * 16 * 64 * 4 + 2 * ECHP_MAX_ROWS * 4 + 256 * 4 + 2 * ECHP_MAX_ROWS + VCH * FL_ROW;
@@ -587,9 +626,10 @@ __device__ __forceinline__ uint32_t addmod4(uint32_t a, uint32_t b, uint32_t p) 
     return lo | (hi << 8);
 }
 
-__global__ void __launch_bounds__(512) k_ech_panel(const EchDesc* __restrict__ descs) {
+template <class Src>
+__global__ void __launch_bounds__(512) k_ech_panel(Src src) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    const EchDesc e = descs[blockIdx.x];
+    const EchDesc e = src.get(blockIdx.x);
     const int rows = e.rows, cols = e.cols;
     const int maxr = rows < cols ? rows : cols;
     const int width = cols + maxr;
@@ -886,11 +926,13 @@ __global__ void __launch_bounds__(512) k_ech_panel(const EchDesc* __restrict__ d
 // ============================================================================ small jobs
 
 constexpr int SMALL_THREADS = 256;
+constexpr int SMALL_ARG_CAP = 16;      // descriptors passed by value (at most 16 x 80 bytes)
 
 // grid: (x blocks striding over elements, y = descriptor)
 // grid: (x blocks striding over rows, y = descriptor); threads stride over columns
-__global__ void __launch_bounds__(SMALL_THREADS) k_gather(const GatherDesc* __restrict__ descs) {
-    const GatherDesc g = descs[blockIdx.y];
+template <class Src>
+__global__ void __launch_bounds__(SMALL_THREADS) k_gather(Src src) {
+    const GatherDesc g = src.get(blockIdx.y);
     for (int x = blockIdx.x; x < g.rows; x += gridDim.x) {
         const int64_t sr = g.srow ? gload<int32_t>(g.srow + x) : x;
         const int64_t dr = g.drow ? gload<int32_t>(g.drow + x) : x;
@@ -906,8 +948,9 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_gather(const GatherDesc* __re
     }
 }
 
-__global__ void __launch_bounds__(SMALL_THREADS) k_fill(const FillDesc* __restrict__ descs) {
-    const FillDesc f = descs[blockIdx.y];
+template <class Src>
+__global__ void __launch_bounds__(SMALL_THREADS) k_fill(Src src) {
+    const FillDesc f = src.get(blockIdx.y);
     if (f.dcol) {
         for (int t = blockIdx.x * SMALL_THREADS + threadIdx.x; t < f.rows; t += gridDim.x * SMALL_THREADS)
             f.dst[(int64_t)t * f.ldd + f.dcol[t]] = (uint8_t)f.diag_value;
@@ -919,8 +962,9 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_fill(const FillDesc* __restri
                             (uint8_t)((x == y && f.diag_value >= 0) ? f.diag_value : f.value));
 }
 
-__global__ void __launch_bounds__(SMALL_THREADS) k_lists(const ListDesc* __restrict__ descs) {
-    const ListDesc l = descs[blockIdx.y];
+template <class Src>
+__global__ void __launch_bounds__(SMALL_THREADS) k_lists(Src src) {
+    const ListDesc l = src.get(blockIdx.y);
     for (int t = blockIdx.x * SMALL_THREADS + threadIdx.x; t < l.npick; t += gridDim.x * SMALL_THREADS)
         l.append[t] = l.add + l.map[l.pick ? l.pick[t] : t];
     for (int s = blockIdx.x * SMALL_THREADS + threadIdx.x; s < l.nkeep; s += gridDim.x * SMALL_THREADS)
@@ -928,8 +972,9 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_lists(const ListDesc* __restr
 }
 
 // rank sort of distinct values: out[rank(t)] = add + (mode ? t : vals[t])
-__global__ void __launch_bounds__(SMALL_THREADS) k_sort(const SortDesc* __restrict__ descs) {
-    const SortDesc s = descs[blockIdx.y];
+template <class Src>
+__global__ void __launch_bounds__(SMALL_THREADS) k_sort(Src src) {
+    const SortDesc s = src.get(blockIdx.y);
     for (int t = blockIdx.x * SMALL_THREADS + threadIdx.x; t < s.n; t += gridDim.x * SMALL_THREADS) {
         int v = s.vals[t], rank = 0;
         for (int u = 0; u < s.n; ++u) rank += s.vals[u] < v;
@@ -988,9 +1033,13 @@ public:
             if (err) *err = "stream creation failed";
             return false;
         }
-        if (hipFuncSetAttribute((const void*)k_ech_panel, hipFuncAttributeMaxDynamicSharedMemorySize,
+        if (hipFuncSetAttribute((const void*)k_ech_panel<DescArg<EchDesc, ECH_ARG_CAP>>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)echp_lds_bytes(ECHP_MAX_ROWS)) != hipSuccess ||
+            hipFuncSetAttribute((const void*)k_ech_panel<DescPtr<EchDesc>>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)echp_lds_bytes(ECHP_MAX_ROWS)) != hipSuccess ||
-            hipFuncSetAttribute((const void*)k_gemm_modp<128>, hipFuncAttributeMaxDynamicSharedMemorySize,
+            hipFuncSetAttribute((const void*)k_gemm_modp<128, GemmArgSrc>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)gemm_lds_bytes<128>()) != hipSuccess ||
+            hipFuncSetAttribute((const void*)k_gemm_modp<128, GemmPtrSrc>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)gemm_lds_bytes<128>()) != hipSuccess) {
             if (err) *err = "cannot reserve LDS for the kernels";
             return false;
@@ -1056,6 +1105,37 @@ public:
         if (bytes) HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, stream_));
     }
     void sync() override { sync_all(); }
+    // pinned host memory the device writes directly: no copy, only a wait for lane 0
+    int32_t* counts_buffer(size_t n) override {
+        if (n > counts_cap_) {
+            sync_all();
+            if (counts_host_) (void)hipHostFree(counts_host_);
+            counts_host_ = nullptr;
+            counts_dev_ = nullptr;
+            counts_cap_ = 0;
+            void* h = nullptr;
+            if (hipHostMalloc(&h, sizeof(int32_t) * n, hipHostMallocMapped) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+            void* d = nullptr;
+            if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+                (void)hipGetLastError();
+                (void)hipHostFree(h);
+                return nullptr;
+            }
+            counts_host_ = (int32_t*)h;
+            counts_dev_ = (int32_t*)d;
+            counts_cap_ = n;
+        }
+        return counts_dev_;
+    }
+    void read_counts(int32_t* host, const int32_t* counts, size_t n) override {
+        HIP_OK(hipStreamSynchronize(stream_));
+        if (counts == counts_dev_ && n <= counts_cap_) memcpy(host, counts_host_, sizeof(int32_t) * n);
+        else download(host, counts, sizeof(int32_t) * n);
+    }
+    void release_counts(int32_t*) override {}
     void set_stream(void* s) override {
         stream_ = (hipStream_t)s;
         cur_ = stream_;
@@ -1100,13 +1180,46 @@ public:
         }
         if (d.empty()) return;
         if (tiles > INT32_MAX) { note_error(hipErrorInvalidValue, "too many gemm tiles"); return; }
-        const GemmDesc* dd = (const GemmDesc*)put(d.data(), d.size() * sizeof(GemmDesc));
-        const GemmTileMap* dm = (const GemmTileMap*)put(maps.data(), maps.size() * sizeof(GemmTileMap));
         hipEvent_t e0 = prof_begin();
-        hipLaunchKernelGGL(k_gemm_modp<TN_>, dim3((unsigned)tiles), dim3(GEMM_THREADS), gemm_lds_bytes<TN_>(), cur_,
-                           dd, dm, (int)d.size());
+        if (d.size() <= (size_t)GEMM_ARG_CAP) {
+            GemmArgSrc a;
+            a.n = (int)d.size();
+            for (size_t i = 0; i < d.size(); ++i) { a.m[i] = maps[i]; a.d[i] = d[i]; }
+            hipLaunchKernelGGL((k_gemm_modp<TN_, GemmArgSrc>), dim3((unsigned)tiles), dim3(GEMM_THREADS),
+                               gemm_lds_bytes<TN_>(), cur_, a);
+        } else {
+            // one upload: the tile maps, then the descriptors (256-byte aligned)
+            const size_t mb = (maps.size() * sizeof(GemmTileMap) + 255) & ~(size_t)255;
+            std::vector<uint8_t> blob(mb + d.size() * sizeof(GemmDesc));
+            memcpy(blob.data(), maps.data(), maps.size() * sizeof(GemmTileMap));
+            memcpy(blob.data() + mb, d.data(), d.size() * sizeof(GemmDesc));
+            const uint8_t* dev = (const uint8_t*)put(blob.data(), blob.size());
+            GemmPtrSrc a;
+            a.n = (int)d.size();
+            a.m = (const GemmTileMap*)dev;
+            a.d = (const GemmDesc*)(dev + mb);
+            hipLaunchKernelGGL((k_gemm_modp<TN_, GemmPtrSrc>), dim3((unsigned)tiles), dim3(GEMM_THREADS),
+                               gemm_lds_bytes<TN_>(), cur_, a);
+        }
         HIP_OK(hipGetLastError());
         prof_end(0, e0);
+    }
+
+    // launch `kernel` over descriptors: up to CAP by value, otherwise uploaded
+    template <int CAP, typename D, typename KArg, typename KPtr>
+    void launch_descs(const D* ds, size_t cnt, KArg karg, KPtr kptr, dim3 grid, dim3 block, size_t shm, int kind) {
+        hipEvent_t e0 = prof_begin();
+        if (cnt <= (size_t)CAP) {
+            DescArg<D, CAP> a;
+            for (size_t i = 0; i < cnt; ++i) a.d[i] = ds[i];
+            hipLaunchKernelGGL(karg, grid, block, shm, cur_, a);
+        } else {
+            DescPtr<D> a;
+            a.p = (const D*)put(ds, cnt * sizeof(D));
+            hipLaunchKernelGGL(kptr, grid, block, shm, cur_, a);
+        }
+        HIP_OK(hipGetLastError());
+        prof_end(kind, e0);
     }
 
     void ech(const std::vector<EchDesc>& ds) override {
@@ -1116,11 +1229,11 @@ public:
         if (maxrows_all <= ECHP_MAX_ROWS && !getenv("GFECH_ECH_SIMPLE")) {
             int threads = std::max(64, (maxrows_all + 63) / 64 * 64);
             size_t shm = echp_lds_bytes(maxrows_all);
-            const EchDesc* dd = (const EchDesc*)put(ds.data(), ds.size() * sizeof(EchDesc));
-            hipEvent_t e0 = prof_begin();
-            hipLaunchKernelGGL(k_ech_panel, dim3((unsigned)ds.size()), dim3(threads), shm, cur_, dd);
-            HIP_OK(hipGetLastError());
-            prof_end(1, e0);
+            for (size_t off = 0; off < ds.size(); off += 65535) {
+                const size_t cnt = std::min<size_t>(65535, ds.size() - off);
+                launch_descs<ECH_ARG_CAP>(ds.data() + off, cnt, k_ech_panel<DescArg<EchDesc, ECH_ARG_CAP>>,
+                                          k_ech_panel<DescPtr<EchDesc>>, dim3((unsigned)cnt), dim3(threads), shm, 1);
+            }
             return;
         }
         int maxrows = 0, maxw = 0;
@@ -1133,43 +1246,44 @@ public:
         for (const EchDesc& e : ds) maxr_all = std::max(maxr_all, std::min(e.rows, e.cols));
         size_t shm = ((size_t)(2 * maxrows + maxw + 15) & ~(size_t)15) + 2 * sizeof(int) * (size_t)maxr_all;
         if (shm > 64 * 1024) { note_error(hipErrorInvalidValue, "ech block too large for LDS"); return; }
-        const EchDesc* dd = (const EchDesc*)put(ds.data(), ds.size() * sizeof(EchDesc));
-        hipEvent_t e0 = prof_begin();
-        hipLaunchKernelGGL(k_ech, dim3((unsigned)ds.size()), dim3(ECH_THREADS), shm, cur_, dd);
-        HIP_OK(hipGetLastError());
-        prof_end(1, e0);
+        for (size_t off = 0; off < ds.size(); off += 65535) {
+            const size_t cnt = std::min<size_t>(65535, ds.size() - off);
+            launch_descs<ECH_ARG_CAP>(ds.data() + off, cnt, k_ech<DescArg<EchDesc, ECH_ARG_CAP>>,
+                                      k_ech<DescPtr<EchDesc>>, dim3((unsigned)cnt), dim3(ECH_THREADS), shm, 1);
+        }
     }
 
-    template <typename D, typename F>
-    void small(const std::vector<D>& ds, F kernel, int64_t (*work)(const D&)) {
+    template <typename D, typename KArg, typename KPtr>
+    void small(const std::vector<D>& ds, KArg karg, KPtr kptr, int64_t (*work)(const D&)) {
         if (ds.empty()) return;
         int64_t mx = 1;
         for (const D& x : ds) mx = std::max(mx, work(x));
         int64_t bx = std::min<int64_t>((mx + SMALL_THREADS - 1) / SMALL_THREADS, 4096);
         for (size_t off = 0; off < ds.size(); off += 65535) {
             size_t cnt = std::min<size_t>(65535, ds.size() - off);
-            const D* dd = (const D*)put(ds.data() + off, cnt * sizeof(D));
-            hipEvent_t e0 = prof_begin();
-            hipLaunchKernelGGL(kernel, dim3((unsigned)bx, (unsigned)cnt), dim3(SMALL_THREADS), 0, cur_, dd);
-            HIP_OK(hipGetLastError());
-            prof_end(2, e0);
+            launch_descs<SMALL_ARG_CAP>(ds.data() + off, cnt, karg, kptr, dim3((unsigned)bx, (unsigned)cnt),
+                                        dim3(SMALL_THREADS), 0, 2);
         }
     }
 
     void gather(const std::vector<GatherDesc>& ds) override {
         // one block per row (up to the cap); the work function counts rows x threads
-        small<GatherDesc>(ds, k_gather, [](const GatherDesc& g) -> int64_t { return (int64_t)g.rows * SMALL_THREADS; });
+        small<GatherDesc>(ds, k_gather<DescArg<GatherDesc, SMALL_ARG_CAP>>, k_gather<DescPtr<GatherDesc>>,
+                          [](const GatherDesc& g) -> int64_t { return (int64_t)g.rows * SMALL_THREADS; });
     }
     void fill(const std::vector<FillDesc>& ds) override {
-        small<FillDesc>(ds, k_fill, [](const FillDesc& f) -> int64_t {
-            return f.dcol ? (int64_t)f.rows : (int64_t)f.rows * SMALL_THREADS;
-        });
+        small<FillDesc>(ds, k_fill<DescArg<FillDesc, SMALL_ARG_CAP>>, k_fill<DescPtr<FillDesc>>,
+                        [](const FillDesc& f) -> int64_t {
+                            return f.dcol ? (int64_t)f.rows : (int64_t)f.rows * SMALL_THREADS;
+                        });
     }
     void lists(const std::vector<ListDesc>& ds) override {
-        small<ListDesc>(ds, k_lists, [](const ListDesc& l) -> int64_t { return std::max(l.npick, l.nkeep); });
+        small<ListDesc>(ds, k_lists<DescArg<ListDesc, SMALL_ARG_CAP>>, k_lists<DescPtr<ListDesc>>,
+                        [](const ListDesc& l) -> int64_t { return std::max(l.npick, l.nkeep); });
     }
     void sort(const std::vector<SortDesc>& ds) override {
-        small<SortDesc>(ds, k_sort, [](const SortDesc& s) -> int64_t { return (int64_t)s.n; });
+        small<SortDesc>(ds, k_sort<DescArg<SortDesc, SMALL_ARG_CAP>>, k_sort<DescPtr<SortDesc>>,
+                        [](const SortDesc& s) -> int64_t { return (int64_t)s.n; });
     }
 
     int64_t count_out_of_range(const uint8_t* A, int64_t m, int64_t n, int64_t lda, int32_t p) override {
@@ -1266,6 +1380,9 @@ private:
     hipStream_t lane1_ = nullptr;    // lane 1
     hipStream_t cur_ = nullptr;      // the lane kernels go to
     std::vector<hipEvent_t> marks_, mark_pool_;
+    int32_t* counts_host_ = nullptr;   // counts_buffer(): host view
+    int32_t* counts_dev_ = nullptr;    // and device view
+    size_t counts_cap_ = 0;
     int mark_base_ = 0;              // id of marks_[0]
     void* ring_host_ = nullptr;
     void* ring_dev_ = nullptr;
