@@ -75,7 +75,7 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="block size (0 = the library's choice)")
     ap.add_argument("--block-rows", type=int, default=0, help="block rows a_i (overrides --block)")
     ap.add_argument("--block-cols", type=int, default=0, help="block columns b_j (overrides --block)")
-    ap.add_argument("--cpu-sample", type=int, default=1600, help="oracle sample size (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=2000, help="oracle sample size (0 = skip)")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the steps without per-launch device events (no roofline / kernel_ms)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -108,23 +108,26 @@ def main():
     stream = torch.cuda.current_stream(dev)
     kw = dict(block_rows=args.block_rows or args.block, block_cols=args.block_cols or args.block)
 
-    def solve(profile):
+    def solve(profile: int):
+        """profile: 0 no device events, 1 every launch, 2 the MAD launches only"""
         return lib.echelonise_dev(A.data_ptr(), n, n, n, p, stream=stream.cuda_stream, profile=profile, **kw)
 
     rank = None
     for w in range(args.warmup):
         t1 = time.perf_counter()
-        r = solve(False)
+        r = solve(0)
         rank = r.rank
         r.free()
         log(f"warmup {w}: {time.perf_counter() - t1:.3f} s, rank {rank}")
 
+    # timed steps: device events around the MAD launches only (the roofline
+    # kernel); every other launch runs without events
     times, stats = [], []
     torch.cuda.synchronize()
     for s in range(args.steps):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        r = solve(not args.no_kernel_events)
+        r = solve(0 if args.no_kernel_events else 2)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         times.append(dt)
@@ -132,6 +135,12 @@ def main():
         stats.append(r.stats())
         r.free()
         log(f"step {s}: {dt:.3f} s, rank {rank}")
+    # one more (untimed) solve with every launch timed, for the per-kind breakdown
+    breakdown = None
+    if not args.no_kernel_events:
+        r = solve(1)
+        breakdown = r.stats()
+        r.free()
 
     mean = sum(times) / len(times)
     st = stats[-1]
@@ -164,9 +173,11 @@ def main():
         "latency_ms": {"p50": pct(0.5) * 1e3, "p99": pct(0.99) * 1e3},
         "work": {"mac_total": mac_mad + st["mac_ech"], "mac_mad": mac_mad, "mac_ech": st["mac_ech"],
                  "mac_alg_per_s": (mac_mad + st["mac_ech"]) / mean},
-        "kernel_ms": {"mad": mad_ms, "ech": st["ms_ech"], "small": st["ms_small"],
-                      "launches_mad": mad_launches, "launches_ech": st["launches_ech"],
-                      "launches_small": st["launches_small"]},
+        "kernel_ms": None if breakdown is None else {
+            "note": "one extra untimed solve with every launch timed",
+            "mad": breakdown["ms_mad"], "ech": breakdown["ms_ech"], "small": breakdown["ms_small"],
+            "launches_mad": breakdown["launches_mad"], "launches_ech": breakdown["launches_ech"],
+            "launches_small": breakdown["launches_small"]},
         "roofline": {"bound": "mfma", "kernel": "k_gemm_modp (MAD mod p, int8 MFMA)",
                      "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
                      "frac": achieved / INT8_PEAK_TOPS, "traffic": None,

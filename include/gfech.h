@@ -55,7 +55,8 @@ typedef struct gfech_opts {
     int64_t block_rows;     /* a_i target (Section 3.1); 0 = automatic */
     int64_t block_cols;     /* b_j target; 0 = automatic */
     int32_t skip_range_check; /* 1: the caller guarantees entries < p (no validation pass) */
-    int32_t profile;        /* 1: time every kernel launch with device events (see gfech_stats) */
+    int32_t profile;        /* 1: time every kernel launch with device events, 2: only the MAD
+                               launches (see gfech_stats); 0: no events */
     int32_t reserved[6];
 } gfech_opts;
 

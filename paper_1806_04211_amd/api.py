@@ -151,7 +151,7 @@ def _opts(block_rows=0, block_cols=0, skip_range_check=False, profile=False):
     o.block_rows = int(block_rows)
     o.block_cols = int(block_cols)
     o.skip_range_check = 1 if skip_range_check else 0
-    o.profile = 1 if profile else 0
+    o.profile = int(profile)
     return o
 
 

@@ -89,7 +89,7 @@ gfech_status run(gfech::Backend* be, std::vector<gfech::Problem>& probs, gfech_r
                  const gfech_opts* opts) {
     std::vector<std::unique_ptr<gfech::Result>> res;
     std::string err;
-    int rc = gfech::run_chief(*be, probs, res, &err, opts && opts->profile);
+    int rc = gfech::run_chief(*be, probs, res, &err, opts ? opts->profile : 0);
     if (rc) return fail(rc == 4 ? GFECH_E_NOMEM : GFECH_E_DEVICE, err);
     for (size_t q = 0; q < res.size(); ++q) {
         outs[q] = new gfech_result();

@@ -913,10 +913,10 @@ void flush(Backend& be, Ops& ops, Stats& st) {
 }  // namespace
 
 int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::unique_ptr<Result>>& out,
-              std::string* err, bool profile) {
+              std::string* err, int profile) {
     if (profile) {
         be.take_profile();
-        be.set_profile(true);
+        be.set_profile(profile);
     }
     Stats shared;
     std::vector<Stats> st(probs.size());
@@ -1087,7 +1087,7 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
     Backend::Profile prof;
     if (profile) {
         prof = be.take_profile();
-        be.set_profile(false);
+        be.set_profile(0);
     }
     for (auto& pl : plans) pl->release_maps();
     be.release(arena);

@@ -65,6 +65,6 @@ std::vector<int32_t> even_blocks(int64_t total, int64_t target);
 // jobs share launches).  Returns 0 or a backend error code; results are
 // appended to `out` in problem order.
 int run_chief(Backend& be, const std::vector<Problem>& probs,
-              std::vector<std::unique_ptr<Result>>& out, std::string* err, bool profile = false);
+              std::vector<std::unique_ptr<Result>>& out, std::string* err, int profile = 0);
 
 }  // namespace gfech

@@ -1180,7 +1180,7 @@ public:
         }
         if (d.empty()) return;
         if (tiles > INT32_MAX) { note_error(hipErrorInvalidValue, "too many gemm tiles"); return; }
-        hipEvent_t e0 = prof_begin();
+        hipEvent_t e0 = prof_begin(0);
         if (d.size() <= (size_t)GEMM_ARG_CAP) {
             GemmArgSrc a;
             a.n = (int)d.size();
@@ -1208,7 +1208,7 @@ public:
     // launch `kernel` over descriptors: up to CAP by value, otherwise uploaded
     template <int CAP, typename D, typename KArg, typename KPtr>
     void launch_descs(const D* ds, size_t cnt, KArg karg, KPtr kptr, dim3 grid, dim3 block, size_t shm, int kind) {
-        hipEvent_t e0 = prof_begin();
+        hipEvent_t e0 = prof_begin(kind);
         if (cnt <= (size_t)CAP) {
             DescArg<D, CAP> a;
             for (size_t i = 0; i < cnt; ++i) a.d[i] = ds[i];
@@ -1297,7 +1297,7 @@ public:
         return err_ ? -1 : (int64_t)bad;
     }
 
-    void set_profile(bool on) override { prof_ = on; }
+    void set_profile(int level) override { prof_ = level; }
     Profile take_profile() override {
         Profile pr;
         sync_all();
@@ -1326,8 +1326,9 @@ private:
         HIP_OK(hipEventCreate(&e));
         return e;
     }
-    hipEvent_t prof_begin() {
-        if (!prof_) return nullptr;
+    // level 1: every launch; level 2: MAD launches only (kind 0)
+    hipEvent_t prof_begin(int kind) {
+        if (!prof_ || (prof_ == 2 && kind != 0)) return nullptr;
         hipEvent_t e = new_event();
         HIP_OK(hipEventRecord(e, cur_));
         return e;
@@ -1390,7 +1391,7 @@ private:
     void* counter_ = nullptr;
     int err_ = 0;
     int num_cu_ = 0;
-    bool prof_ = false;
+    int prof_ = 0;
     std::vector<Ev> evs_;
     std::vector<hipEvent_t> pool_;
     std::map<void*, size_t> sizes_;
