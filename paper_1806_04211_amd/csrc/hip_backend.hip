@@ -899,15 +899,34 @@ __global__ void __launch_bounds__(512) k_ech_panel(Src src) {
         e.prow[t] = prl[t];
         e.pcol[t] = pcl[t];
     }
-    if (x == 0) {
-        int q = 0;
-        for (int rr = 0; rr < rows; ++rr)
-            if (!sel[rr]) e.qrow[q++] = rr;
-        q = 0;
-        int t = 0;
-        for (int y = 0; y < cols; ++y) {
-            if (t < r && pcl[t] == y) { ++t; continue; }
-            e.qcol[q++] = y;
+    // non-pivot rows and columns, ascending: the position of an unselected row
+    // (column) is the number of unselected rows (columns) before it, counted a
+    // wave-wide ballot at a time
+    if (wave == 0) {
+        int base = 0;
+        for (int r0 = 0; r0 < rows; r0 += 64) {
+            const int rr = r0 + lane;
+            const bool un = rr < rows && !sel[rr];
+            const unsigned long long b = __ballot(un);
+            if (un) e.qrow[base + __popcll(b & ((1ull << lane) - 1))] = rr;
+            base += __popcll(b);
+        }
+    }
+    if (wave == (nwaves > 1 ? 1 : 0)) {
+        // pcl is ascending: column y is a pivot column iff it equals pcl[t] for
+        // t = (pivot columns below y); walk it with a per-lane binary search
+        int base = 0;
+        for (int y0 = 0; y0 < cols; y0 += 64) {
+            const int y = y0 + lane;
+            int lo = 0, hi = r;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (pcl[mid] < y) lo = mid + 1; else hi = mid;
+            }
+            const bool np = y < cols && !(lo < r && pcl[lo] == y);
+            const unsigned long long b = __ballot(np);
+            if (np) e.qcol[base + __popcll(b & ((1ull << lane) - 1))] = y;
+            base += __popcll(b);
         }
     }
     __syncthreads();
@@ -920,6 +939,424 @@ __global__ void __launch_bounds__(512) k_ech_panel(Src src) {
     for (int s2 = wave; s2 < rows - r; s2 += nwaves) {
         const uint8_t* src = e.work + (int64_t)gload<int32_t>(e.qrow + s2) * e.ldw + cols;
         for (int u = lane; u < r; u += 64) gstore<uint8_t>(e.Ko + (int64_t)s2 * e.ldk + u, gload<uint8_t>(src + u));
+    }
+}
+
+// ============================================================================ ECH, at most 256 rows, p <= 46
+//
+// The same elimination as k_ech_panel (columns in order; the pivot of a
+// column is the first not-yet-selected row with a non-zero entry; pivot rows
+// scaled to -1 and kept reduced against each other; outputs as in EchDesc),
+// for blocks of at most 256 rows over GF(p), p <= 46, with the whole working
+// matrix W = [H | T] held in LDS (row length LW: the columns of H, padded to
+// 16, then the transformation columns, one per pivot).
+//
+// Panels of 32 columns are eliminated by wave 0 alone: lane l holds rows l,
+// l + 64, l + 128 and l + 192, each as 16 words of two 16-bit entries, and the
+// panel's transformation F (one column per pivot of the panel) the same way.
+// Sums stay unreduced inside a panel: an entry receives at most 32 products,
+// each at most (p - 1)^2 <= 45^2, so it stays below 2^16 and one packed
+// 16-bit multiply-add updates two entries.  A pivot step needs no barrier: a
+// ballot finds the pivot row, its lane publishes its words in LDS, each lane
+// reduces one of the 64 entries, and all lanes read them back.  After a
+// panel all four waves apply F to the remaining columns and to the
+// transformation columns of earlier pivots with MFMA, in place in LDS:
+//     W[x][y] := (x a pivot of this panel ? 0 : W[x][y]) + sum_t F[x][t] W[pivot row t][y]
+constexpr int ECHS_MAX_ROWS = 256;
+constexpr int ECHS_MAX_P = 46;
+constexpr int ECHS_THREADS = 256;
+constexpr int ECHS_PW = 32;        // panel width
+constexpr int ECHS_VCH = 64;       // columns per trailing-update chunk
+
+__host__ __device__ inline int echs_tc(int cols) { return (cols + 15) & ~15; }
+__host__ __device__ inline int echs_lw(int cols, int maxr) { return echs_tc(cols) + ((maxr + 15) & ~15); }
+// LDS: W, the panel transformation F (rows x 32), the transposed pivot rows
+// of one chunk (64 x 32), published pivot words (64 dwords), prl, pcl,
+// qrow (256 ints each), the inverse table (64), sel and inpanel (256 bytes
+// each), and 16 bytes of counters
+__host__ __device__ inline size_t echs_lds_bytes(int rows, int cols) {
+    const int maxr = rows < cols ? rows : cols;
+    const size_t rows16 = (size_t)((rows + 15) & ~15);
+    return rows16 * (size_t)echs_lw(cols, maxr) + rows16 * ECHS_PW + (size_t)ECHS_VCH * ECHS_PW + 64 * 4 +
+           3 * 256 * 4 + 64 * 4 + 2 * 256 + 16;
+}
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+// two 16-bit multiply-adds: (a.lo * b.lo + c.lo, a.hi * b.hi + c.hi), mod 2^16
+__device__ __forceinline__ uint32_t pkmad16(uint32_t a, uint32_t b, uint32_t c) {
+    const u16x2 r = __builtin_bit_cast(u16x2, a) * __builtin_bit_cast(u16x2, b) + __builtin_bit_cast(u16x2, c);
+    return __builtin_bit_cast(uint32_t, r);
+}
+
+// acc[w] += f2 * v[w] in 16-bit halves, w < NW
+template <int NW>
+__device__ __forceinline__ void pkmad_words(uint32_t* acc, const uint32_t* v, uint32_t f2) {
+#pragma unroll
+    for (int w = 0; w < NW; ++w) acc[w] = pkmad16(f2, v[w], acc[w]);
+}
+
+template <class Src>
+__global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const EchDesc e = src.get(blockIdx.x);
+    const int rows = e.rows, cols = e.cols;
+    const int maxr = rows < cols ? rows : cols;
+    const int TC = echs_tc(cols), LW = echs_lw(cols, maxr);
+    const int rows16 = (rows + 15) & ~15;
+    const uint32_t p = (uint32_t)e.p;
+    const float inv = 1.0f / (float)p;
+    const int x = threadIdx.x, lane = x & 63, wave = x >> 6;
+
+    uint8_t* W = smem;                                       // [rows16][LW]
+    uint8_t* Fl = W + (size_t)rows16 * LW;                   // [rows16][32]
+    uint8_t* Vt = Fl + rows16 * ECHS_PW;                     // [64][32]
+    uint32_t* pb = (uint32_t*)(Vt + ECHS_VCH * ECHS_PW);     // [32] published words, [32] reduced
+    int* prl = (int*)(pb + 64);                              // pivot rows, pivot order
+    int* pcl = prl + 256;                                    // pivot columns
+    int* qrl = pcl + 256;                                    // non-pivot rows (outputs)
+    uint32_t* invt = (uint32_t*)(qrl + 256);                 // -1/v mod p
+    uint8_t* sel = (uint8_t*)(invt + 64);                    // row selected
+    uint8_t* inpanel = sel + 256;                            // row selected in the current panel
+    int* shared_rp = (int*)(inpanel + 256);                   // [2]: pivots of the panel, by panel parity
+
+    // invt[v] = -1/v mod p, by search (p <= 46)
+    if (x < 64) {
+        uint32_t iv = 0;
+        if (x > 0 && (uint32_t)x < p)
+            for (uint32_t j = 1; j < p; ++j)
+                if (mod22(__umul24((uint32_t)x, j), inv, p) == 1u) iv = p - j;
+        invt[x] = iv;
+    }
+    for (int i = x; i < 256; i += ECHS_THREADS) { sel[i] = 0; inpanel[i] = 0; }
+    // W = [H | 0], rows beyond `rows` zero.  Thread x covers 16-byte chunks
+    // x, x + 256, ...; the loads of 8 chunks are in flight together.
+    {
+        const int cpr = LW >> 4;                     // chunks per row
+        const int nch = rows16 * cpr;
+        const bool hal = ((((uintptr_t)e.H) | (uintptr_t)e.ldh) & 15) == 0;
+        for (int c0 = x; c0 < nch; c0 += 8 * ECHS_THREADS) {
+            uint4 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int c = c0 + u * ECHS_THREADS;
+                v[u] = make_uint4(0, 0, 0, 0);
+                if (c < nch) {
+                    const int rr = c / cpr, y = (c - rr * cpr) * 16;
+                    if (rr < rows && y < cols) {
+                        const uint8_t* sp = e.H + (int64_t)rr * e.ldh + y;
+                        v[u] = (hal && y + 16 <= cols) ? gload<uint4>(sp) : load16_lim(sp, cols - y);
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int c = c0 + u * ECHS_THREADS;
+                if (c < nch) *(uint4*)(W + (size_t)c * 16) = v[u];
+            }
+        }
+    }
+    __syncthreads();
+
+    int r = 0;
+    for (int c0 = 0; c0 < cols && r < maxr; c0 += ECHS_PW) {
+        const int wc = min(ECHS_PW, cols - c0);
+        if (wave == 0) {
+            uint32_t D[4][16], F[4][16];
+            bool sl[4], ok[4];
+            uint32_t scale[4];
+            int pidx[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = lane + 64 * q;
+                ok[q] = row < rows;
+                sl[q] = !ok[q] || sel[row];
+                scale[q] = 1;
+                pidx[q] = -1;
+                uint4 a = make_uint4(0, 0, 0, 0), b = make_uint4(0, 0, 0, 0);
+                if (ok[q]) {
+                    a = *(const uint4*)(W + (size_t)row * LW + c0);
+                    b = *(const uint4*)(W + (size_t)row * LW + c0 + 16);
+                }
+                const uint32_t d[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    // columns 4i .. 4i + 3 into words 2i (columns 4i, 4i + 1) and 2i + 1
+                    uint32_t lo = __builtin_amdgcn_perm(0u, d[i], 0x0c010c00u);
+                    uint32_t hi = __builtin_amdgcn_perm(0u, d[i], 0x0c030c02u);
+                    if (wc < ECHS_PW) {   // columns past the block hold other data: clear them
+                        if (4 * i >= wc) lo &= 0u; else if (4 * i + 1 >= wc) lo &= 0xffffu;
+                        if (4 * i + 2 >= wc) hi &= 0u; else if (4 * i + 3 >= wc) hi &= 0xffffu;
+                    }
+                    D[q][2 * i] = lo;
+                    D[q][2 * i + 1] = hi;
+                }
+#pragma unroll
+                for (int w = 0; w < 16; ++w) F[q][w] = 0;
+            }
+            int rp = 0;
+            // column k = 2 kk + h sits in word 0, half h: the words rotate left
+            // by one after each pair of columns, so every index is static
+#pragma clang loop unroll(disable)
+            for (int kk = 0; kk < ECHS_PW / 2; ++kk) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int k = 2 * kk + h;
+                    if (k < wc && r + rp < maxr) {
+                        uint32_t red[4];
+                        bool cand[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            red[q] = mod22((D[q][0] >> (16 * h)) & 0xffffu, inv, p);
+                            cand[q] = !sl[q] && red[q] != 0;
+                        }
+                        int Q = -1, L = 0;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const unsigned long long bq = __ballot(cand[q]);
+                            if (Q < 0 && bq) { Q = q; L = __ffsll((long long)bq) - 1; }
+                        }
+                        if (Q >= 0) {
+                            // the pivot row publishes its words; its own transformation
+                            // entry (index rp) is 1
+                            if (lane == L) {
+                                const uint32_t one = 1u << (16 * (rp & 1));
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) {
+                                    if (q == Q) {
+#pragma unroll
+                                        for (int w = 0; w < 16; w += 4) {
+                                            *(uint4*)(pb + w) = make_uint4(D[q][w], D[q][w + 1], D[q][w + 2], D[q][w + 3]);
+                                            *(uint4*)(pb + 16 + w) = make_uint4(
+                                                F[q][w] + (w == (rp >> 1) ? one : 0u), F[q][w + 1] + (w + 1 == (rp >> 1) ? one : 0u),
+                                                F[q][w + 2] + (w + 2 == (rp >> 1) ? one : 0u), F[q][w + 3] + (w + 3 == (rp >> 1) ? one : 0u));
+                                        }
+                                    }
+                                }
+                            }
+                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                            __builtin_amdgcn_wave_barrier();
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                            const uint16_t* pb16 = (const uint16_t*)pb;
+                            ((uint16_t*)(pb + 32))[lane] = (uint16_t)mod22(pb16[lane], inv, p);
+                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                            __builtin_amdgcn_wave_barrier();
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                            uint32_t pv[32];
+#pragma unroll
+                            for (int w = 0; w < 32; w += 4) {
+                                const uint4 t4 = *(const uint4*)(pb + 32 + w);
+                                pv[w] = t4.x; pv[w + 1] = t4.y; pv[w + 2] = t4.z; pv[w + 3] = t4.w;
+                            }
+                            const uint32_t s = invt[(pv[0] >> (16 * h)) & 0xffffu];   // -1 / pivot
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const bool me = (q == Q) && (lane == L);
+                                const uint32_t f = me ? 0u : mod22(__umul24(red[q], s), inv, p);
+                                const uint32_t f2 = f * 0x10001u;
+#pragma unroll
+                                for (int w = 0; w < 16; ++w) D[q][w] = pkmad16(f2, pv[w], D[q][w]);
+                                // F entries past rp are zero in every row: update the
+                                // first 8 (rp + 1) / 8 words only
+                                switch (rp >> 3) {
+                                    case 0: pkmad_words<4>(F[q], pv + 16, f2); break;
+                                    case 1: pkmad_words<8>(F[q], pv + 16, f2); break;
+                                    case 2: pkmad_words<12>(F[q], pv + 16, f2); break;
+                                    default: pkmad_words<16>(F[q], pv + 16, f2); break;
+                                }
+                                if (me) {
+                                    sl[q] = true;
+                                    scale[q] = s;
+                                    pidx[q] = rp;
+                                }
+                            }
+                            if (lane == 0) {
+                                const int prow = 64 * Q + L;
+                                prl[r + rp] = prow;
+                                pcl[r + rp] = c0 + k;
+                                sel[prow] = 1;
+                                inpanel[prow] = 1;
+                            }
+                            ++rp;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t t0 = D[q][0];
+#pragma unroll
+                    for (int w = 0; w < 15; ++w) D[q][w] = D[q][w + 1];
+                    D[q][15] = t0;
+                }
+            }
+            // reduce, give each pivot row its own transformation entry 1 and scale it
+            // to pivot -1, then write the panel, F (for the MFMA) and the new
+            // transformation columns (F itself) back to LDS
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (!ok[q]) continue;
+                const int row = lane + 64 * q;
+                const uint32_t sc = scale[q];
+                uint32_t pk[8], fk[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    uint32_t v[4], g[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int col = 4 * i + j;
+                        const uint32_t wd = D[q][col >> 1], fw = F[q][col >> 1];
+                        const uint32_t dv = (col & 1) ? (wd >> 16) : (wd & 0xffffu);
+                        uint32_t fv = (col & 1) ? (fw >> 16) : (fw & 0xffffu);
+                        if (col == pidx[q]) fv += 1;
+                        v[j] = mod22(__umul24(dv, sc), inv, p);
+                        g[j] = mod22(__umul24(fv, sc), inv, p);
+                    }
+                    pk[i] = v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
+                    fk[i] = g[0] | (g[1] << 8) | (g[2] << 16) | (g[3] << 24);
+                }
+                uint8_t* wr = W + (size_t)row * LW;
+                if (wc == ECHS_PW) {
+                    *(uint4*)(wr + c0) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+                    *(uint4*)(wr + c0 + 16) = make_uint4(pk[4], pk[5], pk[6], pk[7]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < ECHS_PW; ++j)
+                        if (j < wc) wr[c0 + j] = (uint8_t)(pk[j >> 2] >> (8 * (j & 3)));
+                }
+                *(uint4*)(Fl + row * ECHS_PW) = make_uint4(fk[0], fk[1], fk[2], fk[3]);
+                *(uint4*)(Fl + row * ECHS_PW + 16) = make_uint4(fk[4], fk[5], fk[6], fk[7]);
+#pragma unroll
+                for (int t = 0; t < ECHS_PW; ++t)
+                    if (t < rp) wr[TC + r + t] = (uint8_t)(fk[t >> 2] >> (8 * (t & 3)));
+            }
+            for (int rr = lane; rr < rows16; rr += 64)   // rows past `rows` (padding of the MFMA tiles)
+                if (rr >= rows) { *(uint4*)(Fl + rr * ECHS_PW) = make_uint4(0, 0, 0, 0); *(uint4*)(Fl + rr * ECHS_PW + 16) = make_uint4(0, 0, 0, 0); }
+            if (lane == 0) shared_rp[(c0 / ECHS_PW) & 1] = rp;
+        }
+        __syncthreads();
+        const int rp = shared_rp[(c0 / ECHS_PW) & 1];
+        if (rp > 0) {
+            int prow_off[8];     // W offsets of pivot rows (x & 3) * 8 .. + 7 of this panel, -1 past rp
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int t = (x & 3) * 8 + j;
+                prow_off[j] = t < rp ? prl[r + t] * LW : -1;
+            }
+            // segment 0: data columns right of the panel; segment 1: transformation
+            // columns of the pivots of earlier panels
+            for (int seg = 0; seg < 2; ++seg) {
+                const int ybeg = seg == 0 ? c0 + ECHS_PW : TC;
+                const int yend = seg == 0 ? cols : TC + r;
+                for (int y0 = ybeg; y0 < yend; y0 += ECHS_VCH) {
+                    const int nc = min(ECHS_VCH, yend - y0);
+                    {   // Vt[yy][t] = W[pivot row t][y0 + yy]
+                        const int yy = x >> 2;
+                        uint32_t lo = 0, hi = 0;
+                        if (yy < nc) {
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) {
+                                const uint32_t b = prow_off[j] >= 0 ? W[prow_off[j] + y0 + yy] : 0u;
+                                if (j < 4) lo |= b << (8 * j); else hi |= b << (8 * (j - 4));
+                            }
+                        }
+                        *(uint2*)(Vt + yy * ECHS_PW + (x & 3) * 8) = make_uint2(lo, hi);
+                    }
+                    __syncthreads();
+                    // a wave owns row blocks rb = wave, wave + 4, ...: for each, the
+                    // products of the (up to) four 16-column blocks first, then the updates
+                    const int ncb = (nc + 15) >> 4;
+                    for (int rb = wave; rb < (rows16 >> 4); rb += ECHS_THREADS / 64) {
+                        v4i av = v4i{0, 0, 0, 0};
+                        if (lane < 32) av = *(const v4i*)(Fl + (rb * 16 + (lane & 15)) * ECHS_PW + (lane >> 4) * 16);
+                        v4i acc[4];
+#pragma unroll
+                        for (int cb = 0; cb < 4; ++cb) {
+                            acc[cb] = v4i{0, 0, 0, 0};
+                            if (cb < ncb) {
+                                v4i bv = v4i{0, 0, 0, 0};
+                                if (lane < 32) bv = *(const v4i*)(Vt + (cb * 16 + (lane & 15)) * ECHS_PW + (lane >> 4) * 16);
+                                acc[cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(bv, av, acc[cb], 0, 0, 0);
+                            }
+                        }
+                        const int row = rb * 16 + (lane & 15);
+                        if (row < rows) {
+                            const bool keep = !inpanel[row];
+                            uint32_t* wrow = (uint32_t*)(W + (size_t)row * LW + y0);
+                            uint32_t old[4];
+#pragma unroll
+                            for (int cb = 0; cb < 4; ++cb) {
+                                const int cc = cb * 16 + (lane >> 4) * 4;
+                                old[cb] = cc < nc ? wrow[cc >> 2] : 0u;
+                            }
+#pragma unroll
+                            for (int cb = 0; cb < 4; ++cb) {
+                                const int cc = cb * 16 + (lane >> 4) * 4;
+                                if (cc < nc) {
+                                    uint32_t out = 0;
+#pragma unroll
+                                    for (int j = 0; j < 4; ++j) {
+                                        const uint32_t ob = (old[cb] >> (8 * j)) & 0xffu;
+                                        const uint32_t nv = mod22((keep ? ob : 0u) + (uint32_t)acc[cb][j], inv, p);
+                                        out |= (cc + j < nc ? nv : ob) << (8 * j);
+                                    }
+                                    wrow[cc >> 2] = out;
+                                }
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (int t = x; t < rp; t += ECHS_THREADS) inpanel[prl[r + t]] = 0;
+            __syncthreads();
+        }
+        r += rp;
+    }
+    // ---- outputs
+    if (x == 0) *e.rcount = r;
+    for (int t = x; t < r; t += ECHS_THREADS) {
+        e.prow[t] = prl[t];
+        e.pcol[t] = pcl[t];
+    }
+    if (wave == 0) {
+        int base = 0;
+        for (int r0 = 0; r0 < rows; r0 += 64) {
+            const int rr = r0 + lane;
+            const bool un = rr < rows && !sel[rr];
+            const unsigned long long bq = __ballot(un);
+            if (un) {
+                const int pos = base + __popcll(bq & ((1ull << lane) - 1));
+                e.qrow[pos] = rr;
+                qrl[pos] = rr;
+            }
+            base += __popcll(bq);
+        }
+    }
+    if (wave == 1) {
+        int base = 0;
+        for (int y0 = 0; y0 < cols; y0 += 64) {
+            const int y = y0 + lane;
+            int lo = 0, hi = r;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (pcl[mid] < y) lo = mid + 1; else hi = mid;
+            }
+            const bool np = y < cols && !(lo < r && pcl[lo] == y);
+            const unsigned long long bq = __ballot(np);
+            if (np) e.qcol[base + __popcll(bq & ((1ull << lane) - 1))] = y;
+            base += __popcll(bq);
+        }
+    }
+    __syncthreads();
+    // M (rows of the pivots), K (non-pivot rows), R (pivot rows at the non-pivot columns)
+    for (int t = wave; t < r; t += ECHS_THREADS / 64) {
+        const uint8_t* wr = W + (size_t)prl[t] * LW;
+        for (int u = lane; u < r; u += 64) gstore<uint8_t>(e.Mo + (int64_t)t * e.ldm + u, wr[TC + u]);
+        for (int k2 = lane; k2 < cols - r; k2 += 64)
+            gstore<uint8_t>(e.Ro + (int64_t)t * e.ldr + k2, wr[gload<int32_t>(e.qcol + k2)]);
+    }
+    for (int s2 = wave; s2 < rows - r; s2 += ECHS_THREADS / 64) {
+        const uint8_t* wr = W + (size_t)qrl[s2] * LW + TC;
+        for (int u = lane; u < r; u += 64) gstore<uint8_t>(e.Ko + (int64_t)s2 * e.ldk + u, wr[u]);
     }
 }
 
@@ -1044,6 +1481,16 @@ public:
             if (err) *err = "cannot reserve LDS for the kernels";
             return false;
         }
+        // the LDS-resident ECH takes up to 160 KB per workgroup where the device allows it
+        echs_lds_max_ = 160 * 1024;
+        if (hipFuncSetAttribute((const void*)k_ech_lds<DescArg<EchDesc, ECH_ARG_CAP>>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)echs_lds_max_) != hipSuccess ||
+            hipFuncSetAttribute((const void*)k_ech_lds<DescPtr<EchDesc>>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)echs_lds_max_) != hipSuccess) {
+            (void)hipGetLastError();
+            echs_lds_max_ = 64 * 1024;
+        }
+        no_lds_ech_ = getenv("GFECH_ECH_NO_LDS") != nullptr;
         return true;
     }
 
@@ -1224,6 +1671,27 @@ public:
 
     void ech(const std::vector<EchDesc>& ds) override {
         if (ds.empty()) return;
+        // blocks of at most 256 rows over p <= 46 whose working matrix fits in
+        // LDS: k_ech_lds; the others below
+        std::vector<EchDesc> lds, rest;
+        size_t shm_lds = 0;
+        for (const EchDesc& e : ds) {
+            const size_t need = echs_lds_bytes(e.rows, e.cols);
+            if (e.rows <= ECHS_MAX_ROWS && e.p <= ECHS_MAX_P && need <= echs_lds_max_ && !no_lds_ech_) {
+                lds.push_back(e);
+                shm_lds = std::max(shm_lds, need);
+            } else {
+                rest.push_back(e);
+            }
+        }
+        for (size_t off = 0; off < lds.size(); off += 65535) {
+            const size_t cnt = std::min<size_t>(65535, lds.size() - off);
+            launch_descs<ECH_ARG_CAP>(lds.data() + off, cnt, k_ech_lds<DescArg<EchDesc, ECH_ARG_CAP>>,
+                                      k_ech_lds<DescPtr<EchDesc>>, dim3((unsigned)cnt), dim3(ECHS_THREADS), shm_lds, 1);
+        }
+        if (!rest.empty()) ech_global(rest);
+    }
+    void ech_global(const std::vector<EchDesc>& ds) {
         int maxrows_all = 0;
         for (const EchDesc& e : ds) maxrows_all = std::max(maxrows_all, e.rows);
         if (maxrows_all <= ECHP_MAX_ROWS && !getenv("GFECH_ECH_SIMPLE")) {
@@ -1385,6 +1853,8 @@ private:
     int32_t* counts_dev_ = nullptr;    // and device view
     size_t counts_cap_ = 0;
     int mark_base_ = 0;              // id of marks_[0]
+    size_t echs_lds_max_ = 0;        // LDS the LDS-resident ECH may use
+    bool no_lds_ech_ = false;
     void* ring_host_ = nullptr;
     void* ring_dev_ = nullptr;
     size_t ring_off_ = 0;

@@ -91,10 +91,13 @@ def test_mad_batch_grouped():
         assert np.array_equal(dD.cpu().numpy().reshape(M, N), exp)
 
 
-ECH_SHAPES = [(1, 1), (5, 9), (9, 5), (64, 64), (100, 37), (37, 100), (300, 300), (513, 200), (200, 700)]
+ECH_SHAPES = [(1, 1), (5, 9), (9, 5), (64, 64), (100, 37), (37, 100), (300, 300), (513, 200), (200, 700),
+              # blocks of at most 256 rows (working matrix in LDS when p <= 46): full panels, ragged
+              # last panels, more columns than fit, one column
+              (256, 288), (256, 256), (250, 301), (256, 33), (129, 400), (64, 1500), (256, 1)]
 
 
-@pytest.mark.parametrize("p", [2, 3, 5, 251])
+@pytest.mark.parametrize("p", [2, 3, 5, 7, 43, 47, 251])
 @pytest.mark.parametrize("shape", ECH_SHAPES)
 def test_ech_block(shape, p):
     torch = torch_cuda()
