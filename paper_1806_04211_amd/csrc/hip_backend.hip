@@ -438,6 +438,39 @@ __global__ void __launch_bounds__(GEMM_THREADS, TN_ == 128 ? 2 : 1) k_gemm_modp(
     const bool small = p <= 127 && (uint64_t)g.K * (p - 1) * (p - 1) + (p - 1) < (1u << 22);
     const float inv = 1.0f / (float)p;
     const ModP mod(p);
+    const auto reduce4 = [&](const v4i& a, uint32_t cw) -> uint32_t {
+        uint32_t out = 0;
+        if (small) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) out |= mod22((uint32_t)a[e] + ((cw >> (8 * e)) & 0xffu), inv, p) << (8 * e);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) out |= mod(a[e] + (int)((cw >> (8 * e)) & 0xffu)) << (8 * e);
+        }
+        return out;
+    };
+    const bool whole = m0 + TM <= g.M && n0 + TN_ <= g.N &&
+                       ((((uintptr_t)g.D) | (uintptr_t)g.ldd | (uintptr_t)g.C | (uintptr_t)g.ldc) & 3) == 0;
+    if (whole) {
+        // interior tile with dword-aligned rows: every C word is loaded before any
+        // is used, so the loads of the whole tile are in flight together
+        uint32_t cw[8][JN];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int row = m0 + wm + i * 16 + r16;
+            const uint8_t* cp = g.C ? g.C + (int64_t)(g.crow ? gload<int32_t>(g.crow + row) : row) * g.ldc : nullptr;
+#pragma unroll
+            for (int j = 0; j < JN; ++j)
+                cw[i][j] = cp ? gload<uint32_t>(cp + n0 + wn + j * 16 + (lane >> 4) * 4) : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            uint8_t* dp = g.D + (int64_t)(m0 + wm + i * 16 + r16) * g.ldd + n0 + wn + (lane >> 4) * 4;
+#pragma unroll
+            for (int j = 0; j < JN; ++j) gstore<uint32_t>(dp + j * 16, reduce4(acc[i][j], cw[i][j]));
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const int row = m0 + wm + i * 16 + r16;
@@ -450,15 +483,7 @@ __global__ void __launch_bounds__(GEMM_THREADS, TN_ == 128 ? 2 : 1) k_gemm_modp(
             if (col >= g.N) continue;
             const int rem = g.N - col;
             const uint32_t cw = crow_ptr ? load4_lim(crow_ptr + col, rem) : 0u;
-            uint32_t out = 0;
-            if (small) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    out |= mod22((uint32_t)acc[i][j][e] + ((cw >> (8 * e)) & 0xffu), inv, p) << (8 * e);
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) out |= mod(acc[i][j][e] + (int)((cw >> (8 * e)) & 0xffu)) << (8 * e);
-            }
+            const uint32_t out = reduce4(acc[i][j], cw);
             uint8_t* dp = drow_ptr + col;
             if (rem >= 4 && (((uintptr_t)dp) & 3) == 0) {
                 gstore<uint32_t>(dp, out);
