@@ -95,16 +95,18 @@ struct DescPtr {
 
 // ============================================================================ GEMM mod p
 //
-// Workgroup tile TM x TN_ of D (TN_ = 128 or 256), 4 waves in 2 x 2, each
-// wave 128 x TN_/2 as 8 x (TN_/32) blocks of v_mfma_i32_16x16x64_i8.  The
-// MFMA is issued with the operands swapped (the B tile as the first operand)
-// so that each lane's four results are four consecutive columns of one row of
-// D: the epilogue reduces, packs and stores them as one dword.  K advances in
-// steps of TK through two LDS stages; the next step's global loads are in
-// registers while the current step computes.  A is kept [m][k] in LDS and B
-// transposed [n][k], so both MFMA operands read 16 consecutive k bytes per
-// lane; the 16-byte k-chunks of B's rows are XOR-swizzled against bank
-// conflicts of the transposing writes.
+// Workgroup tile TM x TN of D, 4 waves in 2 x 2, each wave 128 x 64 as 8 x 4
+// blocks of v_mfma_i32_16x16x64_i8.  The MFMA is issued with the operands
+// swapped (the B tile as the first operand) so that each lane's four results
+// are four consecutive columns of one row of D: the epilogue reduces, packs
+// and stores them as one dword.  K advances in steps of TK through two LDS
+// stages; the next step's global loads are in registers while the current
+// step computes.  A is kept [m][k] in LDS (rows padded to 80 bytes).  B is
+// kept as it is stored, [k][n], the 16-byte chunk c of row k at position
+// c ^ (k & 7); the MFMA wants 16 consecutive k of one column per lane, which
+// ds_read_b64_tr_b8 delivers: within each group of 16 lanes, lane pairs
+// (2t, 2t + 1) address the two halves of a 16-byte row t (t < 8), and lane c
+// of the group receives byte c of each of the 8 rows.
 //
 // Exactness: residues of p <= 127 are used as they are, residues of p > 127
 // are centred (x >= 128 becomes x - p), so every product is an int8 x int8
@@ -113,12 +115,12 @@ struct DescPtr {
 // float quotient estimate (mod22), otherwise with a Barrett step (ModP).
 
 constexpr int TM = 256;          // rows of D per workgroup tile
+constexpr int TN = 128;          // columns of D per workgroup tile
 constexpr int TK = 64;           // reduction depth per LDS stage
-constexpr int LDS_ROW = 80;      // bytes per LDS row (64 data + 16 pad)
+constexpr int LDS_ROW = 80;      // bytes per LDS row of the A tile (64 data + 16 pad)
 constexpr int GEMM_THREADS = 256;
 
-template <int TN_>
-constexpr size_t gemm_lds_bytes() { return (size_t)2 * (TM + TN_) * LDS_ROW; }
+constexpr size_t gemm_lds_bytes() { return 2 * ((size_t)TM * LDS_ROW + (size_t)TK * TN); }
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
@@ -179,22 +181,6 @@ __device__ __forceinline__ uint4 load16_lim(const uint8_t* p, int rem) {
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-// 8 bytes starting at p, `rem` (>= 1) valid; same rules as load16_lim
-__device__ __forceinline__ uint2 load8_lim(const uint8_t* p, int rem) {
-    if (rem >= 12) {
-        uintptr_t a = (uintptr_t)p;
-        const uint32_t* q = (const uint32_t*)(a & ~(uintptr_t)3);
-        uint32_t sh = (uint32_t)(a & 3);
-        uint32_t w0 = gload<uint32_t>(q), w1 = gload<uint32_t>(q + 1);
-        if (sh == 0) return make_uint2(w0, w1);
-        uint32_t w2 = gload<uint32_t>(q + 2);
-        return make_uint2(__builtin_amdgcn_alignbyte(w1, w0, sh), __builtin_amdgcn_alignbyte(w2, w1, sh));
-    }
-    uint32_t w[2] = {0, 0};
-    int n = rem < 8 ? rem : 8;
-    for (int b = 0; b < n; ++b) w[b >> 2] |= (uint32_t)gload<uint8_t>(p + b) << (8 * (b & 3));
-    return make_uint2(w[0], w[1]);
-}
 
 // 4 bytes starting at p, `rem` (>= 1) valid
 __device__ __forceinline__ uint32_t load4_lim(const uint8_t* p, int rem) {
@@ -212,18 +198,6 @@ __device__ __forceinline__ uint32_t centre(uint32_t w, uint32_t adj) {
     return w + hi * adj;
 }
 
-// transpose a 4 x 4 block of bytes: in r[i] byte j is element (i, j); out c[j] byte i is element (i, j)
-__device__ __forceinline__ void transpose4x4(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t r3, uint32_t& c0,
-                                             uint32_t& c1, uint32_t& c2, uint32_t& c3) {
-    const uint32_t t0 = __builtin_amdgcn_perm(r1, r0, 0x05010400u);   // r0.b0 r1.b0 r0.b1 r1.b1
-    const uint32_t t1 = __builtin_amdgcn_perm(r3, r2, 0x05010400u);   // r2.b0 r3.b0 r2.b1 r3.b1
-    const uint32_t t2 = __builtin_amdgcn_perm(r1, r0, 0x07030602u);   // r0.b2 r1.b2 r0.b3 r1.b3
-    const uint32_t t3 = __builtin_amdgcn_perm(r3, r2, 0x07030602u);   // r2.b2 r3.b2 r2.b3 r3.b3
-    c0 = __builtin_amdgcn_perm(t1, t0, 0x05040100u);
-    c1 = __builtin_amdgcn_perm(t1, t0, 0x07060302u);
-    c2 = __builtin_amdgcn_perm(t3, t2, 0x05040100u);
-    c3 = __builtin_amdgcn_perm(t3, t2, 0x07060302u);
-}
 
 // 16 bytes at p for an interior tile (no bounds checks): one vector load
 // when p is 16-byte aligned, else aligned dwords realigned with alignbyte
@@ -241,55 +215,29 @@ __device__ __forceinline__ uint4 load16_any(const uint8_t* p) {
     return make_uint4(__builtin_amdgcn_alignbyte(w1, w0, sh), __builtin_amdgcn_alignbyte(w2, w1, sh),
                       __builtin_amdgcn_alignbyte(w3, w2, sh), __builtin_amdgcn_alignbyte(w4, w3, sh));
 }
-__device__ __forceinline__ uint2 load8_any(const uint8_t* p) {
-    const uintptr_t a = (uintptr_t)p;
-    if ((a & 7) == 0) return gload<uint2>(p);
-    const uint32_t* q = (const uint32_t*)(a & ~(uintptr_t)3);
-    const uint32_t sh = (uint32_t)(a & 3);
-    const uint32_t w0 = gload<uint32_t>(q), w1 = gload<uint32_t>(q + 1);
-    if (sh == 0) return make_uint2(w0, w1);
-    const uint32_t w2 = gload<uint32_t>(q + 2);
-    return make_uint2(__builtin_amdgcn_alignbyte(w1, w0, sh), __builtin_amdgcn_alignbyte(w2, w1, sh));
-}
 
-// B columns per thread and k-row: TN_ / 16 bytes, as TN_ / 64 dwords
-template <int TN_>
 struct GemmRegs {
-    uint4 a[4];                   // A: four 16-byte chunks (rows of the A tile)
-    uint32_t b[4][TN_ / 64];      // B: four k-rows x TN_/16 columns
+    uint4 a[4];     // A: four 16-byte chunks (rows of the A tile)
+    uint4 b[2];     // B: k-rows (tid >> 3) and (tid >> 3) + 32, 16 columns from 16 (tid & 7)
 };
-
-template <int TN_>
-__device__ __forceinline__ void set_b(GemmRegs<TN_>& R, int t, uint4 v) {
-    if constexpr (TN_ == 256) { R.b[t][0] = v.x; R.b[t][1] = v.y; R.b[t][2] = v.z; R.b[t][3] = v.w; }
-}
-template <int TN_>
-__device__ __forceinline__ void set_b(GemmRegs<TN_>& R, int t, uint2 v) {
-    if constexpr (TN_ == 128) { R.b[t][0] = v.x; R.b[t][1] = v.y; }
-}
 
 // Interior tiles (FAST): no bounds checks, so the loads stay in flight while
 // the MFMAs of the current step run.  Otherwise every chunk is checked.
-template <bool FAST, int TN_>
+template <bool FAST>
 __device__ __forceinline__ void gemm_load(const GemmDesc& g, int m0, int n0, int k0, int tid, uint32_t adj,
-                                          GemmRegs<TN_>& R) {
-    constexpr int NB = TN_ / 16;                 // bytes of a B k-row per thread
-    const int kg = tid >> 4, ng = tid & 15;
+                                          GemmRegs& R) {
+    const int kr = tid >> 3, cb = (tid & 7) * 16;
     if (FAST) {
-        int64_t br[4];
+        int64_t br[2];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) br[t] = g.brow ? gload<int32_t>(g.brow + k0 + kg * 4 + t) : k0 + kg * 4 + t;
+        for (int h = 0; h < 2; ++h) br[h] = g.brow ? gload<int32_t>(g.brow + k0 + kr + 32 * h) : k0 + kr + 32 * h;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int c = tid + s * GEMM_THREADS;
             R.a[s] = gload<uint4>(g.A + (int64_t)(m0 + (c >> 2)) * g.lda + k0 + (c & 3) * 16);
         }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const uint8_t* bp = g.B + br[t] * g.ldb + n0 + ng * NB;
-            if constexpr (NB == 16) set_b(R, t, load16_any(bp));
-            else set_b(R, t, load8_any(bp));
-        }
+        for (int h = 0; h < 2; ++h) R.b[h] = load16_any(g.B + br[h] * g.ldb + n0 + cb);
         if (adj) {
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
@@ -297,9 +245,10 @@ __device__ __forceinline__ void gemm_load(const GemmDesc& g, int m0, int n0, int
                 R.a[s].z = centre(R.a[s].z, adj); R.a[s].w = centre(R.a[s].w, adj);
             }
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int w = 0; w < NB / 4; ++w) R.b[t][w] = centre(R.b[t][w], adj);
+            for (int h = 0; h < 2; ++h) {
+                R.b[h].x = centre(R.b[h].x, adj); R.b[h].y = centre(R.b[h].y, adj);
+                R.b[h].z = centre(R.b[h].z, adj); R.b[h].w = centre(R.b[h].w, adj);
+            }
         }
         return;
     }
@@ -316,58 +265,43 @@ __device__ __forceinline__ void gemm_load(const GemmDesc& g, int m0, int n0, int
         R.a[s] = v;
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int gk = k0 + kg * 4 + t, gn = n0 + ng * NB;
-        if constexpr (NB == 16) {
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (gk < g.K && gn < g.N) {
-                const int64_t br = g.brow ? gload<int32_t>(g.brow + gk) : gk;
-                v = load16_lim(g.B + br * g.ldb + gn, g.N - gn);
-                if (adj) { v.x = centre(v.x, adj); v.y = centre(v.y, adj); v.z = centre(v.z, adj); v.w = centre(v.w, adj); }
-            }
-            set_b(R, t, v);
-        } else {
-            uint2 v = make_uint2(0, 0);
-            if (gk < g.K && gn < g.N) {
-                const int64_t br = g.brow ? gload<int32_t>(g.brow + gk) : gk;
-                v = load8_lim(g.B + br * g.ldb + gn, g.N - gn);
-                if (adj) { v.x = centre(v.x, adj); v.y = centre(v.y, adj); }
-            }
-            set_b(R, t, v);
+    for (int h = 0; h < 2; ++h) {
+        const int gk = k0 + kr + 32 * h, gn = n0 + cb;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (gk < g.K && gn < g.N) {
+            const int64_t br = g.brow ? gload<int32_t>(g.brow + gk) : gk;
+            v = load16_lim(g.B + br * g.ldb + gn, g.N - gn);
+            if (adj) { v.x = centre(v.x, adj); v.y = centre(v.y, adj); v.z = centre(v.z, adj); v.w = centre(v.w, adj); }
         }
+        R.b[h] = v;
     }
 }
 
-template <int TN_>
-__device__ __forceinline__ void gemm_store_lds(const GemmRegs<TN_>& R, uint8_t* As, uint8_t* Bs, int tid) {
-    constexpr int NB = TN_ / 16;
+__device__ __forceinline__ void gemm_store_lds(const GemmRegs& R, uint8_t* As, uint8_t* Bs, int tid) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const int c = tid + s * GEMM_THREADS;
         *(uint4*)(As + (c >> 2) * LDS_ROW + (c & 3) * 16) = R.a[s];
     }
-    const int kg = tid >> 4, ng = tid & 15;
-#pragma unroll
-    for (int w = 0; w < NB / 4; ++w) {
-        uint32_t c[4];
-        transpose4x4(R.b[0][w], R.b[1][w], R.b[2][w], R.b[3][w], c[0], c[1], c[2], c[3]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            // column n, k bytes 4 kg .. 4 kg + 3: chunk (kg >> 2) of row n sits at chunk (kg >> 2) ^ ((n >> 3) & 3)
-            const int n = ng * NB + w * 4 + q;
-            *(uint32_t*)(Bs + n * LDS_ROW + ((((kg >> 2) ^ ((n >> 3) & 3)) << 4) | ((kg & 3) << 2))) = c[q];
-        }
-    }
+    // k-rows kr and kr + 32 share the swizzle (kr & 7)
+    const int kr = tid >> 3, pos = ((tid & 7) ^ (kr & 7)) << 4;
+    *(uint4*)(Bs + kr * TN + pos) = R.b[0];
+    *(uint4*)(Bs + (kr + 32) * TN + pos) = R.b[1];
 }
 
-template <int TN_, class Src>
-__global__ void __launch_bounds__(GEMM_THREADS, TN_ == 128 ? 2 : 1) k_gemm_modp(Src src) {
-    constexpr int NB = TN_ / 16;
-    constexpr int JN = TN_ / 32;          // 16-column MFMA blocks per wave
+typedef int v2i __attribute__((ext_vector_type(2)));
+// 8 bytes per lane through ds_read_b64_tr_b8 (see the comment at the top of this section)
+__device__ __forceinline__ v2i lds_read_tr8(const uint8_t* p) {
+    return __builtin_amdgcn_ds_read_tr8_b64_v2i32((__attribute__((address_space(3))) v2i*)(p));
+}
+
+template <class Src>
+__global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
+    constexpr int JN = TN / 32;           // 16-column MFMA blocks per wave
     extern __shared__ __attribute__((aligned(16))) uint8_t gsm[];
-    // stage s: A tile at As(s) ([m][k]), B tile at Bs(s) (transposed: [n][k])
+    // stage s: A tile at As(s) ([m][k]), B tile at Bs(s) ([k][n], swizzled)
     const auto As = [](int s) { return gsm + s * (TM * LDS_ROW); };
-    const auto Bs = [](int s) { return gsm + 2 * TM * LDS_ROW + s * (TN_ * LDS_ROW); };
+    const auto Bs = [](int s) { return gsm + 2 * TM * LDS_ROW + s * (TK * TN); };
 
     // which descriptor owns this tile (binary search over the prefix sums)
     const int tile = blockIdx.x;
@@ -381,12 +315,12 @@ __global__ void __launch_bounds__(GEMM_THREADS, TN_ == 128 ? 2 : 1) k_gemm_modp(
     const int local = tile - gm.first_tile;
     const int tn = gm.tiles_n;
     const int m0 = (local / tn) * TM;
-    const int n0 = (local % tn) * TN_;
+    const int n0 = (local % tn) * TN;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm = (wave >> 1) * 128;     // wave's 128 x TN_/2 sub-tile
-    const int wn = (wave & 1) * (TN_ / 2);
+    const int wm = (wave >> 1) * 128;     // wave's 128 x 64 sub-tile
+    const int wn = (wave & 1) * (TN / 2);
     const uint32_t p = (uint32_t)g.p;
     const uint32_t adj = p > 127 ? 256u - p : 0u;
 
@@ -400,11 +334,11 @@ __global__ void __launch_bounds__(GEMM_THREADS, TN_ == 128 ? 2 : 1) k_gemm_modp(
     // steps that may use the unchecked loads: the whole tile inside D, A rows
     // 16-byte aligned, and B rows either aligned for the vector load or with
     // 3 spare columns after the tile for the realigning read
-    const bool b_aligned = (((uintptr_t)g.B | (uintptr_t)g.ldb) & (NB - 1)) == 0;
-    const bool fast = m0 + TM <= g.M && n0 + TN_ <= g.N && ((uintptr_t)g.A & 15) == 0 && (g.lda & 15) == 0 &&
-                      (b_aligned || n0 + TN_ + 3 <= g.N);
+    const bool b_aligned = (((uintptr_t)g.B | (uintptr_t)g.ldb) & 15) == 0;
+    const bool fast = m0 + TM <= g.M && n0 + TN <= g.N && ((uintptr_t)g.A & 15) == 0 && (g.lda & 15) == 0 &&
+                      (b_aligned || n0 + TN + 3 <= g.N);
     const int nk_fast = fast ? g.K / TK : 0;
-    GemmRegs<TN_> R;
+    GemmRegs R;
     if (nk > 0) {
         if (nk_fast > 0) gemm_load<true>(g, m0, n0, 0, tid, adj, R);
         else gemm_load<false>(g, m0, n0, 0, tid, adj, R);
@@ -417,11 +351,15 @@ __global__ void __launch_bounds__(GEMM_THREADS, TN_ == 128 ? 2 : 1) k_gemm_modp(
         const int st = ks & 1;
         if (ks + 1 < nk_fast) gemm_load<true>(g, m0, n0, (ks + 1) * TK, tid, adj, R);
         else if (ks + 1 < nk) gemm_load<false>(g, m0, n0, (ks + 1) * TK, tid, adj, R);
+        // B operand of block j: lane 16 q + c gets column wn + 16 j + c, k = 16 q .. 16 q + 15,
+        // from rows 16 q + t and 16 q + 8 + t (t = c / 2, whose swizzle is t) at half c & 1
         v4i bf[JN];
 #pragma unroll
         for (int j = 0; j < JN; ++j) {
-            const int n = wn + j * 16 + r16;
-            bf[j] = *(const v4i*)(Bs(st) + n * LDS_ROW + ((kq >> 4) ^ ((n >> 3) & 3)) * 16);
+            const int t = r16 >> 1;
+            const uint8_t* rp = Bs(st) + (kq + t) * TN + ((((wn >> 4) + j) ^ t) << 4) + ((r16 & 1) << 3);
+            const v2i lo = lds_read_tr8(rp), hi = lds_read_tr8(rp + 8 * TN);
+            bf[j] = v4i{lo.x, lo.y, hi.x, hi.y};
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
@@ -449,7 +387,7 @@ __global__ void __launch_bounds__(GEMM_THREADS, TN_ == 128 ? 2 : 1) k_gemm_modp(
         }
         return out;
     };
-    const bool whole = m0 + TM <= g.M && n0 + TN_ <= g.N &&
+    const bool whole = m0 + TM <= g.M && n0 + TN <= g.N &&
                        ((((uintptr_t)g.D) | (uintptr_t)g.ldd | (uintptr_t)g.C | (uintptr_t)g.ldc) & 3) == 0;
     if (whole) {
         // interior tile with dword-aligned rows: every C word is loaded before any
@@ -1499,10 +1437,10 @@ public:
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)echp_lds_bytes(ECHP_MAX_ROWS)) != hipSuccess ||
             hipFuncSetAttribute((const void*)k_ech_panel<DescPtr<EchDesc>>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)echp_lds_bytes(ECHP_MAX_ROWS)) != hipSuccess ||
-            hipFuncSetAttribute((const void*)k_gemm_modp<128, GemmArgSrc>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)gemm_lds_bytes<128>()) != hipSuccess ||
-            hipFuncSetAttribute((const void*)k_gemm_modp<128, GemmPtrSrc>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)gemm_lds_bytes<128>()) != hipSuccess) {
+            hipFuncSetAttribute((const void*)k_gemm_modp<GemmArgSrc>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)gemm_lds_bytes()) != hipSuccess ||
+            hipFuncSetAttribute((const void*)k_gemm_modp<GemmPtrSrc>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)gemm_lds_bytes()) != hipSuccess) {
             if (err) *err = "cannot reserve LDS for the kernels";
             return false;
         }
@@ -1633,10 +1571,8 @@ public:
     int error() const override { return err_; }
 
     // 256 x 128 tiles: at occupancy 2 they run faster at every shape measured
-    // than 256 x 256 tiles (occupancy 1), whose latencies stay exposed
-    void gemm(const std::vector<GemmDesc>& ds) override { gemm_t<128>(ds); }
-    template <int TN_>
-    void gemm_t(const std::vector<GemmDesc>& ds) {
+    // than 256 x 256 tiles did (occupancy 1), whose latencies stay exposed
+    void gemm(const std::vector<GemmDesc>& ds) override {
         std::vector<GemmDesc> d;
         std::vector<GemmTileMap> maps;
         int64_t tiles = 0;
@@ -1644,7 +1580,7 @@ public:
             if (g.M <= 0 || g.N <= 0) continue;
             if (g.K > 65536) { note_error(hipErrorInvalidValue, "gemm K > 65536"); return; }
             GemmTileMap t;
-            t.tiles_n = (g.N + TN_ - 1) / TN_;
+            t.tiles_n = (g.N + TN - 1) / TN;
             t.first_tile = (int32_t)tiles;
             tiles += (int64_t)((g.M + TM - 1) / TM) * t.tiles_n;
             d.push_back(g);
@@ -1657,8 +1593,8 @@ public:
             GemmArgSrc a;
             a.n = (int)d.size();
             for (size_t i = 0; i < d.size(); ++i) { a.m[i] = maps[i]; a.d[i] = d[i]; }
-            hipLaunchKernelGGL((k_gemm_modp<TN_, GemmArgSrc>), dim3((unsigned)tiles), dim3(GEMM_THREADS),
-                               gemm_lds_bytes<TN_>(), cur_, a);
+            hipLaunchKernelGGL((k_gemm_modp<GemmArgSrc>), dim3((unsigned)tiles), dim3(GEMM_THREADS),
+                               gemm_lds_bytes(), cur_, a);
         } else {
             // one upload: the tile maps, then the descriptors (256-byte aligned)
             const size_t mb = (maps.size() * sizeof(GemmTileMap) + 255) & ~(size_t)255;
@@ -1670,8 +1606,8 @@ public:
             a.n = (int)d.size();
             a.m = (const GemmTileMap*)dev;
             a.d = (const GemmDesc*)(dev + mb);
-            hipLaunchKernelGGL((k_gemm_modp<TN_, GemmPtrSrc>), dim3((unsigned)tiles), dim3(GEMM_THREADS),
-                               gemm_lds_bytes<TN_>(), cur_, a);
+            hipLaunchKernelGGL((k_gemm_modp<GemmPtrSrc>), dim3((unsigned)tiles), dim3(GEMM_THREADS),
+                               gemm_lds_bytes(), cur_, a);
         }
         HIP_OK(hipGetLastError());
         prof_end(0, e0);
