@@ -64,6 +64,182 @@ def copy_calibration(torch, mib: int):
     print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
 
 
+def percentile(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(round(q * (len(xs) - 1))))] if xs else 0.0
+
+
+def batch_inputs(torch, count, seed=0):
+    """The batched workload of synth.batch_mix (n log-uniform in [32, 512],
+    p from {2, 3, 5, 7, 251}, 10 % rank-deficient), in one device buffer:
+    uniform matrices generated on the device, deficient ones on the host."""
+    import numpy as np
+
+    import synth
+    from synth import torch_gen
+    rng = np.random.default_rng([seed, 0xBA7C])
+    ns = np.rint(np.exp(rng.uniform(np.log(32), np.log(512), count))).astype(int)
+    ps = rng.choice(np.asarray([2, 3, 5, 7, 251]), size=count)
+    defi = rng.random(count) < 0.10
+    offs = np.concatenate([[0], np.cumsum(ns.astype(np.int64) ** 2)])
+    buf = torch.empty(int(offs[-1]), dtype=torch.uint8, device="cuda:0")
+    for t in range(count):
+        n, p = int(ns[t]), int(ps[t])
+        if defi[t]:
+            A = torch.from_numpy(synth.deficient(seed, 1000 + t, n, n, p).ravel()).to("cuda:0")
+        else:
+            A = torch_gen.uniform(seed, 1000 + t, n, n, p).reshape(-1)
+        buf[int(offs[t]):int(offs[t + 1])] = A
+    torch.cuda.synchronize()
+    return buf, [(int(buf.data_ptr() + offs[t]), int(ns[t]), int(ns[t]), int(ns[t]), int(ps[t])) for t in range(count)]
+
+
+def run_batch(torch, args):
+    """Many small matrices: one batched call against one call per matrix."""
+    import paper_1806_04211_amd as gf
+    lib = gf.library()
+    t0 = time.perf_counter()
+    buf, probs = batch_inputs(torch, args.count)
+    log(f"{len(probs)} matrices ready in {time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def batched():
+        res, sts = lib.echelonise_batch(probs, on_device=True, stream=stream)
+        assert all(st == 0 for st in sts)
+        return res
+
+    for _ in range(args.warmup):
+        [r.free() for r in batched()]
+    times = []
+    for s in range(args.steps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res = batched()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+        ranks = [r.rank for r in res]
+        [r.free() for r in res]
+        log(f"batched step {s}: {times[-1]:.3f} s")
+    # the plain path: one call (one launch sequence) per matrix
+    lat = []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for (ptr, m, n, lda, p) in probs:
+        t2 = time.perf_counter()
+        r = lib.echelonise_dev(ptr, m, n, lda, p, stream=stream)
+        lat.append(time.perf_counter() - t2)
+        r.free()
+    per_call = time.perf_counter() - t1
+    mean = sum(times) / len(times)
+    print(json.dumps({
+        "metric": "batched solves/s (4096 matrices n in [32, 512], one call) vs one call per matrix",
+        "value": len(probs) / mean, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": mean * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"{len(probs)} square matrices, n log-uniform in [32, 512], p from {{2, 3, 5, 7, 251}}, "
+                               "10 % rank-deficient, seed 0", "count": len(probs)},
+        "per_call": {"solves_per_s": len(probs) / per_call, "latency_ms": {"p50": percentile(lat, 0.5) * 1e3,
+                                                                           "p99": percentile(lat, 0.99) * 1e3}},
+        "speedup_vs_per_call": per_call / mean,
+        "rank_sum": int(sum(ranks)),
+    }), flush=True)
+
+
+def serve_request(rng_seed, t):
+    """Request t of the serving workload: n log-uniform in [64, 8192],
+    m = n U[0.75, 1.25], p from {2, 3, 5, 251}, uniform entries of stream t."""
+    import numpy as np
+    rng = np.random.default_rng([rng_seed, 0x5E7E, t])
+    n = int(np.rint(np.exp(rng.uniform(np.log(64), np.log(8192)))))
+    m = max(1, int(round(n * rng.uniform(0.75, 1.25))))
+    p = int(rng.choice([2, 3, 5, 251]))
+    return m, n, p
+
+
+def run_serve(torch, args):
+    """Poisson arrivals through the server (continuous batching) against a
+    first-come first-served loop of single calls on the same arrivals."""
+    import numpy as np
+
+    import paper_1806_04211_amd as gf
+    from synth import torch_gen
+    lib = gf.library()
+    nreq = args.requests
+    shapes = [serve_request(0, t) for t in range(nreq)]
+
+    # every input is generated before any timing and stays in device memory
+    t0 = time.perf_counter()
+    inputs = [torch_gen.uniform(0, 2000 + t, m, n, p) for t, (m, n, p) in enumerate(shapes)]
+    torch.cuda.synchronize()
+    log(f"{nreq} inputs ready in {time.perf_counter() - t0:.1f} s "
+        f"({sum(m * n for m, n, _ in shapes) / 2**30:.2f} GiB)")
+
+    def submit(srv, t):
+        m, n, p = shapes[t]
+        return srv.submit_dev(inputs[t].data_ptr(), m, n, n, p)
+
+    # service time of every request alone (the plain path), which also
+    # calibrates the capacity of the served path below
+    service = []
+    for t in range(nreq):
+        m, n, p = shapes[t]
+        t1 = time.perf_counter()
+        r = lib.echelonise_dev(inputs[t].data_ptr(), m, n, n, p)
+        service.append(time.perf_counter() - t1)
+        r.free()
+    log(f"plain path: {sum(service):.2f} s of service for {nreq} requests")
+    # capacity of the server: all requests at once
+    srv = lib.server()
+    t1 = time.perf_counter()
+    tickets = [submit(srv, t) for t in range(nreq)]
+    for tk in tickets:
+        srv.wait(tk).free()
+    burst = time.perf_counter() - t1
+    mu = nreq / burst
+    lam = args.load * mu
+    log(f"server capacity {mu:.1f} solves/s (burst {burst:.2f} s); arrival rate {lam:.1f}/s")
+    arrivals = np.cumsum(np.random.default_rng(0).exponential(1.0 / lam, nreq))
+    # served: requests arrive at their times; finished ones are collected between arrivals
+    pending, done_at = {}, {}
+    t0 = time.perf_counter()
+    for t in range(nreq):
+        while time.perf_counter() - t0 < arrivals[t]:
+            for tk in list(pending):
+                r = srv.poll(tk)
+                if r is not None:
+                    done_at[pending.pop(tk)] = time.perf_counter() - t0
+                    r.free()
+        pending[submit(srv, t)] = t
+    while pending:
+        for tk in list(pending):
+            r = srv.poll(tk)
+            if r is not None:
+                done_at[pending.pop(tk)] = time.perf_counter() - t0
+                r.free()
+    span = time.perf_counter() - t0
+    srv.close()
+    lat = [done_at[t] - arrivals[t] for t in range(nreq)]
+    # the plain path on the same arrivals: one request at a time, first come first served
+    fin, plain_lat = 0.0, []
+    for t in range(nreq):
+        fin = max(fin, arrivals[t]) + service[t]
+        plain_lat.append(fin - arrivals[t])
+    print(json.dumps({
+        "metric": "served solves/s and p50/p99 latency (Poisson arrivals, continuous batching) vs one call at a time",
+        "value": nreq / span, "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": span * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"{nreq} requests, n log-uniform in [64, 8192], m = n U[0.75, 1.25], p from "
+                               f"{{2, 3, 5, 251}}, Poisson arrivals at {args.load} x capacity ({lam:.1f}/s)",
+                   "requests": nreq, "arrival_rate": lam},
+        "latency_ms": {"p50": percentile(lat, 0.5) * 1e3, "p99": percentile(lat, 0.99) * 1e3},
+        "capacity_solves_per_s": mu,
+        "plain": {"solves_per_s": nreq / fin, "latency_ms": {"p50": percentile(plain_lat, 0.5) * 1e3,
+                                                            "p99": percentile(plain_lat, 0.99) * 1e3},
+                  "service_s": sum(service)},
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +256,12 @@ def main():
                     help="time the steps without per-launch device events (no roofline / kernel_ms)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates HBM byte counters)")
+    ap.add_argument("--workload", choices=["single", "batch", "serve"], default="single",
+                    help="single: the one large matrix (default); batch: many small matrices in one call; "
+                         "serve: a Poisson stream of requests through the server")
+    ap.add_argument("--count", type=int, default=4096, help="batch: number of matrices")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
+    ap.add_argument("--load", type=float, default=0.8, help="serve: arrival rate as a fraction of capacity")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the method here runs on a "
@@ -90,6 +272,12 @@ def main():
 
     if args.copy_mib > 0:
         copy_calibration(torch, args.copy_mib)
+        return
+    if args.workload == "batch":
+        run_batch(torch, args)
+        return
+    if args.workload == "serve":
+        run_serve(torch, args)
         return
 
     import paper_1806_04211_amd as gf

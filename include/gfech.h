@@ -192,6 +192,37 @@ gfech_status gfech_ech_dev(const uint8_t* H, int64_t rows, int64_t cols, int64_t
                            uint8_t* M, int64_t ldm, uint8_t* K, int64_t ldk, uint8_t* R, int64_t ldr,
                            int64_t* rank, void* stream);
 
+/* ---------------------------------------------------------------- serving
+ * A server echelonises requests as they arrive (continuous batching): a
+ * worker thread keeps every admitted request's block state in device memory
+ * and advances all of them together, one phase of the method each per
+ * iteration, so requests submitted while others run join at the next
+ * iteration and their jobs share launches.  Requests are admitted in arrival
+ * order while the device memory they hold (an upper bound per request) fits
+ * the budget; a request whose bound alone exceeds the budget is refused.
+ * Results are the same as from gfech_echelonise_u8 on the same input (the
+ * default blocking).  The functions are thread-safe. */
+typedef struct gfech_server gfech_server;
+typedef struct gfech_server_cfg {
+    int64_t hbm_budget_bytes;   /* device memory for admitted requests; 0 = 200 GB */
+    int32_t max_active;         /* requests in flight at once; 0 = no limit but the budget */
+    int32_t reserved[5];
+} gfech_server_cfg;
+gfech_status gfech_server_create(const gfech_server_cfg* cfg, gfech_server** out);
+/* Queue one problem.  The input (host or device memory, as the flag says) is
+ * checked (entries < p) and copied before the call returns; *ticket names the
+ * request.  GFECH_E_TOO_BIG: the request alone exceeds the budget. */
+gfech_status gfech_server_submit(gfech_server* srv, const gfech_problem* prob, int32_t input_on_device,
+                                 uint64_t* ticket);
+/* Non-blocking: *out receives the result of a finished request (the caller
+ * owns it) or NULL while it is queued or running.  A ticket is answered once;
+ * unknown tickets give GFECH_E_ARG, failed requests their error status. */
+gfech_status gfech_server_poll(gfech_server* srv, uint64_t ticket, gfech_result** out);
+/* Blocking form of gfech_server_poll. */
+gfech_status gfech_server_wait(gfech_server* srv, uint64_t ticket, gfech_result** out);
+/* Drops queued requests, lets running ones finish, frees unclaimed results. */
+void gfech_server_destroy(gfech_server* srv);
+
 const char* gfech_strerror(gfech_status s);
 /* Detail of the last failure on this thread ("" if none). */
 const char* gfech_last_error(void);

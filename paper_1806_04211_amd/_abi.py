@@ -39,6 +39,10 @@ class Stats(ctypes.Structure):
                 ("launches_mad", c_i64), ("launches_ech", c_i64), ("launches_small", c_i64)]
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", c_i64), ("max_active", c_i32), ("reserved", c_i32 * 5)]
+
+
 class MadDesc(ctypes.Structure):
     _fields_ = [("M", c_i64), ("N", c_i64), ("K", c_i64), ("p", c_u32), ("reserved", c_u32),
                 ("A", vp), ("lda", c_i64), ("B", vp), ("ldb", c_i64), ("brow", vp),
@@ -72,6 +76,11 @@ SIGNATURES = {
     "gfech_mad_batch_dev": (ctypes.c_int, [c_i64, vp, vp]),
     "gfech_ech_dev": (ctypes.c_int, [vp, c_i64, c_i64, c_i64, c_u32, vp, vp, vp, vp, vp, c_i64, vp, c_i64, vp,
                                      c_i64, i64p, vp]),
+    "gfech_server_create": (ctypes.c_int, [vp, ctypes.POINTER(vp)]),
+    "gfech_server_submit": (ctypes.c_int, [vp, vp, c_i32, ctypes.POINTER(ctypes.c_uint64)]),
+    "gfech_server_poll": (ctypes.c_int, [vp, ctypes.c_uint64, ctypes.POINTER(vp)]),
+    "gfech_server_wait": (ctypes.c_int, [vp, ctypes.c_uint64, ctypes.POINTER(vp)]),
+    "gfech_server_destroy": (None, [vp]),
 }
 
 

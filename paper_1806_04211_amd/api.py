@@ -208,6 +208,9 @@ class Library:
                                            vp(M), ldm, vp(K), ldk, vp(R), ldr, ctypes.byref(r), vp(stream)))
         return r.value
 
+    def server(self, hbm_budget_bytes: int = 0, max_active: int = 0) -> "Server":
+        return Server(self, hbm_budget_bytes, max_active)
+
     def echelonise_batch(self, problems, on_device: bool = False, stream: int = 0, block_rows=0, block_cols=0,
                          profile=False):
         """problems: list of (A, p) with A a host numpy array (on_device=False) or
@@ -234,3 +237,61 @@ class Library:
                                         outs, sts)
         res = [Result(self.lib, outs[t]) if outs[t] else None for t in range(cnt)]
         return res, [int(sts[t]) for t in range(cnt)]
+
+
+class Server:
+    """Owns one gfech_server* (continuous batching of elimination requests)."""
+
+    def __init__(self, lib: "Library", hbm_budget_bytes: int = 0, max_active: int = 0):
+        self._lib = lib.lib
+        cfg = _abi.ServerCfg()
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.max_active = int(max_active)
+        out = ctypes.c_void_p()
+        st = self._lib.gfech_server_create(ctypes.byref(cfg), ctypes.byref(out))
+        if st != _abi.GFECH_OK:
+            raise GfechError(st, self._lib.gfech_last_error().decode())
+        self._h = out
+
+    def _check(self, st):
+        if st != _abi.GFECH_OK:
+            raise GfechError(st, self._lib.gfech_last_error().decode())
+
+    def submit(self, A, p: int) -> int:
+        """A: host numpy array (m x n uint8).  Returns the ticket."""
+        A = np.ascontiguousarray(np.asarray(A, np.uint8))
+        m, n = A.shape
+        pr = _abi.Problem()
+        pr.A = A.ctypes.data if A.size else 0
+        pr.m, pr.n, pr.lda, pr.p = m, n, max(n, 1), p
+        t = ctypes.c_uint64()
+        self._check(self._lib.gfech_server_submit(self._h, ctypes.byref(pr), 0, ctypes.byref(t)))
+        return t.value
+
+    def submit_dev(self, ptr: int, m: int, n: int, lda: int, p: int) -> int:
+        """ptr: device address of an m x n uint8 matrix.  Returns the ticket."""
+        pr = _abi.Problem()
+        pr.A = ptr
+        pr.m, pr.n, pr.lda, pr.p = m, n, lda, p
+        t = ctypes.c_uint64()
+        self._check(self._lib.gfech_server_submit(self._h, ctypes.byref(pr), 1, ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """The Result when finished, else None."""
+        out = ctypes.c_void_p()
+        self._check(self._lib.gfech_server_poll(self._h, ticket, ctypes.byref(out)))
+        return Result(self._lib, out.value) if out.value else None
+
+    def wait(self, ticket: int) -> Result:
+        out = ctypes.c_void_p()
+        self._check(self._lib.gfech_server_wait(self._h, ticket, ctypes.byref(out)))
+        return Result(self._lib, out.value)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.gfech_server_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        self.close()

@@ -13,7 +13,7 @@ SOURCES = [os.path.join(CSRC, f) for f in ("hip_backend.hip", "chief.cpp", "api.
 HEADERS = [os.path.join(CSRC, f) for f in ("backend.h", "chief.h")] + [os.path.join(ROOT, "include", "gfech.h")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed-fp32 instructions are kept out of every kernel
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 

@@ -1,11 +1,16 @@
 // C ABI of libgfech (declared in include/gfech.h): argument checks, host /
 // device staging, block-size choice and the result getters.  All arithmetic
 // runs in the backend's kernels through the Chief.
+#include <chrono>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/gfech.h"
@@ -38,9 +43,6 @@ bool is_prime(uint32_t p) {
     return true;
 }
 
-// Block sizes (Section 3.1: roughly square blocks).  Matrices up to the
-// single-block limit are one block: one ECH then does the whole job.  Blocks
-// of at most 512 rows keep every ECH on the register-panel kernel.
 // Blocking (Section 3.1).  Up to 512 x 512 the whole matrix is one block
 // (one ECH job).  Larger matrices get blocks of 256 rows and 2048 columns:
 // the ECH jobs on the critical path stay short (their cost grows with the
@@ -531,6 +533,239 @@ gfech_status gfech_ech_dev(const uint8_t* H, int64_t rows, int64_t cols, int64_t
     be->set_stream(nullptr);
     *rank = r;
     return be->error() ? fail(GFECH_E_DEVICE, "device error") : GFECH_OK;
+}
+
+// ---------------------------------------------------------------- serving
+
+struct gfech_server {
+    struct Req {
+        uint64_t ticket = 0;
+        gfech::Problem pr;
+        uint8_t* input = nullptr;     // device copy, owned until the request finishes
+        size_t footprint = 0;
+    };
+    gfech::Backend* be = nullptr;
+    void* stream = nullptr;
+    size_t budget = 0;
+    int32_t max_active = 0;
+    std::mutex mu;                    // queue, running, finished, stop
+    std::condition_variable work, done;
+    std::deque<Req> queue;
+    std::map<int64_t, Req> running;   // engine id -> request
+    std::map<uint64_t, std::pair<gfech_status, gfech_result*>> finished;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::unique_ptr<gfech::Engine> eng;   // used with g_mu held
+    std::thread worker;
+
+    // admit what fits, advance every active problem by one phase, hand out
+    // the finished ones; the backend is used with g_mu held
+    bool iterate() {
+        std::lock_guard<std::mutex> lk(g_mu);
+        be->set_stream(stream);
+        {
+            std::lock_guard<std::mutex> q(mu);
+            while (!queue.empty() && (max_active <= 0 || (int32_t)eng->active() < max_active) &&
+                   (eng->active() == 0 || eng->bytes_in_use() + queue.front().footprint <= budget)) {
+                Req r = queue.front();
+                int st = 0;
+                const int64_t id = eng->add(r.pr, &st);
+                if (id < 0) {
+                    if (eng->active() > 0) break;            // wait until memory frees up
+                    queue.pop_front();
+                    be->release(r.input);
+                    finished[r.ticket] = {GFECH_E_NOMEM, nullptr};
+                    done.notify_all();
+                    continue;
+                }
+                queue.pop_front();
+                running[id] = r;
+            }
+        }
+        if (eng->active()) eng->step();
+        std::vector<gfech::Engine::Done> fin = eng->take_done();
+        if (!fin.empty()) {
+            std::lock_guard<std::mutex> q(mu);
+            for (auto& d : fin) {
+                auto it = running.find(d.id);
+                if (it == running.end()) continue;
+                be->release(it->second.input);
+                gfech_result* res = nullptr;
+                if (d.result) {
+                    res = new gfech_result();
+                    res->r = std::move(d.result);
+                }
+                finished[it->second.ticket] = {d.status ? (d.status == 4 ? GFECH_E_NOMEM : GFECH_E_DEVICE) : GFECH_OK,
+                                               res};
+                running.erase(it);
+            }
+            done.notify_all();
+        }
+        be->set_stream(nullptr);
+        return eng->active() > 0;
+    }
+
+    void loop() {
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> q(mu);
+                work.wait(q, [&] { return stop || !queue.empty() || !running.empty(); });
+                if (stop && running.empty()) break;
+            }
+            iterate();
+        }
+    }
+};
+
+gfech_status gfech_server_create(const gfech_server_cfg* cfg, gfech_server** out) {
+    if (!out) return fail(GFECH_E_ARG, "out is NULL");
+    *out = nullptr;
+    gfech_status st = GFECH_OK;
+    std::unique_ptr<gfech_server> s(new gfech_server());
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        s->be = get_backend(&st);
+        if (!s->be) return st;
+        s->stream = s->be->create_stream();
+        s->eng.reset(new gfech::Engine(*s->be));
+    }
+    s->budget = (cfg && cfg->hbm_budget_bytes > 0) ? (size_t)cfg->hbm_budget_bytes : ((size_t)200 << 30);
+    s->max_active = cfg ? cfg->max_active : 0;
+    gfech_server* raw = s.get();
+    s->worker = std::thread([raw] { raw->loop(); });
+    *out = s.release();
+    return GFECH_OK;
+}
+
+gfech_status gfech_server_submit(gfech_server* s, const gfech_problem* prob, int32_t input_on_device,
+                                 uint64_t* ticket) {
+    if (!s || !prob || !ticket) return fail(GFECH_E_ARG, "null argument");
+    *ticket = 0;
+    const int64_t m = prob->m, n = prob->n, lda = prob->lda;
+    const uint32_t p = prob->p;
+    gfech_status st = check_common(m, n, lda, p, prob->A);
+    if (st) return st;
+    if (!input_on_device) {
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t j = 0; j < n; ++j)
+                if (prob->A[i * lda + j] >= p) return fail(GFECH_E_RANGE, "entry >= p");
+    }
+    gfech_server::Req r;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        s->be->set_stream(s->stream);
+        if (input_on_device && m > 0 && n > 0) {
+            const int64_t bad = s->be->count_out_of_range(prob->A, m, n, lda, (int32_t)p);
+            if (bad != 0) {
+                s->be->set_stream(nullptr);
+                return fail(bad > 0 ? GFECH_E_RANGE : GFECH_E_DEVICE, bad > 0 ? "entry >= p" : "device error");
+            }
+        }
+        // the request owns a packed device copy of its input
+        if (m > 0 && n > 0) {
+            r.input = (uint8_t*)s->be->alloc((size_t)(m * n));
+            if (!r.input) {
+                s->be->set_stream(nullptr);
+                return fail(GFECH_E_NOMEM, "device allocation of the input failed");
+            }
+            if (input_on_device && lda == n) {
+                s->be->copy(r.input, prob->A, (size_t)(m * n));
+            } else if (input_on_device) {
+                for (int64_t i = 0; i < m; ++i) s->be->copy(r.input + i * n, prob->A + i * lda, (size_t)n);
+            } else if (lda == n) {
+                s->be->upload(r.input, prob->A, (size_t)(m * n));
+            } else {
+                std::vector<uint8_t> tmp((size_t)(m * n));
+                for (int64_t i = 0; i < m; ++i) memcpy(tmp.data() + i * n, prob->A + i * lda, (size_t)n);
+                s->be->upload(r.input, tmp.data(), (size_t)(m * n));
+            }
+        }
+        s->be->set_stream(nullptr);
+        r.pr.A = r.input;
+        r.pr.m = m;
+        r.pr.n = n;
+        r.pr.lda = std::max<int64_t>(n, 1);
+        r.pr.p = (int32_t)p;
+        choose_blocks(m, n, nullptr, r.pr.row_blocks, r.pr.col_blocks);
+        r.footprint = s->eng->footprint(r.pr);
+    }
+    if (r.footprint > s->budget) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        s->be->release(r.input);
+        return fail(GFECH_E_TOO_BIG, "the problem alone exceeds the memory budget");
+    }
+    {
+        std::lock_guard<std::mutex> q(s->mu);
+        r.ticket = s->next_ticket++;
+        *ticket = r.ticket;
+        s->queue.push_back(r);
+    }
+    s->work.notify_all();
+    return GFECH_OK;
+}
+
+namespace {
+// with s->mu held: the outcome of a ticket, if there is one
+gfech_status take_finished(gfech_server* s, uint64_t ticket, gfech_result** out, bool* known) {
+    auto it = s->finished.find(ticket);
+    if (it != s->finished.end()) {
+        const gfech_status st = it->second.first;
+        *out = it->second.second;
+        s->finished.erase(it);
+        *known = true;
+        return st == GFECH_OK ? GFECH_OK : fail(st, "request failed");
+    }
+    *known = false;
+    for (auto& r : s->queue) if (r.ticket == ticket) *known = true;
+    for (auto& kv : s->running) if (kv.second.ticket == ticket) *known = true;
+    return GFECH_OK;
+}
+}  // namespace
+
+gfech_status gfech_server_poll(gfech_server* s, uint64_t ticket, gfech_result** out) {
+    if (!s || !out) return fail(GFECH_E_ARG, "null argument");
+    *out = nullptr;
+    std::lock_guard<std::mutex> q(s->mu);
+    bool known = false;
+    gfech_status st = take_finished(s, ticket, out, &known);
+    if (!known) return fail(GFECH_E_ARG, "unknown ticket");
+    return st;
+}
+
+gfech_status gfech_server_wait(gfech_server* s, uint64_t ticket, gfech_result** out) {
+    if (!s || !out) return fail(GFECH_E_ARG, "null argument");
+    *out = nullptr;
+    std::unique_lock<std::mutex> q(s->mu);
+    for (;;) {
+        bool known = false;
+        gfech_status st = take_finished(s, ticket, out, &known);
+        if (!known) return fail(GFECH_E_ARG, "unknown ticket");
+        if (*out || st != GFECH_OK) return st;
+        s->done.wait(q);
+    }
+}
+
+void gfech_server_destroy(gfech_server* s) {
+    if (!s) return;
+    // queued requests are dropped, running ones finish (locks: g_mu before mu, never the reverse)
+    std::deque<gfech_server::Req> dropped;
+    {
+        std::lock_guard<std::mutex> q(s->mu);
+        s->stop = true;
+        dropped.swap(s->queue);
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (auto& r : dropped) s->be->release(r.input);
+    }
+    s->work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto& kv : s->finished) delete kv.second.second;
+    s->finished.clear();
+    s->eng.reset();
+    s->be->destroy_stream(s->stream);
+    delete s;
 }
 
 const char* gfech_strerror(gfech_status s) {

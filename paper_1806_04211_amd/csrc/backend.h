@@ -76,6 +76,8 @@ struct EchDesc {
 // Index-list update used by Extend / UNH (Section 4.2) and ClearDown's UNH:
 //   append[t]  = add + map[pick[t]]   for t < npick   (new elements, in pick order)
 //   keep_out[s] = map[keep[s]]        for s < nkeep   (the remaining complement)
+// A null pick or keep means the identity (t, s); a null map means the
+// identity too (so map == pick == nullptr writes add + t).
 // keep_out must not alias map.
 struct ListDesc {
     int32_t npick = 0, nkeep = 0, add = 0;
@@ -116,6 +118,9 @@ public:
     virtual int64_t count_out_of_range(const uint8_t* A, int64_t m, int64_t n, int64_t lda, int32_t p) = 0;
     // stream for subsequent work (a hipStream_t for the HIP backend)
     virtual void set_stream(void* stream) { (void)stream; }
+    // a stream of the library's own (default priority), and its release
+    virtual void* create_stream() { return nullptr; }
+    virtual void destroy_stream(void* stream) { (void)stream; }
     // Two lanes of work: lane 0 is the caller's stream, lane 1 a second stream
     // whose work may overlap lane 0's.  mark() records the point reached by a
     // lane's queued work; wait_mark() makes a lane wait for such a point.

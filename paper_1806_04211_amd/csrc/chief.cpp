@@ -240,15 +240,16 @@ public:
                 g.ldd = br.ldC;
                 ops.gather.push_back(g);
             }
-            std::vector<int32_t> io(ai);
-            std::iota(io.begin(), io.end(), 0);
-            if (ai) be_.upload(br.U[0], io.data(), sizeof(int32_t) * ai);
+            ListDesc l;                       // U = 0 .. a_i - 1
+            l.npick = (int32_t)ai;
+            l.append = br.U[0];
+            ops.lists.push_back(l);
         }
         for (int j = 0; j < b_; ++j) {
-            int64_t bj = pr_.col_blocks[j];
-            std::vector<int32_t> io(bj);
-            std::iota(io.begin(), io.end(), 0);
-            be_.upload(cols_[j].Gbar[0], io.data(), sizeof(int32_t) * bj);
+            ListDesc l;                       // Gamma-bar = 0 .. b_j - 1
+            l.npick = pr_.col_blocks[j];
+            l.append = cols_[j].Gbar[0];
+            ops.lists.push_back(l);
         }
     }
 
@@ -912,72 +913,101 @@ void flush(Backend& be, Ops& ops, Stats& st) {
 
 }  // namespace
 
-int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::unique_ptr<Result>>& out,
-              std::string* err, int profile) {
-    if (profile) {
-        be.take_profile();
-        be.set_profile(profile);
-    }
-    Stats shared;
-    std::vector<Stats> st(probs.size());
-    std::vector<std::unique_ptr<Plan>> plans;
-    plans.reserve(probs.size());
-    size_t total = 0;
-    std::vector<size_t> base_off;
-    int64_t ncounts = 0;
-    std::vector<int64_t> count_off;
-    int maxL = 0;
-    for (size_t q = 0; q < probs.size(); ++q) {
-        plans.emplace_back(new Plan(be, probs[q], st[q]));
-        size_t sz = plans.back()->plan_memory();
-        base_off.push_back(total);
-        total += (sz + kAlign - 1) / kAlign * kAlign;
-        count_off.push_back(ncounts);
-        ncounts += plans.back()->blockcols();
-        maxL = std::max(maxL, plans.back()->layers());
-    }
-    // GFECH_SEPARATE_BUFFERS=1: every sub-buffer is its own allocation, so a
-    // bounds-checking backend can tell any overrun of one buffer into the next
-    const char* sep_env = getenv("GFECH_SEPARATE_BUFFERS");
-    const bool separate = sep_env && sep_env[0] == '1';
-    std::vector<void*> pieces;
-    uint8_t* arena = separate ? nullptr : (uint8_t*)be.alloc(std::max<size_t>(total, 1));
-    int32_t* counts = be.counts_buffer((size_t)std::max<int64_t>(ncounts, 1));
-    if ((!separate && !arena) || !counts) {
-        be.release(arena);
-        be.release_counts(counts);
-        if (err) *err = "device allocation of the block arena failed";
-        return 4;
-    }
-    std::vector<int32_t> hcounts(std::max<int64_t>(ncounts, 1));
-    Ops ops;
-    for (size_t q = 0; q < plans.size(); ++q) {
-        if (separate) {
-            std::map<size_t, uint8_t*> where;
-            for (auto& sl : plans[q]->slots()) {
-                uint8_t* ptr = (uint8_t*)be.alloc(std::max<size_t>(sl.second, 1));
-                if (!ptr) {
-                    for (void* v : pieces) be.release(v);
-                    be.release_counts(counts);
-                    if (err) *err = "device allocation of a sub-buffer failed";
-                    return 4;
-                }
-                pieces.push_back(ptr);
-                where[sl.first] = ptr;
-            }
-            plans[q]->bind([&](size_t off) { return where.at(off); }, counts + count_off[q]);
-        } else {
-            uint8_t* base = arena + base_off[q];
-            plans[q]->bind([base](size_t off) { return base + off; }, counts + count_off[q]);
-        }
-        plans[q]->init(ops);
-    }
-    flush(be, ops, shared);
+// ============================================================================ engine
 
-    // Step 1, layer by layer, on two lanes (see the header comment)
-    int bulk_done = -1;      // lane 1's mark after the last bulk part issued
-    Ops b1, b3, b4, b6;      // the bulk part of the previous layer, not issued yet
-    auto issue_bulk = [&](int ready) {
+namespace {
+
+enum Phase { kStep1, kAssemble, kClearUp, kFinished };
+
+// capacity of the pivot-count pool: one int per block column of each active problem
+constexpr size_t kCountsCap = 1 << 18;
+
+}  // namespace
+
+struct Engine::Impl {
+    struct Job {
+        int64_t id = 0;
+        Problem pr;
+        Stats st;
+        std::unique_ptr<Plan> plan;
+        uint8_t* arena = nullptr;
+        std::vector<void*> pieces;
+        size_t counts_off = 0, counts_n = 0;
+        Phase phase = kStep1;
+        int layer = 0;
+        size_t cu_step = 0;
+        std::unique_ptr<Result> res;
+        size_t bytes = 0;
+        int status = 0;
+    };
+
+    Impl(Backend& b, const Engine* e) : be(b), owner(e) {
+        const char* gr = getenv("GFECH_CLEARUP_GROUP");
+        group_rank = gr ? std::max<int64_t>(1, atoll(gr)) : 2048;
+        counts = be.counts_buffer(kCountsCap);
+        if (counts) holes.push_back({0, kCountsCap});
+        hcounts.resize(kCountsCap);
+    }
+    ~Impl() {
+        be.sync();
+        for (auto& j : jobs) release(*j);
+        if (counts) be.release_counts(counts);
+    }
+
+    Backend& be;
+    const Engine* owner;
+    Stats shared;
+    std::vector<std::unique_ptr<Job>> jobs;
+    Ops init_ops;              // the initial jobs of problems added since the last step
+    std::vector<Done> done;
+    int64_t next_id = 0;
+    size_t bytes_in_use = 0;
+    int bulk_done = -1;        // lane 1's mark after the last bulk part issued
+    Ops b1, b3, b4, b6;        // the bulk part of the previous layer, not issued yet
+    int32_t* counts = nullptr;
+    std::vector<std::pair<size_t, size_t>> holes;   // free ranges of the counts pool
+    size_t counts_high = 0;
+    std::vector<int32_t> hcounts;
+    int64_t group_rank = 2048;
+
+    bool take_counts(size_t n, size_t* off) {
+        n = std::max<size_t>(n, 1);
+        for (auto& h : holes) {
+            if (h.second >= n) {
+                *off = h.first;
+                h.first += n;
+                h.second -= n;
+                counts_high = std::max(counts_high, *off + n);
+                return true;
+            }
+        }
+        return false;
+    }
+    void give_counts(size_t off, size_t n) {
+        n = std::max<size_t>(n, 1);
+        holes.push_back({off, n});
+        std::sort(holes.begin(), holes.end());
+        std::vector<std::pair<size_t, size_t>> merged;
+        for (auto& h : holes) {
+            if (!merged.empty() && merged.back().first + merged.back().second == h.first) merged.back().second += h.second;
+            else if (h.second) merged.push_back(h);
+        }
+        holes.swap(merged);
+    }
+
+    void release(Job& j) {
+        if (j.plan) j.plan->release_maps();
+        be.release(j.arena);
+        for (void* v : j.pieces) be.release(v);
+        j.arena = nullptr;
+        j.pieces.clear();
+        if (j.counts_n) give_counts(j.counts_off, j.counts_n);
+        j.counts_n = 0;
+        bytes_in_use -= j.bytes;
+        j.bytes = 0;
+    }
+
+    void issue_bulk(int ready) {
         if (b1.empty() && b3.empty() && b4.empty() && b6.empty()) return;
         be.set_lane(1);
         be.wait_mark(1, ready);
@@ -987,127 +1017,290 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
         flush(be, b6, shared);
         bulk_done = be.mark(1);
         be.set_lane(0);
-    };
-    for (int L = 0; L < maxL; ++L) {
-        for (auto& pl : plans) pl->begin_layer(L);
-        for (auto& pl : plans) pl->cd_extract(ops);
-        flush(be, ops, shared);
-        for (auto& pl : plans) pl->cd_mad(ops);
-        flush(be, ops, shared);
-        // the previous layer's bulk part starts after this layer's ClearDown
-        // MADs and is issued after this layer's ECHs, so the ECHs (one
-        // workgroup each) reach the device first: issued behind a large
-        // product, an ECH would wait for that product's last tiles
-        const int ready = be.mark(0);
-        bool any = false;
-        for (auto& pl : plans) { pl->cd_ech(ops, false); any = any || pl->any_ech(); }
-        flush(be, ops, shared);
-        issue_bulk(ready);
-        for (auto& pl : plans) pl->clear_counts();
-        if (any) {
-            be.read_counts(hcounts.data(), counts, (size_t)ncounts);
-            shared.syncs++;
-            if (be.error()) break;
-            bool again = false;
-            for (size_t q = 0; q < plans.size(); ++q)
-                again = plans[q]->absorb_counts(hcounts.data() + count_off[q], false) || again;
-            if (again) {
-                for (auto& pl : plans) pl->cd_ech(ops, true);
-                flush(be, ops, shared);
-                be.read_counts(hcounts.data(), counts, (size_t)ncounts);
-                shared.syncs++;
-                if (be.error()) break;
-                for (size_t q = 0; q < plans.size(); ++q) plans[q]->absorb_counts(hcounts.data() + count_off[q], true);
+    }
+
+    void read_counts() {
+        be.read_counts(hcounts.data(), counts, std::max<size_t>(counts_high, 1));
+        shared.syncs++;
+    }
+
+    int64_t add(const Problem& pr, int* status) {
+        std::unique_ptr<Job> j(new Job());
+        j->pr = pr;
+        j->plan.reset(new Plan(be, j->pr, j->st));
+        const size_t sz = j->plan->plan_memory();
+        j->counts_n = std::max<size_t>(j->plan->blockcols(), 1);
+        if (!counts || !take_counts(j->counts_n, &j->counts_off)) {
+            j->counts_n = 0;
+            if (status) *status = 4;
+            return -1;
+        }
+        // GFECH_SEPARATE_BUFFERS=1: every sub-buffer is its own allocation, so a
+        // bounds-checking backend can tell any overrun of one buffer into the next
+        const char* sep_env = getenv("GFECH_SEPARATE_BUFFERS");
+        if (sep_env && sep_env[0] == '1') {
+            std::map<size_t, uint8_t*> where;
+            for (auto& sl : j->plan->slots()) {
+                uint8_t* ptr = (uint8_t*)be.alloc(std::max<size_t>(sl.second, 1));
+                if (!ptr) {
+                    release(*j);
+                    if (status) *status = 4;
+                    return -1;
+                }
+                j->pieces.push_back(ptr);
+                where[sl.first] = ptr;
+            }
+            j->plan->bind([&](size_t off) { return where.at(off); }, counts + j->counts_off);
+        } else {
+            j->arena = (uint8_t*)be.alloc(std::max<size_t>(sz, 1));
+            if (!j->arena) {
+                release(*j);
+                if (status) *status = 4;
+                return -1;
+            }
+            uint8_t* base = j->arena;
+            j->plan->bind([base](size_t off) { return base + off; }, counts + j->counts_off);
+        }
+        j->bytes = owner->footprint(j->pr);
+        bytes_in_use += j->bytes;
+        j->plan->init(init_ops);
+        j->id = next_id++;
+        j->phase = j->plan->layers() > 0 ? kStep1 : kAssemble;
+        jobs.push_back(std::move(j));
+        if (status) *status = 0;
+        return jobs.back()->id;
+    }
+
+    void fail_all(int rc) {
+        be.sync();
+        for (auto& j : jobs) {
+            release(*j);
+            Done d;
+            d.id = j->id;
+            d.status = rc;
+            done.push_back(std::move(d));
+        }
+        jobs.clear();
+    }
+
+    size_t step() {
+        if (be.error()) {
+            fail_all(be.error());
+            return 0;
+        }
+        Ops ops;
+        flush(be, init_ops, shared);
+        std::vector<Plan*> s1;
+        for (auto& j : jobs)
+            if (j->phase == kStep1) s1.push_back(j->plan.get());
+        // ---- Step 1: one layer of every problem in it (see the header comment for the lanes)
+        if (!s1.empty()) {
+            for (size_t q = 0; q < jobs.size(); ++q)
+                if (jobs[q]->phase == kStep1) jobs[q]->plan->begin_layer(jobs[q]->layer);
+            for (Plan* pl : s1) pl->cd_extract(ops);
+            flush(be, ops, shared);
+            for (Plan* pl : s1) pl->cd_mad(ops);
+            flush(be, ops, shared);
+            // the previous layer's bulk part starts after this layer's ClearDown
+            // MADs and is issued after this layer's ECHs, so the ECHs (one
+            // workgroup each) reach the device first: issued behind a large
+            // product, an ECH would wait for that product's last tiles
+            const int ready = be.mark(0);
+            bool any = false;
+            for (Plan* pl : s1) { pl->cd_ech(ops, false); any = any || pl->any_ech(); }
+            flush(be, ops, shared);
+            issue_bulk(ready);
+            for (Plan* pl : s1) pl->clear_counts();
+            if (any) {
+                read_counts();
+                if (be.error()) { fail_all(be.error()); return 0; }
+                bool again = false;
+                for (auto& j : jobs)
+                    if (j->phase == kStep1) again = j->plan->absorb_counts(hcounts.data() + j->counts_off, false) || again;
+                if (again) {
+                    for (Plan* pl : s1) pl->cd_ech(ops, true);
+                    flush(be, ops, shared);
+                    read_counts();
+                    if (be.error()) { fail_all(be.error()); return 0; }
+                    for (auto& j : jobs)
+                        if (j->phase == kStep1) j->plan->absorb_counts(hcounts.data() + j->counts_off, true);
+                }
+            }
+            // the UpdateRow products below read columns the previous bulk part wrote
+            if (bulk_done >= 0) be.wait_mark(0, bulk_done);
+            for (Plan* pl : s1) pl->ur1(ops, b1);
+            flush(be, ops, shared);
+            for (Plan* pl : s1) pl->cd_post(ops);
+            flush(be, ops, shared);
+            for (Plan* pl : s1) pl->cd_mad2(ops);
+            for (Plan* pl : s1) pl->ur3(ops, b3);
+            flush(be, ops, shared);
+            for (Plan* pl : s1) pl->cd_commit();
+            for (Plan* pl : s1) pl->ur4(ops, b4);
+            flush(be, ops, shared);
+            for (Plan* pl : s1) pl->ur6(ops, b6);
+            flush(be, ops, shared);
+            for (Plan* pl : s1) pl->ur_commit();
+            shared.layers++;
+            bool finished = false;
+            for (auto& j : jobs) {
+                if (j->phase != kStep1) continue;
+                j->st.layers++;
+                if (++j->layer >= j->plan->layers()) {
+                    j->phase = kAssemble;
+                    finished = true;
+                }
+            }
+            // a problem leaving Step 1 needs its last bulk part before the assembly
+            if (finished) {
+                issue_bulk(be.mark(0));
+                if (bulk_done >= 0) be.wait_mark(0, bulk_done);
+            }
+        } else {
+            issue_bulk(be.mark(0));
+            if (bulk_done >= 0) be.wait_mark(0, bulk_done);
+        }
+        if (be.error()) { fail_all(be.error()); return 0; }
+
+        // ---- assembly of the result (and Step 2, implicit), then Step 3's plan
+        std::vector<Job*> asmj;
+        for (auto& j : jobs)
+            if (j->phase == kAssemble) asmj.push_back(j.get());
+        if (!asmj.empty()) {
+            for (Job* j : asmj) {
+                j->res.reset(new Result());
+                j->res->be = &be;
+                if (!j->plan->assemble_lists(*j->res, ops)) j->status = 4;
+            }
+            flush(be, ops, shared);
+            for (Job* j : asmj) if (!j->status) j->plan->repack(*j->res, ops);
+            flush(be, ops, shared);
+            for (Job* j : asmj) if (!j->status) j->plan->repack_diag(*j->res, ops);
+            flush(be, ops, shared);
+            for (Job* j : asmj) if (!j->status) j->plan->k_assemble(*j->res, ops);
+            flush(be, ops, shared);
+            for (Job* j : asmj) {
+                if (!j->status) j->plan->plan_clearup(*j->res, group_rank);
+                j->phase = j->status ? kFinished : kClearUp;
+                j->cu_step = 0;
             }
         }
-        // the UpdateRow products below read columns the previous bulk part wrote
-        if (bulk_done >= 0) be.wait_mark(0, bulk_done);
-        for (auto& pl : plans) pl->ur1(ops, b1);
-        flush(be, ops, shared);
-        for (auto& pl : plans) pl->cd_post(ops);
-        flush(be, ops, shared);
-        for (auto& pl : plans) pl->cd_mad2(ops);
-        for (auto& pl : plans) pl->ur3(ops, b3);
-        flush(be, ops, shared);
-        for (auto& pl : plans) pl->cd_commit();
-        for (auto& pl : plans) pl->ur4(ops, b4);
-        flush(be, ops, shared);
-        for (auto& pl : plans) pl->ur6(ops, b6);
-        flush(be, ops, shared);
-        for (auto& pl : plans) pl->ur_commit();
-        shared.layers++;
-    }
-    issue_bulk(be.mark(0));
-    if (bulk_done >= 0) be.wait_mark(0, bulk_done);
-    int rc = be.error();
-    if (rc) {
-        be.release(arena);
-        for (void* v : pieces) be.release(v);
-        be.release_counts(counts);
-        if (err) *err = "device error during Step 1";
-        return rc;
-    }
-    // Step 2 is implicit (see the header comment); assembly and Step 3
-    std::vector<std::unique_ptr<Result>> res(plans.size());
-    for (size_t q = 0; q < plans.size(); ++q) {
-        res[q].reset(new Result());
-        res[q]->be = &be;
-        if (!plans[q]->assemble_lists(*res[q], ops)) {
-            flush(be, ops, shared);
+        // ---- Step 3: the next ClearUp launch of every problem in it
+        bool cu = false;
+        for (auto& j : jobs) {
+            if (j->phase != kClearUp) continue;
+            if (j->cu_step < j->plan->clearup_steps()) {
+                j->plan->clearup_step(j->cu_step++, ops);
+                cu = true;
+            }
+        }
+        if (cu) flush(be, ops, shared);
+        for (auto& j : jobs)
+            if (j->phase == kClearUp && j->cu_step >= j->plan->clearup_steps()) j->phase = kFinished;
+
+        // ---- finished problems: their work must be complete before their memory is reused
+        bool fin = false;
+        for (auto& j : jobs) fin = fin || j->phase == kFinished;
+        if (fin) {
             be.sync();
-            for (auto& pl : plans) pl->release_maps();
-            be.release(arena);
-            for (void* v : pieces) be.release(v);
-            be.release_counts(counts);
-            if (err) *err = "device allocation of the result failed";
-            return 4;
+            const int rc = be.error();
+            std::vector<std::unique_ptr<Job>> keep;
+            for (auto& j : jobs) {
+                if (j->phase != kFinished) {
+                    keep.push_back(std::move(j));
+                    continue;
+                }
+                release(*j);
+                Done d;
+                d.id = j->id;
+                d.status = rc ? rc : j->status;
+                if (!d.status) {
+                    Stats st = j->st;
+                    st.launches = shared.launches;
+                    st.gemms = shared.gemms;
+                    st.syncs = shared.syncs;
+                    j->res->stats = st;
+                    d.result = std::move(j->res);
+                }
+                done.push_back(std::move(d));
+            }
+            jobs.swap(keep);
+        }
+        return jobs.size();
+    }
+};
+
+Engine::Engine(Backend& be) : impl_(new Impl(be, this)) {}
+Engine::~Engine() = default;
+
+size_t Engine::footprint(const Problem& pr) const {
+    Stats st;
+    Plan plan(impl_->be, pr, st);
+    size_t bytes = plan.plan_memory() + kAlign;
+    // the result (at most rank min(m, n)) and the assembly maps
+    const size_t r = (size_t)std::min(pr.m, pr.n);
+    bytes += r * (size_t)((pr.n + (int64_t)r + 63) / 64 * 64) + (size_t)(pr.m - (int64_t)r) * r;
+    bytes += sizeof(int32_t) * (size_t)(3 * pr.m + 3 * pr.n + 4 * r) + 16 * kAlign;
+    return bytes;
+}
+int64_t Engine::add(const Problem& pr, int* status) { return impl_->add(pr, status); }
+size_t Engine::step() { return impl_->step(); }
+size_t Engine::active() const { return impl_->jobs.size(); }
+size_t Engine::bytes_in_use() const { return impl_->bytes_in_use; }
+std::vector<Engine::Done> Engine::take_done() {
+    std::vector<Done> d;
+    d.swap(impl_->done);
+    return d;
+}
+const Stats& Engine::totals() const { return impl_->shared; }
+
+int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::unique_ptr<Result>>& out,
+              std::string* err, int profile) {
+    if (profile) {
+        be.take_profile();
+        be.set_profile(profile);
+    }
+    std::vector<std::unique_ptr<Result>> res(probs.size());
+    int rc = 0;
+    {
+        Engine eng(be);
+        std::vector<int64_t> ids;
+        for (const Problem& pr : probs) {
+            int st = 0;
+            const int64_t id = eng.add(pr, &st);
+            if (id < 0) {
+                if (err) *err = "device allocation of the block arena failed";
+                rc = st ? st : 4;
+                break;
+            }
+            ids.push_back(id);
+        }
+        while (!rc && eng.active()) eng.step();
+        for (auto& d : eng.take_done()) {
+            if (d.status && !rc) {
+                rc = d.status;
+                if (err) *err = rc == 4 ? "device allocation of the result failed" : "device error";
+            }
+            if (d.result && d.id < (int64_t)res.size()) res[(size_t)d.id] = std::move(d.result);
+        }
+        if (!rc) {
+            be.sync();
+            rc = be.error();
+            if (rc && err) *err = "device error";
         }
     }
-    flush(be, ops, shared);
-    for (size_t q = 0; q < plans.size(); ++q) plans[q]->repack(*res[q], ops);
-    flush(be, ops, shared);
-    for (size_t q = 0; q < plans.size(); ++q) plans[q]->repack_diag(*res[q], ops);
-    flush(be, ops, shared);
-    for (size_t q = 0; q < plans.size(); ++q) plans[q]->k_assemble(*res[q], ops);
-    flush(be, ops, shared);
-    // Step 3: the plans' ClearUp launches in lockstep
-    const char* gr_env = getenv("GFECH_CLEARUP_GROUP");
-    const int64_t group_rank = gr_env ? std::max<int64_t>(1, atoll(gr_env)) : 2048;
-    size_t nsteps = 0;
-    for (size_t q = 0; q < plans.size(); ++q) {
-        plans[q]->plan_clearup(*res[q], group_rank);
-        nsteps = std::max(nsteps, plans[q]->clearup_steps());
-    }
-    for (size_t s = 0; s < nsteps; ++s) {
-        for (auto& pl : plans) pl->clearup_step(s, ops);
-        flush(be, ops, shared);
-    }
-    be.sync();
-    rc = be.error();
     Backend::Profile prof;
     if (profile) {
         prof = be.take_profile();
         be.set_profile(0);
     }
-    for (auto& pl : plans) pl->release_maps();
-    be.release(arena);
-    for (void* v : pieces) be.release(v);
-    be.release_counts(counts);
-    if (rc) {
-        if (err) *err = "device error during assembly / Step 3";
-        return rc;
-    }
-    for (size_t q = 0; q < plans.size(); ++q) {
-        Stats s = st[q];
-        s.layers = shared.layers;
-        s.launches = shared.launches;
-        s.gemms = shared.gemms;
-        s.syncs = shared.syncs;
+    if (rc) return rc;
+    for (size_t q = 0; q < res.size(); ++q) {
+        if (!res[q]) return 6;
         for (int k = 0; k < 3; ++k) {
-            s.kernel_ms[k] = prof.ms[k];
-            s.kernel_launches[k] = prof.launches[k];
+            res[q]->stats.kernel_ms[k] = prof.ms[k];
+            res[q]->stats.kernel_launches[k] = prof.launches[k];
         }
-        res[q]->stats = s;
         out.push_back(std::move(res[q]));
     }
     return 0;

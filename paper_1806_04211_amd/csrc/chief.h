@@ -61,6 +61,42 @@ struct Problem {
 // target <= 0 means a single block.
 std::vector<int32_t> even_blocks(int64_t total, int64_t target);
 
+// The method on any number of independent problems that may join at any
+// time.  Each problem is a state machine (Step 1 layer by layer, then the
+// assembly of the result and Step 2, then Step 3's ClearUp launches one per
+// iteration); one call of step() advances every active problem by one phase,
+// and the jobs of all problems in the same phase share launches.  Problems
+// added between calls of step() join the next iteration (continuous batching).
+class Engine {
+public:
+    explicit Engine(Backend& be);
+    ~Engine();
+    // Device bytes a problem holds while active (its block arena, the result,
+    // the assembly maps), an upper bound.
+    size_t footprint(const Problem& pr) const;
+    // Adds a problem (copied; its input must stay valid until it finishes).
+    // Returns its id (>= 0), or -1 with *status set (device memory exhausted).
+    int64_t add(const Problem& pr, int* status);
+    // One iteration; returns the number of problems still active.
+    size_t step();
+    size_t active() const;
+    size_t bytes_in_use() const;
+    // Problems finished since the last call: id, status (0 or a backend error
+    // code) and the result (null on error).
+    struct Done {
+        int64_t id = -1;
+        int status = 0;
+        std::unique_ptr<Result> result;
+    };
+    std::vector<Done> take_done();
+    // launches, gemms, syncs and layers of every iteration so far
+    const Stats& totals() const;
+
+private:
+    struct Impl;
+    std::unique_ptr<Impl> impl_;
+};
+
 // Run the whole method on a set of independent problems in lockstep (their
 // jobs share launches).  Returns 0 or a backend error code; results are
 // appended to `out` in problem order.

@@ -1365,10 +1365,14 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_fill(Src src) {
 template <class Src>
 __global__ void __launch_bounds__(SMALL_THREADS) k_lists(Src src) {
     const ListDesc l = src.get(blockIdx.y);
-    for (int t = blockIdx.x * SMALL_THREADS + threadIdx.x; t < l.npick; t += gridDim.x * SMALL_THREADS)
-        l.append[t] = l.add + l.map[l.pick ? l.pick[t] : t];
-    for (int s = blockIdx.x * SMALL_THREADS + threadIdx.x; s < l.nkeep; s += gridDim.x * SMALL_THREADS)
-        l.keep_out[s] = l.map[l.keep ? l.keep[s] : s];
+    for (int t = blockIdx.x * SMALL_THREADS + threadIdx.x; t < l.npick; t += gridDim.x * SMALL_THREADS) {
+        const int u = l.pick ? l.pick[t] : t;
+        l.append[t] = l.add + (l.map ? l.map[u] : u);
+    }
+    for (int s = blockIdx.x * SMALL_THREADS + threadIdx.x; s < l.nkeep; s += gridDim.x * SMALL_THREADS) {
+        const int u = l.keep ? l.keep[s] : s;
+        l.keep_out[s] = l.map ? l.map[u] : u;
+    }
 }
 
 // rank sort of distinct values: out[rank(t)] = add + (mode ? t : vals[t])
@@ -1551,6 +1555,20 @@ public:
         cur_ = stream_;
     }
     void set_lane(int lane) override { cur_ = lane == 1 ? lane1_ : stream_; }
+    void* create_stream() override {
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return st;
+    }
+    void destroy_stream(void* st) override {
+        if (!st) return;
+        sync_all();
+        HIP_OK(hipStreamSynchronize((hipStream_t)st));
+        HIP_OK(hipStreamDestroy((hipStream_t)st));
+    }
     int mark(int lane) override {
         hipEvent_t e = nullptr;
         if (!mark_pool_.empty()) {

@@ -25,7 +25,7 @@ def build(force: bool = False, extra_flags=()) -> str:
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < newest:
         os.makedirs(BUILD, exist_ok=True)
         tmp = LIB + f".tmp{os.getpid()}"
-        cmd = ["g++", "-O1", "-g", "-std=c++17", "-shared", "-fPIC", "-Wall", "-Wno-unused-function",
+        cmd = ["g++", "-O1", "-g", "-std=c++17", "-shared", "-fPIC", "-pthread", "-Wall", "-Wno-unused-function",
                *extra_flags, "-o", tmp, *SRCS]
         subprocess.check_call(cmd)
         os.replace(tmp, LIB)

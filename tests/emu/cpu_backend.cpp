@@ -188,16 +188,24 @@ public:
             if (l.npick) {
                 ok &= chk(l.append, sizeof(int32_t) * l.npick, "list append");
                 if (l.pick) ok &= chk(l.pick, sizeof(int32_t) * l.npick, "list pick");
-                for (int t = 0; ok && t < l.npick; ++t) ok &= chk(l.map + (l.pick ? l.pick[t] : t), 4, "list map");
+                if (l.map)
+                    for (int t = 0; ok && t < l.npick; ++t) ok &= chk(l.map + (l.pick ? l.pick[t] : t), 4, "list map");
             }
             if (l.nkeep) {
                 ok &= chk(l.keep_out, sizeof(int32_t) * l.nkeep, "list keep_out");
                 if (l.keep) ok &= chk(l.keep, sizeof(int32_t) * l.nkeep, "list keep");
-                for (int t = 0; ok && t < l.nkeep; ++t) ok &= chk(l.map + (l.keep ? l.keep[t] : t), 4, "list map");
+                if (l.map)
+                    for (int t = 0; ok && t < l.nkeep; ++t) ok &= chk(l.map + (l.keep ? l.keep[t] : t), 4, "list map");
             }
             if (!ok) continue;
-            for (int t = 0; t < l.npick; ++t) l.append[t] = l.add + l.map[l.pick ? l.pick[t] : t];
-            for (int s = 0; s < l.nkeep; ++s) l.keep_out[s] = l.map[l.keep ? l.keep[s] : s];
+            for (int t = 0; t < l.npick; ++t) {
+                const int u = l.pick ? l.pick[t] : t;
+                l.append[t] = l.add + (l.map ? l.map[u] : u);
+            }
+            for (int s = 0; s < l.nkeep; ++s) {
+                const int u = l.keep ? l.keep[s] : s;
+                l.keep_out[s] = l.map ? l.map[u] : u;
+            }
         }
     }
 
