@@ -64,6 +64,28 @@ def copy_calibration(torch, mib: int):
     print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
 
 
+PROFILE = os.path.join(ROOT, "profiles", "k_gemm_modp_40000_gf7.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1806_04211_amd", "csrc", "hip_backend.hip")
+
+
+def profiled_traffic():
+    """HBM bytes per MAD launch from the committed counter summary, when it was
+    taken on the current kernel source (same sha256); otherwise None."""
+    import hashlib
+    try:
+        fields = {}
+        for line in open(PROFILE):
+            if ":" in line and line.split(":", 1)[0].strip() in ("source_sha256", "traffic_bytes_per_launch"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        if fields.get("source_sha256") == sha and "traffic_bytes_per_launch" in fields:
+            return float(fields["traffic_bytes_per_launch"])
+    except OSError:
+        pass
+    return None
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     return xs[min(len(xs) - 1, int(round(q * (len(xs) - 1))))] if xs else 0.0
@@ -368,8 +390,9 @@ def main():
             "launches_small": breakdown["launches_small"]},
         "roofline": {"bound": "mfma", "kernel": "k_gemm_modp (MAD mod p, int8 MFMA)",
                      "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
-                     "frac": achieved / INT8_PEAK_TOPS, "traffic": None,
+                     "frac": achieved / INT8_PEAK_TOPS, "traffic": profiled_traffic(),
                      "per_launch": {"mac": mac_mad / max(mad_launches, 1),
+                                    "bytes": st["mad_bytes"] / max(mad_launches, 1),
                                     "avg_ms": mad_ms / max(mad_launches, 1)}},
         "check": {"rank": rank, "rank_expected": min(n, k)},
     }

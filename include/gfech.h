@@ -144,6 +144,10 @@ typedef struct gfech_stats {
      * kernel, the ECH kernel and the extract / riffle / list kernels */
     double ms_mad, ms_ech, ms_small;
     int64_t launches_mad, launches_ech, launches_small;
+    /* operand bytes of every MAD launched (A, B and C read once, D written
+     * once), summed over the launches of the engine run that produced this
+     * result */
+    double mad_bytes;
 } gfech_stats;
 gfech_status gfech_get_stats(const gfech_result* res, gfech_stats* stats);
 

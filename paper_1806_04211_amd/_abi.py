@@ -36,7 +36,8 @@ class Stats(ctypes.Structure):
                 ("layers", c_i64), ("echs", c_i64), ("gemms", c_i64), ("launches", c_i64), ("syncs", c_i64),
                 ("block_rows", c_i64), ("block_cols", c_i64),
                 ("ms_mad", ctypes.c_double), ("ms_ech", ctypes.c_double), ("ms_small", ctypes.c_double),
-                ("launches_mad", c_i64), ("launches_ech", c_i64), ("launches_small", c_i64)]
+                ("launches_mad", c_i64), ("launches_ech", c_i64), ("launches_small", c_i64),
+                ("mad_bytes", ctypes.c_double)]
 
 
 class ServerCfg(ctypes.Structure):

@@ -435,6 +435,7 @@ gfech_status gfech_get_stats(const gfech_result* res, gfech_stats* s) {
     s->launches_mad = t.kernel_launches[0];
     s->launches_ech = t.kernel_launches[1];
     s->launches_small = t.kernel_launches[2];
+    s->mad_bytes = t.mad_bytes;
     return GFECH_OK;
 }
 

@@ -906,7 +906,13 @@ void flush(Backend& be, Ops& ops, Stats& st) {
     if (!ops.fill.empty()) { be.fill(ops.fill); st.launches++; }
     if (!ops.lists.empty()) { be.lists(ops.lists); st.launches++; }
     if (!ops.sort.empty()) { be.sort(ops.sort); st.launches++; }
-    if (!ops.gemm.empty()) { be.gemm(ops.gemm); st.launches++; st.gemms += (int64_t)ops.gemm.size(); }
+    if (!ops.gemm.empty()) {
+        be.gemm(ops.gemm);
+        st.launches++;
+        st.gemms += (int64_t)ops.gemm.size();
+        for (const GemmDesc& g : ops.gemm)
+            st.mad_bytes += (double)g.M * g.K + (double)g.K * g.N + (g.C ? 2.0 : 1.0) * g.M * g.N;
+    }
     if (!ops.ech.empty()) { be.ech(ops.ech); st.launches++; }
     ops = Ops();
 }
@@ -1218,6 +1224,7 @@ struct Engine::Impl {
                     Stats st = j->st;
                     st.launches = shared.launches;
                     st.gemms = shared.gemms;
+                    st.mad_bytes = shared.mad_bytes;
                     st.syncs = shared.syncs;
                     j->res->stats = st;
                     d.result = std::move(j->res);

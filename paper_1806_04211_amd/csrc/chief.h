@@ -21,6 +21,7 @@ struct Stats {
     double urt_mad = 0;    // UpdateRowTrafo MADs / MULs on the transformation blocks
     double cu_mad = 0;     // ClearUp MADs (Step 3)
     double gather_bytes = 0;   // bytes moved by extracts / riffles / copies
+    double mad_bytes = 0;      // operand bytes of the MAD launches: A, B, C read once, D written once
     int64_t layers = 0, echs = 0, gemms = 0, launches = 0, syncs = 0;
     // kernel time by kind when profiling was requested (device events): gemm, ech, small jobs
     double kernel_ms[3] = {0, 0, 0};

@@ -9,6 +9,7 @@
 //  - k_gather, k_fill, k_lists, k_sort, k_range: extracts, riffles and the
 //                  index-list jobs (HBM-bound).
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cstdio>
@@ -1606,13 +1607,11 @@ public:
         }
         if (d.empty()) return;
         if (tiles > INT32_MAX) { note_error(hipErrorInvalidValue, "too many gemm tiles"); return; }
-        hipEvent_t e0 = prof_begin(0);
         if (d.size() <= (size_t)GEMM_ARG_CAP) {
             GemmArgSrc a;
             a.n = (int)d.size();
             for (size_t i = 0; i < d.size(); ++i) { a.m[i] = maps[i]; a.d[i] = d[i]; }
-            hipLaunchKernelGGL((k_gemm_modp<GemmArgSrc>), dim3((unsigned)tiles), dim3(GEMM_THREADS),
-                               gemm_lds_bytes(), cur_, a);
+            go(0, k_gemm_modp<GemmArgSrc>, dim3((unsigned)tiles), dim3(GEMM_THREADS), gemm_lds_bytes(), a);
         } else {
             // one upload: the tile maps, then the descriptors (256-byte aligned)
             const size_t mb = (maps.size() * sizeof(GemmTileMap) + 255) & ~(size_t)255;
@@ -1624,28 +1623,24 @@ public:
             a.n = (int)d.size();
             a.m = (const GemmTileMap*)dev;
             a.d = (const GemmDesc*)(dev + mb);
-            hipLaunchKernelGGL((k_gemm_modp<GemmPtrSrc>), dim3((unsigned)tiles), dim3(GEMM_THREADS),
-                               gemm_lds_bytes(), cur_, a);
+            go(0, k_gemm_modp<GemmPtrSrc>, dim3((unsigned)tiles), dim3(GEMM_THREADS), gemm_lds_bytes(), a);
         }
         HIP_OK(hipGetLastError());
-        prof_end(0, e0);
     }
 
     // launch `kernel` over descriptors: up to CAP by value, otherwise uploaded
     template <int CAP, typename D, typename KArg, typename KPtr>
     void launch_descs(const D* ds, size_t cnt, KArg karg, KPtr kptr, dim3 grid, dim3 block, size_t shm, int kind) {
-        hipEvent_t e0 = prof_begin(kind);
         if (cnt <= (size_t)CAP) {
             DescArg<D, CAP> a;
             for (size_t i = 0; i < cnt; ++i) a.d[i] = ds[i];
-            hipLaunchKernelGGL(karg, grid, block, shm, cur_, a);
+            go(kind, karg, grid, block, shm, a);
         } else {
             DescPtr<D> a;
             a.p = (const D*)put(ds, cnt * sizeof(D));
-            hipLaunchKernelGGL(kptr, grid, block, shm, cur_, a);
+            go(kind, kptr, grid, block, shm, a);
         }
         HIP_OK(hipGetLastError());
-        prof_end(kind, e0);
     }
 
     void ech(const std::vector<EchDesc>& ds) override {
@@ -1773,17 +1768,18 @@ private:
         HIP_OK(hipEventCreate(&e));
         return e;
     }
-    // level 1: every launch; level 2: MAD launches only (kind 0)
-    hipEvent_t prof_begin(int kind) {
-        if (!prof_ || (prof_ == 2 && kind != 0)) return nullptr;
-        hipEvent_t e = new_event();
-        HIP_OK(hipEventRecord(e, cur_));
-        return e;
-    }
-    void prof_end(int kind, hipEvent_t a) {
-        if (!prof_ || !a) return;
-        hipEvent_t b = new_event();
-        HIP_OK(hipEventRecord(b, cur_));
+    // Launch on the current lane.  When launches of this kind are profiled
+    // (level 1: every launch; level 2: MAD launches only, kind 0) the launch
+    // carries a start and a stop event that take the dispatch's own begin and
+    // end timestamps, so the recorded time is the kernel's execution alone.
+    template <typename F, typename... Args>
+    void go(int kind, F kernel, dim3 grid, dim3 block, size_t shm, Args... args) {
+        if (!prof_ || (prof_ == 2 && kind != 0)) {
+            hipLaunchKernelGGL(kernel, grid, block, shm, cur_, args...);
+            return;
+        }
+        hipEvent_t a = new_event(), b = new_event();
+        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)shm, cur_, a, b, 0, args...);
         evs_.push_back({a, b, kind});
     }
 
