@@ -18,6 +18,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "backend.h"
@@ -915,15 +916,17 @@ __global__ void __launch_bounds__(512) k_ech_panel(Src src) {
 // matrix W = [H | T] held in LDS (row length LW: the columns of H, padded to
 // 16, then the transformation columns, one per pivot).
 //
-// Panels of 32 columns are eliminated by wave 0 alone: lane l holds rows l,
-// l + 64, l + 128 and l + 192, each as 16 words of two 16-bit entries, and the
-// panel's transformation F (one column per pivot of the panel) the same way.
-// Sums stay unreduced inside a panel: an entry receives at most 32 products,
-// each at most (p - 1)^2 <= 45^2, so it stays below 2^16 and one packed
-// 16-bit multiply-add updates two entries.  A pivot step needs no barrier: a
-// ballot finds the pivot row, its lane publishes its words in LDS, each lane
-// reduces one of the 64 entries, and all lanes read them back.  After a
-// panel all four waves apply F to the remaining columns and to the
+// Panels of 32 columns: thread x holds row x's 32 panel entries as 16 words
+// of two 16-bit entries, and its row of the panel's transformation F (one
+// column per pivot of the panel) the same way.  Sums stay unreduced inside a
+// panel: an entry receives at most 32 products, each at most (p - 1)^2 <=
+// 45^2, so it stays below 2^16 and one packed 16-bit multiply-add updates two
+// entries.  A pivot step takes two barriers: each wave posts the ballot of
+// its candidate rows, every thread picks the first candidate from the four
+// ballots (the paper's pivot rule); the pivot row's thread publishes its
+// words in LDS, the lanes of its wave reduce the 64 entries, one each, and
+// after the second barrier every thread reads them and updates its row.
+// After a panel the four waves apply F to the remaining columns and to the
 // transformation columns of earlier pivots with MFMA, in place in LDS:
 //     W[x][y] := (x a pivot of this panel ? 0 : W[x][y]) + sum_t F[x][t] W[pivot row t][y]
 constexpr int ECHS_MAX_ROWS = 256;
@@ -935,14 +938,23 @@ constexpr int ECHS_VCH = 64;       // columns per trailing-update chunk
 __host__ __device__ inline int echs_tc(int cols) { return (cols + 15) & ~15; }
 __host__ __device__ inline int echs_lw(int cols, int maxr) { return echs_tc(cols) + ((maxr + 15) & ~15); }
 // LDS: W, the panel transformation F (rows x 32), the transposed pivot rows
-// of one chunk (64 x 32), published pivot words (64 dwords), prl, pcl,
-// qrow (256 ints each), the inverse table (64), sel and inpanel (256 bytes
-// each), and 16 bytes of counters
+// of one chunk (64 x 32), the published pivot row (64 dwords, -1/pivot and
+// two sets of four wave ballots: 88 dwords), prl, pcl, qrow (256 ints each),
+// the inverse table (64), sel and inpanel (256 bytes each)
 __host__ __device__ inline size_t echs_lds_bytes(int rows, int cols) {
     const int maxr = rows < cols ? rows : cols;
     const size_t rows16 = (size_t)((rows + 15) & ~15);
-    return rows16 * (size_t)echs_lw(cols, maxr) + rows16 * ECHS_PW + (size_t)ECHS_VCH * ECHS_PW + 64 * 4 +
-           3 * 256 * 4 + 64 * 4 + 2 * 256 + 16;
+    return rows16 * (size_t)echs_lw(cols, maxr) + rows16 * ECHS_PW + (size_t)ECHS_VCH * ECHS_PW + 88 * 4 +
+           3 * 256 * 4 + 64 * 4 + 2 * 256;
+}
+
+// f(std::integral_constant<int, K>) for K = K0 .. N - 1, unrolled at compile time
+template <int K0, int N, class Fn>
+__device__ __forceinline__ void static_for(Fn&& f) {
+    if constexpr (K0 < N) {
+        f(std::integral_constant<int, K0>{});
+        static_for<K0 + 1, N>(f);
+    }
 }
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
@@ -974,14 +986,14 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
     uint8_t* W = smem;                                       // [rows16][LW]
     uint8_t* Fl = W + (size_t)rows16 * LW;                   // [rows16][32]
     uint8_t* Vt = Fl + rows16 * ECHS_PW;                     // [64][32]
-    uint32_t* pb = (uint32_t*)(Vt + ECHS_VCH * ECHS_PW);     // [32] published words, [32] reduced
-    int* prl = (int*)(pb + 64);                              // pivot rows, pivot order
+    uint32_t* pb = (uint32_t*)(Vt + ECHS_VCH * ECHS_PW);     // [32] published words, [32] reduced, -1/pivot
+    unsigned long long* mskb = (unsigned long long*)(pb + 72); // [2][4] candidate rows of each wave, by column parity
+    int* prl = (int*)(pb + 88);                              // pivot rows, pivot order
     int* pcl = prl + 256;                                    // pivot columns
     int* qrl = pcl + 256;                                    // non-pivot rows (outputs)
     uint32_t* invt = (uint32_t*)(qrl + 256);                 // -1/v mod p
     uint8_t* sel = (uint8_t*)(invt + 64);                    // row selected
     uint8_t* inpanel = sel + 256;                            // row selected in the current panel
-    int* shared_rp = (int*)(inpanel + 256);                   // [2]: pivots of the panel, by panel parity
 
     // invt[v] = -1/v mod p, by search (p <= 46)
     if (x < 64) {
@@ -1022,144 +1034,108 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
     __syncthreads();
 
     int r = 0;
+    bool my_sel = x >= rows;     // thread x owns row x for the whole elimination
     for (int c0 = 0; c0 < cols && r < maxr; c0 += ECHS_PW) {
         const int wc = min(ECHS_PW, cols - c0);
-        if (wave == 0) {
-            uint32_t D[4][16], F[4][16];
-            bool sl[4], ok[4];
-            uint32_t scale[4];
-            int pidx[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int row = lane + 64 * q;
-                ok[q] = row < rows;
-                sl[q] = !ok[q] || sel[row];
-                scale[q] = 1;
-                pidx[q] = -1;
+        int rp = 0;
+        {
+            const bool ok = x < rows;
+            // the row's panel entries: column k in half (k & 1) of word k / 2
+            uint32_t D[16], F[16];
+            uint32_t scale = 1;
+            int pidx = -1;
+            {
                 uint4 a = make_uint4(0, 0, 0, 0), b = make_uint4(0, 0, 0, 0);
-                if (ok[q]) {
-                    a = *(const uint4*)(W + (size_t)row * LW + c0);
-                    b = *(const uint4*)(W + (size_t)row * LW + c0 + 16);
+                if (ok) {
+                    a = *(const uint4*)(W + (size_t)x * LW + c0);
+                    b = *(const uint4*)(W + (size_t)x * LW + c0 + 16);
                 }
                 const uint32_t d[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
-                    // columns 4i .. 4i + 3 into words 2i (columns 4i, 4i + 1) and 2i + 1
                     uint32_t lo = __builtin_amdgcn_perm(0u, d[i], 0x0c010c00u);
                     uint32_t hi = __builtin_amdgcn_perm(0u, d[i], 0x0c030c02u);
                     if (wc < ECHS_PW) {   // columns past the block hold other data: clear them
                         if (4 * i >= wc) lo &= 0u; else if (4 * i + 1 >= wc) lo &= 0xffffu;
                         if (4 * i + 2 >= wc) hi &= 0u; else if (4 * i + 3 >= wc) hi &= 0xffffu;
                     }
-                    D[q][2 * i] = lo;
-                    D[q][2 * i + 1] = hi;
+                    D[2 * i] = lo;
+                    D[2 * i + 1] = hi;
                 }
 #pragma unroll
-                for (int w = 0; w < 16; ++w) F[q][w] = 0;
+                for (int w = 0; w < 16; ++w) F[w] = 0;
             }
-            int rp = 0;
-            // column k = 2 kk + h sits in word 0, half h: the words rotate left
-            // by one after each pair of columns, so every index is static
-#pragma clang loop unroll(disable)
-            for (int kk = 0; kk < ECHS_PW / 2; ++kk) {
+            // Column k of the panel (k static, so every register index is).  Every
+            // decision below is taken from LDS values all threads read alike, so
+            // rp stays uniform.
+            static_for<0, ECHS_PW>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                if (k >= wc || r + rp >= maxr) return;
+                constexpr int wk = k >> 1, hk = 16 * (k & 1);
+                const uint32_t red = mod22((D[wk] >> hk) & 0xffffu, inv, p);
+                const unsigned long long bm = __ballot(!my_sel && red != 0u);
+                // by column parity: a column without a pivot has no second barrier
+                unsigned long long* msk = mskb + 4 * (k & 1);
+                if (lane == 0) msk[wave] = bm;
+                __syncthreads();
+                const unsigned long long m0w = msk[0], m1w = msk[1], m2w = msk[2], m3w = msk[3];
+                const int Q = m0w ? 0 : m1w ? 1 : m2w ? 2 : m3w ? 3 : -1;
+                if (Q < 0) return;    // no candidate row: not a pivot column
+                const unsigned long long mq = Q == 0 ? m0w : Q == 1 ? m1w : Q == 2 ? m2w : m3w;
+                const int prow = 64 * Q + (__ffsll((long long)mq) - 1);   // first candidate row
+                const bool me = x == prow;
+                if (me) {
+                    // publish the row's unreduced words; its own transformation
+                    // entry (index rp) is 1; and -1 / pivot
+                    const uint32_t sv = invt[red];
+                    const uint32_t one = 1u << (16 * (rp & 1));
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int k = 2 * kk + h;
-                    if (k < wc && r + rp < maxr) {
-                        uint32_t red[4];
-                        bool cand[4];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            red[q] = mod22((D[q][0] >> (16 * h)) & 0xffffu, inv, p);
-                            cand[q] = !sl[q] && red[q] != 0;
-                        }
-                        int Q = -1, L = 0;
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const unsigned long long bq = __ballot(cand[q]);
-                            if (Q < 0 && bq) { Q = q; L = __ffsll((long long)bq) - 1; }
-                        }
-                        if (Q >= 0) {
-                            // the pivot row publishes its words; its own transformation
-                            // entry (index rp) is 1
-                            if (lane == L) {
-                                const uint32_t one = 1u << (16 * (rp & 1));
-#pragma unroll
-                                for (int q = 0; q < 4; ++q) {
-                                    if (q == Q) {
-#pragma unroll
-                                        for (int w = 0; w < 16; w += 4) {
-                                            *(uint4*)(pb + w) = make_uint4(D[q][w], D[q][w + 1], D[q][w + 2], D[q][w + 3]);
-                                            *(uint4*)(pb + 16 + w) = make_uint4(
-                                                F[q][w] + (w == (rp >> 1) ? one : 0u), F[q][w + 1] + (w + 1 == (rp >> 1) ? one : 0u),
-                                                F[q][w + 2] + (w + 2 == (rp >> 1) ? one : 0u), F[q][w + 3] + (w + 3 == (rp >> 1) ? one : 0u));
-                                        }
-                                    }
-                                }
-                            }
-                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                            __builtin_amdgcn_wave_barrier();
-                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                            const uint16_t* pb16 = (const uint16_t*)pb;
-                            ((uint16_t*)(pb + 32))[lane] = (uint16_t)mod22(pb16[lane], inv, p);
-                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                            __builtin_amdgcn_wave_barrier();
-                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                            uint32_t pv[32];
-#pragma unroll
-                            for (int w = 0; w < 32; w += 4) {
-                                const uint4 t4 = *(const uint4*)(pb + 32 + w);
-                                pv[w] = t4.x; pv[w + 1] = t4.y; pv[w + 2] = t4.z; pv[w + 3] = t4.w;
-                            }
-                            const uint32_t s = invt[(pv[0] >> (16 * h)) & 0xffffu];   // -1 / pivot
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                const bool me = (q == Q) && (lane == L);
-                                const uint32_t f = me ? 0u : mod22(__umul24(red[q], s), inv, p);
-                                const uint32_t f2 = f * 0x10001u;
-#pragma unroll
-                                for (int w = 0; w < 16; ++w) D[q][w] = pkmad16(f2, pv[w], D[q][w]);
-                                // F entries past rp are zero in every row: update the
-                                // first 8 (rp + 1) / 8 words only
-                                switch (rp >> 3) {
-                                    case 0: pkmad_words<4>(F[q], pv + 16, f2); break;
-                                    case 1: pkmad_words<8>(F[q], pv + 16, f2); break;
-                                    case 2: pkmad_words<12>(F[q], pv + 16, f2); break;
-                                    default: pkmad_words<16>(F[q], pv + 16, f2); break;
-                                }
-                                if (me) {
-                                    sl[q] = true;
-                                    scale[q] = s;
-                                    pidx[q] = rp;
-                                }
-                            }
-                            if (lane == 0) {
-                                const int prow = 64 * Q + L;
-                                prl[r + rp] = prow;
-                                pcl[r + rp] = c0 + k;
-                                sel[prow] = 1;
-                                inpanel[prow] = 1;
-                            }
-                            ++rp;
-                        }
+                    for (int w = 0; w < 16; w += 4) {
+                        *(uint4*)(pb + w) = make_uint4(D[w], D[w + 1], D[w + 2], D[w + 3]);
+                        *(uint4*)(pb + 16 + w) = make_uint4(
+                            F[w] + (w == (rp >> 1) ? one : 0u), F[w + 1] + (w + 1 == (rp >> 1) ? one : 0u),
+                            F[w + 2] + (w + 2 == (rp >> 1) ? one : 0u), F[w + 3] + (w + 3 == (rp >> 1) ? one : 0u));
                     }
+                    pb[64] = sv;
                 }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const uint32_t t0 = D[q][0];
-#pragma unroll
-                    for (int w = 0; w < 15; ++w) D[q][w] = D[q][w + 1];
-                    D[q][15] = t0;
+                if (wave == Q) {
+                    // the pivot's wave reduces the 64 published entries, one per lane
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    ((uint16_t*)(pb + 32))[lane] = (uint16_t)mod22(((const uint16_t*)pb)[lane], inv, p);
                 }
-            }
-            // reduce, give each pivot row its own transformation entry 1 and scale it
-            // to pivot -1, then write the panel, F (for the MFMA) and the new
+                __syncthreads();
+                uint32_t pv[32];
+#pragma unroll
+                for (int w = 0; w < 32; w += 4) {
+                    const uint4 t4 = *(const uint4*)(pb + 32 + w);
+                    pv[w] = t4.x; pv[w + 1] = t4.y; pv[w + 2] = t4.z; pv[w + 3] = t4.w;
+                }
+                const uint32_t sv = pb[64];
+                const uint32_t f = me ? 0u : mod22(__umul24(red, sv), inv, p);
+                const uint32_t f2 = f * 0x10001u;
+                // the reduced pivot row is zero in the panel's earlier columns and
+                // in transformation entries past rp <= k
+#pragma unroll
+                for (int w = wk; w < 16; ++w) D[w] = pkmad16(f2, pv[w], D[w]);
+#pragma unroll
+                for (int w = 0; w <= wk; ++w) F[w] = pkmad16(f2, pv[16 + w], F[w]);
+                if (me) {
+                    my_sel = true;
+                    scale = sv;
+                    pidx = rp;
+                    prl[r + rp] = prow;
+                    pcl[r + rp] = c0 + k;
+                    sel[prow] = 1;
+                    inpanel[prow] = 1;
+                }
+                ++rp;
+            });
+            // reduce, give the pivot row its own transformation entry 1 and scale
+            // it to pivot -1, then write the panel, F (for the MFMA) and the new
             // transformation columns (F itself) back to LDS
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (!ok[q]) continue;
-                const int row = lane + 64 * q;
-                const uint32_t sc = scale[q];
+            if (ok) {
                 uint32_t pk[8], fk[8];
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
@@ -1167,17 +1143,17 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int col = 4 * i + j;
-                        const uint32_t wd = D[q][col >> 1], fw = F[q][col >> 1];
+                        const uint32_t wd = D[col >> 1], fw = F[col >> 1];
                         const uint32_t dv = (col & 1) ? (wd >> 16) : (wd & 0xffffu);
                         uint32_t fv = (col & 1) ? (fw >> 16) : (fw & 0xffffu);
-                        if (col == pidx[q]) fv += 1;
-                        v[j] = mod22(__umul24(dv, sc), inv, p);
-                        g[j] = mod22(__umul24(fv, sc), inv, p);
+                        if (col == pidx) fv += 1;
+                        v[j] = mod22(__umul24(dv, scale), inv, p);
+                        g[j] = mod22(__umul24(fv, scale), inv, p);
                     }
                     pk[i] = v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
                     fk[i] = g[0] | (g[1] << 8) | (g[2] << 16) | (g[3] << 24);
                 }
-                uint8_t* wr = W + (size_t)row * LW;
+                uint8_t* wr = W + (size_t)x * LW;
                 if (wc == ECHS_PW) {
                     *(uint4*)(wr + c0) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
                     *(uint4*)(wr + c0 + 16) = make_uint4(pk[4], pk[5], pk[6], pk[7]);
@@ -1186,18 +1162,17 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
                     for (int j = 0; j < ECHS_PW; ++j)
                         if (j < wc) wr[c0 + j] = (uint8_t)(pk[j >> 2] >> (8 * (j & 3)));
                 }
-                *(uint4*)(Fl + row * ECHS_PW) = make_uint4(fk[0], fk[1], fk[2], fk[3]);
-                *(uint4*)(Fl + row * ECHS_PW + 16) = make_uint4(fk[4], fk[5], fk[6], fk[7]);
+                *(uint4*)(Fl + x * ECHS_PW) = make_uint4(fk[0], fk[1], fk[2], fk[3]);
+                *(uint4*)(Fl + x * ECHS_PW + 16) = make_uint4(fk[4], fk[5], fk[6], fk[7]);
 #pragma unroll
                 for (int t = 0; t < ECHS_PW; ++t)
                     if (t < rp) wr[TC + r + t] = (uint8_t)(fk[t >> 2] >> (8 * (t & 3)));
+            } else if (x < rows16) {   // rows past `rows` (padding of the MFMA tiles)
+                *(uint4*)(Fl + x * ECHS_PW) = make_uint4(0, 0, 0, 0);
+                *(uint4*)(Fl + x * ECHS_PW + 16) = make_uint4(0, 0, 0, 0);
             }
-            for (int rr = lane; rr < rows16; rr += 64)   // rows past `rows` (padding of the MFMA tiles)
-                if (rr >= rows) { *(uint4*)(Fl + rr * ECHS_PW) = make_uint4(0, 0, 0, 0); *(uint4*)(Fl + rr * ECHS_PW + 16) = make_uint4(0, 0, 0, 0); }
-            if (lane == 0) shared_rp[(c0 / ECHS_PW) & 1] = rp;
         }
         __syncthreads();
-        const int rp = shared_rp[(c0 / ECHS_PW) & 1];
         if (rp > 0) {
             int prow_off[8];     // W offsets of pivot rows (x & 3) * 8 .. + 7 of this panel, -1 past rp
 #pragma unroll
