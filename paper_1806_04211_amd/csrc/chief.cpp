@@ -97,9 +97,22 @@ struct Ops {
     }
 };
 
+// The bulk part of a layer's UpdateRow / UpdateRowTrafo products: `near` holds
+// the columns of the block column after the priority one (which the next
+// layer's priority products of the same block row overwrite), `far` the rest.
+struct Bulk {
+    Ops near, far;
+    bool empty() const { return near.empty() && far.empty(); }
+};
+
+// Copies of the per-block-column job scratch, used round robin by layer: the
+// bulk part of layer L reads copy L mod kScratchCopies while layers L + 1 and
+// L + 2 write the other copies
+constexpr int kScratchCopies = 3;
+
 struct TaskState {      // one (i, j) of the current layer
     int i = 0, j = 0;
-    int par = 0;        // layer parity: which copy of the job scratch this layer uses
+    int par = 0;        // which copy of the job scratch this layer uses (layer mod kScratchCopies)
     bool active = false, did_ech = false;
     int32_t alpha = 0;  // rows of block row i when the layer started
     int32_t r = 0;      // pivots of block column j before ClearDown
@@ -166,17 +179,17 @@ public:
                 bc.oGbar[s] = ar.take(sizeof(int32_t) * bj);
             }
             bc.oGam = ar.take(sizeof(int32_t) * bj);
-            for (int s = 0; s < 2; ++s) {
+            for (int s = 0; s < kScratchCopies; ++s) {
                 bc.oAA[s] = ar.take(amax_ * bj);
                 bc.oAM[s] = ar.take(bj * bj);
                 bc.oAK[s] = ar.take(amax_ * bj);
                 bc.oProw[s] = ar.take(sizeof(int32_t) * std::max<int64_t>(amax_, 1));
                 bc.oQrow[s] = ar.take(sizeof(int32_t) * std::max<int64_t>(amax_, 1));
+                bc.oAE[s] = ar.take(bc.cap * bj);
             }
             bc.oH = ar.take(amax_ * bj);
             bc.ldW = 2 * bj;
             bc.oW = ar.take(amax_ * bc.ldW);
-            bc.oAE = ar.take(bc.cap * bj);
             bc.oPcol = ar.take(sizeof(int32_t) * bj);
             bc.oQcol = ar.take(sizeof(int32_t) * bj);
         }
@@ -206,16 +219,18 @@ public:
             for (int s = 0; s < 2; ++s) {
                 bc.DR[s] = at(bc.oDR[s]);
                 bc.Gbar[s] = (int32_t*)at(bc.oGbar[s]);
+            }
+            for (int s = 0; s < kScratchCopies; ++s) {
                 bc.AA[s] = at(bc.oAA[s]);
                 bc.AM[s] = at(bc.oAM[s]);
                 bc.AK[s] = at(bc.oAK[s]);
                 bc.Prow[s] = (int32_t*)at(bc.oProw[s]);
                 bc.Qrow[s] = (int32_t*)at(bc.oQrow[s]);
+                bc.AE[s] = at(bc.oAE[s]);
             }
             bc.Gam = (int32_t*)at(bc.oGam);
             bc.H = at(bc.oH);
             bc.W = at(bc.oW);
-            bc.AE = at(bc.oAE);
             bc.Pcol = (int32_t*)at(bc.oPcol);
             bc.Qcol = (int32_t*)at(bc.oQcol);
         }
@@ -263,7 +278,7 @@ public:
             t.j = L - i;
             t.alpha = alpha_[i];
             t.r = rankc_[t.j];
-            t.par = L & 1;
+            t.par = L % kScratchCopies;
             t.active = t.alpha > 0;
             tasks_.push_back(t);
         }
@@ -314,7 +329,7 @@ public:
     // UpdateRow / UpdateRowTrafo step (1): Z := C + A.A * B over all blocks
     // k > j of the panel, and Z := K + A.A * M for h != i (K's new columns are
     // the zero columns CRZ adds)
-    void ur1(Ops& pri, Ops& bulk) {
+    void ur1(Ops& pri, Bulk& bulk) {
         for (auto& t : tasks_) {
             if (!t.active || t.r == 0) continue;
             BR& br = rows_[t.i];
@@ -339,7 +354,7 @@ public:
                 g.B = P_ + bc.prow0 * ldP_ + n_ + R0_[h]; g.ldb = ldP_;
                 g.C = br.K[br.cur] + R0_[h]; g.ldc = br.ldK;
                 g.D = br.K[br.cur] + R0_[h]; g.ldd = br.ldK;
-                push_gemm(bulk, g, st_.urt_mad);
+                push_gemm(bulk.far, g, st_.urt_mad);
             }
         }
     }
@@ -436,7 +451,7 @@ public:
                 GatherDesc g;
                 g.rows = t.r; g.cols = t.rp;
                 g.src = bc.DR[bc.dcur]; g.lds = bc.ld; g.scol = bc.Pcol;
-                g.dst = bc.AE; g.ldd = bj;
+                g.dst = bc.AE[t.par]; g.ldd = bj;
                 ops.gather.push_back(g);
                 st_.gather_bytes += 2.0 * t.r * t.rp;
                 if (rest > 0) {
@@ -473,7 +488,7 @@ public:
             if (rest == 0) continue;
             GemmDesc g;
             g.M = t.r; g.N = rest; g.K = t.rp; g.p = p_;
-            g.A = bc.AE; g.lda = bj;
+            g.A = bc.AE[t.par]; g.lda = bj;
             g.B = bc.DR[1 - bc.dcur] + (int64_t)t.r * bc.ld; g.ldb = bc.ld;
             g.C = bc.DR[1 - bc.dcur]; g.ldc = bc.ld;
             g.D = bc.DR[1 - bc.dcur]; g.ldd = bc.ld;
@@ -498,7 +513,7 @@ public:
     }
 
     // UpdateRow / UpdateRowTrafo step (3): X := A.M * V with V = rho' Z (and ADI for h = i)
-    void ur3(Ops& pri, Ops& bulk) {
+    void ur3(Ops& pri, Bulk& bulk) {
         for (auto& t : tasks_) {
             if (!t.active || t.rp == 0) continue;
             BR& br = rows_[t.i];
@@ -522,7 +537,7 @@ public:
                     g.A = bc.AM[t.par]; g.lda = bj;
                     g.B = br.K[br.cur] + R0_[h]; g.ldb = br.ldK; g.brow = bc.Prow[t.par];
                     g.D = X + n_ + R0_[h]; g.ldd = ldP_;
-                    push_gemm(bulk, g, st_.urt_mad);
+                    push_gemm(bulk.far, g, st_.urt_mad);
                 }
                 if (h == t.i) {
                     // V's identity columns (ADI) make X := A.M there
@@ -530,7 +545,7 @@ public:
                     c.rows = t.rp; c.cols = t.rp;
                     c.src = bc.AM[t.par]; c.lds = bj;
                     c.dst = X + n_ + R0_[h] + w; c.ldd = ldP_;
-                    bulk.gather.push_back(c);
+                    bulk.far.gather.push_back(c);
                     st_.gather_bytes += 2.0 * t.rp * t.rp;
                 }
             }
@@ -538,7 +553,7 @@ public:
     }
 
     // step (4): S := B + A.E * X  (for h = i the stored M block is zero), RRF = append
-    void ur4(Ops& pri, Ops& bulk) {
+    void ur4(Ops& pri, Bulk& bulk) {
         for (auto& t : tasks_) {
             if (!t.active || t.rp == 0 || t.r == 0) continue;
             BC& bc = cols_[t.j];
@@ -549,7 +564,7 @@ public:
             if (n_ - c0 > 0) {
                 GemmDesc g;
                 g.M = t.r; g.N = (int32_t)(n_ - c0); g.K = t.rp; g.p = p_;
-                g.A = bc.AE; g.lda = bj;
+                g.A = bc.AE[t.par]; g.lda = bj;
                 g.B = X + c0; g.ldb = ldP_;
                 g.C = Brow + c0; g.ldc = ldP_; g.D = Brow + c0; g.ldd = ldP_;
                 push_split(pri, bulk, g, t.j, st_.ur_mad);
@@ -559,16 +574,16 @@ public:
                 if (w == 0) continue;
                 GemmDesc g;
                 g.M = t.r; g.N = w; g.K = t.rp; g.p = p_;
-                g.A = bc.AE; g.lda = bj;
+                g.A = bc.AE[t.par]; g.lda = bj;
                 g.B = X + n_ + R0_[h]; g.ldb = ldP_;
                 g.C = Brow + n_ + R0_[h]; g.ldc = ldP_; g.D = Brow + n_ + R0_[h]; g.ldd = ldP_;
-                push_gemm(bulk, g, st_.urt_mad);
+                push_gemm(bulk.far, g, st_.urt_mad);
             }
         }
     }
 
     // step (6): C := W + A.K * V with W = rho'-bar Z, written compacted to the other panel
-    void ur6(Ops& pri, Ops& bulk) {
+    void ur6(Ops& pri, Bulk& bulk) {
         for (auto& t : tasks_) {
             if (!t.active || t.rp == 0) continue;
             BR& br = rows_[t.i];
@@ -595,7 +610,7 @@ public:
                     g.B = br.K[br.cur] + R0_[h]; g.ldb = br.ldK; g.brow = bc.Prow[t.par];
                     g.C = br.K[br.cur] + R0_[h]; g.ldc = br.ldK; g.crow = bc.Qrow[t.par];
                     g.D = br.K[1 - br.cur] + R0_[h]; g.ldd = br.ldK;
-                    push_gemm(bulk, g, st_.urt_mad);
+                    push_gemm(bulk.far, g, st_.urt_mad);
                 }
                 if (h == t.i) {
                     // V is the identity on the new columns and W is zero there: K := A.K
@@ -603,7 +618,7 @@ public:
                     c.rows = left; c.cols = t.rp;
                     c.src = bc.AK[t.par]; c.lds = bj;
                     c.dst = br.K[1 - br.cur] + R0_[h] + w; c.ldd = br.ldK;
-                    bulk.gather.push_back(c);
+                    bulk.far.gather.push_back(c);
                     st_.gather_bytes += 2.0 * left * t.rp;
                 }
             }
@@ -821,19 +836,21 @@ private:
         int cur = 0, ucur = 0;
     };
     struct BC {
-        size_t oDR[2] = {0, 0}, oGbar[2] = {0, 0}, oGam = 0, oH = 0, oW = 0, oAE = 0;
-        size_t oAA[2] = {0, 0}, oAM[2] = {0, 0}, oAK[2] = {0, 0}, oProw[2] = {0, 0}, oQrow[2] = {0, 0};
+        size_t oDR[2] = {0, 0}, oGbar[2] = {0, 0}, oGam = 0, oH = 0, oW = 0;
+        size_t oAA[kScratchCopies] = {}, oAM[kScratchCopies] = {}, oAK[kScratchCopies] = {};
+        size_t oProw[kScratchCopies] = {}, oQrow[kScratchCopies] = {}, oAE[kScratchCopies] = {};
         size_t oPcol = 0, oQcol = 0;
         uint8_t* DR[2] = {nullptr, nullptr};
         int32_t* Gbar[2] = {nullptr, nullptr};
         int32_t* Gam = nullptr;
-        // by layer parity (read by the bulk lane one layer late)
-        uint8_t* AA[2] = {nullptr, nullptr};
-        uint8_t* AM[2] = {nullptr, nullptr};
-        uint8_t* AK[2] = {nullptr, nullptr};
-        int32_t* Prow[2] = {nullptr, nullptr};
-        int32_t* Qrow[2] = {nullptr, nullptr};
-        uint8_t *H = nullptr, *W = nullptr, *AE = nullptr;
+        // by layer mod kScratchCopies (read by the bulk lane up to two layers late)
+        uint8_t* AA[kScratchCopies] = {};
+        uint8_t* AM[kScratchCopies] = {};
+        uint8_t* AK[kScratchCopies] = {};
+        int32_t* Prow[kScratchCopies] = {};
+        int32_t* Qrow[kScratchCopies] = {};
+        uint8_t* AE[kScratchCopies] = {};
+        uint8_t *H = nullptr, *W = nullptr;
         int32_t *Pcol = nullptr, *Qcol = nullptr;
         int64_t cap = 0, ld = 0, ldW = 0, prow0 = 0;
         int dcur = 0, gcur = 0;
@@ -863,19 +880,23 @@ private:
 
     // g covers the data columns [C0_{j+1}, n) of a product of task (i, j):
     // block column j + 1 goes to `pri`, the columns after it to `bulk`
-    void push_split(Ops& pri, Ops& bulk, const GemmDesc& g, int j, double& counter) {
-        const int32_t n1 = (int32_t)std::min<int64_t>(g.N, C0_[j + 2] - C0_[j + 1]);
-        GemmDesc a = g;
-        a.N = n1;
-        push_gemm(pri, a, counter);
-        if (g.N > n1) {
+    // columns [C0_[j + 1], C0_[j + 2]) to the priority lane, the next block
+    // column to the bulk part's near set, the rest to its far set
+    void push_split(Ops& pri, Bulk& bulk, const GemmDesc& g, int j, double& counter) {
+        const int64_t e1 = std::min<int64_t>(g.N, C0_[j + 2] - C0_[j + 1]);
+        const int64_t e2 = j + 3 <= b_ ? std::min<int64_t>(g.N, C0_[j + 3] - C0_[j + 1]) : g.N;
+        const auto part = [&](Ops& ops, int64_t lo, int64_t hi) {
+            if (hi <= lo) return;
             GemmDesc c = g;
-            c.N = g.N - n1;
-            c.B = g.B + n1;
-            if (g.C) c.C = g.C + n1;
-            c.D = g.D + n1;
-            push_gemm(bulk, c, counter);
-        }
+            c.N = (int32_t)(hi - lo);
+            c.B = g.B + lo;
+            if (g.C) c.C = g.C + lo;
+            c.D = g.D + lo;
+            push_gemm(ops, c, counter);
+        };
+        part(pri, 0, e1);
+        part(bulk.near, e1, e2);
+        part(bulk.far, e2, g.N);
     }
 
     Backend& be_;
@@ -969,7 +990,8 @@ struct Engine::Impl {
     int64_t next_id = 0;
     size_t bytes_in_use = 0;
     int bulk_done = -1;        // lane 1's mark after the last bulk part issued
-    Ops b1, b3, b4, b6;        // the bulk part of the previous layer, not issued yet
+    int near_done = -1;        // lane 1's mark after that bulk part's near set
+    Bulk b1, b3, b4, b6;       // the bulk part of the previous layer, not issued yet
     int32_t* counts = nullptr;
     std::vector<std::pair<size_t, size_t>> holes;   // free ranges of the counts pool
     size_t counts_high = 0;
@@ -1013,14 +1035,25 @@ struct Engine::Impl {
         j.bytes = 0;
     }
 
+    // the near sets first, so the next layer's priority products wait only
+    // for them; the far sets run on behind them
     void issue_bulk(int ready) {
-        if (b1.empty() && b3.empty() && b4.empty() && b6.empty()) return;
+        if (b1.empty() && b3.empty() && b4.empty() && b6.empty()) {
+            // nothing new: a wait for the near set must cover every far set issued so far
+            near_done = bulk_done;
+            return;
+        }
         be.set_lane(1);
         be.wait_mark(1, ready);
-        flush(be, b1, shared);
-        flush(be, b3, shared);
-        flush(be, b4, shared);
-        flush(be, b6, shared);
+        flush(be, b1.near, shared);
+        flush(be, b3.near, shared);
+        flush(be, b4.near, shared);
+        flush(be, b6.near, shared);
+        near_done = be.mark(1);
+        flush(be, b1.far, shared);
+        flush(be, b3.far, shared);
+        flush(be, b4.far, shared);
+        flush(be, b6.far, shared);
         bulk_done = be.mark(1);
         be.set_lane(0);
     }
@@ -1132,8 +1165,12 @@ struct Engine::Impl {
                         if (j->phase == kStep1) j->plan->absorb_counts(hcounts.data() + j->counts_off, true);
                 }
             }
-            // the UpdateRow products below read columns the previous bulk part wrote
-            if (bulk_done >= 0) be.wait_mark(0, bulk_done);
+            // The priority products below overwrite the columns of the previous
+            // bulk part's near set.  Its far set (blocks after that) may still
+            // run: nothing on this lane touches those columns before the next
+            // layer's near set, which lane 1 runs after it, and the scratch it
+            // reads is the copy of two layers back.
+            if (near_done >= 0) be.wait_mark(0, near_done);
             for (Plan* pl : s1) pl->ur1(ops, b1);
             flush(be, ops, shared);
             for (Plan* pl : s1) pl->cd_post(ops);
