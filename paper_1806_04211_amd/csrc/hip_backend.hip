@@ -101,14 +101,21 @@ struct DescPtr {
 // blocks of v_mfma_i32_16x16x64_i8.  The MFMA is issued with the operands
 // swapped (the B tile as the first operand) so that each lane's four results
 // are four consecutive columns of one row of D: the epilogue reduces, packs
-// and stores them as one dword.  K advances in steps of TK through two LDS
-// stages; the next step's global loads are in registers while the current
-// step computes.  A is kept [m][k] in LDS (rows padded to 80 bytes).  B is
-// kept as it is stored, [k][n], the 16-byte chunk c of row k at position
-// c ^ (k & 7); the MFMA wants 16 consecutive k of one column per lane, which
-// ds_read_b64_tr_b8 delivers: within each group of 16 lanes, lane pairs
-// (2t, 2t + 1) address the two halves of a 16-byte row t (t < 8), and lane c
-// of the group receives byte c of each of the 8 rows.
+// and stores them as one dword.  K advances in steps of TK.  A is kept [m][k]
+// in LDS, 64-byte rows, the 16-byte chunk c of row m at position
+// c ^ ((m >> 2) & 3), so the 16 lanes reading one chunk of 16 rows hit 16
+// different bank groups.  B is kept as it is stored, [k][n], the 16-byte
+// chunk c of row k at position c ^ (k & 7); the MFMA wants 16 consecutive k
+// of one column per lane, which ds_read_b64_tr_b8 delivers: within each group
+// of 16 lanes, lane pairs (2t, 2t + 1) address the two halves of a 16-byte
+// row t (t < 8), and lane c of the group receives byte c of each of the 8
+// rows.
+//
+// Interior tiles with unpermuted, 16-byte aligned operands over p <= 127
+// stream both tiles straight into LDS (global_load_lds_dwordx4: lane l of a
+// wave writes the 16 bytes at the wave's LDS base + 16 l, from any address it
+// chooses) through three stages, two steps ahead of the MFMAs.  The other
+// tiles go through registers, one step ahead, in two of the stages.
 //
 // Exactness: residues of p <= 127 are used as they are, residues of p > 127
 // are centred (x >= 128 becomes x - p), so every product is an int8 x int8
@@ -119,10 +126,15 @@ struct DescPtr {
 constexpr int TM = 256;          // rows of D per workgroup tile
 constexpr int TN = 128;          // columns of D per workgroup tile
 constexpr int TK = 64;           // reduction depth per LDS stage
-constexpr int LDS_ROW = 80;      // bytes per LDS row of the A tile (64 data + 16 pad)
 constexpr int GEMM_THREADS = 256;
+constexpr int GEMM_A_STAGE = TM * TK;                    // bytes of one A tile
+constexpr int GEMM_STAGE = GEMM_A_STAGE + TK * TN;       // A tile, then B tile
+constexpr int GEMM_STAGES = 3;
 
-constexpr size_t gemm_lds_bytes() { return 2 * ((size_t)TM * LDS_ROW + (size_t)TK * TN); }
+constexpr size_t gemm_lds_bytes() { return (size_t)GEMM_STAGES * GEMM_STAGE; }
+
+// LDS byte offset of 16-byte chunk c (< 4) of row m of an A tile
+__device__ __forceinline__ int a_chunk_pos(int m, int c) { return m * TK + ((c ^ ((m >> 2) & 3)) << 4); }
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
@@ -283,12 +295,25 @@ __device__ __forceinline__ void gemm_store_lds(const GemmRegs& R, uint8_t* As, u
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const int c = tid + s * GEMM_THREADS;
-        *(uint4*)(As + (c >> 2) * LDS_ROW + (c & 3) * 16) = R.a[s];
+        *(uint4*)(As + a_chunk_pos(c >> 2, c & 3)) = R.a[s];
     }
     // k-rows kr and kr + 32 share the swizzle (kr & 7)
     const int kr = tid >> 3, pos = ((tid & 7) ^ (kr & 7)) << 4;
     *(uint4*)(Bs + kr * TN + pos) = R.b[0];
     *(uint4*)(Bs + (kr + 32) * TN + pos) = R.b[1];
+}
+
+// 16 bytes from global address g into LDS at (wave-uniform) lds_base + 16 * lane.
+// Written as assembly so that the compiler does not guard later LDS reads
+// with a wait for every load in flight; the kernel waits itself (vm_wait).
+__device__ __forceinline__ void dma16(const void* g, uint32_t lds_base) {
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds_base) : "memory");
+}
+// s_waitcnt vmcnt(N) alone (expcnt and lgkmcnt left at their maximum)
+template <int N>
+__device__ __forceinline__ void vm_wait() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
 typedef int v2i __attribute__((ext_vector_type(2)));
@@ -301,9 +326,9 @@ template <class Src>
 __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
     constexpr int JN = TN / 32;           // 16-column MFMA blocks per wave
     extern __shared__ __attribute__((aligned(16))) uint8_t gsm[];
-    // stage s: A tile at As(s) ([m][k]), B tile at Bs(s) ([k][n], swizzled)
-    const auto As = [](int s) { return gsm + s * (TM * LDS_ROW); };
-    const auto Bs = [](int s) { return gsm + 2 * TM * LDS_ROW + s * (TK * TN); };
+    // stage s: A tile at As(s) ([m][k], swizzled), B tile at Bs(s) ([k][n], swizzled)
+    const auto As = [](int s) { return gsm + s * GEMM_STAGE; };
+    const auto Bs = [](int s) { return gsm + s * GEMM_STAGE + GEMM_A_STAGE; };
 
     // which descriptor owns this tile (binary search over the prefix sums)
     const int tile = blockIdx.x;
@@ -340,19 +365,11 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
     const bool fast = m0 + TM <= g.M && n0 + TN <= g.N && ((uintptr_t)g.A & 15) == 0 && (g.lda & 15) == 0 &&
                       (b_aligned || n0 + TN + 3 <= g.N);
     const int nk_fast = fast ? g.K / TK : 0;
-    GemmRegs R;
-    if (nk > 0) {
-        if (nk_fast > 0) gemm_load<true>(g, m0, n0, 0, tid, adj, R);
-        else gemm_load<false>(g, m0, n0, 0, tid, adj, R);
-        gemm_store_lds(R, As(0), Bs(0), tid);
-    }
-    __syncthreads();
     const int r16 = lane & 15;
     const int kq = (lane >> 4) * 16;
-    for (int ks = 0; ks < nk; ++ks) {
-        const int st = ks & 1;
-        if (ks + 1 < nk_fast) gemm_load<true>(g, m0, n0, (ks + 1) * TK, tid, adj, R);
-        else if (ks + 1 < nk) gemm_load<false>(g, m0, n0, (ks + 1) * TK, tid, adj, R);
+
+    // one K step on LDS stage st
+    const auto mma_step = [&](int st) {
         // B operand of block j: lane 16 q + c gets column wn + 16 j + c, k = 16 q .. 16 q + 15,
         // from rows 16 q + t and 16 q + 8 + t (t = c / 2, whose swizzle is t) at half c & 1
         v4i bf[JN];
@@ -360,17 +377,84 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
         for (int j = 0; j < JN; ++j) {
             const int t = r16 >> 1;
             const uint8_t* rp = Bs(st) + (kq + t) * TN + ((((wn >> 4) + j) ^ t) << 4) + ((r16 & 1) << 3);
-            const v2i lo = lds_read_tr8(rp), hi = lds_read_tr8(rp + 8 * TN);
-            bf[j] = v4i{lo.x, lo.y, hi.x, hi.y};
+            const v2i lo2 = lds_read_tr8(rp), hi2 = lds_read_tr8(rp + 8 * TN);
+            bf[j] = v4i{lo2.x, lo2.y, hi2.x, hi2.y};
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const v4i af = *(const v4i*)(As(st) + (wm + i * 16 + r16) * LDS_ROW + kq);
+            const v4i af = *(const v4i*)(As(st) + a_chunk_pos(wm + i * 16 + r16, lane >> 4));
 #pragma unroll
             for (int j = 0; j < JN; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(bf[j], af, acc[i][j], 0, 0, 0);
         }
-        if (ks + 1 < nk) gemm_store_lds(R, As(st ^ 1), Bs(st ^ 1), tid);
+    };
+
+    GemmRegs R;
+    if (nk_fast > 0 && b_aligned && !g.brow && adj == 0) {
+        // ---- streamed into LDS, two steps ahead.  Per wave and stage: four
+        // 1 KB pieces of the A tile (chunk P = piece * 64 + lane is row P / 4,
+        // position P % 4) and two of the B tile (chunk P is k-row P / 8,
+        // position P % 8), each lane loading the global chunk its LDS position holds.
+        const uint32_t lds0 = (uint32_t)(uintptr_t)gsm;
+        const uint8_t* asrc[4];
+        const uint8_t* bsrc[2];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int P = (wave * 4 + t) * 64 + lane, row = P >> 2, pos = P & 3;
+            asrc[t] = g.A + (int64_t)(m0 + row) * g.lda + ((pos ^ ((row >> 2) & 3)) << 4);
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int P = (wave * 2 + t) * 64 + lane, kr = P >> 3, pos = P & 7;
+            bsrc[t] = g.B + (int64_t)kr * g.ldb + n0 + ((pos ^ (kr & 7)) << 4);
+        }
+        const int64_t bstep = (int64_t)TK * g.ldb;
+        const auto issue = [&](int ks, int st) {
+            const uint32_t base = lds0 + (uint32_t)(st * GEMM_STAGE);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                dma16(asrc[t] + (int64_t)ks * TK, __builtin_amdgcn_readfirstlane(base + (uint32_t)((wave * 4 + t) * 1024)));
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                dma16(bsrc[t] + ks * bstep,
+                      __builtin_amdgcn_readfirstlane(base + (uint32_t)(GEMM_A_STAGE + (wave * 2 + t) * 1024)));
+        };
+        issue(0, 0);
+        if (nk_fast > 1) issue(1, 1);
+        int st = 0;
+        for (int ks = 0; ks < nk; ++ks) {
+            if (ks < nk_fast) {
+                // this wave's pieces of step ks have landed (at most the 6 of step
+                // ks + 1 still in flight); the barrier makes every wave's visible
+                // and ends every wave's reads of step ks - 1, whose stage step
+                // ks + 2 then overwrites
+                if (ks + 1 < nk_fast) vm_wait<6>(); else vm_wait<0>();
+                __syncthreads();
+                if (ks + 2 < nk_fast) issue(ks + 2, st == 0 ? 2 : st - 1);
+            } else {
+                // the K tail (one step): the stage was last read two steps ago
+                gemm_load<false>(g, m0, n0, ks * TK, tid, adj, R);
+                gemm_store_lds(R, As(st), Bs(st), tid);
+                __syncthreads();
+            }
+            mma_step(st);
+            st = st == 2 ? 0 : st + 1;
+        }
+    } else {
+        // ---- through registers, one step ahead, stages 0 and 1
+        if (nk > 0) {
+            if (nk_fast > 0) gemm_load<true>(g, m0, n0, 0, tid, adj, R);
+            else gemm_load<false>(g, m0, n0, 0, tid, adj, R);
+            gemm_store_lds(R, As(0), Bs(0), tid);
+        }
         __syncthreads();
+        for (int ks = 0; ks < nk; ++ks) {
+            const int st = ks & 1;
+            if (ks + 1 < nk_fast) gemm_load<true>(g, m0, n0, (ks + 1) * TK, tid, adj, R);
+            else if (ks + 1 < nk) gemm_load<false>(g, m0, n0, (ks + 1) * TK, tid, adj, R);
+            mma_step(st);
+            if (ks + 1 < nk) gemm_store_lds(R, As(st ^ 1), Bs(st ^ 1), tid);
+            __syncthreads();
+        }
     }
 
     // ---- epilogue: D = (Cin + acc) mod p.  Lane holds, for block (i, j), row
