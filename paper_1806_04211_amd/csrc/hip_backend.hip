@@ -389,7 +389,13 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
     };
 
     GemmRegs R;
+    // LDS epilogue: the C tile arrives in LDS during the last step, D leaves
+    // through LDS as whole 16-byte row chunks.  Stage of the last step, or -1.
+    int epi_st = -1;
+    const bool al16_c = !g.C || (!g.crow && ((((uintptr_t)g.C) | (uintptr_t)g.ldc) & 15) == 0);
+    const bool al16_d = ((((uintptr_t)g.D) | (uintptr_t)g.ldd) & 15) == 0;
     if (nk_fast > 0 && b_aligned && !g.brow && adj == 0) {
+        const bool lds_epi = al16_c && al16_d;
         // ---- streamed into LDS, two steps ahead.  Per wave and stage: four
         // 1 KB pieces of the A tile (chunk P = piece * 64 + lane is row P / 4,
         // position P % 4) and two of the B tile (chunk P is k-row P / 8,
@@ -436,6 +442,23 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
                 gemm_store_lds(R, As(st), Bs(st), tid);
                 __syncthreads();
             }
+            if (ks == nk - 1 && lds_epi) {
+                // the last step: the other two stages are free; the C tile goes
+                // there (rows 0..191 in the next stage, 192..255 in the one after)
+                // while the last MFMAs run
+                epi_st = st;
+                if (g.C) {
+                    const uint32_t s1 = lds0 + (uint32_t)((st == 2 ? 0 : st + 1) * GEMM_STAGE);
+                    const uint32_t s2 = lds0 + (uint32_t)((st == 0 ? 2 : st - 1) * GEMM_STAGE);
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const int r0 = (wave * 8 + t) * 8, row = r0 + (lane >> 3), pos = lane & 7;
+                        const uint32_t base = r0 < 192 ? s1 + (uint32_t)(r0 * TN) : s2 + (uint32_t)((r0 - 192) * TN);
+                        dma16(g.C + (int64_t)(m0 + row) * g.ldc + n0 + ((pos ^ ((row >> 1) & 7)) << 4),
+                              __builtin_amdgcn_readfirstlane(base));
+                    }
+                }
+            }
             mma_step(st);
             st = st == 2 ? 0 : st + 1;
         }
@@ -473,6 +496,35 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
         }
         return out;
     };
+    if (epi_st >= 0) {
+        // C tile row m at cl(m), its 16-byte chunk c at position c ^ ((m >> 1) & 7):
+        // the 16 lanes reading one chunk of 16 rows hit 16 different bank groups
+        uint8_t* const s1 = As(epi_st == 2 ? 0 : epi_st + 1);
+        uint8_t* const s2 = As(epi_st == 0 ? 2 : epi_st - 1);
+        const auto cl = [&](int m) { return m < 192 ? s1 + m * TN : s2 + (m - 192) * TN; };
+        vm_wait<0>();
+        __syncthreads();
+        // each lane reads its C words and writes its D words in their place
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int row = wm + i * 16 + r16;
+            uint8_t* rp = cl(row);
+#pragma unroll
+            for (int j = 0; j < JN; ++j) {
+                uint32_t* w = (uint32_t*)(rp + (((((wn >> 4) + j) ^ ((row >> 1) & 7))) << 4) + (lane >> 4) * 4);
+                *w = reduce4(acc[i][j], g.C ? *w : 0u);
+            }
+        }
+        __syncthreads();
+        // whole 16-byte chunks of D rows: chunk P = tid + 256 u is row P / 8, position P % 8
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int P = tid + u * GEMM_THREADS, row = P >> 3, pos = P & 7;
+            const uint4 v = *(const uint4*)(cl(row) + pos * 16);
+            gstore<uint4>(g.D + (int64_t)(m0 + row) * g.ldd + n0 + ((pos ^ ((row >> 1) & 7)) << 4), v);
+        }
+        return;
+    }
     const bool whole = m0 + TM <= g.M && n0 + TN <= g.N &&
                        ((((uintptr_t)g.D) | (uintptr_t)g.ldd | (uintptr_t)g.C | (uintptr_t)g.ldc) & 3) == 0;
     if (whole) {
