@@ -121,10 +121,11 @@ public:
     // a stream of the library's own (default priority), and its release
     virtual void* create_stream() { return nullptr; }
     virtual void destroy_stream(void* stream) { (void)stream; }
-    // Two lanes of work: lane 0 is the caller's stream, lane 1 a second stream
-    // whose work may overlap lane 0's.  mark() records the point reached by a
-    // lane's queued work; wait_mark() makes a lane wait for such a point.
-    // Memory transfers (upload, download, zero, copy) always run on lane 0.
+    // Three lanes of work: lane 0 is the caller's stream, lanes 1 and 2 streams
+    // whose work may overlap lane 0's and each other's.  mark() records the
+    // point reached by a lane's queued work; wait_mark() makes a lane wait for
+    // such a point (of any lane).  Memory transfers (upload, download, zero,
+    // copy) always run on lane 0.
     virtual void set_lane(int lane) { (void)lane; }
     virtual int mark(int lane) { (void)lane; return 0; }
     virtual void wait_mark(int lane, int mark) { (void)lane; (void)mark; }

@@ -18,19 +18,23 @@
 // a column range reserved for block row h.  The pivot rows B_j,k and M_j,h of
 // block column j live in rows of one pivot matrix P.
 //
-// Lookahead on two lanes (streams).  Every UpdateRow / UpdateRowTrafo
+// Lookahead on three lanes (streams).  Every UpdateRow / UpdateRowTrafo
 // product is column-separable: output column c depends only on column c of
 // its inputs.  So the products of task (i, j) are split by output columns
 // into a priority part, block column j + 1 (the one the next ClearDown of
-// block row i reads), which runs on lane 0 with the ClearDowns, and a bulk
-// part (block columns j + 2.. and every transformation column), which runs
-// on lane 1.  Lane 0 runs layer L + 1's ClearDowns (extract, MADs, ECH) while
-// lane 1 runs layer L's bulk part (started after layer L + 1's ClearDown
-// MADs, and issued after its ECHs so that they reach the device first); lane 0 waits for that bulk
-// part only before layer L + 1's own UpdateRow products, which read columns
-// it wrote.  The job scratch the bulk part reads (A.A, A.M, A.K, the row
-// lists of the ECH) is kept twice, by layer parity, so layer L + 1's
-// ClearDowns cannot overwrite what layer L's bulk part still reads.
+// block row i reads), and a bulk part: a near set (block column j + 2, which
+// the next layer's priority part of block row i overwrites) and a far set
+// (block columns j + 3.. and every transformation column).  Lane 0 runs the
+// ClearDowns and the priority part; lane 1 runs the previous layer's bulk
+// part, near set first, starting after the ClearDown MADs and issued after
+// the ECHs so that they reach the device first; lane 2 runs the priority
+// part of UpdateRow (1), which needs the near set and nothing the ECH
+// computes, beside the ECH.  Lane 0 waits for lane 2 (so for the near set)
+// before the rest of the layer's products; the far set runs on and is done
+// before lane 1 reaches the next layer's near set.  The job scratch the bulk
+// part reads (A.A, A.M, A.K, A.E, the row lists of the ECH) is kept in three
+// copies, by layer mod 3, so the next two layers' ClearDowns cannot
+// overwrite what a bulk part still reads.
 #include "chief.h"
 
 #include <algorithm>
@@ -991,7 +995,9 @@ struct Engine::Impl {
     size_t bytes_in_use = 0;
     int bulk_done = -1;        // lane 1's mark after the last bulk part issued
     int near_done = -1;        // lane 1's mark after that bulk part's near set
+    int u1_done = -1;          // lane 2's mark after this layer's UpdateRow (1) priority products
     Bulk b1, b3, b4, b6;       // the bulk part of the previous layer, not issued yet
+    Ops u1;                    // this layer's UpdateRow (1) priority products
     int32_t* counts = nullptr;
     std::vector<std::pair<size_t, size_t>> holes;   // free ranges of the counts pool
     size_t counts_high = 0;
@@ -1149,6 +1155,19 @@ struct Engine::Impl {
             for (Plan* pl : s1) { pl->cd_ech(ops, false); any = any || pl->any_ech(); }
             flush(be, ops, shared);
             issue_bulk(ready);
+            // UpdateRow (1)'s priority products overwrite the near set's columns
+            // and need nothing this layer's ECH computes: lane 2 runs them beside
+            // the ECH (their bulk part joins the next layer's, b1 being empty now)
+            for (Plan* pl : s1) pl->ur1(u1, b1);
+            u1_done = -1;
+            if (!u1.empty()) {
+                be.set_lane(2);
+                be.wait_mark(2, ready);
+                if (near_done >= 0) be.wait_mark(2, near_done);
+                flush(be, u1, shared);
+                u1_done = be.mark(2);
+                be.set_lane(0);
+            }
             for (Plan* pl : s1) pl->clear_counts();
             if (any) {
                 read_counts();
@@ -1165,14 +1184,14 @@ struct Engine::Impl {
                         if (j->phase == kStep1) j->plan->absorb_counts(hcounts.data() + j->counts_off, true);
                 }
             }
-            // The priority products below overwrite the columns of the previous
-            // bulk part's near set.  Its far set (blocks after that) may still
-            // run: nothing on this lane touches those columns before the next
-            // layer's near set, which lane 1 runs after it, and the scratch it
-            // reads is the copy of two layers back.
-            if (near_done >= 0) be.wait_mark(0, near_done);
-            for (Plan* pl : s1) pl->ur1(ops, b1);
-            flush(be, ops, shared);
+            // The priority products below read what UpdateRow (1) wrote on lane 2
+            // (after the previous bulk part's near set, whose columns they
+            // overwrite).  That bulk part's far set (blocks after those) may
+            // still run: nothing on this lane touches its columns before the
+            // next layer's near set, which lane 1 runs after it, and the
+            // scratch it reads is the copy of two layers back.
+            if (u1_done >= 0) be.wait_mark(0, u1_done);
+            else if (near_done >= 0) be.wait_mark(0, near_done);
             for (Plan* pl : s1) pl->cd_post(ops);
             flush(be, ops, shared);
             for (Plan* pl : s1) pl->cd_mad2(ops);

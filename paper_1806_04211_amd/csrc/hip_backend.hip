@@ -1171,10 +1171,184 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
 
     int r = 0;
     bool my_sel = x >= rows;     // thread x owns row x for the whole elimination
+    int* const act = qrl;        // the panel's active rows (scratch until the outputs)
+    uint32_t* const Gl = (uint32_t*)Vt;   // [32][16] words: the panel's pivot rows in terms of the original ones
     for (int c0 = 0; c0 < cols && r < maxr; c0 += ECHS_PW) {
         const int wc = min(ECHS_PW, cols - c0);
         int rp = 0;
-        {
+        // ---- Pivot search by wave 0 alone, over the first (up to) 64 unselected
+        // rows, one per lane: no row after them can be a pivot while one of them
+        // is a candidate.  A column where none is, while later unselected rows
+        // exist, sends the panel to the four-wave elimination below.  Otherwise
+        // the panel's pivot rows are known as combinations G of the original
+        // rows, every other row x is cleared by the pivot rows with its own
+        // entries at the pivot columns as coefficients (the pivot rows are -1
+        // at their own pivot column and 0 at the others), and one MFMA pass
+        // applies it all, the panel's columns included.
+        if (wave == 0) {
+            int total = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = 64 * q + lane;
+                const bool un = row < rows && !sel[row];
+                const unsigned long long bq = __ballot(un);
+                const int pos = total + __popcll(bq & ((1ull << lane) - 1));
+                if (un && pos < 64) act[pos] = row;
+                total += __popcll(bq);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int arow = lane < total ? act[lane] : -1;
+            const bool spill = total > 64;
+            uint32_t D[16], F[16];
+            {
+                uint4 a = make_uint4(0, 0, 0, 0), b = make_uint4(0, 0, 0, 0);
+                if (arow >= 0) {
+                    a = *(const uint4*)(W + (size_t)arow * LW + c0);
+                    b = *(const uint4*)(W + (size_t)arow * LW + c0 + 16);
+                }
+                const uint32_t d[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    uint32_t lo = __builtin_amdgcn_perm(0u, d[i], 0x0c010c00u);
+                    uint32_t hi = __builtin_amdgcn_perm(0u, d[i], 0x0c030c02u);
+                    if (wc < ECHS_PW) {
+                        if (4 * i >= wc) lo &= 0u; else if (4 * i + 1 >= wc) lo &= 0xffffu;
+                        if (4 * i + 2 >= wc) hi &= 0u; else if (4 * i + 3 >= wc) hi &= 0xffffu;
+                    }
+                    D[2 * i] = lo;
+                    D[2 * i + 1] = hi;
+                }
+#pragma unroll
+                for (int w = 0; w < 16; ++w) F[w] = 0;
+            }
+            bool asel = arow < 0, fb = false;
+            uint32_t scale = 1;
+            int pidx = -1, pcolk = 0, rpa = 0;
+            static_for<0, ECHS_PW>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                if (fb || k >= wc || r + rpa >= maxr) return;
+                constexpr int wk = k >> 1, hk = 16 * (k & 1);
+                const uint32_t red = mod22((D[wk] >> hk) & 0xffffu, inv, p);
+                const unsigned long long bm = __ballot(!asel && red != 0u);
+                if (!bm) {
+                    if (spill) fb = true;
+                    return;
+                }
+                const bool me = lane == __ffsll((long long)bm) - 1;
+                if (me) {
+                    const uint32_t sv = invt[red];
+                    const uint32_t one = 1u << (16 * (rpa & 1));
+#pragma unroll
+                    for (int w = 0; w < 16; w += 4) {
+                        *(uint4*)(pb + w) = make_uint4(D[w], D[w + 1], D[w + 2], D[w + 3]);
+                        *(uint4*)(pb + 16 + w) = make_uint4(
+                            F[w] + (w == (rpa >> 1) ? one : 0u), F[w + 1] + (w + 1 == (rpa >> 1) ? one : 0u),
+                            F[w + 2] + (w + 2 == (rpa >> 1) ? one : 0u), F[w + 3] + (w + 3 == (rpa >> 1) ? one : 0u));
+                    }
+                    pb[64] = sv;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                ((uint16_t*)(pb + 32))[lane] = (uint16_t)mod22(((const uint16_t*)pb)[lane], inv, p);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                uint32_t pv[32];
+#pragma unroll
+                for (int w = 0; w < 32; w += 4) {
+                    const uint4 t4 = *(const uint4*)(pb + 32 + w);
+                    pv[w] = t4.x; pv[w + 1] = t4.y; pv[w + 2] = t4.z; pv[w + 3] = t4.w;
+                }
+                const uint32_t sv = pb[64];
+                const uint32_t f2 = (me ? 0u : mod22(__umul24(red, sv), inv, p)) * 0x10001u;
+#pragma unroll
+                for (int w = wk; w < 16; ++w) D[w] = pkmad16(f2, pv[w], D[w]);
+#pragma unroll
+                for (int w = 0; w <= wk; ++w) F[w] = pkmad16(f2, pv[16 + w], F[w]);
+                if (me) {
+                    asel = true;
+                    scale = sv;
+                    pidx = rpa;
+                    pcolk = k;
+                }
+                ++rpa;
+                // the next step publishes into pb again: every lane has read it
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            });
+            if (!fb && pidx >= 0) {
+                // G row pidx = scale (F + e_pidx), reduced, as 16 words of 16-bit pairs
+#pragma unroll
+                for (int w = 0; w < 16; ++w) {
+                    const uint32_t fw = F[w];
+                    uint32_t lo = fw & 0xffffu, hi = fw >> 16;
+                    if (2 * w == pidx) lo += 1;
+                    if (2 * w + 1 == pidx) hi += 1;
+                    F[w] = mod22(__umul24(lo, scale), inv, p) | (mod22(__umul24(hi, scale), inv, p) << 16);
+                }
+#pragma unroll
+                for (int w = 0; w < 16; w += 4)
+                    *(uint4*)(Gl + pidx * 16 + w) = make_uint4(F[w], F[w + 1], F[w + 2], F[w + 3]);
+                prl[r + pidx] = arow;
+                pcl[r + pidx] = c0 + pcolk;
+                sel[arow] = 1;
+                inpanel[arow] = (uint8_t)(pidx + 1);
+            }
+            if (lane == 0) pb[65] = fb ? 0xffffffffu : (uint32_t)rpa;
+        }
+        __syncthreads();
+        const int fast_rp = (int)pb[65];
+        if (fast_rp >= 0) {
+            rp = fast_rp;
+            my_sel = x >= rows || sel[x];
+            if (x < rows) {
+                // F row of x: G's row for a pivot row, else sum_t W[x][pivot column t] G[t]
+                uint32_t Fw[16];
+                const int ip = inpanel[x];
+                if (ip) {
+#pragma unroll
+                    for (int w = 0; w < 16; w += 4) {
+                        const uint4 g4 = *(const uint4*)(Gl + (ip - 1) * 16 + w);
+                        Fw[w] = g4.x; Fw[w + 1] = g4.y; Fw[w + 2] = g4.z; Fw[w + 3] = g4.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int w = 0; w < 16; ++w) Fw[w] = 0;
+                    const uint8_t* wr = W + (size_t)x * LW;
+                    for (int t = 0; t < rp; ++t) {
+                        const uint32_t f2 = (uint32_t)wr[pcl[r + t]] * 0x10001u;
+#pragma unroll
+                        for (int w = 0; w < 16; w += 4) {
+                            const uint4 g4 = *(const uint4*)(Gl + t * 16 + w);
+                            Fw[w] = pkmad16(f2, g4.x, Fw[w]);
+                            Fw[w + 1] = pkmad16(f2, g4.y, Fw[w + 1]);
+                            Fw[w + 2] = pkmad16(f2, g4.z, Fw[w + 2]);
+                            Fw[w + 3] = pkmad16(f2, g4.w, Fw[w + 3]);
+                        }
+                    }
+#pragma unroll
+                    for (int w = 0; w < 16; ++w)
+                        Fw[w] = mod22(Fw[w] & 0xffffu, inv, p) | (mod22(Fw[w] >> 16, inv, p) << 16);
+                }
+                uint32_t fk[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    fk[i] = __builtin_amdgcn_perm(Fw[2 * i + 1], Fw[2 * i], 0x06040200u);
+                *(uint4*)(Fl + x * ECHS_PW) = make_uint4(fk[0], fk[1], fk[2], fk[3]);
+                *(uint4*)(Fl + x * ECHS_PW + 16) = make_uint4(fk[4], fk[5], fk[6], fk[7]);
+                uint8_t* wr = W + (size_t)x * LW;
+#pragma unroll
+                for (int t = 0; t < ECHS_PW; ++t)
+                    if (t < rp) wr[TC + r + t] = (uint8_t)(fk[t >> 2] >> (8 * (t & 3)));
+            } else if (x < rows16) {
+                *(uint4*)(Fl + x * ECHS_PW) = make_uint4(0, 0, 0, 0);
+                *(uint4*)(Fl + x * ECHS_PW + 16) = make_uint4(0, 0, 0, 0);
+            }
+        } else {
             const bool ok = x < rows;
             // the row's panel entries: column k in half (k & 1) of word k / 2
             uint32_t D[16], F[16];
@@ -1319,7 +1493,7 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
             // segment 0: data columns right of the panel; segment 1: transformation
             // columns of the pivots of earlier panels
             for (int seg = 0; seg < 2; ++seg) {
-                const int ybeg = seg == 0 ? c0 + ECHS_PW : TC;
+                const int ybeg = seg == 0 ? (fast_rp >= 0 ? c0 : c0 + ECHS_PW) : TC;
                 const int yend = seg == 0 ? cols : TC + r;
                 for (int y0 = ybeg; y0 < yend; y0 += ECHS_VCH) {
                     const int nc = min(ECHS_VCH, yend - y0);
@@ -1543,9 +1717,11 @@ public:
             if (err) *err = "counter allocation failed";
             return false;
         }
-        // lane 1: a second stream at the default priority; non-blocking, so it
-        // never synchronises implicitly with the legacy default stream
-        if (hipStreamCreateWithFlags(&lane1_, hipStreamNonBlocking) != hipSuccess) {
+        // lanes 1 and 2: streams of their own at the default priority;
+        // non-blocking, so they never synchronise implicitly with the legacy
+        // default stream
+        if (hipStreamCreateWithFlags(&lane1_, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&lane2_, hipStreamNonBlocking) != hipSuccess) {
             if (err) *err = "stream creation failed";
             return false;
         }
@@ -1666,7 +1842,8 @@ public:
         stream_ = (hipStream_t)s;
         cur_ = stream_;
     }
-    void set_lane(int lane) override { cur_ = lane == 1 ? lane1_ : stream_; }
+    void set_lane(int lane) override { cur_ = lane_stream(lane); }
+    hipStream_t lane_stream(int lane) const { return lane == 1 ? lane1_ : lane == 2 ? lane2_ : stream_; }
     void* create_stream() override {
         hipStream_t st = nullptr;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
@@ -1689,14 +1866,14 @@ public:
         } else {
             HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         }
-        HIP_OK(hipEventRecord(e, lane == 1 ? lane1_ : stream_));
+        HIP_OK(hipEventRecord(e, lane_stream(lane)));
         marks_.push_back(e);
         return mark_base_ + (int)marks_.size() - 1;
     }
     void wait_mark(int lane, int m) override {
         // marks below mark_base_ were passed by a full synchronisation already
         if (m < mark_base_ || m - mark_base_ >= (int)marks_.size()) return;
-        HIP_OK(hipStreamWaitEvent(lane == 1 ? lane1_ : stream_, marks_[m - mark_base_], 0));
+        HIP_OK(hipStreamWaitEvent(lane_stream(lane), marks_[m - mark_base_], 0));
     }
     int error() const override { return err_; }
 
@@ -1921,9 +2098,10 @@ private:
         HIP_OK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, cur_));   // ordered before the launch reading it
         return d;
     }
-    // both lanes drained; the marks can be reused
+    // every lane drained; the marks can be reused
     void sync_all() {
         HIP_OK(hipStreamSynchronize(lane1_));
+        HIP_OK(hipStreamSynchronize(lane2_));
         HIP_OK(hipStreamSynchronize(stream_));
         for (hipEvent_t e : marks_) mark_pool_.push_back(e);
         mark_base_ += (int)marks_.size();
@@ -1933,6 +2111,7 @@ private:
 
     hipStream_t stream_ = nullptr;   // lane 0: the caller's stream
     hipStream_t lane1_ = nullptr;    // lane 1
+    hipStream_t lane2_ = nullptr;    // lane 2
     hipStream_t cur_ = nullptr;      // the lane kernels go to
     std::vector<hipEvent_t> marks_, mark_pool_;
     int32_t* counts_host_ = nullptr;   // counts_buffer(): host view

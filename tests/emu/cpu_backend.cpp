@@ -48,24 +48,35 @@ public:
     void copy(void* dst, const void* src, size_t bytes) override {
         if (bytes && chk(dst, bytes, "copy") && chk(src, bytes, "copy")) memmove(dst, src, bytes);
     }
-    // Lanes: lane 1's jobs are queued and run as late as the planner's marks
-    // allow (when lane 0 waits for them, or at sync).  Any job the planner
-    // ordered wrongly across the lanes then reads or overwrites data out of
-    // turn, and the results stop matching the oracle.  GFECH_EMU_EAGER=1
-    // runs everything at once instead.
+    // Lanes: the jobs of lanes 1 and 2 are queued and run as late as the
+    // planner's marks allow (when lane 0 waits for them, when a queued wait of
+    // the other lane needs them, or at sync).  Any job the planner ordered
+    // wrongly across the lanes then reads or overwrites data out of turn, and
+    // the results stop matching the oracle.  GFECH_EMU_EAGER=1 runs
+    // everything at once instead.  A mark is (queue length << 2) | lane; lane
+    // 0's work is always complete, so its marks are 0.
     void set_lane(int lane) override { lane_ = lane; }
-    int mark(int lane) override { return lane == 1 ? (int)(q1_.size() * 2 + 1) : 0; }
+    int mark(int lane) override { return lane == 0 ? 0 : (int)((q_[lane].size() << 2) | (size_t)lane); }
     void wait_mark(int lane, int m) override {
-        if (lane == 0 && (m & 1)) drain((size_t)(m >> 1));
+        const int src = m & 3;
+        if (src == 0 || src == lane) return;
+        const size_t upto = (size_t)(m >> 2);
+        if (lane == 0 || !defer_) drain(src, upto);
+        else q_[lane].push_back([this, src, upto] { drain(src, upto); });
     }
-    void drain(size_t upto) {
-        while (done1_ < upto && done1_ < q1_.size()) {
-            auto f = std::move(q1_[done1_]);
-            ++done1_;
+    void drain(int lane, size_t upto) {
+        while (done_[lane] < upto && done_[lane] < q_[lane].size()) {
+            auto f = std::move(q_[lane][done_[lane]]);
+            ++done_[lane];
             f();
         }
     }
-    void sync() override { drain(q1_.size()); }
+    void sync() override {
+        while (done_[1] < q_[1].size() || done_[2] < q_[2].size()) {
+            drain(1, q_[1].size());
+            drain(2, q_[2].size());
+        }
+    }
     int error() const override { return err_; }
 
     // every byte a job touches must lie inside one live allocation
@@ -96,7 +107,7 @@ public:
     }
 
     void gemm(const std::vector<GemmDesc>& ds) override {
-        if (lane_ == 1 && defer_) { q1_.push_back([this, ds] { gemm_now(ds); }); return; }
+        if (lane_ != 0 && defer_) { q_[lane_].push_back([this, ds] { gemm_now(ds); }); return; }
         gemm_now(ds);
     }
     void gemm_now(const std::vector<GemmDesc>& ds) {
@@ -121,7 +132,7 @@ public:
     }
 
     void gather(const std::vector<GatherDesc>& ds) override {
-        if (lane_ == 1 && defer_) { q1_.push_back([this, ds] { gather_now(ds); }); return; }
+        if (lane_ != 0 && defer_) { q_[lane_].push_back([this, ds] { gather_now(ds); }); return; }
         gather_now(ds);
     }
     void gather_now(const std::vector<GatherDesc>& ds) {
@@ -155,7 +166,7 @@ public:
     }
 
     void fill(const std::vector<FillDesc>& ds) override {
-        if (lane_ == 1 && defer_) { q1_.push_back([this, ds] { fill_now(ds); }); return; }
+        if (lane_ != 0 && defer_) { q_[lane_].push_back([this, ds] { fill_now(ds); }); return; }
         fill_now(ds);
     }
     void fill_now(const std::vector<FillDesc>& ds) {
@@ -179,7 +190,7 @@ public:
     }
 
     void lists(const std::vector<ListDesc>& ds) override {
-        if (lane_ == 1 && defer_) { q1_.push_back([this, ds] { lists_now(ds); }); return; }
+        if (lane_ != 0 && defer_) { q_[lane_].push_back([this, ds] { lists_now(ds); }); return; }
         lists_now(ds);
     }
     void lists_now(const std::vector<ListDesc>& ds) {
@@ -210,7 +221,7 @@ public:
     }
 
     void sort(const std::vector<SortDesc>& ds) override {
-        if (lane_ == 1 && defer_) { q1_.push_back([this, ds] { sort_now(ds); }); return; }
+        if (lane_ != 0 && defer_) { q_[lane_].push_back([this, ds] { sort_now(ds); }); return; }
         sort_now(ds);
     }
     void sort_now(const std::vector<SortDesc>& ds) {
@@ -233,7 +244,7 @@ public:
     }
 
     void ech(const std::vector<EchDesc>& ds) override {
-        if (lane_ == 1 && defer_) { q1_.push_back([this, ds] { ech_now(ds); }); return; }
+        if (lane_ != 0 && defer_) { q_[lane_].push_back([this, ds] { ech_now(ds); }); return; }
         ech_now(ds);
     }
     void ech_now(const std::vector<EchDesc>& ds) {
@@ -261,8 +272,8 @@ private:
     int err_ = 0;
     int lane_ = 0;
     bool defer_ = !(getenv("GFECH_EMU_EAGER") && getenv("GFECH_EMU_EAGER")[0] == '1');
-    std::vector<std::function<void()>> q1_;
-    size_t done1_ = 0;
+    std::vector<std::function<void()>> q_[3];
+    size_t done_[3] = {0, 0, 0};
 
     static uint32_t inv(uint32_t a, uint32_t p) {   // a^(p-2)
         uint32_t r = 1, b = a % p, x = p - 2;

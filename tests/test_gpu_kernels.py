@@ -100,11 +100,39 @@ ECH_SHAPES = [(1, 1), (5, 9), (9, 5), (64, 64), (100, 37), (37, 100), (300, 300)
 @pytest.mark.parametrize("p", [2, 3, 5, 7, 43, 47, 251])
 @pytest.mark.parametrize("shape", ECH_SHAPES)
 def test_ech_block(shape, p):
-    torch = torch_cuda()
-    lib = gpu_library()
     rows, cols = shape
     say(f"ech {shape} p={p}")
     H = synth.deficient(p, rows * 1000 + cols, rows, cols, p) if rows > 3 else synth.uniform(p, 9, rows, cols, p)
+    check_ech(H, p)
+
+
+def _structured(kind, rows, cols, p):
+    H = synth.uniform(p, rows * 7 + cols, rows, cols, p)
+    if kind == "zero_lead":        # the first 70 rows zero: the first 64 unselected rows are no candidates
+        H[:70] = 0
+    elif kind == "zero_stripes":   # every 3rd row zero and a zero column band
+        H[::3] = 0
+        H[:, 40:90] = 0
+    elif kind == "late_rank":      # only the last 30 rows independent of the rest
+        H[: rows - 30] = np.outer(np.arange(rows - 30) % p, H[rows - 30]) % p
+    return H
+
+
+# blocks whose pivot search by one wave finds every pivot (uniform) or misses a
+# column while later rows could hold its pivot (the others)
+@pytest.mark.parametrize("p", [2, 7, 43])
+@pytest.mark.parametrize("kind", ["uniform", "zero_lead", "zero_stripes", "late_rank"])
+@pytest.mark.parametrize("shape", [(256, 288), (200, 150), (100, 300)])
+def test_ech_block_structured(shape, kind, p):
+    rows, cols = shape
+    say(f"ech structured {kind} {shape} p={p}")
+    check_ech(_structured(kind, rows, cols, p), p)
+
+
+def check_ech(H, p):
+    torch = torch_cuda()
+    lib = gpu_library()
+    rows, cols = H.shape
     mr = min(rows, cols)
     dH = dev(torch, H)
     i32 = lambda k: torch.zeros(max(k, 1), dtype=torch.int32, device="cuda:0")
