@@ -184,7 +184,7 @@ void expand_rref_ops(const gfech::Result& R, uint8_t* E, int64_t lde, gfech::Bac
     if (n - r > 0) {
         gfech::GatherDesc g;
         g.rows = (int32_t)r; g.cols = (int32_t)(n - r); g.neg_p = R.p;
-        g.src = R.Pfinal + r; g.lds = R.ldP;
+        g.src = R.Pfinal + R.offR; g.lds = R.ldP;
         g.dst = E; g.ldd = lde; g.dcol = R.upsilon_bar;
         be->gather({g});
     }
@@ -199,7 +199,7 @@ void expand_transform_ops(const gfech::Result& R, uint8_t* T, int64_t ldt, gfech
     if (r > 0) {
         gfech::GatherDesc g;
         g.rows = (int32_t)r; g.cols = (int32_t)r; g.neg_p = R.p;
-        g.src = R.Pfinal + R.n; g.lds = R.ldP;
+        g.src = R.Pfinal + R.offM; g.lds = R.ldP;
         g.dst = T; g.ldd = ldt; g.dcol = R.varrho;
         be->gather({g});
         if (m - r > 0) {
@@ -331,7 +331,7 @@ gfech_status gfech_get_R(const gfech_result* res, uint8_t* R_, int64_t ldr) {
     const gfech::Result& R = *res->r;
     if (R.r > 0 && R.n - R.r > 0 && (!R_ || ldr < R.n - R.r)) return fail(GFECH_E_ARG, "bad R buffer");
     std::lock_guard<std::mutex> lk(g_mu);
-    return download_matrix(R.be, R.Pfinal + R.r, R.ldP, R.r, R.n - R.r, R_, ldr);
+    return download_matrix(R.be, R.Pfinal + R.offR, R.ldP, R.r, R.n - R.r, R_, ldr);
 }
 
 gfech_status gfech_get_M(const gfech_result* res, uint8_t* M, int64_t ldm) {
@@ -339,7 +339,7 @@ gfech_status gfech_get_M(const gfech_result* res, uint8_t* M, int64_t ldm) {
     const gfech::Result& R = *res->r;
     if (R.r > 0 && (!M || ldm < R.r)) return fail(GFECH_E_ARG, "bad M buffer");
     std::lock_guard<std::mutex> lk(g_mu);
-    return download_matrix(R.be, R.Pfinal + R.n, R.ldP, R.r, R.r, M, ldm);
+    return download_matrix(R.be, R.Pfinal + R.offM, R.ldP, R.r, R.r, M, ldm);
 }
 
 gfech_status gfech_get_K(const gfech_result* res, uint8_t* K, int64_t ldk) {
@@ -405,8 +405,8 @@ gfech_status gfech_expand_transform(const gfech_result* res, uint8_t* T, int64_t
 gfech_status gfech_device_view(const gfech_result* res, gfech_view* v) {
     if (!res || !v) return fail(GFECH_E_ARG, "NULL argument");
     const gfech::Result& R = *res->r;
-    v->R = R.Pfinal + R.r; v->ldr = R.ldP;
-    v->M = R.Pfinal + R.n; v->ldm = R.ldP;
+    v->R = R.Pfinal + R.offR; v->ldr = R.ldP;
+    v->M = R.Pfinal + R.offM; v->ldm = R.ldP;
     v->K = R.Kfinal; v->ldk = R.ldK;
     v->gamma = R.upsilon; v->gamma_bar = R.upsilon_bar;
     v->rho = R.varrho; v->rho_bar = R.varrho_bar;

@@ -649,7 +649,9 @@ public:
         res.m = m_; res.n = n_; res.r = r_; res.p = p_;
         res.row_blocks = pr_.row_blocks;
         res.col_blocks = pr_.col_blocks;
-        res.ldP = (n_ + r_ + 63) / 64 * 64;   // 64-byte aligned rows for the vector loads
+        res.offR = (r_ + 15) / 16 * 16;
+        res.offM = (res.offR + n_ - r_ + 15) / 16 * 16;
+        res.ldP = (res.offM + r_ + 63) / 64 * 64;   // 64-byte aligned rows for the vector loads
         res.ldK = r_;
         auto ialloc = [&](int64_t cnt) { return (int32_t*)be_.alloc(sizeof(int32_t) * std::max<int64_t>(cnt, 1)); };
         res.Pfinal = (uint8_t*)be_.alloc((size_t)std::max<int64_t>(r_ * res.ldP, 1));
@@ -738,12 +740,26 @@ public:
     // columns of rows selected later were never written and are zero.
     void repack(Result& res, Ops& ops) {
         if (r_ == 0) return;
-        GatherDesc g;
-        g.rows = (int32_t)r_; g.cols = (int32_t)(n_ + r_);
-        g.src = P_; g.lds = ldP_; g.srow = rowmap_; g.scol = colmap_;
-        g.dst = res.Pfinal; g.ldd = res.ldP;
-        ops.gather.push_back(g);
+        // X, R and M to their column ranges (colmap_ lists the source columns of [X R M])
+        const int64_t part[3][3] = {{0, 0, r_}, {r_, res.offR, n_ - r_}, {n_, res.offM, r_}};
+        for (const auto& q : part) {
+            if (q[2] == 0) continue;
+            GatherDesc g;
+            g.rows = (int32_t)r_; g.cols = (int32_t)q[2];
+            g.src = P_; g.lds = ldP_; g.srow = rowmap_; g.scol = colmap_ + q[0];
+            g.dst = res.Pfinal + q[1]; g.ldd = res.ldP;
+            ops.gather.push_back(g);
+        }
         st_.gather_bytes += 2.0 * r_ * (n_ + r_);
+        // the gaps before R and before M
+        const int64_t gap[2][2] = {{r_, res.offR}, {res.offR + n_ - r_, res.offM}};
+        for (const auto& q : gap) {
+            if (q[1] == q[0]) continue;
+            FillDesc f;
+            f.rows = (int32_t)r_; f.cols = (int32_t)(q[1] - q[0]);
+            f.dst = res.Pfinal + q[0]; f.ldd = res.ldP;
+            ops.fill.push_back(f);
+        }
     }
 
     void repack_diag(Result& res, Ops& ops) {
@@ -754,7 +770,7 @@ public:
             GatherDesc g;
             g.rows = rj; g.cols = nj;
             g.src = bc.DR[bc.dcur]; g.lds = bc.ld; g.srow = ordj_ + rowoff_[j];
-            g.dst = res.Pfinal + rowoff_[j] * res.ldP + r_ + noff_[j]; g.ldd = res.ldP;
+            g.dst = res.Pfinal + rowoff_[j] * res.ldP + res.offR + noff_[j]; g.ldd = res.ldP;
             ops.gather.push_back(g);
         }
         // K: (m - r) x r, rows = the final non-selected rows of each block row,
@@ -870,9 +886,14 @@ private:
     // on the columns from block column kc's remnant to the end
     bool clearup_desc(Result& res, int kc, int64_t rlo, int64_t rhi, int64_t plo, int64_t phi, int, GemmDesc& g) {
         if (rhi - rlo <= 0 || phi - plo <= 0) return false;
-        int64_t c0 = r_ + noff_[kc];
-        int64_t width = n_ + r_ - c0;
-        if (width <= 0) return false;
+        // from block column kc's remnant to the end of M, started at the 16-byte
+        // boundary at or before it inside R: the pivot rows of block columns
+        // >= kc are zero in every column of earlier block columns, so the
+        // columns added on the left keep their values
+        const int64_t c0u = res.offR + noff_[kc];
+        const int64_t c0 = std::max<int64_t>(res.offR, c0u & ~(int64_t)15);
+        const int64_t width = res.offM + r_ - c0;
+        if (c0u >= res.offM + r_) return false;
         g = GemmDesc();
         g.M = (int32_t)(rhi - rlo); g.N = (int32_t)width; g.K = (int32_t)(phi - plo); g.p = p_;
         g.A = res.Pfinal + rlo * res.ldP + plo; g.lda = res.ldP;
@@ -1302,7 +1323,7 @@ size_t Engine::footprint(const Problem& pr) const {
     size_t bytes = plan.plan_memory() + kAlign;
     // the result (at most rank min(m, n)) and the assembly maps
     const size_t r = (size_t)std::min(pr.m, pr.n);
-    bytes += r * (size_t)((pr.n + (int64_t)r + 63) / 64 * 64) + (size_t)(pr.m - (int64_t)r) * r;
+    bytes += r * (size_t)((pr.n + (int64_t)r + 32 + 63) / 64 * 64) + (size_t)(pr.m - (int64_t)r) * r;
     bytes += sizeof(int32_t) * (size_t)(3 * pr.m + 3 * pr.n + 4 * r) + 16 * kAlign;
     return bytes;
 }

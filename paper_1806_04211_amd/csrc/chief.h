@@ -34,11 +34,14 @@ struct Result {
     Backend* be = nullptr;
     int64_t m = 0, n = 0, r = 0;
     int32_t p = 0;
-    // Pfinal: r x (n + r), leading dimension ldP.  Columns [0, r) are scratch
-    // (the cleared X blocks), [r, n) hold the remnant R (Eq. (3), rows ordered by
-    // pivot column, columns = non-pivot columns ascending), [n, n + r) hold M
-    // (columns ordered by selected row).
+    // Pfinal: r rows, leading dimension ldP.  Columns [0, r) are scratch (the
+    // cleared X blocks), [offR, offR + n - r) hold the remnant R (Eq. (3), rows
+    // ordered by pivot column, columns = non-pivot columns ascending),
+    // [offM, offM + r) hold M (columns ordered by selected row); offR and offM
+    // are the first multiples of 16 at or after r and offR + n - r, so the
+    // products of Step 3 see 16-byte aligned rows; the gaps are zero.
     uint8_t* Pfinal = nullptr; int64_t ldP = 0;
+    int64_t offR = 0, offM = 0;
     uint8_t* Kfinal = nullptr; int64_t ldK = 0;   // (m - r) x r
     int32_t* upsilon = nullptr;      // r pivot columns, ascending
     int32_t* upsilon_bar = nullptr;  // n - r

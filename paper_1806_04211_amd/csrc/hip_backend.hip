@@ -1619,17 +1619,31 @@ constexpr int SMALL_ARG_CAP = 16;      // descriptors passed by value (at most 1
 template <class Src>
 __global__ void __launch_bounds__(SMALL_THREADS) k_gather(Src src) {
     const GatherDesc g = src.get(blockIdx.y);
+    constexpr int U = 8;   // elements per thread in flight: the map loads, then the data loads, then the stores
     for (int x = blockIdx.x; x < g.rows; x += gridDim.x) {
         const int64_t sr = g.srow ? gload<int32_t>(g.srow + x) : x;
         const int64_t dr = g.drow ? gload<int32_t>(g.drow + x) : x;
         const uint8_t* src = g.src + sr * g.lds;
         uint8_t* dst = g.dst + dr * g.ldd;
-        for (int y = threadIdx.x; y < g.cols; y += SMALL_THREADS) {
-            const int64_t sc = g.scol ? gload<int32_t>(g.scol + y) : y;
-            uint32_t v = gload<uint8_t>(src + sc);
-            if (g.neg_p) v = (uint32_t)((g.neg_p - (int)v) % g.neg_p);
-            const int64_t dc = g.dcol ? gload<int32_t>(g.dcol + y) : y;
-            gstore<uint8_t>(dst + dc, (uint8_t)v);
+        for (int y0 = threadIdx.x; y0 < g.cols; y0 += SMALL_THREADS * U) {
+            int64_t sc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int y = y0 + u * SMALL_THREADS;
+                sc[u] = y < g.cols ? (g.scol ? (int64_t)gload<int32_t>(g.scol + y) : (int64_t)y) : -1;
+            }
+            uint32_t v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = sc[u] >= 0 ? (uint32_t)gload<uint8_t>(src + sc[u]) : 0u;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int y = y0 + u * SMALL_THREADS;
+                if (y >= g.cols) break;
+                uint32_t w = v[u];
+                if (g.neg_p) w = (uint32_t)((g.neg_p - (int)w) % g.neg_p);
+                const int64_t dc = g.dcol ? gload<int32_t>(g.dcol + y) : y;
+                gstore<uint8_t>(dst + dc, (uint8_t)w);
+            }
         }
     }
 }
