@@ -161,8 +161,9 @@ public:
         for (int i = 0; i < a_; ++i) {
             BR& br = rows_[i];
             int64_t ai = pr_.row_blocks[i];
-            br.ldC = std::max<int64_t>(n_, 1);
-            br.ldK = R0_[i] + ai;
+            // 64-byte aligned rows, so the products take the streamed MAD path
+            br.ldC = std::max<int64_t>((n_ + 63) / 64 * 64, 64);
+            br.ldK = (R0_[i] + ai + 63) / 64 * 64;
             for (int s = 0; s < 2; ++s) {
                 br.oC[s] = ar.take(ai * br.ldC);
                 br.oK[s] = ar.take(ai * br.ldK);
@@ -198,7 +199,7 @@ public:
             bc.oQcol = ar.take(sizeof(int32_t) * bj);
         }
         prow_total_ = prow;
-        ldP_ = n_ + m_;
+        ldP_ = (n_ + m_ + 63) / 64 * 64;
         oP_ = ar.take(prow_total_ * ldP_);
         arena_bytes_ = ar.size;
         slots_ = ar.slots;

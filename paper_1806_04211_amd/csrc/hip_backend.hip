@@ -1620,11 +1620,41 @@ template <class Src>
 __global__ void __launch_bounds__(SMALL_THREADS) k_gather(Src src) {
     const GatherDesc g = src.get(blockIdx.y);
     constexpr int U = 8;   // elements per thread in flight: the map loads, then the data loads, then the stores
+    // rows copied without a column map move as 16-byte chunks
+    const bool vec = !g.dcol && !g.neg_p && !g.scol && ((((uintptr_t)g.dst) | (uintptr_t)g.ldd) & 15) == 0 &&
+                     ((((uintptr_t)g.src) | (uintptr_t)g.lds) & 3) == 0;
     for (int x = blockIdx.x; x < g.rows; x += gridDim.x) {
         const int64_t sr = g.srow ? gload<int32_t>(g.srow + x) : x;
         const int64_t dr = g.drow ? gload<int32_t>(g.drow + x) : x;
         const uint8_t* src = g.src + sr * g.lds;
         uint8_t* dst = g.dst + dr * g.ldd;
+        if (vec) {
+            constexpr int V = 4;   // chunks per thread in flight
+            for (int c0 = threadIdx.x * 16; c0 < g.cols; c0 += SMALL_THREADS * 16 * V) {
+                uint4 v[V];
+#pragma unroll
+                for (int u = 0; u < V; ++u) {
+                    const int c = c0 + u * SMALL_THREADS * 16;
+                    v[u] = make_uint4(0, 0, 0, 0);
+                    if (c + 16 <= g.cols) {
+                        const uint32_t* q = (const uint32_t*)(src + c);
+                        v[u] = make_uint4(gload<uint32_t>(q), gload<uint32_t>(q + 1), gload<uint32_t>(q + 2),
+                                          gload<uint32_t>(q + 3));
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < V; ++u) {
+                    const int c = c0 + u * SMALL_THREADS * 16;
+                    if (c >= g.cols) break;
+                    if (c + 16 <= g.cols) {
+                        gstore<uint4>(dst + c, v[u]);
+                    } else {
+                        for (int i = c; i < g.cols; ++i) gstore<uint8_t>(dst + i, gload<uint8_t>(src + i));
+                    }
+                }
+            }
+            continue;
+        }
         for (int y0 = threadIdx.x; y0 < g.cols; y0 += SMALL_THREADS * U) {
             int64_t sc[U];
 #pragma unroll
