@@ -63,6 +63,9 @@ struct FillDesc {
 // scratch of rows x (cols + min(rows, cols)) bytes with leading dimension ldw.
 struct EchDesc {
     int32_t rows = 0, cols = 0, p = 0;
+    // qcol continues with cols, cols + 1, .., cols + qtail - 1 (columns of the
+    // caller's beyond the ones given, known to hold no pivot)
+    int32_t qtail = 0;
     const uint8_t* H = nullptr; int64_t ldh = 0;
     uint8_t* work = nullptr; int64_t ldw = 0;
     int32_t* rcount = nullptr;

@@ -391,6 +391,9 @@ public:
             else { t.H = br.C[br.cur] + C0_[t.j]; t.ldh = br.ldC; }
             EchDesc e;
             e.rows = t.alpha; e.cols = t.w; e.p = p_;
+            // the columns after the leading ones hold no pivot when every row is
+            // selected there (otherwise the ECH runs again on all of H)
+            e.qtail = t.split ? w - t.w : 0;
             e.H = t.H; e.ldh = t.ldh;
             e.work = bc.W; e.ldw = bc.ldW;
             e.rcount = counts_ + t.j;
@@ -448,9 +451,6 @@ public:
                 g.B = t.H + t.w; g.ldb = t.ldh; g.brow = bc.Prow[t.par];
                 g.D = bc.DR[1 - bc.dcur] + (int64_t)t.r * bc.ld + (t.w - t.rp); g.ldd = bc.ld;
                 push_gemm(ops, g, st_.cd_mad);
-                std::vector<int32_t> tail(w - t.w);
-                std::iota(tail.begin(), tail.end(), t.w);
-                be_.upload(bc.Qcol + (t.w - t.rp), tail.data(), sizeof(int32_t) * tail.size());
             }
             if (t.r > 0) {
                 GatherDesc g;

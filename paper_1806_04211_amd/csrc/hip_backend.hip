@@ -145,7 +145,7 @@ struct GemmTileMap {           // per-descriptor tile grid, device side
 
 // MAD descriptors with their tile grids: by value (up to GEMM_ARG_CAP) or
 // through pointers into one uploaded block
-constexpr int GEMM_ARG_CAP = 12;
+constexpr int GEMM_ARG_CAP = 36;
 struct GemmArgSrc {
     int n;
     GemmTileMap m[GEMM_ARG_CAP];
@@ -678,6 +678,7 @@ __global__ void __launch_bounds__(ECH_THREADS) k_ech(Src src) {
         q = 0;
         for (int y = 0; y < cols; ++y)
             if (!prow_l[y]) e.qcol[q++] = y;
+        for (int y = 0; y < e.qtail; ++y) e.qcol[q + y] = cols + y;
     }
     __syncthreads();
     // Mo[t][u] = T[prow[t]][u];  Ro[t][k] = W[prow[t]][qcol[k]];  Ko[s][u] = T[qrow[s]][u]
@@ -707,7 +708,7 @@ constexpr int PW = 32;          // panel width
 constexpr int FL_ROW = 80;      // LDS bytes per row of F (64 used by the MFMA, zero beyond the panel)
 constexpr int VCH = 64;         // columns per trailing-update chunk
 constexpr int ECHP_MAX_ROWS = 512;
-constexpr int ECH_ARG_CAP = 8;         // descriptors passed by value (8 x 136 bytes)
+constexpr int ECH_ARG_CAP = 28;        // descriptors passed by value (28 x 136 bytes)
 
 __host__ __device__ constexpr size_t echp_fixed_lds() {
     return 128 + 2 * 16 * 64 * 4 + 2 * ECHP_MAX_ROWS * 4 + 256 * 4 + 2 * ECHP_MAX_ROWS + VCH * FL_ROW;
@@ -1029,6 +1030,7 @@ __global__ void __launch_bounds__(512) k_ech_panel(Src src) {
             if (np) e.qcol[base + __popcll(b & ((1ull << lane) - 1))] = y;
             base += __popcll(b);
         }
+        for (int y = lane; y < e.qtail; y += 64) e.qcol[base + y] = cols + y;
     }
     __syncthreads();
     for (int t = wave; t < r; t += nwaves) {
@@ -1594,6 +1596,7 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
             if (np) e.qcol[base + __popcll(bq & ((1ull << lane) - 1))] = y;
             base += __popcll(bq);
         }
+        for (int y = lane; y < e.qtail; y += 64) e.qcol[base + y] = cols + y;
     }
     __syncthreads();
     // M (rows of the pivots), K (non-pivot rows), R (pivot rows at the non-pivot columns)
@@ -1612,7 +1615,7 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
 // ============================================================================ small jobs
 
 constexpr int SMALL_THREADS = 256;
-constexpr int SMALL_ARG_CAP = 16;      // descriptors passed by value (at most 16 x 80 bytes)
+constexpr int SMALL_ARG_CAP = 48;      // descriptors passed by value (at most 48 x 80 bytes)
 
 // grid: (x blocks striding over elements, y = descriptor)
 // grid: (x blocks striding over rows, y = descriptor); threads stride over columns

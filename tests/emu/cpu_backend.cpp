@@ -325,6 +325,7 @@ private:
         for (int x = 0; x < rows; ++x) if (!selected[x]) e.qrow[q++] = x;
         q = 0;
         for (int y = 0; y < cols; ++y) if (!pc[y]) e.qcol[q++] = y;
+        for (int y = 0; y < e.qtail; ++y) e.qcol[q + y] = cols + y;
         // outputs
         for (int t = 0; t < r; ++t) {
             for (int u = 0; u < r; ++u) e.Mo[(int64_t)t * e.ldm + u] = W(prow[t], cols + u);
