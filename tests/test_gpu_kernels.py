@@ -11,7 +11,10 @@ from tests.gpu_util import dev, gpu_library, say, torch_cuda
 pytestmark = pytest.mark.gpu
 
 MAD_SHAPES = [(1, 1, 1), (17, 33, 5), (128, 128, 64), (130, 257, 65), (300, 129, 200), (64, 1000, 3),
-              (513, 70, 130), (7, 9, 300), (256, 384, 1024)]
+              (513, 70, 130), (7, 9, 300), (256, 384, 1024),
+              # 16-byte aligned rows: interior tiles stream through LDS (p <= 127), with a K
+              # tail, a single K step, and edge tiles in the same launch
+              (512, 256, 208), (256, 256, 96), (600, 400, 320), (256, 128, 64)]
 PRIMES = [2, 3, 7, 127, 131, 251]
 
 
@@ -157,3 +160,31 @@ def check_ech(H, p):
     assert np.array_equal(gM, M[:, perm])
     assert np.array_equal(gK, K[:, perm])
     assert np.array_equal(gR, R)
+
+
+def test_mad_batch_streamed():
+    """More descriptors than travel as kernel arguments, 16-byte aligned rows
+    (interior tiles stream through LDS), with C, over p <= 127."""
+    torch = torch_cuda()
+    lib = gpu_library()
+    rng = np.random.default_rng(2)
+    descs, keep, exps = [], [], []
+    for t in range(40):
+        M = int(rng.choice([256, 300, 512]))
+        N = int(rng.choice([128, 144, 256, 400]))
+        K = int(rng.choice([64, 80, 192, 256]))
+        p = int(rng.choice([2, 7, 43, 127]))
+        A = rng.integers(0, p, (M, K)).astype(np.uint8)
+        B = rng.integers(0, p, (K, N)).astype(np.uint8)
+        C = rng.integers(0, p, (M, N)).astype(np.uint8)
+        dA, dB, dC = dev(torch, A), dev(torch, B), dev(torch, C)
+        dD = torch.zeros(M * N, dtype=torch.uint8, device="cuda:0")
+        keep += [dA, dB, dC, dD]
+        descs.append(dict(M=M, N=N, K=K, p=p, A=dA.data_ptr(), lda=K, B=dB.data_ptr(), ldb=N, C=dC.data_ptr(),
+                          ldc=N, D=dD.data_ptr(), ldd=N))
+        exps.append((dD, jobs.mad(C, A, B, p), M, N))
+    say("mad batch of 40, streamed")
+    lib.mad_batch_dev(descs)
+    torch.cuda.synchronize()
+    for dD, exp, M, N in exps:
+        assert np.array_equal(dD.cpu().numpy().reshape(M, N), exp)
