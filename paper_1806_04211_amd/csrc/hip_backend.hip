@@ -1174,7 +1174,7 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
     int r = 0;
     bool my_sel = x >= rows;     // thread x owns row x for the whole elimination
     int* const act = qrl;        // the panel's active rows (scratch until the outputs)
-    uint32_t* const Gl = (uint32_t*)Vt;   // [32][16] words: the panel's pivot rows in terms of the original ones
+    uint8_t* const Gt = Vt;   // [32][32] Gt[s][t]: coefficient of original pivot row s in the panel's pivot row t
     for (int c0 = 0; c0 < cols && r < maxr; c0 += ECHS_PW) {
         const int wc = min(ECHS_PW, cols - c0);
         int rp = 0;
@@ -1293,8 +1293,10 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
                     F[w] = mod22(__umul24(lo, scale), inv, p) | (mod22(__umul24(hi, scale), inv, p) << 16);
                 }
 #pragma unroll
-                for (int w = 0; w < 16; w += 4)
-                    *(uint4*)(Gl + pidx * 16 + w) = make_uint4(F[w], F[w + 1], F[w + 2], F[w + 3]);
+                for (int w = 0; w < 16; ++w) {
+                    Gt[(2 * w) * ECHS_PW + pidx] = (uint8_t)F[w];
+                    Gt[(2 * w + 1) * ECHS_PW + pidx] = (uint8_t)(F[w] >> 16);
+                }
                 prl[r + pidx] = arow;
                 pcl[r + pidx] = c0 + pcolk;
                 sel[arow] = 1;
@@ -1307,48 +1309,62 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
         if (fast_rp >= 0) {
             rp = fast_rp;
             my_sel = x >= rows || sel[x];
-            if (x < rows) {
-                // F row of x: G's row for a pivot row, else sum_t W[x][pivot column t] G[t]
-                uint32_t Fw[16];
-                const int ip = inpanel[x];
-                if (ip) {
+            if (rp > 0) {
+                // F = Wc G by MFMA (K = 32, one row block of 16 rows per step):
+                // Wc[x][t] = W[x][pivot column t] for a row that is not a pivot of
+                // this panel, the unit vector e_t for the panel's pivot t (its F row
+                // is G's row t); entries t >= rp are zero.  The lanes of a quarter
+                // hold k = kq .. kq + 7; the output lane holds F[row][4 (lane / 16) + j]
+                // and F[row][16 + 4 (lane / 16) + j].
+                const int kq = (lane >> 4) * 8;
+                const bool contig = pcl[r + rp - 1] == c0 + rp - 1;   // pivot columns c0 .. c0 + rp - 1
+                int pcol[8];
+                uint64_t kmask = 0;
 #pragma unroll
-                    for (int w = 0; w < 16; w += 4) {
-                        const uint4 g4 = *(const uint4*)(Gl + (ip - 1) * 16 + w);
-                        Fw[w] = g4.x; Fw[w + 1] = g4.y; Fw[w + 2] = g4.z; Fw[w + 3] = g4.w;
-                    }
-                } else {
+                for (int j = 0; j < 8; ++j) {
+                    const bool in = kq + j < rp;
+                    pcol[j] = in ? pcl[r + kq + j] : -1;
+                    if (in) kmask |= 0xffull << (8 * j);
+                }
+                const long bv0 = *(const long*)(Gt + (lane & 15) * ECHS_PW + kq);
+                const long bv1 = *(const long*)(Gt + (16 + (lane & 15)) * ECHS_PW + kq);
+                for (int rb = wave; rb < (rows16 >> 4); rb += ECHS_THREADS / 64) {
+                    const int row = rb * 16 + (lane & 15);
+                    uint64_t av = 0;
+                    if (row < rows) {
+                        const int ip = inpanel[row];
+                        const uint8_t* wr = W + (size_t)row * LW;
+                        if (ip) {
+                            const int u = ip - 1 - kq;
+                            av = (u >= 0 && u < 8) ? 1ull << (8 * u) : 0ull;
+                        } else if (contig) {
+                            av = *(const uint64_t*)(wr + c0 + kq) & kmask;
+                        } else {
 #pragma unroll
-                    for (int w = 0; w < 16; ++w) Fw[w] = 0;
-                    const uint8_t* wr = W + (size_t)x * LW;
-                    for (int t = 0; t < rp; ++t) {
-                        const uint32_t f2 = (uint32_t)wr[pcl[r + t]] * 0x10001u;
-#pragma unroll
-                        for (int w = 0; w < 16; w += 4) {
-                            const uint4 g4 = *(const uint4*)(Gl + t * 16 + w);
-                            Fw[w] = pkmad16(f2, g4.x, Fw[w]);
-                            Fw[w + 1] = pkmad16(f2, g4.y, Fw[w + 1]);
-                            Fw[w + 2] = pkmad16(f2, g4.z, Fw[w + 2]);
-                            Fw[w + 3] = pkmad16(f2, g4.w, Fw[w + 3]);
+                            for (int j = 0; j < 8; ++j)
+                                if (pcol[j] >= 0) av |= (uint64_t)wr[pcol[j]] << (8 * j);
                         }
                     }
+                    const v4i f0 = __builtin_amdgcn_mfma_i32_16x16x32_i8(bv0, (long)av, v4i{0, 0, 0, 0}, 0, 0, 0);
+                    const v4i f1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(bv1, (long)av, v4i{0, 0, 0, 0}, 0, 0, 0);
+                    uint32_t w0 = 0, w1 = 0;
 #pragma unroll
-                    for (int w = 0; w < 16; ++w)
-                        Fw[w] = mod22(Fw[w] & 0xffffu, inv, p) | (mod22(Fw[w] >> 16, inv, p) << 16);
+                    for (int j = 0; j < 4; ++j) {
+                        w0 |= mod22((uint32_t)f0[j], inv, p) << (8 * j);
+                        w1 |= mod22((uint32_t)f1[j], inv, p) << (8 * j);
+                    }
+                    const int s0 = (lane >> 4) * 4;
+                    *(uint32_t*)(Fl + row * ECHS_PW + s0) = w0;
+                    *(uint32_t*)(Fl + row * ECHS_PW + 16 + s0) = w1;
+                    if (row < rows) {
+                        uint8_t* wt = W + (size_t)row * LW + TC + r;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            if (s0 + j < rp) wt[s0 + j] = (uint8_t)(w0 >> (8 * j));
+                            if (16 + s0 + j < rp) wt[16 + s0 + j] = (uint8_t)(w1 >> (8 * j));
+                        }
+                    }
                 }
-                uint32_t fk[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    fk[i] = __builtin_amdgcn_perm(Fw[2 * i + 1], Fw[2 * i], 0x06040200u);
-                *(uint4*)(Fl + x * ECHS_PW) = make_uint4(fk[0], fk[1], fk[2], fk[3]);
-                *(uint4*)(Fl + x * ECHS_PW + 16) = make_uint4(fk[4], fk[5], fk[6], fk[7]);
-                uint8_t* wr = W + (size_t)x * LW;
-#pragma unroll
-                for (int t = 0; t < ECHS_PW; ++t)
-                    if (t < rp) wr[TC + r + t] = (uint8_t)(fk[t >> 2] >> (8 * (t & 3)));
-            } else if (x < rows16) {
-                *(uint4*)(Fl + x * ECHS_PW) = make_uint4(0, 0, 0, 0);
-                *(uint4*)(Fl + x * ECHS_PW + 16) = make_uint4(0, 0, 0, 0);
             }
         } else {
             const bool ok = x < rows;
