@@ -3,7 +3,7 @@
 //
 //  - k_gemm_modp   MAD / MUL mod p (the O(n^3) work of UpdateRow,
 //                  UpdateRowTrafo, ClearDown and ClearUp) on int8 MFMA
-//                  (v_mfma_i32_16x16x64_i8) with int32 accumulation; one
+//                  (v_mfma_i32_32x32x32_i8) with int32 accumulation; one
 //                  launch runs every descriptor of a phase.
 //  - k_ech         ECH (Remark 2.3): one workgroup per block.
 //  - k_gather, k_fill, k_lists, k_sort, k_range: extracts, riffles and the
@@ -97,11 +97,13 @@ struct DescPtr {
 
 // ============================================================================ GEMM mod p
 //
-// Workgroup tile TM x TN of D, 4 waves in 2 x 2, each wave 128 x 64 as 8 x 4
-// blocks of v_mfma_i32_16x16x64_i8.  The MFMA is issued with the operands
-// swapped (the B tile as the first operand) so that each lane's four results
-// are four consecutive columns of one row of D: the epilogue reduces, packs
-// and stores them as one dword.  K advances in steps of TK.  A is kept [m][k]
+// Workgroup tile TM x TN of D, 4 waves in 2 x 2, each wave 128 x 64 as 4 x 2
+// blocks of v_mfma_i32_32x32x32_i8 (on this chip it retires half again as
+// many products per cycle as the 16 x 16 x 64 form).  The MFMA is issued with
+// the operands swapped (the B tile as the first operand) so that a lane's
+// results come in runs of four consecutive columns of one row of D: the
+// epilogue reduces, packs and stores each run as one dword.  K advances in
+// steps of TK, two MFMA k-steps of 32 each.  A is kept [m][k]
 // in LDS, 64-byte rows, the 16-byte chunk c of row m at position
 // c ^ ((m >> 2) & 3), so the 16 lanes reading one chunk of 16 rows hit 16
 // different bank groups.  B is kept as it is stored, [k][n], the 16-byte
@@ -153,6 +155,15 @@ struct GemmArgSrc {
     __device__ __forceinline__ int count() const { return n; }
     __device__ __forceinline__ GemmTileMap map(int i) const { return m[i]; }
     __device__ __forceinline__ GemmDesc get(int i) const { return d[i]; }
+    // the descriptor that owns `tile`: the last one whose first tile is at or
+    // before it (first tiles ascend, the first is 0), counted over every
+    // entry at once rather than by a chain of dependent loads
+    __device__ __forceinline__ int find(int tile) const {
+        int c = 0;
+#pragma unroll
+        for (int i = 1; i < GEMM_ARG_CAP; ++i) c += (i < n && m[i].first_tile <= tile) ? 1 : 0;
+        return c;
+    }
 };
 struct GemmPtrSrc {
     int n;
@@ -161,6 +172,22 @@ struct GemmPtrSrc {
     __device__ __forceinline__ int count() const { return n; }
     __device__ __forceinline__ GemmTileMap map(int i) const { return m[i]; }
     __device__ __forceinline__ GemmDesc get(int i) const { return d[i]; }
+    // as GemmArgSrc::find; each lane of the wave tests entries lane, lane + 64, ...
+    __device__ __forceinline__ int find(int tile) const {
+        const int lane = (int)(threadIdx.x & 63);
+        int c = 0;
+        for (int b = 0; b < n; b += 256) {
+            bool le[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = b + 64 * u + lane;
+                le[u] = i < n && m[i].first_tile <= tile;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) c += __popcll(__ballot(le[u]));
+        }
+        return c - 1;
+    }
 };
 
 // v mod p for 0 <= v < 2^22.  With inv = fl(1/p), fl(v * inv) differs from
@@ -322,21 +349,27 @@ __device__ __forceinline__ v2i lds_read_tr8(const uint8_t* p) {
     return __builtin_amdgcn_ds_read_tr8_b64_v2i32((__attribute__((address_space(3))) v2i*)(p));
 }
 
+typedef int v16i __attribute__((ext_vector_type(16)));
+
 template <class Src>
 __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
-    constexpr int JN = TN / 32;           // 16-column MFMA blocks per wave
+    constexpr int IM = 4;                 // 32-row MFMA blocks per wave
+    constexpr int JN = TN / 64;           // 32-column MFMA blocks per wave
     extern __shared__ __attribute__((aligned(16))) uint8_t gsm[];
     // stage s: A tile at As(s) ([m][k], swizzled), B tile at Bs(s) ([k][n], swizzled)
     const auto As = [](int s) { return gsm + s * GEMM_STAGE; };
     const auto Bs = [](int s) { return gsm + s * GEMM_STAGE + GEMM_A_STAGE; };
 
-    // which descriptor owns this tile (binary search over the prefix sums)
-    const int tile = blockIdx.x;
-    int lo = 0, hi = src.count() - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (src.map(mid).first_tile <= tile) lo = mid; else hi = mid - 1;
-    }
+    // Workgroups are dealt to the 8 XCDs in turn (workgroup b to XCD b mod 8),
+    // each with its own L2.  Tiles are renumbered so that XCD x takes one
+    // contiguous range of them: the tiles of one descriptor, which share A
+    // panels, then mostly run on the same XCD.
+    const int tile = [] {
+        const int nt = (int)gridDim.x, b = (int)blockIdx.x;
+        const int q = nt >> 3, rem = nt & 7, x = b & 7;
+        return x * q + (x < rem ? x : rem) + (b >> 3);
+    }();
+    const int lo = src.find(tile);
     const GemmDesc g = src.get(lo);
     const GemmTileMap gm = src.map(lo);
     const int local = tile - gm.first_tile;
@@ -351,11 +384,13 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
     const uint32_t p = (uint32_t)g.p;
     const uint32_t adj = p > 127 ? 256u - p : 0u;
 
-    v4i acc[8][JN];
+    v16i acc[IM][JN];
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < IM; ++i)
 #pragma unroll
-        for (int j = 0; j < JN; ++j) acc[i][j] = v4i{0, 0, 0, 0};
+        for (int j = 0; j < JN; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0;
 
     const int nk = (g.K + TK - 1) / TK;
     // steps that may use the unchecked loads: the whole tile inside D, A rows
@@ -366,25 +401,34 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
                       (b_aligned || n0 + TN + 3 <= g.N);
     const int nk_fast = fast ? g.K / TK : 0;
     const int r16 = lane & 15;
-    const int kq = (lane >> 4) * 16;
+    const int r32 = lane & 31;
+    const int kh = lane >> 5;
 
-    // one K step on LDS stage st
+    // one K step on LDS stage st: two halves of 32, each 4 x 2 MFMAs 32 x 32 x 32
     const auto mma_step = [&](int st) {
-        // B operand of block j: lane 16 q + c gets column wn + 16 j + c, k = 16 q .. 16 q + 15,
-        // from rows 16 q + t and 16 q + 8 + t (t = c / 2, whose swizzle is t) at half c & 1
-        v4i bf[JN];
 #pragma unroll
-        for (int j = 0; j < JN; ++j) {
-            const int t = r16 >> 1;
-            const uint8_t* rp = Bs(st) + (kq + t) * TN + ((((wn >> 4) + j) ^ t) << 4) + ((r16 & 1) << 3);
-            const v2i lo2 = lds_read_tr8(rp), hi2 = lds_read_tr8(rp + 8 * TN);
-            bf[j] = v4i{lo2.x, lo2.y, hi2.x, hi2.y};
-        }
+        for (int h = 0; h < 2; ++h) {
+            // B operand of block j: lane 32 kh + c gets column wn + 32 j + c and
+            // k = 32 h + 16 kh .. + 15; its group of 16 lanes reads rows k0 + t and
+            // k0 + 8 + t (t = r16 / 2, whose swizzle is t) of the 16-column chunk
+            // (wn + 32 j) / 16 + (c >= 16) at half r16 & 1
+            v4i bf[JN];
+            const int k0 = 32 * h + 16 * kh, t = r16 >> 1;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const v4i af = *(const v4i*)(As(st) + a_chunk_pos(wm + i * 16 + r16, lane >> 4));
+            for (int j = 0; j < JN; ++j) {
+                const int ch = (wn >> 4) + 2 * j + ((lane >> 4) & 1);
+                const uint8_t* rp = Bs(st) + (k0 + t) * TN + ((ch ^ t) << 4) + ((r16 & 1) << 3);
+                const v2i lo2 = lds_read_tr8(rp), hi2 = lds_read_tr8(rp + 8 * TN);
+                bf[j] = v4i{lo2.x, lo2.y, hi2.x, hi2.y};
+            }
+            // A operand of block i: row wm + 32 i + r32, the same 16 k (chunk 2 h + kh)
 #pragma unroll
-            for (int j = 0; j < JN; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(bf[j], af, acc[i][j], 0, 0, 0);
+            for (int i = 0; i < IM; ++i) {
+                const v4i af = *(const v4i*)(As(st) + a_chunk_pos(wm + i * 32 + r32, 2 * h + kh));
+#pragma unroll
+                for (int j = 0; j < JN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(bf[j], af, acc[i][j], 0, 0, 0);
+            }
         }
     };
 
@@ -480,8 +524,12 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
         }
     }
 
-    // ---- epilogue: D = (Cin + acc) mod p.  Lane holds, for block (i, j), row
-    // wm + 16 i + lane % 16 and the four columns wn + 16 j + 4 (lane / 16) + e.
+    // ---- epilogue: D = (Cin + acc) mod p.  Lane holds, for block (i, j) and
+    // q < 4, row wm + 32 i + lane % 32 and the four columns
+    // wn + 32 j + 8 q + 4 (lane / 32) + e in acc[i][j][4 q + e].
+    const auto acc4 = [&](int i, int j, int q) {
+        return v4i{acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2], acc[i][j][4 * q + 3]};
+    };
     const bool small = p <= 127 && (uint64_t)g.K * (p - 1) * (p - 1) + (p - 1) < (1u << 22);
     const float inv = 1.0f / (float)p;
     const ModP mod(p);
@@ -506,14 +554,17 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
         __syncthreads();
         // each lane reads its C words and writes its D words in their place
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int row = wm + i * 16 + r16;
+        for (int i = 0; i < IM; ++i) {
+            const int row = wm + i * 32 + r32;
             uint8_t* rp = cl(row);
 #pragma unroll
-            for (int j = 0; j < JN; ++j) {
-                uint32_t* w = (uint32_t*)(rp + (((((wn >> 4) + j) ^ ((row >> 1) & 7))) << 4) + (lane >> 4) * 4);
-                *w = reduce4(acc[i][j], g.C ? *w : 0u);
-            }
+            for (int j = 0; j < JN; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int ch = (wn >> 4) + 2 * j + (q >> 1);
+                    uint32_t* w = (uint32_t*)(rp + ((ch ^ ((row >> 1) & 7)) << 4) + (q & 1) * 8 + kh * 4);
+                    *w = reduce4(acc4(i, j, q), g.C ? *w : 0u);
+                }
         }
         __syncthreads();
         // whole 16-byte chunks of D rows: chunk P = tid + 256 u is row P / 8, position P % 8
@@ -530,36 +581,41 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
     if (whole) {
         // interior tile with dword-aligned rows: every C word is loaded before any
         // is used, so the loads of the whole tile are in flight together
-        uint32_t cw[8][JN];
+        uint32_t cw[IM][JN][4];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int row = m0 + wm + i * 16 + r16;
+        for (int i = 0; i < IM; ++i) {
+            const int row = m0 + wm + i * 32 + r32;
             const uint8_t* cp = g.C ? g.C + (int64_t)(g.crow ? gload<int32_t>(g.crow + row) : row) * g.ldc : nullptr;
 #pragma unroll
             for (int j = 0; j < JN; ++j)
-                cw[i][j] = cp ? gload<uint32_t>(cp + n0 + wn + j * 16 + (lane >> 4) * 4) : 0u;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    cw[i][j][q] = cp ? gload<uint32_t>(cp + n0 + wn + j * 32 + q * 8 + kh * 4) : 0u;
         }
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            uint8_t* dp = g.D + (int64_t)(m0 + wm + i * 16 + r16) * g.ldd + n0 + wn + (lane >> 4) * 4;
+        for (int i = 0; i < IM; ++i) {
+            uint8_t* dp = g.D + (int64_t)(m0 + wm + i * 32 + r32) * g.ldd + n0 + wn + kh * 4;
 #pragma unroll
-            for (int j = 0; j < JN; ++j) gstore<uint32_t>(dp + j * 16, reduce4(acc[i][j], cw[i][j]));
+            for (int j = 0; j < JN; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) gstore<uint32_t>(dp + j * 32 + q * 8, reduce4(acc4(i, j, q), cw[i][j][q]));
         }
         return;
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int row = m0 + wm + i * 16 + r16;
+    for (int i = 0; i < IM; ++i) {
+        const int row = m0 + wm + i * 32 + r32;
         if (row >= g.M) continue;
         const uint8_t* crow_ptr = g.C ? g.C + (int64_t)(g.crow ? gload<int32_t>(g.crow + row) : row) * g.ldc : nullptr;
         uint8_t* drow_ptr = g.D + (int64_t)row * g.ldd;
 #pragma unroll
-        for (int j = 0; j < JN; ++j) {
-            const int col = n0 + wn + j * 16 + (lane >> 4) * 4;
+        for (int jq = 0; jq < JN * 4; ++jq) {
+            const int j = jq >> 2, q = jq & 3;
+            const int col = n0 + wn + j * 32 + q * 8 + kh * 4;
             if (col >= g.N) continue;
             const int rem = g.N - col;
             const uint32_t cw = crow_ptr ? load4_lim(crow_ptr + col, rem) : 0u;
-            const uint32_t out = reduce4(acc[i][j], cw);
+            const uint32_t out = reduce4(acc4(i, j, q), cw);
             uint8_t* dp = drow_ptr + col;
             if (rem >= 4 && (((uintptr_t)dp) & 3) == 0) {
                 gstore<uint32_t>(dp, out);
