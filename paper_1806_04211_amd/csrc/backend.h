@@ -124,8 +124,8 @@ public:
     // a stream of the library's own (default priority), and its release
     virtual void* create_stream() { return nullptr; }
     virtual void destroy_stream(void* stream) { (void)stream; }
-    // Three lanes of work: lane 0 is the caller's stream, lanes 1 and 2 streams
-    // whose work may overlap lane 0's and each other's.  mark() records the
+    // Four lanes of work: lane 0 is the caller's stream, lanes 1, 2 and 3
+    // streams whose work may overlap lane 0's and each other's.  mark() records the
     // point reached by a lane's queued work; wait_mark() makes a lane wait for
     // such a point (of any lane).  Memory transfers (upload, download, zero,
     // copy) always run on lane 0.

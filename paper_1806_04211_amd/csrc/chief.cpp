@@ -18,23 +18,27 @@
 // a column range reserved for block row h.  The pivot rows B_j,k and M_j,h of
 // block column j live in rows of one pivot matrix P.
 //
-// Lookahead on three lanes (streams).  Every UpdateRow / UpdateRowTrafo
+// Lookahead on four lanes (streams).  Every UpdateRow / UpdateRowTrafo
 // product is column-separable: output column c depends only on column c of
 // its inputs.  So the products of task (i, j) are split by output columns
 // into a priority part, block column j + 1 (the one the next ClearDown of
 // block row i reads), and a bulk part: a near set (block column j + 2, which
-// the next layer's priority part of block row i overwrites) and a far set
-// (block columns j + 3.. and every transformation column).  Lane 0 runs the
-// ClearDowns and the priority part; lane 1 runs the previous layer's bulk
-// part, near set first, starting after the ClearDown MADs and issued after
-// the ECHs so that they reach the device first; lane 2 runs the priority
-// part of UpdateRow (1), which needs the near set and nothing the ECH
-// computes, beside the ECH.  Lane 0 waits for lane 2 (so for the near set)
-// before the rest of the layer's products; the far set runs on and is done
-// before lane 1 reaches the next layer's near set.  The job scratch the bulk
-// part reads (A.A, A.M, A.K, A.E, the row lists of the ECH) is kept in three
-// copies, by layer mod 3, so the next two layers' ClearDowns cannot
-// overwrite what a bulk part still reads.
+// the next layer's priority part of block row i overwrites), a mid set
+// (block column j + 3, the next layer's near set) and a far set (block
+// columns j + 4.. and every transformation column).  Lane 0 runs the
+// ClearDowns and the priority part; lane 1 runs the previous layer's near
+// and mid sets, lane 3 its far set, both starting after the ClearDown MADs
+// and issued after the ECHs so that the ECHs reach the device first; lane 2
+// runs the priority part of UpdateRow (1), which needs the near set and
+// nothing the ECH computes, beside the ECH.  Lane 0 waits for lane 2 (so for
+// the near set) before the rest of the layer's products.  The sets of
+// consecutive layers of a block row update the same blocks from block
+// column j + 3 on, so a mid set waits for the previous layer's far set
+// (block j + 3 is in both); the far sets follow each other on lane 3 and run
+// beside the next layer's near set.  The job scratch the bulk part reads
+// (A.A, A.M, A.K, A.E, the row lists of the ECH) is kept in three copies, by
+// layer mod 3; lane 0 waits for a far set before the ClearDowns of the
+// layer that reuses its copy.
 #include "chief.h"
 
 #include <algorithm>
@@ -103,10 +107,11 @@ struct Ops {
 
 // The bulk part of a layer's UpdateRow / UpdateRowTrafo products: `near` holds
 // the columns of the block column after the priority one (which the next
-// layer's priority products of the same block row overwrite), `far` the rest.
+// layer's priority products of the same block row overwrite), `mid` those of
+// the block column after that (the next layer's near set), `far` the rest.
 struct Bulk {
-    Ops near, far;
-    bool empty() const { return near.empty() && far.empty(); }
+    Ops near, mid, far;
+    bool empty() const { return near.empty() && mid.empty() && far.empty(); }
 };
 
 // Copies of the per-block-column job scratch, used round robin by layer: the
@@ -911,6 +916,7 @@ private:
     void push_split(Ops& pri, Bulk& bulk, const GemmDesc& g, int j, double& counter) {
         const int64_t e1 = std::min<int64_t>(g.N, C0_[j + 2] - C0_[j + 1]);
         const int64_t e2 = j + 3 <= b_ ? std::min<int64_t>(g.N, C0_[j + 3] - C0_[j + 1]) : g.N;
+        const int64_t e3 = j + 4 <= b_ ? std::min<int64_t>(g.N, C0_[j + 4] - C0_[j + 1]) : g.N;
         const auto part = [&](Ops& ops, int64_t lo, int64_t hi) {
             if (hi <= lo) return;
             GemmDesc c = g;
@@ -922,7 +928,8 @@ private:
         };
         part(pri, 0, e1);
         part(bulk.near, e1, e2);
-        part(bulk.far, e2, g.N);
+        part(bulk.mid, e2, e3);
+        part(bulk.far, e3, g.N);
     }
 
     Backend& be_;
@@ -1015,8 +1022,10 @@ struct Engine::Impl {
     std::vector<Done> done;
     int64_t next_id = 0;
     size_t bytes_in_use = 0;
-    int bulk_done = -1;        // lane 1's mark after the last bulk part issued
+    int mid_done = -1;         // lane 1's mark after the last bulk part issued (its mid set)
     int near_done = -1;        // lane 1's mark after that bulk part's near set
+    int far_done = -1;         // lane 3's mark after its far set
+    int far_wait = -1;         // the far set lane 0 waits for before the next layer's ClearDowns
     int u1_done = -1;          // lane 2's mark after this layer's UpdateRow (1) priority products
     Bulk b1, b3, b4, b6;       // the bulk part of the previous layer, not issued yet
     Ops u1;                    // this layer's UpdateRow (1) priority products
@@ -1064,11 +1073,12 @@ struct Engine::Impl {
     }
 
     // the near sets first, so the next layer's priority products wait only
-    // for them; the far sets run on behind them
+    // for them, then the mid sets (after the previous far sets, which update
+    // their blocks too); the far sets run on lane 3
     void issue_bulk(int ready) {
         if (b1.empty() && b3.empty() && b4.empty() && b6.empty()) {
-            // nothing new: a wait for the near set must cover every far set issued so far
-            near_done = bulk_done;
+            // nothing new: a wait for the near set must cover every mid set issued so far
+            near_done = mid_done;
             return;
         }
         be.set_lane(1);
@@ -1078,12 +1088,25 @@ struct Engine::Impl {
         flush(be, b4.near, shared);
         flush(be, b6.near, shared);
         near_done = be.mark(1);
+        if (far_done >= 0) be.wait_mark(1, far_done);
+        flush(be, b1.mid, shared);
+        flush(be, b3.mid, shared);
+        flush(be, b4.mid, shared);
+        flush(be, b6.mid, shared);
+        mid_done = be.mark(1);
+        be.set_lane(3);
+        be.wait_mark(3, ready);
         flush(be, b1.far, shared);
         flush(be, b3.far, shared);
         flush(be, b4.far, shared);
         flush(be, b6.far, shared);
-        bulk_done = be.mark(1);
+        far_done = be.mark(3);
         be.set_lane(0);
+    }
+    // lane 0 waits for every bulk part issued so far
+    void wait_bulk() {
+        if (mid_done >= 0) be.wait_mark(0, mid_done);
+        if (far_done >= 0) be.wait_mark(0, far_done);
     }
 
     void read_counts() {
@@ -1162,6 +1185,11 @@ struct Engine::Impl {
             if (j->phase == kStep1) s1.push_back(j->plan.get());
         // ---- Step 1: one layer of every problem in it (see the header comment for the lanes)
         if (!s1.empty()) {
+            // the bulk part issued two layers back reads the scratch copy this
+            // layer's ClearDowns write: its mid set is behind the near set lane 0
+            // waited for in the previous layer, its far set is waited for here
+            if (far_wait >= 0) be.wait_mark(0, far_wait);
+            far_wait = far_done;
             for (size_t q = 0; q < jobs.size(); ++q)
                 if (jobs[q]->phase == kStep1) jobs[q]->plan->begin_layer(jobs[q]->layer);
             for (Plan* pl : s1) pl->cd_extract(ops);
@@ -1238,11 +1266,11 @@ struct Engine::Impl {
             // a problem leaving Step 1 needs its last bulk part before the assembly
             if (finished) {
                 issue_bulk(be.mark(0));
-                if (bulk_done >= 0) be.wait_mark(0, bulk_done);
+                wait_bulk();
             }
         } else {
             issue_bulk(be.mark(0));
-            if (bulk_done >= 0) be.wait_mark(0, bulk_done);
+            wait_bulk();
         }
         if (be.error()) { fail_all(be.error()); return 0; }
 

@@ -1127,19 +1127,19 @@ constexpr int ECHS_MAX_ROWS = 256;
 constexpr int ECHS_MAX_P = 46;
 constexpr int ECHS_THREADS = 256;
 constexpr int ECHS_PW = 32;        // panel width
-constexpr int ECHS_VCH = 64;       // columns per trailing-update chunk
+constexpr int ECHS_CH = 32;        // columns per trailing-update chunk
 
 __host__ __device__ inline int echs_tc(int cols) { return (cols + 15) & ~15; }
 __host__ __device__ inline int echs_lw(int cols, int maxr) { return echs_tc(cols) + ((maxr + 15) & ~15); }
-// LDS: W, the panel transformation F (rows x 32), the transposed pivot rows
-// of one chunk (64 x 32), the published pivot row (64 dwords, -1/pivot and
+// LDS: W, the panel transformation F (rows x 32), G^T of the panel found
+// by one wave (32 x 32), the published pivot row (64 dwords, -1/pivot and
 // two sets of four wave ballots: 88 dwords), prl, pcl, qrow (256 ints each),
-// the inverse table (64), sel and inpanel (256 bytes each)
+// the inverse table (64), sel and two inpanel arrays (256 bytes each)
 __host__ __device__ inline size_t echs_lds_bytes(int rows, int cols) {
     const int maxr = rows < cols ? rows : cols;
     const size_t rows16 = (size_t)((rows + 15) & ~15);
-    return rows16 * (size_t)echs_lw(cols, maxr) + rows16 * ECHS_PW + (size_t)ECHS_VCH * ECHS_PW + 88 * 4 +
-           3 * 256 * 4 + 64 * 4 + 2 * 256;
+    return rows16 * (size_t)echs_lw(cols, maxr) + rows16 * ECHS_PW + (size_t)ECHS_PW * ECHS_PW + 88 * 4 +
+           3 * 256 * 4 + 64 * 4 + 3 * 256;
 }
 
 // f(std::integral_constant<int, K>) for K = K0 .. N - 1, unrolled at compile time
@@ -1179,15 +1179,15 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
 
     uint8_t* W = smem;                                       // [rows16][LW]
     uint8_t* Fl = W + (size_t)rows16 * LW;                   // [rows16][32]
-    uint8_t* Vt = Fl + rows16 * ECHS_PW;                     // [64][32]
-    uint32_t* pb = (uint32_t*)(Vt + ECHS_VCH * ECHS_PW);     // [32] published words, [32] reduced, -1/pivot
+    uint8_t* Gt = Fl + rows16 * ECHS_PW;                     // [32][32] Gt[s][t]: coefficient of original pivot row s in the panel's pivot row t
+    uint32_t* pb = (uint32_t*)(Gt + ECHS_PW * ECHS_PW);      // [32] published words, [32] reduced, -1/pivot
     unsigned long long* mskb = (unsigned long long*)(pb + 72); // [2][4] candidate rows of each wave, by column parity
     int* prl = (int*)(pb + 88);                              // pivot rows, pivot order
     int* pcl = prl + 256;                                    // pivot columns
     int* qrl = pcl + 256;                                    // non-pivot rows (outputs)
     uint32_t* invt = (uint32_t*)(qrl + 256);                 // -1/v mod p
     uint8_t* sel = (uint8_t*)(invt + 64);                    // row selected
-    uint8_t* inpanel = sel + 256;                            // row selected in the current panel
+    uint8_t* inpanels = sel + 256;                           // [2][256] row a pivot of the panel, by panel parity
 
     // invt[v] = -1/v mod p, by search (p <= 46)
     if (x < 64) {
@@ -1197,7 +1197,7 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
                 if (mod22(__umul24((uint32_t)x, j), inv, p) == 1u) iv = p - j;
         invt[x] = iv;
     }
-    for (int i = x; i < 256; i += ECHS_THREADS) { sel[i] = 0; inpanel[i] = 0; }
+    for (int i = x; i < 256; i += ECHS_THREADS) { sel[i] = 0; inpanels[i] = 0; inpanels[256 + i] = 0; }
     // W = [H | 0], rows beyond `rows` zero.  Thread x covers 16-byte chunks
     // x, x + 256, ...; the loads of 8 chunks are in flight together.
     {
@@ -1230,20 +1230,301 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
     int r = 0;
     bool my_sel = x >= rows;     // thread x owns row x for the whole elimination
     int* const act = qrl;        // the panel's active rows (scratch until the outputs)
-    uint8_t* const Gt = Vt;   // [32][32] Gt[s][t]: coefficient of original pivot row s in the panel's pivot row t
-    for (int c0 = 0; c0 < cols && r < maxr; c0 += ECHS_PW) {
-        const int wc = min(ECHS_PW, cols - c0);
-        int rp = 0;
-        // ---- Pivot search by wave 0 alone, over the first (up to) 64 unselected
-        // rows, one per lane: no row after them can be a pivot while one of them
-        // is a candidate.  A column where none is, while later unselected rows
-        // exist, sends the panel to the four-wave elimination below.  Otherwise
-        // the panel's pivot rows are known as combinations G of the original
-        // rows, every other row x is cleared by the pivot rows with its own
-        // entries at the pivot columns as coefficients (the pivot rows are -1
-        // at their own pivot column and 0 at the others), and one MFMA pass
-        // applies it all, the panel's columns included.
-        if (wave == 0) {
+    // ---- Pivot search by wave 0 alone, over the first (up to) 64 unselected
+    // rows, one per lane: no row after them can be a pivot while one of them
+    // is a candidate.  A column where none is, while later unselected rows
+    // exist, sends the panel to the four-wave elimination below.  Otherwise
+    // the panel's pivot rows are known as combinations G of the original
+    // rows, every other row x is cleared by the pivot rows with its own
+    // entries at the pivot columns as coefficients (the pivot rows are -1
+    // at their own pivot column and 0 at the others), and one MFMA pass
+    // applies it all, the panel's columns included.
+    // Panel c0's pivot search (wave 0) runs in the iteration of the panel
+    // before it, beside that panel's trailing update; the iteration at
+    // c0 = -32 only searches panel 0.  The two inpanel arrays alternate by
+    // panel, so the search can mark the next panel's pivots while the update
+    // still reads the current panel's.
+    for (int c0 = -ECHS_PW; c0 < cols && r < maxr; c0 += ECHS_PW) {
+        const int pi = (c0 + ECHS_PW) / ECHS_PW;
+        uint8_t* const inpanel = inpanels + 256 * (pi & 1);          // the current panel's pivots
+        uint8_t* const inpanel_nx = inpanels + 256 * ((pi + 1) & 1); // the next panel's
+        const int nc0 = c0 + ECHS_PW;
+        int rp = 0, fast_rp = -1;
+        if (c0 >= 0) {
+            const int wc = min(ECHS_PW, cols - c0);
+            fast_rp = (int)pb[65];
+            my_sel = x >= rows || sel[x];
+            if (fast_rp >= 0) {
+                rp = fast_rp;
+                if (rp > 0) {
+                    // F = Wc G by MFMA (K = 32, one row block of 16 rows per step):
+                    // Wc[x][t] = W[x][pivot column t] for a row that is not a pivot of
+                    // this panel, the unit vector e_t for the panel's pivot t (its F row
+                    // is G's row t); entries t >= rp are zero.  The lanes of a quarter
+                    // hold k = kq .. kq + 7; the output lane holds F[row][4 (lane / 16) + j]
+                    // and F[row][16 + 4 (lane / 16) + j].
+                    const int kq = (lane >> 4) * 8;
+                    const bool contig = pcl[r + rp - 1] == c0 + rp - 1;   // pivot columns c0 .. c0 + rp - 1
+                    int pcol[8];
+                    uint64_t kmask = 0;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const bool in = kq + j < rp;
+                        pcol[j] = in ? pcl[r + kq + j] : -1;
+                        if (in) kmask |= 0xffull << (8 * j);
+                    }
+                    const long bv0 = *(const long*)(Gt + (lane & 15) * ECHS_PW + kq);
+                    const long bv1 = *(const long*)(Gt + (16 + (lane & 15)) * ECHS_PW + kq);
+                    for (int rb = wave; rb < (rows16 >> 4); rb += ECHS_THREADS / 64) {
+                        const int row = rb * 16 + (lane & 15);
+                        uint64_t av = 0;
+                        if (row < rows) {
+                            const int ip = inpanel[row];
+                            const uint8_t* wr = W + (size_t)row * LW;
+                            if (ip) {
+                                const int u = ip - 1 - kq;
+                                av = (u >= 0 && u < 8) ? 1ull << (8 * u) : 0ull;
+                            } else if (contig) {
+                                av = *(const uint64_t*)(wr + c0 + kq) & kmask;
+                            } else {
+#pragma unroll
+                                for (int j = 0; j < 8; ++j)
+                                    if (pcol[j] >= 0) av |= (uint64_t)wr[pcol[j]] << (8 * j);
+                            }
+                        }
+                        const v4i f0 = __builtin_amdgcn_mfma_i32_16x16x32_i8(bv0, (long)av, v4i{0, 0, 0, 0}, 0, 0, 0);
+                        const v4i f1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(bv1, (long)av, v4i{0, 0, 0, 0}, 0, 0, 0);
+                        uint32_t w0 = 0, w1 = 0;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            w0 |= mod22((uint32_t)f0[j], inv, p) << (8 * j);
+                            w1 |= mod22((uint32_t)f1[j], inv, p) << (8 * j);
+                        }
+                        const int s0 = (lane >> 4) * 4;
+                        *(uint32_t*)(Fl + row * ECHS_PW + s0) = w0;
+                        *(uint32_t*)(Fl + row * ECHS_PW + 16 + s0) = w1;
+                        if (row < rows) {
+                            uint8_t* wt = W + (size_t)row * LW + TC + r;
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                if (s0 + j < rp) wt[s0 + j] = (uint8_t)(w0 >> (8 * j));
+                                if (16 + s0 + j < rp) wt[16 + s0 + j] = (uint8_t)(w1 >> (8 * j));
+                            }
+                        }
+                    }
+                }
+            } else {
+                const bool ok = x < rows;
+                // the row's panel entries: column k in half (k & 1) of word k / 2
+                uint32_t D[16], F[16];
+                uint32_t scale = 1;
+                int pidx = -1;
+                {
+                    uint4 a = make_uint4(0, 0, 0, 0), b = make_uint4(0, 0, 0, 0);
+                    if (ok) {
+                        a = *(const uint4*)(W + (size_t)x * LW + c0);
+                        b = *(const uint4*)(W + (size_t)x * LW + c0 + 16);
+                    }
+                    const uint32_t d[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        uint32_t lo = __builtin_amdgcn_perm(0u, d[i], 0x0c010c00u);
+                        uint32_t hi = __builtin_amdgcn_perm(0u, d[i], 0x0c030c02u);
+                        if (wc < ECHS_PW) {   // columns past the block hold other data: clear them
+                            if (4 * i >= wc) lo &= 0u; else if (4 * i + 1 >= wc) lo &= 0xffffu;
+                            if (4 * i + 2 >= wc) hi &= 0u; else if (4 * i + 3 >= wc) hi &= 0xffffu;
+                        }
+                        D[2 * i] = lo;
+                        D[2 * i + 1] = hi;
+                    }
+#pragma unroll
+                    for (int w = 0; w < 16; ++w) F[w] = 0;
+                }
+                // Column k of the panel (k static, so every register index is).  Every
+                // decision below is taken from LDS values all threads read alike, so
+                // rp stays uniform.
+                static_for<0, ECHS_PW>([&](auto kc) {
+                    constexpr int k = decltype(kc)::value;
+                    if (k >= wc || r + rp >= maxr) return;
+                    constexpr int wk = k >> 1, hk = 16 * (k & 1);
+                    const uint32_t red = mod22((D[wk] >> hk) & 0xffffu, inv, p);
+                    const unsigned long long bm = __ballot(!my_sel && red != 0u);
+                    // by column parity: a column without a pivot has no second barrier
+                    unsigned long long* msk = mskb + 4 * (k & 1);
+                    if (lane == 0) msk[wave] = bm;
+                    __syncthreads();
+                    const unsigned long long m0w = msk[0], m1w = msk[1], m2w = msk[2], m3w = msk[3];
+                    const int Q = m0w ? 0 : m1w ? 1 : m2w ? 2 : m3w ? 3 : -1;
+                    if (Q < 0) return;    // no candidate row: not a pivot column
+                    const unsigned long long mq = Q == 0 ? m0w : Q == 1 ? m1w : Q == 2 ? m2w : m3w;
+                    const int prow = 64 * Q + (__ffsll((long long)mq) - 1);   // first candidate row
+                    const bool me = x == prow;
+                    if (me) {
+                        // publish the row's unreduced words; its own transformation
+                        // entry (index rp) is 1; and -1 / pivot
+                        const uint32_t sv = invt[red];
+                        const uint32_t one = 1u << (16 * (rp & 1));
+#pragma unroll
+                        for (int w = 0; w < 16; w += 4) {
+                            *(uint4*)(pb + w) = make_uint4(D[w], D[w + 1], D[w + 2], D[w + 3]);
+                            *(uint4*)(pb + 16 + w) = make_uint4(
+                                F[w] + (w == (rp >> 1) ? one : 0u), F[w + 1] + (w + 1 == (rp >> 1) ? one : 0u),
+                                F[w + 2] + (w + 2 == (rp >> 1) ? one : 0u), F[w + 3] + (w + 3 == (rp >> 1) ? one : 0u));
+                        }
+                        pb[64] = sv;
+                    }
+                    if (wave == Q) {
+                        // the pivot's wave reduces the 64 published entries, one per lane
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        ((uint16_t*)(pb + 32))[lane] = (uint16_t)mod22(((const uint16_t*)pb)[lane], inv, p);
+                    }
+                    __syncthreads();
+                    uint32_t pv[32];
+#pragma unroll
+                    for (int w = 0; w < 32; w += 4) {
+                        const uint4 t4 = *(const uint4*)(pb + 32 + w);
+                        pv[w] = t4.x; pv[w + 1] = t4.y; pv[w + 2] = t4.z; pv[w + 3] = t4.w;
+                    }
+                    const uint32_t sv = pb[64];
+                    const uint32_t f = me ? 0u : mod22(__umul24(red, sv), inv, p);
+                    const uint32_t f2 = f * 0x10001u;
+                    // the reduced pivot row is zero in the panel's earlier columns and
+                    // in transformation entries past rp <= k
+#pragma unroll
+                    for (int w = wk; w < 16; ++w) D[w] = pkmad16(f2, pv[w], D[w]);
+#pragma unroll
+                    for (int w = 0; w <= wk; ++w) F[w] = pkmad16(f2, pv[16 + w], F[w]);
+                    if (me) {
+                        my_sel = true;
+                        scale = sv;
+                        pidx = rp;
+                        prl[r + rp] = prow;
+                        pcl[r + rp] = c0 + k;
+                        sel[prow] = 1;
+                        inpanel[prow] = 1;
+                    }
+                    ++rp;
+                });
+                // reduce, give the pivot row its own transformation entry 1 and scale
+                // it to pivot -1, then write the panel, F (for the MFMA) and the new
+                // transformation columns (F itself) back to LDS
+                if (ok) {
+                    uint32_t pk[8], fk[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        uint32_t v[4], g[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int col = 4 * i + j;
+                            const uint32_t wd = D[col >> 1], fw = F[col >> 1];
+                            const uint32_t dv = (col & 1) ? (wd >> 16) : (wd & 0xffffu);
+                            uint32_t fv = (col & 1) ? (fw >> 16) : (fw & 0xffffu);
+                            if (col == pidx) fv += 1;
+                            v[j] = mod22(__umul24(dv, scale), inv, p);
+                            g[j] = mod22(__umul24(fv, scale), inv, p);
+                        }
+                        pk[i] = v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
+                        fk[i] = g[0] | (g[1] << 8) | (g[2] << 16) | (g[3] << 24);
+                    }
+                    uint8_t* wr = W + (size_t)x * LW;
+                    if (wc == ECHS_PW) {
+                        *(uint4*)(wr + c0) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+                        *(uint4*)(wr + c0 + 16) = make_uint4(pk[4], pk[5], pk[6], pk[7]);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < ECHS_PW; ++j)
+                            if (j < wc) wr[c0 + j] = (uint8_t)(pk[j >> 2] >> (8 * (j & 3)));
+                    }
+                    *(uint4*)(Fl + x * ECHS_PW) = make_uint4(fk[0], fk[1], fk[2], fk[3]);
+                    *(uint4*)(Fl + x * ECHS_PW + 16) = make_uint4(fk[4], fk[5], fk[6], fk[7]);
+#pragma unroll
+                    for (int t = 0; t < ECHS_PW; ++t)
+                        if (t < rp) wr[TC + r + t] = (uint8_t)(fk[t >> 2] >> (8 * (t & 3)));
+                } else if (x < rows16) {   // rows past `rows` (padding of the MFMA tiles)
+                    *(uint4*)(Fl + x * ECHS_PW) = make_uint4(0, 0, 0, 0);
+                    *(uint4*)(Fl + x * ECHS_PW + 16) = make_uint4(0, 0, 0, 0);
+                }
+            }
+            __syncthreads();
+        }
+        const bool next = nc0 < cols && r + rp < maxr;
+        if (rp > 0) {
+            // Trailing update, in chunks of 32 columns, each chunk by one wave over
+            // all rows: segment 0 the data columns from the panel on (from the
+            // next panel when the four-wave elimination has written this one),
+            // segment 1 the transformation columns of earlier pivots.  The MFMA's
+            // B operand (16 columns x 8 pivots per group of 16 lanes) is read
+            // from the pivot rows themselves with ds_read_b64_tr_b8 before the
+            // wave writes any of its columns; no other wave touches them.  When
+            // there is a next panel, wave 0 updates its columns first and then
+            // searches it while waves 1 to 3 update the rest.
+            const int ybeg = fast_rp >= 0 ? c0 : nc0;
+            const int n0c = ybeg < cols ? (cols - ybeg + ECHS_CH - 1) / ECHS_CH : 0;
+            const int nch = n0c + (r + ECHS_CH - 1) / ECHS_CH;
+            const int qn = (nc0 - ybeg) / ECHS_CH;     // the next panel's chunk
+            const int kk = (lane >> 4) * 8 + ((lane & 15) >> 1);
+            const int po = (kk < rp ? prl[r + kk] : prl[r]) * LW + ((lane & 1) << 3);
+            const auto chunk = [&](int q) {
+                int y0, nc;
+                if (q < n0c) {
+                    y0 = ybeg + q * ECHS_CH;
+                    nc = min(ECHS_CH, cols - y0);
+                } else {
+                    y0 = TC + (q - n0c) * ECHS_CH;
+                    nc = min(ECHS_CH, TC + r - y0);
+                }
+                const long b0 = __builtin_bit_cast(long, lds_read_tr8(W + po + y0));
+                const long b1 = __builtin_bit_cast(long, lds_read_tr8(W + po + y0 + 16));
+                for (int rb = 0; rb < (rows16 >> 4); ++rb) {
+                    const int row = rb * 16 + (lane & 15);
+                    const long av = *(const long*)(Fl + row * ECHS_PW + (lane >> 4) * 8);
+                    v4i acc[2];
+                    acc[0] = __builtin_amdgcn_mfma_i32_16x16x32_i8(b0, av, v4i{0, 0, 0, 0}, 0, 0, 0);
+                    acc[1] = nc > 16 ? __builtin_amdgcn_mfma_i32_16x16x32_i8(b1, av, v4i{0, 0, 0, 0}, 0, 0, 0)
+                                     : v4i{0, 0, 0, 0};
+                    if (row < rows) {
+                        const bool keep = !inpanel[row];
+                        uint32_t* wrow = (uint32_t*)(W + (size_t)row * LW + y0);
+#pragma unroll
+                        for (int cb = 0; cb < 2; ++cb) {
+                            const int cc = cb * 16 + (lane >> 4) * 4;
+                            if (cc < nc) {
+                                const uint32_t old = wrow[cc >> 2];
+                                uint32_t out = 0;
+#pragma unroll
+                                for (int j = 0; j < 4; ++j) {
+                                    const uint32_t ob = (old >> (8 * j)) & 0xffu;
+                                    const uint32_t nv = mod22((keep ? ob : 0u) + (uint32_t)acc[cb][j], inv, p);
+                                    out |= (cc + j < nc ? nv : ob) << (8 * j);
+                                }
+                                wrow[cc >> 2] = out;
+                            }
+                        }
+                    }
+                }
+            };
+            if (next) {
+                if (wave == 0) {
+                    chunk(qn);
+                } else {
+                    for (int j = wave - 1;; j += 3) {
+                        const int q = j + (j >= qn ? 1 : 0);
+                        if (q >= nch) break;
+                        chunk(q);
+                    }
+                }
+            } else {
+                for (int q = wave; q < nch; q += 4) chunk(q);
+            }
+        }
+        if (next && wave == 0) {
+            // the next panel's columns are final: search it
+            const int c0 = nc0, r_nx = r + rp;
+            const int r = r_nx;
+            uint8_t* const inpanel = inpanel_nx;
+            const int wc = min(ECHS_PW, cols - c0);
             int total = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -1361,277 +1642,7 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
             if (lane == 0) pb[65] = fb ? 0xffffffffu : (uint32_t)rpa;
         }
         __syncthreads();
-        const int fast_rp = (int)pb[65];
-        if (fast_rp >= 0) {
-            rp = fast_rp;
-            my_sel = x >= rows || sel[x];
-            if (rp > 0) {
-                // F = Wc G by MFMA (K = 32, one row block of 16 rows per step):
-                // Wc[x][t] = W[x][pivot column t] for a row that is not a pivot of
-                // this panel, the unit vector e_t for the panel's pivot t (its F row
-                // is G's row t); entries t >= rp are zero.  The lanes of a quarter
-                // hold k = kq .. kq + 7; the output lane holds F[row][4 (lane / 16) + j]
-                // and F[row][16 + 4 (lane / 16) + j].
-                const int kq = (lane >> 4) * 8;
-                const bool contig = pcl[r + rp - 1] == c0 + rp - 1;   // pivot columns c0 .. c0 + rp - 1
-                int pcol[8];
-                uint64_t kmask = 0;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const bool in = kq + j < rp;
-                    pcol[j] = in ? pcl[r + kq + j] : -1;
-                    if (in) kmask |= 0xffull << (8 * j);
-                }
-                const long bv0 = *(const long*)(Gt + (lane & 15) * ECHS_PW + kq);
-                const long bv1 = *(const long*)(Gt + (16 + (lane & 15)) * ECHS_PW + kq);
-                for (int rb = wave; rb < (rows16 >> 4); rb += ECHS_THREADS / 64) {
-                    const int row = rb * 16 + (lane & 15);
-                    uint64_t av = 0;
-                    if (row < rows) {
-                        const int ip = inpanel[row];
-                        const uint8_t* wr = W + (size_t)row * LW;
-                        if (ip) {
-                            const int u = ip - 1 - kq;
-                            av = (u >= 0 && u < 8) ? 1ull << (8 * u) : 0ull;
-                        } else if (contig) {
-                            av = *(const uint64_t*)(wr + c0 + kq) & kmask;
-                        } else {
-#pragma unroll
-                            for (int j = 0; j < 8; ++j)
-                                if (pcol[j] >= 0) av |= (uint64_t)wr[pcol[j]] << (8 * j);
-                        }
-                    }
-                    const v4i f0 = __builtin_amdgcn_mfma_i32_16x16x32_i8(bv0, (long)av, v4i{0, 0, 0, 0}, 0, 0, 0);
-                    const v4i f1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(bv1, (long)av, v4i{0, 0, 0, 0}, 0, 0, 0);
-                    uint32_t w0 = 0, w1 = 0;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        w0 |= mod22((uint32_t)f0[j], inv, p) << (8 * j);
-                        w1 |= mod22((uint32_t)f1[j], inv, p) << (8 * j);
-                    }
-                    const int s0 = (lane >> 4) * 4;
-                    *(uint32_t*)(Fl + row * ECHS_PW + s0) = w0;
-                    *(uint32_t*)(Fl + row * ECHS_PW + 16 + s0) = w1;
-                    if (row < rows) {
-                        uint8_t* wt = W + (size_t)row * LW + TC + r;
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            if (s0 + j < rp) wt[s0 + j] = (uint8_t)(w0 >> (8 * j));
-                            if (16 + s0 + j < rp) wt[16 + s0 + j] = (uint8_t)(w1 >> (8 * j));
-                        }
-                    }
-                }
-            }
-        } else {
-            const bool ok = x < rows;
-            // the row's panel entries: column k in half (k & 1) of word k / 2
-            uint32_t D[16], F[16];
-            uint32_t scale = 1;
-            int pidx = -1;
-            {
-                uint4 a = make_uint4(0, 0, 0, 0), b = make_uint4(0, 0, 0, 0);
-                if (ok) {
-                    a = *(const uint4*)(W + (size_t)x * LW + c0);
-                    b = *(const uint4*)(W + (size_t)x * LW + c0 + 16);
-                }
-                const uint32_t d[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    uint32_t lo = __builtin_amdgcn_perm(0u, d[i], 0x0c010c00u);
-                    uint32_t hi = __builtin_amdgcn_perm(0u, d[i], 0x0c030c02u);
-                    if (wc < ECHS_PW) {   // columns past the block hold other data: clear them
-                        if (4 * i >= wc) lo &= 0u; else if (4 * i + 1 >= wc) lo &= 0xffffu;
-                        if (4 * i + 2 >= wc) hi &= 0u; else if (4 * i + 3 >= wc) hi &= 0xffffu;
-                    }
-                    D[2 * i] = lo;
-                    D[2 * i + 1] = hi;
-                }
-#pragma unroll
-                for (int w = 0; w < 16; ++w) F[w] = 0;
-            }
-            // Column k of the panel (k static, so every register index is).  Every
-            // decision below is taken from LDS values all threads read alike, so
-            // rp stays uniform.
-            static_for<0, ECHS_PW>([&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                if (k >= wc || r + rp >= maxr) return;
-                constexpr int wk = k >> 1, hk = 16 * (k & 1);
-                const uint32_t red = mod22((D[wk] >> hk) & 0xffffu, inv, p);
-                const unsigned long long bm = __ballot(!my_sel && red != 0u);
-                // by column parity: a column without a pivot has no second barrier
-                unsigned long long* msk = mskb + 4 * (k & 1);
-                if (lane == 0) msk[wave] = bm;
-                __syncthreads();
-                const unsigned long long m0w = msk[0], m1w = msk[1], m2w = msk[2], m3w = msk[3];
-                const int Q = m0w ? 0 : m1w ? 1 : m2w ? 2 : m3w ? 3 : -1;
-                if (Q < 0) return;    // no candidate row: not a pivot column
-                const unsigned long long mq = Q == 0 ? m0w : Q == 1 ? m1w : Q == 2 ? m2w : m3w;
-                const int prow = 64 * Q + (__ffsll((long long)mq) - 1);   // first candidate row
-                const bool me = x == prow;
-                if (me) {
-                    // publish the row's unreduced words; its own transformation
-                    // entry (index rp) is 1; and -1 / pivot
-                    const uint32_t sv = invt[red];
-                    const uint32_t one = 1u << (16 * (rp & 1));
-#pragma unroll
-                    for (int w = 0; w < 16; w += 4) {
-                        *(uint4*)(pb + w) = make_uint4(D[w], D[w + 1], D[w + 2], D[w + 3]);
-                        *(uint4*)(pb + 16 + w) = make_uint4(
-                            F[w] + (w == (rp >> 1) ? one : 0u), F[w + 1] + (w + 1 == (rp >> 1) ? one : 0u),
-                            F[w + 2] + (w + 2 == (rp >> 1) ? one : 0u), F[w + 3] + (w + 3 == (rp >> 1) ? one : 0u));
-                    }
-                    pb[64] = sv;
-                }
-                if (wave == Q) {
-                    // the pivot's wave reduces the 64 published entries, one per lane
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    ((uint16_t*)(pb + 32))[lane] = (uint16_t)mod22(((const uint16_t*)pb)[lane], inv, p);
-                }
-                __syncthreads();
-                uint32_t pv[32];
-#pragma unroll
-                for (int w = 0; w < 32; w += 4) {
-                    const uint4 t4 = *(const uint4*)(pb + 32 + w);
-                    pv[w] = t4.x; pv[w + 1] = t4.y; pv[w + 2] = t4.z; pv[w + 3] = t4.w;
-                }
-                const uint32_t sv = pb[64];
-                const uint32_t f = me ? 0u : mod22(__umul24(red, sv), inv, p);
-                const uint32_t f2 = f * 0x10001u;
-                // the reduced pivot row is zero in the panel's earlier columns and
-                // in transformation entries past rp <= k
-#pragma unroll
-                for (int w = wk; w < 16; ++w) D[w] = pkmad16(f2, pv[w], D[w]);
-#pragma unroll
-                for (int w = 0; w <= wk; ++w) F[w] = pkmad16(f2, pv[16 + w], F[w]);
-                if (me) {
-                    my_sel = true;
-                    scale = sv;
-                    pidx = rp;
-                    prl[r + rp] = prow;
-                    pcl[r + rp] = c0 + k;
-                    sel[prow] = 1;
-                    inpanel[prow] = 1;
-                }
-                ++rp;
-            });
-            // reduce, give the pivot row its own transformation entry 1 and scale
-            // it to pivot -1, then write the panel, F (for the MFMA) and the new
-            // transformation columns (F itself) back to LDS
-            if (ok) {
-                uint32_t pk[8], fk[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    uint32_t v[4], g[4];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int col = 4 * i + j;
-                        const uint32_t wd = D[col >> 1], fw = F[col >> 1];
-                        const uint32_t dv = (col & 1) ? (wd >> 16) : (wd & 0xffffu);
-                        uint32_t fv = (col & 1) ? (fw >> 16) : (fw & 0xffffu);
-                        if (col == pidx) fv += 1;
-                        v[j] = mod22(__umul24(dv, scale), inv, p);
-                        g[j] = mod22(__umul24(fv, scale), inv, p);
-                    }
-                    pk[i] = v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24);
-                    fk[i] = g[0] | (g[1] << 8) | (g[2] << 16) | (g[3] << 24);
-                }
-                uint8_t* wr = W + (size_t)x * LW;
-                if (wc == ECHS_PW) {
-                    *(uint4*)(wr + c0) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
-                    *(uint4*)(wr + c0 + 16) = make_uint4(pk[4], pk[5], pk[6], pk[7]);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < ECHS_PW; ++j)
-                        if (j < wc) wr[c0 + j] = (uint8_t)(pk[j >> 2] >> (8 * (j & 3)));
-                }
-                *(uint4*)(Fl + x * ECHS_PW) = make_uint4(fk[0], fk[1], fk[2], fk[3]);
-                *(uint4*)(Fl + x * ECHS_PW + 16) = make_uint4(fk[4], fk[5], fk[6], fk[7]);
-#pragma unroll
-                for (int t = 0; t < ECHS_PW; ++t)
-                    if (t < rp) wr[TC + r + t] = (uint8_t)(fk[t >> 2] >> (8 * (t & 3)));
-            } else if (x < rows16) {   // rows past `rows` (padding of the MFMA tiles)
-                *(uint4*)(Fl + x * ECHS_PW) = make_uint4(0, 0, 0, 0);
-                *(uint4*)(Fl + x * ECHS_PW + 16) = make_uint4(0, 0, 0, 0);
-            }
-        }
-        __syncthreads();
-        if (rp > 0) {
-            int prow_off[8];     // W offsets of pivot rows (x & 3) * 8 .. + 7 of this panel, -1 past rp
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int t = (x & 3) * 8 + j;
-                prow_off[j] = t < rp ? prl[r + t] * LW : -1;
-            }
-            // segment 0: data columns right of the panel; segment 1: transformation
-            // columns of the pivots of earlier panels
-            for (int seg = 0; seg < 2; ++seg) {
-                const int ybeg = seg == 0 ? (fast_rp >= 0 ? c0 : c0 + ECHS_PW) : TC;
-                const int yend = seg == 0 ? cols : TC + r;
-                for (int y0 = ybeg; y0 < yend; y0 += ECHS_VCH) {
-                    const int nc = min(ECHS_VCH, yend - y0);
-                    {   // Vt[yy][t] = W[pivot row t][y0 + yy]
-                        const int yy = x >> 2;
-                        uint32_t lo = 0, hi = 0;
-                        if (yy < nc) {
-#pragma unroll
-                            for (int j = 0; j < 8; ++j) {
-                                const uint32_t b = prow_off[j] >= 0 ? W[prow_off[j] + y0 + yy] : 0u;
-                                if (j < 4) lo |= b << (8 * j); else hi |= b << (8 * (j - 4));
-                            }
-                        }
-                        *(uint2*)(Vt + yy * ECHS_PW + (x & 3) * 8) = make_uint2(lo, hi);
-                    }
-                    __syncthreads();
-                    // a wave owns row blocks rb = wave, wave + 4, ...: for each, the
-                    // products of the (up to) four 16-column blocks first, then the updates
-                    const int ncb = (nc + 15) >> 4;
-                    for (int rb = wave; rb < (rows16 >> 4); rb += ECHS_THREADS / 64) {
-                        v4i av = v4i{0, 0, 0, 0};
-                        if (lane < 32) av = *(const v4i*)(Fl + (rb * 16 + (lane & 15)) * ECHS_PW + (lane >> 4) * 16);
-                        v4i acc[4];
-#pragma unroll
-                        for (int cb = 0; cb < 4; ++cb) {
-                            acc[cb] = v4i{0, 0, 0, 0};
-                            if (cb < ncb) {
-                                v4i bv = v4i{0, 0, 0, 0};
-                                if (lane < 32) bv = *(const v4i*)(Vt + (cb * 16 + (lane & 15)) * ECHS_PW + (lane >> 4) * 16);
-                                acc[cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(bv, av, acc[cb], 0, 0, 0);
-                            }
-                        }
-                        const int row = rb * 16 + (lane & 15);
-                        if (row < rows) {
-                            const bool keep = !inpanel[row];
-                            uint32_t* wrow = (uint32_t*)(W + (size_t)row * LW + y0);
-                            uint32_t old[4];
-#pragma unroll
-                            for (int cb = 0; cb < 4; ++cb) {
-                                const int cc = cb * 16 + (lane >> 4) * 4;
-                                old[cb] = cc < nc ? wrow[cc >> 2] : 0u;
-                            }
-#pragma unroll
-                            for (int cb = 0; cb < 4; ++cb) {
-                                const int cc = cb * 16 + (lane >> 4) * 4;
-                                if (cc < nc) {
-                                    uint32_t out = 0;
-#pragma unroll
-                                    for (int j = 0; j < 4; ++j) {
-                                        const uint32_t ob = (old[cb] >> (8 * j)) & 0xffu;
-                                        const uint32_t nv = mod22((keep ? ob : 0u) + (uint32_t)acc[cb][j], inv, p);
-                                        out |= (cc + j < nc ? nv : ob) << (8 * j);
-                                    }
-                                    wrow[cc >> 2] = out;
-                                }
-                            }
-                        }
-                    }
-                    __syncthreads();
-                }
-            }
-            for (int t = x; t < rp; t += ECHS_THREADS) inpanel[prl[r + t]] = 0;
-            __syncthreads();
-        }
+        for (int t = x; t < rp; t += ECHS_THREADS) inpanel[prl[r + t]] = 0;
         r += rp;
     }
     // ---- outputs
@@ -1836,11 +1847,12 @@ public:
             if (err) *err = "counter allocation failed";
             return false;
         }
-        // lanes 1 and 2: streams of their own at the default priority;
+        // lanes 1, 2 and 3: streams of their own at the default priority;
         // non-blocking, so they never synchronise implicitly with the legacy
         // default stream
         if (hipStreamCreateWithFlags(&lane1_, hipStreamNonBlocking) != hipSuccess ||
-            hipStreamCreateWithFlags(&lane2_, hipStreamNonBlocking) != hipSuccess) {
+            hipStreamCreateWithFlags(&lane2_, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&lane3_, hipStreamNonBlocking) != hipSuccess) {
             if (err) *err = "stream creation failed";
             return false;
         }
@@ -1962,7 +1974,9 @@ public:
         cur_ = stream_;
     }
     void set_lane(int lane) override { cur_ = lane_stream(lane); }
-    hipStream_t lane_stream(int lane) const { return lane == 1 ? lane1_ : lane == 2 ? lane2_ : stream_; }
+    hipStream_t lane_stream(int lane) const {
+        return lane == 1 ? lane1_ : lane == 2 ? lane2_ : lane == 3 ? lane3_ : stream_;
+    }
     void* create_stream() override {
         hipStream_t st = nullptr;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
@@ -2221,6 +2235,7 @@ private:
     void sync_all() {
         HIP_OK(hipStreamSynchronize(lane1_));
         HIP_OK(hipStreamSynchronize(lane2_));
+        HIP_OK(hipStreamSynchronize(lane3_));
         HIP_OK(hipStreamSynchronize(stream_));
         for (hipEvent_t e : marks_) mark_pool_.push_back(e);
         mark_base_ += (int)marks_.size();
@@ -2231,6 +2246,7 @@ private:
     hipStream_t stream_ = nullptr;   // lane 0: the caller's stream
     hipStream_t lane1_ = nullptr;    // lane 1
     hipStream_t lane2_ = nullptr;    // lane 2
+    hipStream_t lane3_ = nullptr;    // lane 3
     hipStream_t cur_ = nullptr;      // the lane kernels go to
     std::vector<hipEvent_t> marks_, mark_pool_;
     int32_t* counts_host_ = nullptr;   // counts_buffer(): host view

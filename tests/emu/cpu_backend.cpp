@@ -48,9 +48,9 @@ public:
     void copy(void* dst, const void* src, size_t bytes) override {
         if (bytes && chk(dst, bytes, "copy") && chk(src, bytes, "copy")) memmove(dst, src, bytes);
     }
-    // Lanes: the jobs of lanes 1 and 2 are queued and run as late as the
+    // Lanes: the jobs of lanes 1, 2 and 3 are queued and run as late as the
     // planner's marks allow (when lane 0 waits for them, when a queued wait of
-    // the other lane needs them, or at sync).  Any job the planner ordered
+    // another lane needs them, or at sync).  Any job the planner ordered
     // wrongly across the lanes then reads or overwrites data out of turn, and
     // the results stop matching the oracle.  GFECH_EMU_EAGER=1 runs
     // everything at once instead.  A mark is (queue length << 2) | lane; lane
@@ -72,9 +72,10 @@ public:
         }
     }
     void sync() override {
-        while (done_[1] < q_[1].size() || done_[2] < q_[2].size()) {
+        while (done_[1] < q_[1].size() || done_[2] < q_[2].size() || done_[3] < q_[3].size()) {
             drain(1, q_[1].size());
             drain(2, q_[2].size());
+            drain(3, q_[3].size());
         }
     }
     int error() const override { return err_; }
@@ -272,8 +273,8 @@ private:
     int err_ = 0;
     int lane_ = 0;
     bool defer_ = !(getenv("GFECH_EMU_EAGER") && getenv("GFECH_EMU_EAGER")[0] == '1');
-    std::vector<std::function<void()>> q_[3];
-    size_t done_[3] = {0, 0, 0};
+    std::vector<std::function<void()>> q_[4];
+    size_t done_[4] = {0, 0, 0, 0};
 
     static uint32_t inv(uint32_t a, uint32_t p) {   // a^(p-2)
         uint32_t r = 1, b = a % p, x = p - 2;
