@@ -1073,9 +1073,9 @@ struct Engine::Impl {
     }
 
     // the near sets first, so the next layer's priority products wait only
-    // for them, then the mid sets (after the previous far sets, which update
-    // their blocks too); the far sets run on lane 3
-    void issue_bulk(int ready) {
+    // for them (issue_near), then the mid sets (after the previous far sets,
+    // which update their blocks too) and the far sets on lane 3 (issue_rest)
+    void issue_near(int ready) {
         if (b1.empty() && b3.empty() && b4.empty() && b6.empty()) {
             // nothing new: a wait for the near set must cover every mid set issued so far
             near_done = mid_done;
@@ -1088,6 +1088,11 @@ struct Engine::Impl {
         flush(be, b4.near, shared);
         flush(be, b6.near, shared);
         near_done = be.mark(1);
+        be.set_lane(0);
+    }
+    void issue_rest(int ready) {
+        if (b1.empty() && b3.empty() && b4.empty() && b6.empty()) return;
+        be.set_lane(1);
         if (far_done >= 0) be.wait_mark(1, far_done);
         flush(be, b1.mid, shared);
         flush(be, b3.mid, shared);
@@ -1102,6 +1107,10 @@ struct Engine::Impl {
         flush(be, b6.far, shared);
         far_done = be.mark(3);
         be.set_lane(0);
+    }
+    void issue_bulk(int ready) {
+        issue_near(ready);
+        issue_rest(ready);
     }
     // lane 0 waits for every bulk part issued so far
     void wait_bulk() {
@@ -1204,11 +1213,13 @@ struct Engine::Impl {
             bool any = false;
             for (Plan* pl : s1) { pl->cd_ech(ops, false); any = any || pl->any_ech(); }
             flush(be, ops, shared);
-            issue_bulk(ready);
+            issue_near(ready);
             // UpdateRow (1)'s priority products overwrite the near set's columns
             // and need nothing this layer's ECH computes: lane 2 runs them beside
-            // the ECH (their bulk part joins the next layer's, b1 being empty now)
-            for (Plan* pl : s1) pl->ur1(u1, b1);
+            // the ECH, issued before the mid and far sets so that they reach the
+            // device ahead of them (their bulk part joins the next layer's)
+            Bulk b1n;
+            for (Plan* pl : s1) pl->ur1(u1, b1n);
             u1_done = -1;
             if (!u1.empty()) {
                 be.set_lane(2);
@@ -1218,6 +1229,8 @@ struct Engine::Impl {
                 u1_done = be.mark(2);
                 be.set_lane(0);
             }
+            issue_rest(ready);
+            b1 = std::move(b1n);
             for (Plan* pl : s1) pl->clear_counts();
             if (any) {
                 read_counts();
