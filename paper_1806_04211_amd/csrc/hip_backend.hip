@@ -1120,9 +1120,12 @@ __global__ void __launch_bounds__(512) k_ech_panel(Src src) {
 // ballots (the paper's pivot rule); the pivot row's thread publishes its
 // words in LDS, the lanes of its wave reduce the 64 entries, one each, and
 // after the second barrier every thread reads them and updates its row.
-// After a panel the four waves apply F to the remaining columns and to the
-// transformation columns of earlier pivots with MFMA, in place in LDS:
+// That is the fallback; the usual panel is eliminated by wave 0 alone (see
+// the pivot search below).  After a panel, F is applied to the remaining
+// columns and to the transformation columns of earlier pivots with MFMA, in
+// place in LDS, one wave per chunk of 32 columns:
 //     W[x][y] := (x a pivot of this panel ? 0 : W[x][y]) + sum_t F[x][t] W[pivot row t][y]
+// while wave 0, once the next panel's columns are done, searches that panel.
 constexpr int ECHS_MAX_ROWS = 256;
 constexpr int ECHS_MAX_P = 46;
 constexpr int ECHS_THREADS = 256;
