@@ -397,9 +397,16 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
     // 16-byte aligned, and B rows either aligned for the vector load or with
     // 3 spare columns after the tile for the realigning read
     const bool b_aligned = (((uintptr_t)g.B | (uintptr_t)g.ldb) & 15) == 0;
-    const bool fast = m0 + TM <= g.M && n0 + TN <= g.N && ((uintptr_t)g.A & 15) == 0 && (g.lda & 15) == 0 &&
-                      (b_aligned || n0 + TN + 3 <= g.N);
+    const bool a_aligned = ((uintptr_t)g.A & 15) == 0 && (g.lda & 15) == 0;
+    const bool fast = m0 + TM <= g.M && n0 + TN <= g.N && a_aligned && (b_aligned || n0 + TN + 3 <= g.N);
     const int nk_fast = fast ? g.K / TK : 0;
+    // The streamed path also takes edge tiles: A rows past M read row M - 1,
+    // B and C chunks past N read column 0 (with N a multiple of 16 a chunk is
+    // wholly inside or outside), so every read stays inside the operands, and
+    // what they contribute lands in rows or columns of D that are not stored.
+    const bool stream = a_aligned && b_aligned && !g.brow && adj == 0 && g.K >= TK &&
+                        (n0 + TN <= g.N || (g.N & 15) == 0);
+    const int nk_str = stream ? g.K / TK : 0;
     const int r16 = lane & 15;
     const int r32 = lane & 31;
     const int kh = lane >> 5;
@@ -438,7 +445,7 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
     int epi_st = -1;
     const bool al16_c = !g.C || (!g.crow && ((((uintptr_t)g.C) | (uintptr_t)g.ldc) & 15) == 0);
     const bool al16_d = ((((uintptr_t)g.D) | (uintptr_t)g.ldd) & 15) == 0;
-    if (nk_fast > 0 && b_aligned && !g.brow && adj == 0) {
+    if (stream) {
         const bool lds_epi = al16_c && al16_d;
         // ---- streamed into LDS, two steps ahead.  Per wave and stage: four
         // 1 KB pieces of the A tile (chunk P = piece * 64 + lane is row P / 4,
@@ -450,12 +457,13 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int P = (wave * 4 + t) * 64 + lane, row = P >> 2, pos = P & 3;
-            asrc[t] = g.A + (int64_t)(m0 + row) * g.lda + ((pos ^ ((row >> 2) & 3)) << 4);
+            asrc[t] = g.A + (int64_t)min(m0 + row, g.M - 1) * g.lda + ((pos ^ ((row >> 2) & 3)) << 4);
         }
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             const int P = (wave * 2 + t) * 64 + lane, kr = P >> 3, pos = P & 7;
-            bsrc[t] = g.B + (int64_t)kr * g.ldb + n0 + ((pos ^ (kr & 7)) << 4);
+            const int col = n0 + ((pos ^ (kr & 7)) << 4);
+            bsrc[t] = g.B + (int64_t)kr * g.ldb + (col < g.N ? col : 0);
         }
         const int64_t bstep = (int64_t)TK * g.ldb;
         const auto issue = [&](int ks, int st) {
@@ -469,42 +477,47 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
                       __builtin_amdgcn_readfirstlane(base + (uint32_t)(GEMM_A_STAGE + (wave * 2 + t) * 1024)));
         };
         issue(0, 0);
-        if (nk_fast > 1) issue(1, 1);
-        int st = 0;
-        for (int ks = 0; ks < nk; ++ks) {
-            if (ks < nk_fast) {
-                // this wave's pieces of step ks have landed (at most the 6 of step
-                // ks + 1 still in flight); the barrier makes every wave's visible
-                // and ends every wave's reads of step ks - 1, whose stage step
-                // ks + 2 then overwrites
-                if (ks + 1 < nk_fast) vm_wait<6>(); else vm_wait<0>();
-                __syncthreads();
-                if (ks + 2 < nk_fast) issue(ks + 2, st == 0 ? 2 : st - 1);
-            } else {
-                // the K tail (one step): the stage was last read two steps ago
-                gemm_load<false>(g, m0, n0, ks * TK, tid, adj, R);
-                gemm_store_lds(R, As(st), Bs(st), tid);
-                __syncthreads();
-            }
-            if (ks == nk - 1 && lds_epi) {
-                // the last step: the other two stages are free; the C tile goes
-                // there (rows 0..191 in the next stage, 192..255 in the one after)
-                // while the last MFMAs run
-                epi_st = st;
-                if (g.C) {
-                    const uint32_t s1 = lds0 + (uint32_t)((st == 2 ? 0 : st + 1) * GEMM_STAGE);
-                    const uint32_t s2 = lds0 + (uint32_t)((st == 0 ? 2 : st - 1) * GEMM_STAGE);
+        if (nk_str > 1) issue(1, 1);
+        // the C tile of the last step goes to the other two stages (rows 0..191
+        // in the next stage, 192..255 in the one after) while its MFMAs run
+        const auto fetch_c = [&](int st) {
+            epi_st = st;
+            if (!g.C) return;
+            const uint32_t s1 = lds0 + (uint32_t)((st == 2 ? 0 : st + 1) * GEMM_STAGE);
+            const uint32_t s2 = lds0 + (uint32_t)((st == 0 ? 2 : st - 1) * GEMM_STAGE);
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) {
-                        const int r0 = (wave * 8 + t) * 8, row = r0 + (lane >> 3), pos = lane & 7;
-                        const uint32_t base = r0 < 192 ? s1 + (uint32_t)(r0 * TN) : s2 + (uint32_t)((r0 - 192) * TN);
-                        dma16(g.C + (int64_t)(m0 + row) * g.ldc + n0 + ((pos ^ ((row >> 1) & 7)) << 4),
-                              __builtin_amdgcn_readfirstlane(base));
-                    }
-                }
+            for (int t = 0; t < 8; ++t) {
+                const int r0 = (wave * 8 + t) * 8, row = r0 + (lane >> 3), pos = lane & 7;
+                const uint32_t base = r0 < 192 ? s1 + (uint32_t)(r0 * TN) : s2 + (uint32_t)((r0 - 192) * TN);
+                const int col = n0 + ((pos ^ ((row >> 1) & 7)) << 4);
+                dma16(g.C + (int64_t)min(m0 + row, g.M - 1) * g.ldc + (col < g.N ? col : 0),
+                      __builtin_amdgcn_readfirstlane(base));
             }
+        };
+        // No load into registers may sit inside this loop: the compiler would
+        // guard every use of a register it writes with a wait for all loads in
+        // flight, the DMA of the next steps included.
+        int st = 0;
+        for (int ks = 0; ks < nk_str; ++ks) {
+            // this wave's pieces of step ks have landed (at most the 6 of step
+            // ks + 1 still in flight); the barrier makes every wave's visible
+            // and ends every wave's reads of step ks - 1, whose stage step
+            // ks + 2 then overwrites
+            if (ks + 1 < nk_str) vm_wait<6>(); else vm_wait<0>();
+            __syncthreads();
+            if (ks + 2 < nk_str) issue(ks + 2, st == 0 ? 2 : st - 1);
+            if (ks == nk - 1 && lds_epi) fetch_c(st);
             mma_step(st);
             st = st == 2 ? 0 : st + 1;
+        }
+        if (nk > nk_str) {
+            // the K tail (one step) through registers: its stage was last read
+            // two steps ago
+            gemm_load<false>(g, m0, n0, nk_str * TK, tid, adj, R);
+            gemm_store_lds(R, As(st), Bs(st), tid);
+            __syncthreads();
+            if (lds_epi) fetch_c(st);
+            mma_step(st);
         }
     } else {
         // ---- through registers, one step ahead, stages 0 and 1
@@ -572,7 +585,8 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
         for (int u = 0; u < 8; ++u) {
             const int P = tid + u * GEMM_THREADS, row = P >> 3, pos = P & 7;
             const uint4 v = *(const uint4*)(cl(row) + pos * 16);
-            gstore<uint4>(g.D + (int64_t)(m0 + row) * g.ldd + n0 + ((pos ^ ((row >> 1) & 7)) << 4), v);
+            const int col = n0 + ((pos ^ ((row >> 1) & 7)) << 4);
+            if (m0 + row < g.M && col < g.N) gstore<uint4>(g.D + (int64_t)(m0 + row) * g.ldd + col, v);
         }
         return;
     }
