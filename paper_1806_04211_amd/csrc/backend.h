@@ -19,8 +19,14 @@ namespace gfech {
 //   D   : M x N output.  D may equal Cin when crow == nullptr and ldc == ldd
 //         (element-wise in place); D never overlaps A or B.
 // Entries are canonical residues in [0, p); K may be 0 (then D = Cin).
+constexpr int32_t kGemmRowsPadded = 1;
+
 struct GemmDesc {
     int32_t M = 0, N = 0, K = 0, p = 0;
+    // kGemmRowsPadded: every row of B and C may be read up to the next
+    // multiple of 16 columns past N (the buffers hold whole rows of their
+    // leading dimension); set by the planner for its own buffers
+    int32_t flags = 0, reserved = 0;
     const uint8_t* A = nullptr; int64_t lda = 0;
     const uint8_t* B = nullptr; int64_t ldb = 0; const int32_t* brow = nullptr;
     const uint8_t* C = nullptr; int64_t ldc = 0; const int32_t* crow = nullptr;

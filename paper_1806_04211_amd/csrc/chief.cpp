@@ -961,6 +961,8 @@ void flush(Backend& be, Ops& ops, Stats& st) {
     if (!ops.lists.empty()) { be.lists(ops.lists); st.launches++; }
     if (!ops.sort.empty()) { be.sort(ops.sort); st.launches++; }
     if (!ops.gemm.empty()) {
+        // every buffer of the plan holds whole rows of its leading dimension
+        for (GemmDesc& g : ops.gemm) g.flags |= kGemmRowsPadded;
         be.gemm(ops.gemm);
         st.launches++;
         st.gemms += (int64_t)ops.gemm.size();

@@ -147,7 +147,7 @@ struct GemmTileMap {           // per-descriptor tile grid, device side
 
 // MAD descriptors with their tile grids: by value (up to GEMM_ARG_CAP) or
 // through pointers into one uploaded block
-constexpr int GEMM_ARG_CAP = 36;
+constexpr int GEMM_ARG_CAP = 32;
 struct GemmArgSrc {
     int n;
     GemmTileMap m[GEMM_ARG_CAP];
@@ -401,11 +401,12 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
     const bool fast = m0 + TM <= g.M && n0 + TN <= g.N && a_aligned && (b_aligned || n0 + TN + 3 <= g.N);
     const int nk_fast = fast ? g.K / TK : 0;
     // The streamed path also takes edge tiles: A rows past M read row M - 1,
-    // B and C chunks past N read column 0 (with N a multiple of 16 a chunk is
-    // wholly inside or outside), so every read stays inside the operands, and
-    // what they contribute lands in rows or columns of D that are not stored.
+    // B and C chunks past N read column 0, so every read stays inside the
+    // operands, and what they contribute lands in rows or columns of D that
+    // are not stored.  A chunk across N reads up to 15 bytes past it: only
+    // when N is a multiple of 16 (no such chunk) or the rows are padded.
     const bool stream = a_aligned && b_aligned && !g.brow && adj == 0 && g.K >= TK &&
-                        (n0 + TN <= g.N || (g.N & 15) == 0);
+                        (n0 + TN <= g.N || (g.N & 15) == 0 || (g.flags & kGemmRowsPadded));
     const int nk_str = stream ? g.K / TK : 0;
     const int r16 = lane & 15;
     const int r32 = lane & 31;
@@ -586,7 +587,15 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
             const int P = tid + u * GEMM_THREADS, row = P >> 3, pos = P & 7;
             const uint4 v = *(const uint4*)(cl(row) + pos * 16);
             const int col = n0 + ((pos ^ ((row >> 1) & 7)) << 4);
-            if (m0 + row < g.M && col < g.N) gstore<uint4>(g.D + (int64_t)(m0 + row) * g.ldd + col, v);
+            if (m0 + row < g.M && col < g.N) {
+                uint8_t* dp = g.D + (int64_t)(m0 + row) * g.ldd + col;
+                if (col + 16 <= g.N) {
+                    gstore<uint4>(dp, v);
+                } else {   // the chunk across N
+                    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+                    for (int b = 0; b < g.N - col; ++b) gstore<uint8_t>(dp + b, (uint8_t)(w[b >> 2] >> (8 * (b & 3))));
+                }
+            }
         }
         return;
     }
