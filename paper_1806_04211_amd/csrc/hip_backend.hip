@@ -405,7 +405,9 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
     // operands, and what they contribute lands in rows or columns of D that
     // are not stored.  A chunk across N reads up to 15 bytes past it: only
     // when N is a multiple of 16 (no such chunk) or the rows are padded.
-    const bool stream = a_aligned && b_aligned && !g.brow && adj == 0 && g.K >= TK &&
+    // Gathered B rows (brow) stream when K is at most 4 steps: the row numbers
+    // of every step are loaded before the first transfer.
+    const bool stream = a_aligned && b_aligned && adj == 0 && g.K >= TK && (!g.brow || g.K <= 4 * TK) &&
                         (n0 + TN <= g.N || (g.N & 15) == 0 || (g.flags & kGemmRowsPadded));
     const int nk_str = stream ? g.K / TK : 0;
     const int r16 = lane & 15;
@@ -460,22 +462,35 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
             const int P = (wave * 4 + t) * 64 + lane, row = P >> 2, pos = P & 3;
             asrc[t] = g.A + (int64_t)min(m0 + row, g.M - 1) * g.lda + ((pos ^ ((row >> 2) & 3)) << 4);
         }
+        // B row of k-row kr of step s: brow[s * TK + kr] when gathered (bix[s][t]
+        // for piece t, loaded now and waited for here, so that no load into a
+        // register is in flight once the transfers start), else s * TK + kr
+        int bix[4][2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             const int P = (wave * 2 + t) * 64 + lane, kr = P >> 3, pos = P & 7;
             const int col = n0 + ((pos ^ (kr & 7)) << 4);
-            bsrc[t] = g.B + (int64_t)kr * g.ldb + (col < g.N ? col : 0);
+            bsrc[t] = g.B + (col < g.N ? col : 0);
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4)
+                bix[s4][t] = g.brow ? (s4 < nk_str ? gload<int32_t>(g.brow + s4 * TK + kr) : 0) : s4 * TK + kr;
         }
-        const int64_t bstep = (int64_t)TK * g.ldb;
+        if (g.brow) {
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) asm volatile("" ::"v"(bix[s4][0]), "v"(bix[s4][1]));
+        }
         const auto issue = [&](int ks, int st) {
             const uint32_t base = lds0 + (uint32_t)(st * GEMM_STAGE);
 #pragma unroll
             for (int t = 0; t < 4; ++t)
                 dma16(asrc[t] + (int64_t)ks * TK, __builtin_amdgcn_readfirstlane(base + (uint32_t)((wave * 4 + t) * 1024)));
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
-                dma16(bsrc[t] + ks * bstep,
+            for (int t = 0; t < 2; ++t) {
+                const int64_t brow_t = g.brow ? (int64_t)(ks == 0 ? bix[0][t] : ks == 1 ? bix[1][t] : ks == 2 ? bix[2][t] : bix[3][t])
+                                              : (int64_t)ks * TK + bix[0][t];
+                dma16(bsrc[t] + brow_t * g.ldb,
                       __builtin_amdgcn_readfirstlane(base + (uint32_t)(GEMM_A_STAGE + (wave * 2 + t) * 1024)));
+            }
         };
         issue(0, 0);
         if (nk_str > 1) issue(1, 1);

@@ -162,6 +162,33 @@ def check_ech(H, p):
     assert np.array_equal(gR, R)
 
 
+@pytest.mark.parametrize("K", [64, 130, 200, 256, 300])
+@pytest.mark.parametrize("with_crow", [False, True])
+def test_mad_gathered_aligned(K, with_crow):
+    """Gathered B rows on 16-byte aligned operands: K up to 4 steps streams
+    through LDS with the row numbers loaded first (K = 130 and 200 end in a
+    tail step, K = 300 takes the register path); edge tiles in M and N."""
+    torch = torch_cuda()
+    lib = gpu_library()
+    p = 43
+    rng = np.random.default_rng(K + 7 * with_crow)
+    M, N = 300, 400
+    Abuf = rng.integers(0, p, (M, K)).astype(np.uint8)
+    Bbuf = rng.integers(0, p, (K + 37, N)).astype(np.uint8)
+    Cbuf = rng.integers(0, p, (M + 11, N)).astype(np.uint8)
+    brow = rng.integers(0, K + 37, size=K).astype(np.int32)          # repeats allowed
+    crow = rng.choice(M + 11, size=M, replace=False).astype(np.int32)
+    dA, dB, dC = dev(torch, Abuf), dev(torch, Bbuf), dev(torch, Cbuf)
+    dD = torch.zeros(M * N, dtype=torch.uint8, device="cuda:0")
+    db, dc = dev(torch, brow), dev(torch, crow)
+    say(f"mad gathered aligned K={K} crow={with_crow}")
+    lib.mad_dev(M, N, K, p, dA.data_ptr(), K, dB.data_ptr(), N, dD.data_ptr(), N,
+                C=dC.data_ptr(), ldc=N, brow=db.data_ptr(), crow=dc.data_ptr() if with_crow else 0)
+    torch.cuda.synchronize()
+    cin = Cbuf[crow] if with_crow else Cbuf[:M]
+    assert np.array_equal(dD.cpu().numpy().reshape(M, N), jobs.mad(cin, Abuf, Bbuf[brow], p))
+
+
 def test_mad_batch_streamed():
     """More descriptors than travel as kernel arguments, 16-byte aligned rows
     (interior tiles stream through LDS), with C, over p <= 127."""
