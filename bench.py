@@ -319,7 +319,8 @@ def main():
     kw = dict(block_rows=args.block_rows or args.block, block_cols=args.block_cols or args.block)
 
     def solve(profile: int):
-        """profile: 0 no device events, 1 every launch, 2 the MAD launches only"""
+        """profile: 0 no device events, 1 every launch, 2 the MAD launches only,
+        3 every fourth MAD launch"""
         return lib.echelonise_dev(A.data_ptr(), n, n, n, p, stream=stream.cuda_stream, profile=profile, **kw)
 
     rank = None
@@ -330,14 +331,16 @@ def main():
         r.free()
         log(f"warmup {w}: {time.perf_counter() - t1:.3f} s, rank {rank}")
 
-    # timed steps: device events around the MAD launches only (the roofline
-    # kernel); every other launch runs without events
+    # timed steps: device events around every fourth MAD launch (the roofline
+    # kernel, a sample in issue order: an event pair costs host time on the
+    # issuing thread, which the solve waits for); every other launch runs
+    # without events
     times, stats = [], []
     torch.cuda.synchronize()
     for s in range(args.steps):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        r = solve(0 if args.no_kernel_events else 2)
+        r = solve(0 if args.no_kernel_events else 3)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         times.append(dt)
@@ -355,9 +358,13 @@ def main():
     mean = sum(times) / len(times)
     st = stats[-1]
     mac_mad = st["mac_cleardown"] + st["mac_updaterow"] + st["mac_trafo"] + st["mac_clearup"]
-    mad_ms = sum(x["ms_mad"] for x in stats) / len(stats)
-    mad_launches = st["launches_mad"]
-    achieved = (2.0 * mac_mad) / (mad_ms * 1e-3) / 1e12 if mad_ms > 0 else 0.0
+    # the timed (sampled) MAD launches of every timed step
+    mad_ms = sum(x["ms_mad"] for x in stats)
+    mad_launches = sum(x["launches_mad"] for x in stats)
+    mac_timed = sum(x["mac_mad_timed"] for x in stats)
+    achieved = (2.0 * mac_timed) / (mad_ms * 1e-3) / 1e12 if mad_ms > 0 else 0.0
+    # MAD launches of one solve (the solve with every launch timed counts them)
+    all_mad_launches = breakdown["launches_mad"] if breakdown else 0
     lat = sorted(times)
 
     def pct(q):
@@ -391,9 +398,10 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "k_gemm_modp (MAD mod p, int8 MFMA)",
                      "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s",
                      "frac": achieved / INT8_PEAK_TOPS, "traffic": profiled_traffic(),
-                     "per_launch": {"mac": mac_mad / max(mad_launches, 1),
-                                    "bytes": st["mad_bytes"] / max(mad_launches, 1),
-                                    "avg_ms": mad_ms / max(mad_launches, 1)}},
+                     "per_launch": {"mac": mac_timed / max(mad_launches, 1),
+                                    "bytes": st["mad_bytes"] / all_mad_launches if all_mad_launches else None,
+                                    "avg_ms": mad_ms / max(mad_launches, 1),
+                                    "timed_launches": mad_launches, "launches_per_solve": all_mad_launches}},
         "check": {"rank": rank, "rank_expected": min(n, k)},
     }
     del A

@@ -37,7 +37,7 @@ class Stats(ctypes.Structure):
                 ("block_rows", c_i64), ("block_cols", c_i64),
                 ("ms_mad", ctypes.c_double), ("ms_ech", ctypes.c_double), ("ms_small", ctypes.c_double),
                 ("launches_mad", c_i64), ("launches_ech", c_i64), ("launches_small", c_i64),
-                ("mad_bytes", ctypes.c_double)]
+                ("mad_bytes", ctypes.c_double), ("mac_mad_timed", ctypes.c_double)]
 
 
 class ServerCfg(ctypes.Structure):

@@ -436,6 +436,7 @@ gfech_status gfech_get_stats(const gfech_result* res, gfech_stats* s) {
     s->launches_ech = t.kernel_launches[1];
     s->launches_small = t.kernel_launches[2];
     s->mad_bytes = t.mad_bytes;
+    s->mac_mad_timed = t.kernel_mac[0];
     return GFECH_OK;
 }
 

@@ -152,6 +152,7 @@ public:
     struct Profile {
         double ms[4] = {0, 0, 0, 0};        // gemm, ech, gather/fill/lists/sort, range check
         int64_t launches[4] = {0, 0, 0, 0};
+        double mac[4] = {0, 0, 0, 0};       // multiply-adds of the timed MAD launches
     };
     virtual void set_profile(int level) { (void)level; }   // 0 off, 1 every launch, 2 MAD launches only
     virtual Profile take_profile() { return Profile(); }

@@ -1428,6 +1428,7 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
         for (int k = 0; k < 3; ++k) {
             res[q]->stats.kernel_ms[k] = prof.ms[k];
             res[q]->stats.kernel_launches[k] = prof.launches[k];
+            res[q]->stats.kernel_mac[k] = prof.mac[k];
         }
         out.push_back(std::move(res[q]));
     }

@@ -26,6 +26,7 @@ struct Stats {
     // kernel time by kind when profiling was requested (device events): gemm, ech, small jobs
     double kernel_ms[3] = {0, 0, 0};
     int64_t kernel_launches[3] = {0, 0, 0};
+    double kernel_mac[3] = {0, 0, 0};   // multiply-adds of the timed MAD launches
     double total_mac() const { return cd_mad + ech + ur_mad + urt_mad + cu_mad; }
 };
 

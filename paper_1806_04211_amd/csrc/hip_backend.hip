@@ -2069,6 +2069,8 @@ public:
         }
         if (d.empty()) return;
         if (tiles > INT32_MAX) { note_error(hipErrorInvalidValue, "too many gemm tiles"); return; }
+        launch_mac_ = 0;
+        for (const GemmDesc& g : d) launch_mac_ += (double)g.M * g.N * g.K;
         if (d.size() <= (size_t)GEMM_ARG_CAP) {
             GemmArgSrc a;
             a.n = (int)d.size();
@@ -2210,6 +2212,7 @@ public:
             if (hipEventElapsedTime(&ms, ev.a, ev.b) == hipSuccess) {
                 pr.ms[ev.kind] += ms;
                 pr.launches[ev.kind] += 1;
+                pr.mac[ev.kind] += ev.mac;
             }
             pool_.push_back(ev.a);
             pool_.push_back(ev.b);
@@ -2219,7 +2222,9 @@ public:
     }
 
 private:
-    struct Ev { hipEvent_t a, b; int kind; };
+    struct Ev { hipEvent_t a, b; int kind; double mac; };
+    double launch_mac_ = 0;     // multiply-adds of the MAD launch being issued
+    int64_t mad_seq_ = 0;       // MAD launches issued at profile level 3
     hipEvent_t new_event() {
         if (!pool_.empty()) {
             hipEvent_t e = pool_.back();
@@ -2236,13 +2241,14 @@ private:
     // end timestamps, so the recorded time is the kernel's execution alone.
     template <typename F, typename... Args>
     void go(int kind, F kernel, dim3 grid, dim3 block, size_t shm, Args... args) {
-        if (!prof_ || (prof_ == 2 && kind != 0)) {
+        const bool timed = prof_ == 1 || (prof_ >= 2 && kind == 0 && (prof_ == 2 || mad_seq_++ % 4 == 0));
+        if (!timed) {
             hipLaunchKernelGGL(kernel, grid, block, shm, cur_, args...);
             return;
         }
         hipEvent_t a = new_event(), b = new_event();
         hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)shm, cur_, a, b, 0, args...);
-        evs_.push_back({a, b, kind});
+        evs_.push_back({a, b, kind, kind == 0 ? launch_mac_ : 0.0});
     }
 
     void note_error(hipError_t e, const char* what) {

@@ -89,3 +89,31 @@ def test_full_rank_inverse():
     assert o.rank == 192
     assert np.array_equal(P.matmul_mod(o.T, A, p), np.eye(192))
     assert np.array_equal(P.matmul_mod(A, o.T, p), np.eye(192))
+
+
+def test_profile_levels_time_the_mad_launches():
+    """Device-event timing leaves the results alone; level 2 times every MAD
+    launch (their multiply-adds are the method's MAD work), level 3 every
+    fourth one."""
+    torch = torch_cuda()
+    lib = gpu_library()
+    m = n = 768
+    p = 7
+    A = synth.uniform(5, 0, m, n, p)
+    say("echelonise 768x768 GF(7) blocks 128x128, profile levels 0 2 3")
+    t = torch.from_numpy(A).to("cuda:0")
+    e = oracle.echelonize(A, p)
+    runs = {}
+    for level in (0, 2, 3):
+        r = lib.echelonise_dev(t.data_ptr(), m, n, n, p, block_rows=128, block_cols=128, profile=level)
+        torch.cuda.synchronize()
+        compare(r.outputs(), e, f"profile {level}")
+        runs[level] = r.stats()
+        r.free()
+    s0, s2, s3 = runs[0], runs[2], runs[3]
+    mad_total = s0["mac_cleardown"] + s0["mac_updaterow"] + s0["mac_trafo"] + s0["mac_clearup"]
+    assert s0["launches_mad"] == 0 and s0["mac_mad_timed"] == 0
+    assert s2["launches_mad"] > 8 and s2["ms_mad"] > 0
+    assert s2["mac_mad_timed"] == mad_total
+    assert s3["launches_mad"] == (s2["launches_mad"] + 3) // 4
+    assert 0 < s3["mac_mad_timed"] < mad_total
