@@ -1263,8 +1263,8 @@ struct Engine::Impl {
             for (Plan* pl : s1) pl->ur3(ops, b3);
             flush(be, ops, shared);
             for (Plan* pl : s1) pl->cd_commit();
+            // steps (4) and (6) touch disjoint data: one launch
             for (Plan* pl : s1) pl->ur4(ops, b4);
-            flush(be, ops, shared);
             for (Plan* pl : s1) pl->ur6(ops, b6);
             flush(be, ops, shared);
             for (Plan* pl : s1) pl->ur_commit();
