@@ -1750,6 +1750,9 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_gather(Src src) {
     // rows copied without a column map move as 16-byte chunks
     const bool vec = !g.dcol && !g.neg_p && !g.scol && ((((uintptr_t)g.dst) | (uintptr_t)g.ldd) & 15) == 0 &&
                      ((((uintptr_t)g.src) | (uintptr_t)g.lds) & 3) == 0;
+    // a column map onto 16-byte aligned destination rows: by chunks (below)
+    const bool runs = !g.dcol && !g.neg_p && g.scol && ((((uintptr_t)g.dst) | (uintptr_t)g.ldd) & 15) == 0 &&
+                      ((((uintptr_t)g.src) | (uintptr_t)g.lds) & 3) == 0;
     for (int x = blockIdx.x; x < g.rows; x += gridDim.x) {
         const int64_t sr = g.srow ? gload<int32_t>(g.srow + x) : x;
         const int64_t dr = g.drow ? gload<int32_t>(g.drow + x) : x;
@@ -1778,6 +1781,36 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_gather(Src src) {
                     } else {
                         for (int i = c; i < g.cols; ++i) gstore<uint8_t>(dst + i, gload<uint8_t>(src + i));
                     }
+                }
+            }
+            continue;
+        }
+        if (runs) {
+            // 16-byte chunks of the destination row: when the chunk's 16 source
+            // columns are consecutive (the column maps of the final assembly are
+            // long ascending runs), one realigned 16-byte load
+            for (int y = threadIdx.x * 16; y < g.cols; y += SMALL_THREADS * 16) {
+                if (y + 16 <= g.cols) {
+                    int32_t ix[16];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) ix[i] = gload<int32_t>(g.scol + y + i);
+                    // the realigned load reads the dwords around the 16 bytes: up
+                    // to 3 bytes past them, which must stay inside the source row
+                    bool run = (int64_t)ix[0] + 20 <= g.lds;
+#pragma unroll
+                    for (int i = 1; i < 16; ++i) run = run && ix[i] == ix[0] + i;
+                    uint4 v;
+                    if (run) {
+                        v = load16_any(src + ix[0]);
+                    } else {
+                        uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) w[i >> 2] |= (uint32_t)gload<uint8_t>(src + ix[i]) << (8 * (i & 3));
+                        v = make_uint4(w[0], w[1], w[2], w[3]);
+                    }
+                    gstore<uint4>(dst + y, v);
+                } else {
+                    for (int i = y; i < g.cols; ++i) gstore<uint8_t>(dst + i, gload<uint8_t>(src + gload<int32_t>(g.scol + i)));
                 }
             }
             continue;
