@@ -56,7 +56,8 @@ typedef struct gfech_opts {
     int64_t block_cols;     /* b_j target; 0 = automatic */
     int32_t skip_range_check; /* 1: the caller guarantees entries < p (no validation pass) */
     int32_t profile;        /* 1: time every kernel launch with device events, 2: only the MAD
-                               launches, 3: every fourth MAD launch (see gfech_stats);
+                               launches, 3: a pseudo-random quarter of the MAD launches
+                               (see gfech_stats);
                                0: no events */
     int32_t reserved[6];
 } gfech_opts;
@@ -150,7 +151,7 @@ typedef struct gfech_stats {
      * result */
     double mad_bytes;
     /* with opts.profile: multiply-adds of the MAD launches that were timed
-     * (all of them at level 2, every fourth at level 3) */
+     * (all of them at level 2, about a quarter at level 3) */
     double mac_mad_timed;
 } gfech_stats;
 gfech_status gfech_get_stats(const gfech_result* res, gfech_stats* stats);

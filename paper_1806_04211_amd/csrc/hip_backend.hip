@@ -2256,6 +2256,17 @@ public:
 
 private:
     struct Ev { hipEvent_t a, b; int kind; double mac; };
+    // profile level 3 times a pseudo-random quarter of the MAD launches (a
+    // fixed stride would beat against the period of a layer's launches):
+    // the finalizer of MurmurHash3 on the launch number
+    static bool sample_quarter(uint64_t x) {
+        x ^= x >> 33;
+        x *= 0xff51afd7ed558ccdull;
+        x ^= x >> 33;
+        x *= 0xc4ceb9fe1a85ec53ull;
+        x ^= x >> 33;
+        return (x & 3) == 0;
+    }
     double launch_mac_ = 0;     // multiply-adds of the MAD launch being issued
     int64_t mad_seq_ = 0;       // MAD launches issued at profile level 3
     hipEvent_t new_event() {
@@ -2274,7 +2285,7 @@ private:
     // end timestamps, so the recorded time is the kernel's execution alone.
     template <typename F, typename... Args>
     void go(int kind, F kernel, dim3 grid, dim3 block, size_t shm, Args... args) {
-        const bool timed = prof_ == 1 || (prof_ >= 2 && kind == 0 && (prof_ == 2 || mad_seq_++ % 4 == 0));
+        const bool timed = prof_ == 1 || (prof_ >= 2 && kind == 0 && (prof_ == 2 || sample_quarter(mad_seq_++)));
         if (!timed) {
             hipLaunchKernelGGL(kernel, grid, block, shm, cur_, args...);
             return;
