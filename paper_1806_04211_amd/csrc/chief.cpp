@@ -1257,13 +1257,17 @@ struct Engine::Impl {
             // scratch it reads is the copy of two layers back.
             if (u1_done >= 0) be.wait_mark(0, u1_done);
             else if (near_done >= 0) be.wait_mark(0, near_done);
+            // Fewer launches on the chain: UpdateRow step (3) needs nothing
+            // ClearDown's remaining parts produce and shares their launch; the
+            // second MAD of ClearDown (which reads the remnant product) and steps
+            // (4) (which reads step (3)) and (6) touch disjoint data and share
+            // the next one.  The second MAD is planned before cd_commit, which
+            // swaps the remnant buffers it names.
             for (Plan* pl : s1) pl->cd_post(ops);
-            flush(be, ops, shared);
-            for (Plan* pl : s1) pl->cd_mad2(ops);
             for (Plan* pl : s1) pl->ur3(ops, b3);
             flush(be, ops, shared);
+            for (Plan* pl : s1) pl->cd_mad2(ops);
             for (Plan* pl : s1) pl->cd_commit();
-            // steps (4) and (6) touch disjoint data: one launch
             for (Plan* pl : s1) pl->ur4(ops, b4);
             for (Plan* pl : s1) pl->ur6(ops, b6);
             flush(be, ops, shared);
