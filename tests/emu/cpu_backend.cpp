@@ -36,16 +36,32 @@ public:
     void release(void* p) override {
         if (!p) return;
         allocs_.erase((uintptr_t)p);
-        free(p);
+        if (fuzz_) quarantine_.push_back(p);
+        else free(p);
     }
-    void zero(void* p, size_t bytes) override { if (bytes && chk(p, bytes, "zero")) memset(p, 0, bytes); }
+    void zero(void* p, size_t bytes) override {
+        if (fuzz_) { on_lane0([this, p, bytes] { if (bytes && chk(p, bytes, "zero")) memset(p, 0, bytes); }); return; }
+        if (bytes && chk(p, bytes, "zero")) memset(p, 0, bytes);
+    }
     void upload(void* dst, const void* src, size_t bytes) override {
+        if (fuzz_) {
+            std::vector<uint8_t> data((const uint8_t*)src, (const uint8_t*)src + bytes);
+            on_lane0([this, dst, bytes, data] { if (bytes && chk(dst, bytes, "upload")) memcpy(dst, data.data(), bytes); });
+            return;
+        }
         if (bytes && chk(dst, bytes, "upload")) memcpy(dst, src, bytes);
     }
     void download(void* dst, const void* src, size_t bytes) override {
+        if (fuzz_) drain(0, q_[0].size());
         if (bytes && chk(src, bytes, "download")) memcpy(dst, src, bytes);
     }
     void copy(void* dst, const void* src, size_t bytes) override {
+        if (fuzz_) {
+            on_lane0([this, dst, src, bytes] {
+                if (bytes && chk(dst, bytes, "copy") && chk(src, bytes, "copy")) memmove(dst, src, bytes);
+            });
+            return;
+        }
         if (bytes && chk(dst, bytes, "copy") && chk(src, bytes, "copy")) memmove(dst, src, bytes);
     }
     // Lanes: the jobs of lanes 1, 2 and 3 are queued and run as late as the
@@ -55,28 +71,87 @@ public:
     // the results stop matching the oracle.  GFECH_EMU_EAGER=1 runs
     // everything at once instead.  A mark is (queue length << 2) | lane; lane
     // 0's work is always complete, so its marks are 0.
+    //
+    // Fuzz mode (gfech_emu_set_fuzz(seed), seed != 0): lane 0 is queued as
+    // well, and the queued jobs of all four lanes run in a seeded random
+    // interleaving that respects only the order within a lane and the
+    // recorded waits.  Memory transfers are lane-0 jobs; a download (and so
+    // the read of the pivot counts) waits for lane 0 alone, as on the device.
+    // A wait missing in either direction (a lane-0 job that needs earlier
+    // work of lanes 1-3, or a job of lanes 1-3 that needs earlier lane-0
+    // work) then lets a job run out of turn for some seeds.  Released memory
+    // is quarantined until every queue is empty, so a queued job that touches
+    // a buffer after its release fails the bounds check instead of landing in
+    // a new allocation.
     void set_lane(int lane) override { lane_ = lane; }
-    int mark(int lane) override { return lane == 0 ? 0 : (int)((q_[lane].size() << 2) | (size_t)lane); }
+    int mark(int lane) override {
+        if (lane == 0 && !fuzz_) return 0;
+        return (int)((q_[lane].size() << 2) | (size_t)lane);
+    }
     void wait_mark(int lane, int m) override {
         const int src = m & 3;
-        if (src == 0 || src == lane) return;
         const size_t upto = (size_t)(m >> 2);
+        if (lane == drop_lane_ && src == drop_src_) return;   // a planted ordering mistake (tests only)
+        if (fuzz_) {
+            if (src == lane || upto == 0) return;
+            Job j;
+            j.wait_lane = src;
+            j.wait_upto = upto;
+            q_[lane].push_back(std::move(j));
+            churn();
+            return;
+        }
+        if (src == 0 || src == lane) return;
         if (lane == 0 || !defer_) drain(src, upto);
-        else q_[lane].push_back([this, src, upto] { drain(src, upto); });
+        else {
+            Job j;
+            j.f = [this, src, upto] { drain(src, upto); };
+            q_[lane].push_back(std::move(j));
+        }
     }
     void drain(int lane, size_t upto) {
+        if (fuzz_) {
+            while (done_[lane] < upto && done_[lane] < q_[lane].size()) {
+                if (!step_random()) {
+                    if (!err_) fprintf(stderr, "emulator: lanes wait for each other\n");
+                    err_ = 6;
+                    return;
+                }
+            }
+            return;
+        }
         while (done_[lane] < upto && done_[lane] < q_[lane].size()) {
-            auto f = std::move(q_[lane][done_[lane]]);
+            auto f = std::move(q_[lane][done_[lane]].f);
             ++done_[lane];
             f();
         }
     }
     void sync() override {
-        while (done_[1] < q_[1].size() || done_[2] < q_[2].size() || done_[3] < q_[3].size()) {
+        while (done_[0] < q_[0].size() || done_[1] < q_[1].size() || done_[2] < q_[2].size() ||
+               done_[3] < q_[3].size()) {
+            if (fuzz_) {
+                if (!step_random()) {
+                    if (!err_) fprintf(stderr, "emulator: lanes wait for each other\n");
+                    err_ = 6;
+                    break;
+                }
+                continue;
+            }
             drain(1, q_[1].size());
             drain(2, q_[2].size());
             drain(3, q_[3].size());
         }
+        for (void* p : quarantine_) free(p);
+        quarantine_.clear();
+    }
+    void drop_waits(int lane, int src) {
+        drop_lane_ = lane;
+        drop_src_ = src;
+    }
+    void set_fuzz(uint64_t seed) {
+        sync();
+        fuzz_ = seed != 0;
+        rng_ = seed * 0x9E3779B97F4A7C15ull + 1;
     }
     int error() const override { return err_; }
 
@@ -108,8 +183,7 @@ public:
     }
 
     void gemm(const std::vector<GemmDesc>& ds) override {
-        if (lane_ != 0 && defer_) { q_[lane_].push_back([this, ds] { gemm_now(ds); }); return; }
-        gemm_now(ds);
+        enqueue([this, ds] { gemm_now(ds); });
     }
     void gemm_now(const std::vector<GemmDesc>& ds) {
         for (const GemmDesc& g : ds) {
@@ -133,8 +207,7 @@ public:
     }
 
     void gather(const std::vector<GatherDesc>& ds) override {
-        if (lane_ != 0 && defer_) { q_[lane_].push_back([this, ds] { gather_now(ds); }); return; }
-        gather_now(ds);
+        enqueue([this, ds] { gather_now(ds); });
     }
     void gather_now(const std::vector<GatherDesc>& ds) {
         for (const GatherDesc& g : ds) {
@@ -167,8 +240,7 @@ public:
     }
 
     void fill(const std::vector<FillDesc>& ds) override {
-        if (lane_ != 0 && defer_) { q_[lane_].push_back([this, ds] { fill_now(ds); }); return; }
-        fill_now(ds);
+        enqueue([this, ds] { fill_now(ds); });
     }
     void fill_now(const std::vector<FillDesc>& ds) {
         for (const FillDesc& f : ds) {
@@ -191,8 +263,7 @@ public:
     }
 
     void lists(const std::vector<ListDesc>& ds) override {
-        if (lane_ != 0 && defer_) { q_[lane_].push_back([this, ds] { lists_now(ds); }); return; }
-        lists_now(ds);
+        enqueue([this, ds] { lists_now(ds); });
     }
     void lists_now(const std::vector<ListDesc>& ds) {
         for (const ListDesc& l : ds) {
@@ -222,8 +293,7 @@ public:
     }
 
     void sort(const std::vector<SortDesc>& ds) override {
-        if (lane_ != 0 && defer_) { q_[lane_].push_back([this, ds] { sort_now(ds); }); return; }
-        sort_now(ds);
+        enqueue([this, ds] { sort_now(ds); });
     }
     void sort_now(const std::vector<SortDesc>& ds) {
         for (const SortDesc& s : ds) {
@@ -238,6 +308,7 @@ public:
     }
 
     int64_t count_out_of_range(const uint8_t* A, int64_t m, int64_t n, int64_t lda, int32_t p) override {
+        if (fuzz_) drain(0, q_[0].size());
         int64_t bad = 0;
         for (int64_t i = 0; i < m; ++i)
             for (int64_t j = 0; j < n; ++j) bad += A[i * lda + j] >= p;
@@ -245,8 +316,7 @@ public:
     }
 
     void ech(const std::vector<EchDesc>& ds) override {
-        if (lane_ != 0 && defer_) { q_[lane_].push_back([this, ds] { ech_now(ds); }); return; }
-        ech_now(ds);
+        enqueue([this, ds] { ech_now(ds); });
     }
     void ech_now(const std::vector<EchDesc>& ds) {
         for (const EchDesc& e : ds) {
@@ -269,12 +339,83 @@ public:
     }
 
 private:
+    // a queued job: work to run, or a wait for lane wait_lane to have run
+    // wait_upto of its jobs (fuzz mode)
+    struct Job {
+        std::function<void()> f;
+        int wait_lane = -1;
+        size_t wait_upto = 0;
+    };
     std::map<uintptr_t, size_t> allocs_;
     int err_ = 0;
     int lane_ = 0;
     bool defer_ = !(getenv("GFECH_EMU_EAGER") && getenv("GFECH_EMU_EAGER")[0] == '1');
-    std::vector<std::function<void()>> q_[4];
+    bool fuzz_ = false;
+    int drop_lane_ = -1, drop_src_ = -1;
+    uint64_t rng_ = 1;
+    std::vector<Job> q_[4];
     size_t done_[4] = {0, 0, 0, 0};
+    std::vector<void*> quarantine_;
+    uint64_t steps_ = 0;
+    uint32_t weight_[4] = {1, 1, 1, 1};
+
+    uint64_t next_rand() {   // xorshift64*
+        rng_ ^= rng_ >> 12;
+        rng_ ^= rng_ << 25;
+        rng_ ^= rng_ >> 27;
+        return rng_ * 0x2545F4914F6CDD1Dull;
+    }
+    void enqueue(std::function<void()> f) {
+        if (fuzz_ || (lane_ != 0 && defer_)) {
+            Job j;
+            j.f = std::move(f);
+            q_[lane_].push_back(std::move(j));
+            if (fuzz_) churn();
+            return;
+        }
+        f();
+    }
+    void on_lane0(std::function<void()> f) {
+        Job j;
+        j.f = std::move(f);
+        q_[0].push_back(std::move(j));
+        churn();
+    }
+    bool runnable(int lane) const {
+        if (done_[lane] >= q_[lane].size()) return false;
+        const Job& j = q_[lane][done_[lane]];
+        return j.wait_lane < 0 || done_[j.wait_lane] >= j.wait_upto;
+    }
+    // run the head of a random lane that can proceed; false if none can.
+    // Lanes are picked with weights (1, 8 or 64, re-drawn every 64 steps), so
+    // that a lane may lag the others by several layers for a while.
+    bool step_random() {
+        if (steps_++ % 64 == 0)
+            for (int l = 0; l < 4; ++l) weight_[l] = 1u << (3 * (next_rand() % 3));
+        int cand[4], nc = 0;
+        uint64_t total = 0;
+        for (int l = 0; l < 4; ++l)
+            if (runnable(l)) { cand[nc++] = l; total += weight_[l]; }
+        if (!nc) return false;
+        uint64_t x = next_rand() % total;
+        int l = cand[0];
+        for (int c = 0; c < nc; ++c) {
+            if (x < weight_[cand[c]]) { l = cand[c]; break; }
+            x -= weight_[cand[c]];
+        }
+        Job j = std::move(q_[l][done_[l]]);
+        ++done_[l];
+        if (j.f) j.f();
+        return true;
+    }
+    // after every enqueue in fuzz mode: usually nothing (jobs stay queued
+    // until a download or a sync forces them, so that many jobs of several
+    // lanes are runnable together), sometimes a few random steps
+    void churn() {
+        if (next_rand() % 8 != 0) return;
+        const int k = 1 + (int)(next_rand() % 3);
+        for (int t = 0; t < k; ++t) if (!step_random()) break;
+    }
 
     static uint32_t inv(uint32_t a, uint32_t p) {   // a^(p-2)
         uint32_t r = 1, b = a % p, x = p - 2;
@@ -342,12 +483,23 @@ private:
     }
 };
 
+CpuBackend& instance() {
+    static CpuBackend be;
+    return be;
+}
+
 }  // namespace
 
 Backend* backend_instance(std::string* err) {
     (void)err;
-    static CpuBackend be;
-    return &be;
+    return &instance();
 }
 
 }  // namespace gfech
+
+// Test hook of the emulator build only: seed != 0 switches the randomized
+// interleaving of all four lanes on (0 switches it off).
+extern "C" void gfech_emu_set_fuzz(uint64_t seed) { gfech::instance().set_fuzz(seed); }
+// Test hook: ignore every wait of `lane` for work of lane `src` (-1: none), a
+// planted ordering mistake that the randomized interleaving must expose.
+extern "C" void gfech_emu_drop_waits(int lane, int src) { gfech::instance().drop_waits(lane, src); }

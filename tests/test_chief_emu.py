@@ -208,3 +208,81 @@ def test_wide_block_columns(lib, p):
         for br, bc in ((4, 80), (5, 120), (3, 45), (8, 160)):
             compare(lib.echelonise(A, p, block_rows=br, block_cols=bc).outputs(), e, f"{A.shape} {br}x{bc}")
     del rng
+
+
+# ------------------------------------------------ randomized lane interleavings (race detection)
+
+@pytest.fixture
+def fuzz(lib):
+    """Switches the emulator's randomized interleaving of all four lanes on
+    for one test: every lane is queued (lane 0 too) and the queued jobs run
+    in a seeded random order that respects only the order within a lane and
+    the planner's recorded waits."""
+    import ctypes
+    fn = lib.lib.gfech_emu_set_fuzz
+    fn.argtypes = [ctypes.c_uint64]
+    fn.restype = None
+    yield fn
+    fn(0)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5, 6])
+def test_random_interleavings_match_oracle(lib, fuzz, seed):
+    fuzz(seed)
+    rng = np.random.default_rng([seed, 31])
+    for trial in range(12):
+        p = int(rng.choice([2, 3, 7, 251]))
+        m, n = (int(x) for x in rng.integers(4, 48, 2))
+        A = synth.deficient(seed, trial, m, n, p) if trial % 3 == 0 else synth.uniform(seed, trial, m, n, p)
+        br, bc = (int(x) for x in rng.integers(1, 10, 2))
+        compare(lib.echelonise(A, p, block_rows=br, block_cols=bc).outputs(), oracle.echelonize(A, p),
+                f"seed {seed} p={p} {m}x{n} blocks {br}x{bc}")
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_random_interleavings_many_layers_and_batches(lib, fuzz, seed):
+    """Many block columns (near, mid and far sets all non-empty, the three
+    scratch copies reused) and a batch whose problems leave Step 1 at
+    different layers, under random interleavings."""
+    fuzz(seed)
+    p = 7
+    A = synth.low_rank_product(seed, 40, 64, 30, p)
+    e = oracle.echelonize(A, p)
+    for br, bc in ((3, 4), (5, 6), (8, 5)):
+        compare(lib.echelonise(A, p, block_rows=br, block_cols=bc).outputs(), e, f"{br}x{bc}")
+    mix = synth.batch_mix(seed, 8, nmin=3, nmax=36)
+    res, sts = lib.echelonise_batch(mix, block_rows=4, block_cols=5)
+    assert all(s == 0 for s in sts)
+    for (B, q), r in zip(mix, res):
+        compare(r.outputs(), oracle.echelonize(B, q))
+
+
+# (lane, lane it waits for): every kind of cross-lane wait the planner records.
+# Lane 2's wait for lane 0 is not listed: lane 2 also waits for lane 1's near
+# set, which waited for the same lane-0 point, so dropping it alone changes
+# nothing.
+PLANTED = [(0, 1), (0, 2), (0, 3), (1, 0), (1, 3), (2, 1), (3, 0)]
+
+
+@pytest.mark.parametrize("lane,src", PLANTED, ids=[f"lane{a}-waits-lane{b}" for a, b in PLANTED])
+def test_random_interleavings_catch_a_missing_wait(lib, fuzz, lane, src):
+    """A planted ordering mistake, in the emulator only: `lane` ignores its
+    waits for work of lane `src`.  Some seed must then change a result."""
+    import ctypes
+    drop = lib.lib.gfech_emu_drop_waits
+    drop.argtypes = [ctypes.c_int, ctypes.c_int]
+    drop.restype = None
+    p = 7
+    A = synth.low_rank_product(5, 40, 64, 30, p)
+    e = oracle.echelonize(A, p)
+    bad = 0
+    try:
+        drop(lane, src)
+        for seed in range(1, 13):
+            fuzz(seed)
+            o = lib.echelonise(A, p, block_rows=3, block_cols=4).outputs()
+            same = all(np.array_equal(getattr(o, k), getattr(e, k)) for k in ("gamma", "rho", "R", "M", "K"))
+            bad += 0 if same else 1
+    finally:
+        drop(-1, -1)
+    assert bad > 0
