@@ -86,6 +86,56 @@ def profiled_traffic():
     return None
 
 
+def exact_matmul_mod(X, Y, p, chunk_rows=4096):
+    """(X @ Y) mod p for residue matrices on the host, exact: products in float32
+    while every sum stays below 2^24 (then every partial sum is an exact
+    integer), else in float64 (below 2^53); row chunks bound the memory."""
+    import numpy as np
+    k = X.shape[1]
+    dt = np.float32 if k * (p - 1) ** 2 < 2 ** 24 else np.float64
+    assert k * (p - 1) ** 2 < 2 ** 53
+    Yf = Y.astype(dt)
+    out = np.empty((X.shape[0], Y.shape[1]), np.int64)
+    for r0 in range(0, X.shape[0], chunk_rows):
+        out[r0:r0 + chunk_rows] = np.remainder(X[r0:r0 + chunk_rows].astype(dt) @ Yf, p).astype(np.int64)
+    return out
+
+
+def check_result(A_host, res, p, rank_expected, vectors=64, seed=0):
+    """Checks of one timed solve's outputs, on the host and outside the library:
+    the pinned rank; gamma and rho strictly increasing; R in reduced echelon
+    shape (row t is zero in the non-pivot columns before its pivot column);
+    and Eq. (2) by Freivalds' method with `vectors` random vectors X:
+        -M (A X)[rho] = X[gamma] - R X[gamma_bar]     (T A X = E X, top rows)
+        K (A X)[rho] + (A X)[rho_bar] = 0            (bottom rows)
+    all mod p.  A wrong M, K, R, gamma or rho passes one vector with
+    probability at most 1/p."""
+    import numpy as np
+    t0 = time.perf_counter()
+    m, n = A_host.shape
+    r = res.rank
+    gamma, rho = res.pivots()
+    gbar, rbar = res.nonpivots()
+    R, M, K = res.get_R(), res.get_M(), res.get_K()
+    out = {"rank": r, "rank_expected": rank_expected, "rank_ok": r == rank_expected}
+    out["orders_ok"] = bool(np.all(np.diff(gamma) > 0) and np.all(np.diff(rho) > 0)
+                            and len(np.intersect1d(gamma, gbar)) == 0 and len(np.intersect1d(rho, rbar)) == 0)
+    # non-pivot columns before pivot column gamma[t]: gamma[t] - t of them
+    lead = (gamma - np.arange(r))[:, None]
+    out["rref_ok"] = bool(not np.any(R[np.arange(n - r)[None, :] < lead]))
+    X = np.random.default_rng([seed, 0xF2E1]).integers(0, p, (n, vectors)).astype(np.uint8)
+    Y = exact_matmul_mod(A_host, X, p)                      # A X, m x vectors
+    Yr = Y[rho].astype(np.uint8)
+    top_l = (-exact_matmul_mod(M, Yr, p)) % p
+    top_r = (X[gamma].astype(np.int64) - exact_matmul_mod(R, X[gbar], p)) % p if n > r else X[gamma] % p
+    bot = (exact_matmul_mod(K, Yr, p) + Y[rbar]) % p if m > r else np.zeros((0, vectors), np.int64)
+    out["freivalds_vectors"] = vectors
+    out["freivalds_ok"] = bool(np.array_equal(top_l, top_r) and not np.any(bot))
+    out["ok"] = bool(out["rank_ok"] and out["orders_ok"] and out["rref_ok"] and out["freivalds_ok"])
+    out["seconds"] = time.perf_counter() - t0
+    return out
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     return xs[min(len(xs) - 1, int(round(q * (len(xs) - 1))))] if xs else 0.0
@@ -279,6 +329,8 @@ def main():
     ap.add_argument("--block-rows", type=int, default=0, help="block rows a_i (overrides --block)")
     ap.add_argument("--block-cols", type=int, default=0, help="block columns b_j (overrides --block)")
     ap.add_argument("--cpu-sample", type=int, default=2000, help="oracle sample size (0 = skip)")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the host-side check (Freivalds) of the last timed solve; only its rank is reported")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the steps without per-launch device events (no roofline / kernel_ms)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -342,6 +394,7 @@ def main():
     # issuing thread, which the solve waits for); every other launch runs
     # without events
     times, stats = [], []
+    last = None
     torch.cuda.synchronize()
     for s in range(args.steps):
         torch.cuda.synchronize()
@@ -352,7 +405,9 @@ def main():
         times.append(dt)
         rank = r.rank
         stats.append(r.stats())
-        r.free()
+        if last is not None:
+            last.free()
+        last = r                      # the last timed solve's result is checked below
         log(f"step {s}: {dt:.3f} s, rank {rank}")
     # one more (untimed) solve with every launch timed, for the per-kind breakdown
     breakdown = None
@@ -408,8 +463,18 @@ def main():
                                     "bytes": st["mad_bytes"] / all_mad_launches if all_mad_launches else None,
                                     "avg_ms": mad_ms / max(mad_launches, 1),
                                     "timed_launches": mad_launches, "launches_per_solve": all_mad_launches}},
-        "check": {"rank": rank, "rank_expected": min(n, k)},
     }
+    # the last timed solve's outputs, checked on the host (outside the library)
+    if args.no_check:
+        out["check"] = {"rank": rank, "rank_expected": min(n, k)}
+        last.free()
+    else:
+        log("checking the last timed solve on the host (Freivalds, 64 vectors)")
+        A_host = A.cpu().numpy()
+        out["check"] = check_result(A_host, last, p, min(n, k))
+        last.free()
+        del A_host
+        log(f"check: {out['check']}")
     del A
     torch.cuda.empty_cache()
     if args.cpu_sample > 0:

@@ -61,7 +61,13 @@ def uniform_rows(seed: int, stream: int, row0: int, rows: int, n: int, p: int) -
 
 
 def low_rank_product(seed: int, m: int, n: int, k: int, p: int) -> np.ndarray:
-    """B @ C mod p with B (m x k) from stream 1 and C (k x n) from stream 2 (rank <= k)."""
+    """B @ C mod p with B (m x k) from stream 1 and C (k x n) from stream 2 (rank <= k).
+    The product is formed in float64, exact while k (p - 1)^2 < 2^53 (every
+    partial sum is then an integer below 2^53), else in int64."""
+    if k * (p - 1) ** 2 < 2 ** 53:
+        B = uniform(seed, 1, m, k, p).astype(np.float64)
+        C = uniform(seed, 2, k, n, p).astype(np.float64)
+        return np.remainder(B @ C, p).astype(np.uint8)
     B = uniform(seed, 1, m, k, p).astype(np.int64)
     C = uniform(seed, 2, k, n, p).astype(np.int64)
     return ((B @ C) % p).astype(np.uint8)

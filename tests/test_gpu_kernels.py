@@ -215,3 +215,61 @@ def test_mad_batch_streamed():
     torch.cuda.synchronize()
     for dD, exp, M, N in exps:
         assert np.array_equal(dD.cpu().numpy().reshape(M, N), exp)
+
+
+# inner dimensions of the large solves' products (2048-wide block columns) and beyond,
+# on 16-byte aligned rows so interior tiles take the streamed path
+LONG_K_SHAPES = [(256, 512, 2048), (512, 384, 4096), (300, 272, 2048)]
+
+
+@pytest.mark.parametrize("p", [2, 7, 127, 131, 251])
+@pytest.mark.parametrize("shape", LONG_K_SHAPES)
+def test_mad_long_k(shape, p):
+    torch = torch_cuda()
+    lib = gpu_library()
+    M, N, K = shape
+    say(f"mad long K {shape} p={p}")
+    rng = np.random.default_rng(M + N + K + p)
+    A = rng.integers(0, p, (M, K)).astype(np.uint8)
+    B = rng.integers(0, p, (K, N)).astype(np.uint8)
+    C = rng.integers(0, p, (M, N)).astype(np.uint8)
+    dA, dB, dC = dev(torch, A), dev(torch, B), dev(torch, C)
+    dD = torch.zeros(M * N, dtype=torch.uint8, device="cuda:0")
+    lib.mad_dev(M, N, K, p, dA.data_ptr(), K, dB.data_ptr(), N, dD.data_ptr(), N, C=dC.data_ptr(), ldc=N)
+    torch.cuda.synchronize()
+    assert np.array_equal(dD.cpu().numpy().reshape(M, N), oracle.mad_c(C, A, B, p))
+
+
+def _extremes(p):
+    """Residues whose centred int8 forms have the largest magnitudes: for
+    p <= 127 every residue is its own form and p - 1 is the largest; for p > 127
+    the residues 127 and 128 have the forms 127 and 128 - p (the most negative)."""
+    return [p - 1, p - 2] if p <= 127 else [127, 128]
+
+
+@pytest.mark.parametrize("p", [7, 127, 131, 251])
+@pytest.mark.parametrize("K", [2048, 4096])
+def test_mad_extreme_operands(K, p):
+    """Every product at the largest magnitudes of either sign, summed over long
+    inner dimensions: all-equal blocks (the largest sums of one sign) and
+    seeded mixtures of the two extreme residues (sums of both signs)."""
+    torch = torch_cuda()
+    lib = gpu_library()
+    M, N = 256, 256
+    hi, lo = _extremes(p)
+    rng = np.random.default_rng(K + p)
+    cases = {
+        "hi*hi": (np.full((M, K), hi, np.uint8), np.full((K, N), hi, np.uint8)),
+        "hi*lo": (np.full((M, K), hi, np.uint8), np.full((K, N), lo, np.uint8)),
+        "lo*lo": (np.full((M, K), lo, np.uint8), np.full((K, N), lo, np.uint8)),
+        "mixed": (rng.choice([hi, lo], (M, K)).astype(np.uint8), rng.choice([hi, lo], (K, N)).astype(np.uint8)),
+    }
+    C = np.full((M, N), p - 1, np.uint8)
+    dC = dev(torch, C)
+    for name, (A, B) in cases.items():
+        say(f"mad extreme {name} K={K} p={p}")
+        dA, dB = dev(torch, A), dev(torch, B)
+        dD = torch.zeros(M * N, dtype=torch.uint8, device="cuda:0")
+        lib.mad_dev(M, N, K, p, dA.data_ptr(), K, dB.data_ptr(), N, dD.data_ptr(), N, C=dC.data_ptr(), ldc=N)
+        torch.cuda.synchronize()
+        assert np.array_equal(dD.cpu().numpy().reshape(M, N), jobs.mad(C, A, B, p)), name

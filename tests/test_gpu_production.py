@@ -1,0 +1,74 @@
+"""End-to-end parity at the library's default blocking (256-row by 2048-column
+blocks above 512 x 512): several block rows and several 2048-wide block
+columns, so the schedule that produces the large benchmark runs (the four
+lanes with their near / mid / far sets, the three copies of the job scratch,
+products with an inner dimension near 2048, the leading-columns ECH and its
+rerun) is compared with the oracle bit for bit on every output."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import gpu_library, say
+from tests.test_gpu_parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _zero_band(seed, m, n, p):
+    """Uniform rows with a band of zero columns across a block-column boundary
+    and duplicated rows: whole block columns hold few or no pivots, so later
+    block columns take rows that earlier ones left unselected."""
+    A = synth.uniform(seed, 0, m, n, p)
+    A[:300, :2500] = 0
+    A[:, 4000:4300] = 0
+    A[5::7] = A[3::7][: len(A[5::7])]
+    return A
+
+
+CASES = [
+    # (name, m, n, p, input)
+    ("lowrank-gf7", 1024, 10752, 7, lambda: synth.low_rank_product(3, 1024, 10752, 1000, 7)),
+    ("uniform-gf251", 1024, 10752, 251, lambda: synth.uniform(4, 0, 1024, 10752, 251)),
+    ("deficient-gf2", 1100, 10000, 2, lambda: synth.deficient(5, 0, 1100, 10000, 2)),
+    ("zeroband-gf3", 600, 6200, 3, lambda: _zero_band(6, 600, 6200, 3)),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_default_blocking_matches_oracle(case):
+    lib = gpu_library()
+    name, m, n, p, make = case
+    A = make()
+    assert A.shape == (m, n)
+    say(f"echelonise {name} {m}x{n} GF({p}) at the default blocking")
+    res = lib.echelonise(A, p)
+    st = res.stats()
+    # the default blocking: 256-row blocks and 2048-wide block columns
+    assert st["block_rows"] == -(-m // 256) and st["block_cols"] == -(-n // 2048)
+    assert st["block_rows"] >= 3 and st["block_cols"] >= 4
+    out = res.outputs()
+    res.free()
+    say(f"oracle {name}")
+    compare(out, oracle.echelonize(A, p), name)
+
+
+def test_batch_sample_of_the_batched_workload():
+    """A sample of the batched workload (n log-uniform in [32, 512], p from
+    {2, 3, 5, 7, 251}, 10 % rank-deficient) in one call, each member against
+    the oracle."""
+    lib = gpu_library()
+    mix = synth.batch_mix(11, 64)
+    ps = [p for _, p in mix]
+    ns = [A.shape[0] for A, _ in mix]
+    assert 251 in ps and max(ns) > 400
+    say("batch sample of 64, n up to 512")
+    res, sts = lib.echelonise_batch(mix)
+    assert all(s == 0 for s in sts)
+    deficient = 0
+    for t, ((A, p), r) in enumerate(zip(mix, res)):
+        e = oracle.echelonize(A, p)
+        deficient += e.rank < A.shape[0]
+        compare(r.outputs(), e, f"problem {t} n={A.shape[0]} p={p}")
+        r.free()
+    assert deficient >= 3

@@ -40,3 +40,11 @@ def test_gf2_pack_roundtrip():
     assert W.shape == (7, 3)
     assert np.array_equal(synth.gf2_unpack(W, 130), A)
     assert int(W[0, 0]) & 1 == int(A[0, 0])
+
+
+def test_low_rank_product_float_path_is_exact():
+    # the float64 product equals the plain int64 one (sums below 2^53)
+    for (m, n, k, p) in ((30, 40, 20, 7), (64, 50, 33, 251), (17, 9, 5, 2)):
+        B = synth.uniform(1, 1, m, k, p).astype(np.int64)
+        C = synth.uniform(1, 2, k, n, p).astype(np.int64)
+        assert np.array_equal(synth.low_rank_product(1, m, n, k, p), ((B @ C) % p).astype(np.uint8))
