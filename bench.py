@@ -329,6 +329,8 @@ def main():
     ap.add_argument("--block-rows", type=int, default=0, help="block rows a_i (overrides --block)")
     ap.add_argument("--block-cols", type=int, default=0, help="block columns b_j (overrides --block)")
     ap.add_argument("--cpu-sample", type=int, default=2000, help="oracle sample size (0 = skip)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the timing of the variants without the transformation")
     ap.add_argument("--no-check", action="store_true",
                     help="skip the host-side check (Freivalds) of the last timed solve; only its rank is reported")
     ap.add_argument("--no-kernel-events", action="store_true",
@@ -464,6 +466,23 @@ def main():
                                     "avg_ms": mad_ms / max(mad_launches, 1),
                                     "timed_launches": mad_launches, "launches_per_solve": all_mad_launches}},
     }
+    # the variants without the transformation (Section 1), one solve each after
+    # a warm-up, beside the full solve's mean
+    if not args.no_variants:
+        out["variants_ms"] = {"rref_and_transform": mean * 1e3}
+        for name, v in (("rref_only", 1), ("rank_only", 2)):
+            lib.echelonise_dev(A.data_ptr(), n, n, n, p, stream=stream.cuda_stream, variant=v, **kw).free()
+            vt = []
+            for _ in range(2):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                r = lib.echelonise_dev(A.data_ptr(), n, n, n, p, stream=stream.cuda_stream, variant=v, **kw)
+                torch.cuda.synchronize()
+                vt.append(time.perf_counter() - t1)
+                assert r.rank == rank
+                r.free()
+            out["variants_ms"][name] = min(vt) * 1e3
+            log(f"variant {name}: {min(vt) * 1e3:.1f} ms")
     # the last timed solve's outputs, checked on the host (outside the library)
     if args.no_check:
         out["check"] = {"rank": rank, "rank_expected": min(n, k)}

@@ -50,6 +50,20 @@ typedef enum gfech_status {
     GFECH_E_STATE = 8       /* call not valid for this object */
 } gfech_status;
 
+/* What a call computes: the variants of Gaussian elimination the paper's
+ * introduction (Section 1) lists, each a subset of the full result.
+ *   GFECH_WANT_RREF_T  the reduced echelon form with the transformation: rank,
+ *                      gamma, rho, R, M, K (the default; everything below);
+ *   GFECH_WANT_RREF    the reduced echelon form without the transformation:
+ *                      rank, gamma, rho and R (E); the UpdateRowTrafo products
+ *                      of Step 1 and the M part of Step 3 are not run, and
+ *                      M, K and T are not available (GFECH_E_STATE);
+ *   GFECH_WANT_RANK    the rank with the pivot columns gamma and the selected
+ *                      rows rho: additionally Step 3 is not run and R and E
+ *                      are not available either.
+ * Every output that a variant provides equals the full result's. */
+enum { GFECH_WANT_RREF_T = 0, GFECH_WANT_RREF = 1, GFECH_WANT_RANK = 2 };
+
 /* Options.  Zero-initialised options (or NULL) select the defaults. */
 typedef struct gfech_opts {
     int64_t block_rows;     /* a_i target (Section 3.1); 0 = automatic */
@@ -59,7 +73,8 @@ typedef struct gfech_opts {
                                launches, 3: a pseudo-random quarter of the MAD launches
                                (see gfech_stats);
                                0: no events */
-    int32_t reserved[6];
+    int32_t variant;        /* GFECH_WANT_*; other values give GFECH_E_ARG */
+    int32_t reserved[5];
 } gfech_opts;
 
 /* Opaque, library-owned result; immutable once returned.  Its matrices stay
@@ -77,6 +92,20 @@ gfech_status gfech_echelonise_u8(const uint8_t* A, int64_t m, int64_t n, int64_t
  * that stream has completed.  The result stays in device memory. */
 gfech_status gfech_echelonise_u8_dev(const uint8_t* A_dev, int64_t m, int64_t n, int64_t lda, uint32_t p,
                                      const gfech_opts* opts, void* stream, gfech_result** out);
+
+/* GF(2) with bit-packed rows (the field of the paper's largest runs,
+ * Section 6): bit b of word w of row i is entry (i, 64 w + b), least
+ * significant bit first; each row has ldw >= ceil(n / 64) words.  Bits past
+ * column n - 1 in a row's last word (pad bits) must be zero: a set pad bit
+ * gives GFECH_E_RANGE (skip_range_check skips that check).  The result is
+ * that of gfech_echelonise_u8 on the unpacked matrix with p = 2 (Eq. (2);
+ * over GF(2), -1 = 1, so the paper's negative form and the standard form
+ * coincide); the input is unpacked on the device to one byte per entry for
+ * the elimination.  Host input, and device input ordered on `stream`. */
+gfech_status gfech_echelonise_gf2(const uint64_t* A, int64_t m, int64_t n, int64_t ldw, const gfech_opts* opts,
+                                  gfech_result** out);
+gfech_status gfech_echelonise_gf2_dev(const uint64_t* A_dev, int64_t m, int64_t n, int64_t ldw,
+                                      const gfech_opts* opts, void* stream, gfech_result** out);
 
 /* One independent problem of a batch. */
 typedef struct gfech_problem {
@@ -105,7 +134,9 @@ gfech_status gfech_pivots(const gfech_result* res, int64_t* gamma, int64_t* rho)
 gfech_status gfech_nonpivots(const gfech_result* res, int64_t* gamma_bar, int64_t* rho_bar);
 
 /* Copy the paper-form matrices into host buffers (row-major, given ld):
- * R is r x (n - r), M is r x r, K is (m - r) x r. */
+ * R is r x (n - r), M is r x r, K is (m - r) x r.  GFECH_E_STATE when the
+ * result's variant does not include the matrix (and likewise for E, T and
+ * the device view's pointers, which are then NULL). */
 gfech_status gfech_get_R(const gfech_result* res, uint8_t* R, int64_t ldr);
 gfech_status gfech_get_M(const gfech_result* res, uint8_t* M, int64_t ldm);
 gfech_status gfech_get_K(const gfech_result* res, uint8_t* K, int64_t ldk);
@@ -153,6 +184,7 @@ typedef struct gfech_stats {
     /* with opts.profile: multiply-adds of the MAD launches that were timed
      * (all of them at level 2, about a quarter at level 3) */
     double mac_mad_timed;
+    int64_t variant;        /* the GFECH_WANT_* the result was computed for */
 } gfech_stats;
 gfech_status gfech_get_stats(const gfech_result* res, gfech_stats* stats);
 

@@ -11,13 +11,16 @@ i64p = ctypes.POINTER(ctypes.c_int64)
 vp = ctypes.c_void_p
 
 GFECH_OK = 0
+GFECH_E_STATE = 8
+# what a call computes (gfech_opts.variant)
+WANT_RREF_T, WANT_RREF, WANT_RANK = 0, 1, 2
 STATUS_NAMES = {0: "GFECH_OK", 1: "GFECH_E_ARG", 2: "GFECH_E_FIELD", 3: "GFECH_E_RANGE", 4: "GFECH_E_NOMEM",
                 5: "GFECH_E_TOO_BIG", 6: "GFECH_E_DEVICE", 7: "GFECH_E_CANCELLED", 8: "GFECH_E_STATE"}
 
 
 class Opts(ctypes.Structure):
     _fields_ = [("block_rows", c_i64), ("block_cols", c_i64), ("skip_range_check", c_i32),
-                ("profile", c_i32), ("reserved", c_i32 * 6)]
+                ("profile", c_i32), ("variant", c_i32), ("reserved", c_i32 * 5)]
 
 
 class Problem(ctypes.Structure):
@@ -37,7 +40,7 @@ class Stats(ctypes.Structure):
                 ("block_rows", c_i64), ("block_cols", c_i64),
                 ("ms_mad", ctypes.c_double), ("ms_ech", ctypes.c_double), ("ms_small", ctypes.c_double),
                 ("launches_mad", c_i64), ("launches_ech", c_i64), ("launches_small", c_i64),
-                ("mad_bytes", ctypes.c_double), ("mac_mad_timed", ctypes.c_double)]
+                ("mad_bytes", ctypes.c_double), ("mac_mad_timed", ctypes.c_double), ("variant", c_i64)]
 
 
 class ServerCfg(ctypes.Structure):
@@ -54,6 +57,8 @@ class MadDesc(ctypes.Structure):
 SIGNATURES = {
     "gfech_echelonise_u8": (ctypes.c_int, [vp, c_i64, c_i64, c_i64, c_u32, vp, ctypes.POINTER(vp)]),
     "gfech_echelonise_u8_dev": (ctypes.c_int, [vp, c_i64, c_i64, c_i64, c_u32, vp, vp, ctypes.POINTER(vp)]),
+    "gfech_echelonise_gf2": (ctypes.c_int, [vp, c_i64, c_i64, c_i64, vp, ctypes.POINTER(vp)]),
+    "gfech_echelonise_gf2_dev": (ctypes.c_int, [vp, c_i64, c_i64, c_i64, vp, vp, ctypes.POINTER(vp)]),
     "gfech_echelonise_batch": (ctypes.c_int, [c_i64, vp, c_i32, vp, vp, ctypes.POINTER(vp), vp]),
     "gfech_rank": (c_i64, [vp]),
     "gfech_shape": (ctypes.c_int, [vp, i64p, i64p, ctypes.POINTER(c_u32)]),

@@ -31,11 +31,12 @@ class Outputs:
     rho: np.ndarray
     gamma_bar: np.ndarray
     rho_bar: np.ndarray
-    R: np.ndarray
-    M: np.ndarray
-    K: np.ndarray
+    R: np.ndarray | None
+    M: np.ndarray | None
+    K: np.ndarray | None
     E: np.ndarray | None = None
     T: np.ndarray | None = None
+    variant: int = 0
 
 
 def _ptr(a: np.ndarray):
@@ -135,23 +136,28 @@ class Result:
                                                          ctypes.c_void_p(stream)))
 
     def outputs(self, expand: bool = True) -> Outputs:
+        """Every output the result's variant includes (the others are None)."""
         m, n, p = self.shape()
         g, rho = self.pivots()
         gb, rb = self.nonpivots()
+        v = int(self.stats()["variant"])
+        has_r, has_t = v != _abi.WANT_RANK, v == _abi.WANT_RREF_T
         o = Outputs(p=p, m=m, n=n, rank=self.rank, gamma=g, rho=rho, gamma_bar=gb, rho_bar=rb,
-                    R=self.get_R(), M=self.get_M(), K=self.get_K())
+                    R=self.get_R() if has_r else None, M=self.get_M() if has_t else None,
+                    K=self.get_K() if has_t else None, variant=v)
         if expand:
-            o.E = self.expand_rref()
-            o.T = self.expand_transform()
+            o.E = self.expand_rref() if has_r else None
+            o.T = self.expand_transform() if has_t else None
         return o
 
 
-def _opts(block_rows=0, block_cols=0, skip_range_check=False, profile=False):
+def _opts(block_rows=0, block_cols=0, skip_range_check=False, profile=False, variant=0):
     o = _abi.Opts()
     o.block_rows = int(block_rows)
     o.block_cols = int(block_cols)
     o.skip_range_check = 1 if skip_range_check else 0
     o.profile = int(profile)
+    o.variant = int(variant)
     return o
 
 
@@ -168,22 +174,42 @@ class Library:
         if st != _abi.GFECH_OK:
             raise GfechError(st, self.lib.gfech_last_error().decode())
 
-    def echelonise(self, A, p: int, block_rows=0, block_cols=0) -> Result:
-        """A: host numpy (m x n, uint8)."""
+    def echelonise(self, A, p: int, block_rows=0, block_cols=0, variant=0) -> Result:
+        """A: host numpy (m x n, uint8).  variant: _abi.WANT_* (what is computed)."""
         A = np.ascontiguousarray(np.asarray(A, dtype=np.uint8))
         m, n = A.shape
         out = ctypes.c_void_p()
-        o = _opts(block_rows, block_cols)
+        o = _opts(block_rows, block_cols, variant=variant)
         self._check(self.lib.gfech_echelonise_u8(_ptr(A), m, n, max(n, 1), p, ctypes.byref(o), ctypes.byref(out)))
         return Result(self.lib, out.value)
 
     def echelonise_dev(self, ptr: int, m: int, n: int, lda: int, p: int, stream: int = 0, block_rows=0,
-                       block_cols=0, skip_range_check=False, profile=False) -> Result:
+                       block_cols=0, skip_range_check=False, profile=False, variant=0) -> Result:
         """ptr: device address of an m x n uint8 matrix with leading dimension lda."""
         out = ctypes.c_void_p()
-        o = _opts(block_rows, block_cols, skip_range_check, profile)
+        o = _opts(block_rows, block_cols, skip_range_check, profile, variant)
         self._check(self.lib.gfech_echelonise_u8_dev(ctypes.c_void_p(ptr), m, n, lda, p, ctypes.byref(o),
                                                      ctypes.c_void_p(stream), ctypes.byref(out)))
+        return Result(self.lib, out.value)
+
+    def echelonise_gf2(self, W, n: int, block_rows=0, block_cols=0, variant=0, skip_range_check=False) -> Result:
+        """W: host numpy uint64 (m x words), GF(2) rows packed least significant bit first."""
+        W = np.ascontiguousarray(np.asarray(W, dtype=np.uint64))
+        m = W.shape[0]
+        ldw = W.shape[1] if W.ndim == 2 else 0
+        out = ctypes.c_void_p()
+        o = _opts(block_rows, block_cols, skip_range_check, variant=variant)
+        self._check(self.lib.gfech_echelonise_gf2(_ptr(W), m, n, max(ldw, (n + 63) // 64, 1), ctypes.byref(o),
+                                                  ctypes.byref(out)))
+        return Result(self.lib, out.value)
+
+    def echelonise_gf2_dev(self, ptr: int, m: int, n: int, ldw: int, stream: int = 0, block_rows=0, block_cols=0,
+                           variant=0, skip_range_check=False) -> Result:
+        """ptr: device address of m rows of ldw uint64 words (GF(2), packed)."""
+        out = ctypes.c_void_p()
+        o = _opts(block_rows, block_cols, skip_range_check, variant=variant)
+        self._check(self.lib.gfech_echelonise_gf2_dev(ctypes.c_void_p(ptr), m, n, ldw, ctypes.byref(o),
+                                                      ctypes.c_void_p(stream), ctypes.byref(out)))
         return Result(self.lib, out.value)
 
     def mad_dev(self, M, N, K, p, A, lda, B, ldb, D, ldd, C=0, ldc=0, brow=0, crow=0, stream=0):
@@ -212,7 +238,7 @@ class Library:
         return Server(self, hbm_budget_bytes, max_active)
 
     def echelonise_batch(self, problems, on_device: bool = False, stream: int = 0, block_rows=0, block_cols=0,
-                         profile=False):
+                         profile=False, variant=0):
         """problems: list of (A, p) with A a host numpy array (on_device=False) or
         (ptr, m, n, lda, p) tuples (on_device=True).  Returns (results, statuses)."""
         cnt = len(problems)
@@ -232,7 +258,7 @@ class Library:
             arr[t].m, arr[t].n, arr[t].lda, arr[t].p = m, n, lda, p
         outs = (ctypes.c_void_p * max(cnt, 1))()
         sts = (ctypes.c_int * max(cnt, 1))()
-        o = _opts(block_rows, block_cols, profile=profile)
+        o = _opts(block_rows, block_cols, profile=profile, variant=variant)
         self.lib.gfech_echelonise_batch(cnt, arr, 1 if on_device else 0, ctypes.byref(o), ctypes.c_void_p(stream),
                                         outs, sts)
         res = [Result(self.lib, outs[t]) if outs[t] else None for t in range(cnt)]

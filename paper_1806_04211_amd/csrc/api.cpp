@@ -79,6 +79,18 @@ gfech_status check_common(int64_t m, int64_t n, int64_t lda, uint32_t p, const v
     return GFECH_OK;
 }
 
+gfech_status check_variant(const gfech_opts* o) {
+    if (o && (o->variant < GFECH_WANT_RREF_T || o->variant > GFECH_WANT_RANK))
+        return fail(GFECH_E_ARG, "unknown variant");
+    return GFECH_OK;
+}
+
+int32_t variant_of(const gfech_opts* o) { return o ? o->variant : GFECH_WANT_RREF_T; }
+
+// the result includes R (and E) / M, K (and T)
+bool has_R(const gfech::Result& R) { return R.want != gfech::kWantRank; }
+bool has_T(const gfech::Result& R) { return R.want == gfech::kWantAll; }
+
 gfech::Backend* get_backend(gfech_status* st) {
     std::string err;
     gfech::Backend* be = gfech::backend_instance(&err);
@@ -106,6 +118,7 @@ gfech_status echelonise_impl(const uint8_t* A, bool on_device, int64_t m, int64_
     *out = nullptr;
     gfech_status st = check_common(m, n, lda, p, A);
     if (st) return st;
+    if ((st = check_variant(opts))) return st;
     bool check = !(opts && opts->skip_range_check);
     if (!on_device && check) {
         for (int64_t i = 0; i < m; ++i)
@@ -144,9 +157,80 @@ gfech_status echelonise_impl(const uint8_t* A, bool on_device, int64_t m, int64_
     probs[0].n = n;
     probs[0].lda = ld;
     probs[0].p = (int32_t)p;
+    probs[0].want = variant_of(opts);
     choose_blocks(m, n, opts, probs[0].row_blocks, probs[0].col_blocks);
     st = run(be, probs, out, opts);
     if (staged) be->release(staged);
+    be->set_stream(nullptr);
+    return st;
+}
+
+// GF(2) input packed in 64-bit words: unpacked on the device into one byte
+// per entry, then the byte path over p = 2
+gfech_status echelonise_gf2_impl(const uint64_t* A, bool on_device, int64_t m, int64_t n, int64_t ldw,
+                                 const gfech_opts* opts, void* stream, gfech_result** out) {
+    if (!out) return fail(GFECH_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (m < 0 || n < 0 || ldw < 0) return fail(GFECH_E_ARG, "negative size");
+    const int64_t words = (n + 63) / 64;
+    if (m > 0 && n > 0 && (!A || ldw < words)) return fail(GFECH_E_ARG, "null input or ldw < ceil(n / 64)");
+    gfech_status st = check_common(m, n, n, 2, A);
+    if (st) return st;
+    if ((st = check_variant(opts))) return st;
+    const bool check = !(opts && opts->skip_range_check);
+    if (!on_device && check && n % 64 && m > 0) {
+        const uint64_t mask = ~((1ull << (n % 64)) - 1);
+        for (int64_t i = 0; i < m; ++i)
+            if (A[i * ldw + n / 64] & mask) return fail(GFECH_E_RANGE, "a pad bit past column n - 1 is set");
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    gfech::Backend* be = get_backend(&st);
+    if (!be) return st;
+    be->set_stream(stream);
+    const uint64_t* packed = A;
+    int64_t ld = ldw;
+    void* staged = nullptr;
+    uint8_t* bytes = nullptr;
+    if (m > 0 && n > 0) {
+        if (!on_device) {
+            staged = be->alloc((size_t)(m * words) * 8);
+            if (!staged) return fail(GFECH_E_NOMEM, "device allocation of the input failed");
+            if (ldw == words) {
+                be->upload(staged, A, (size_t)(m * words) * 8);
+            } else {
+                std::vector<uint64_t> tmp((size_t)(m * words));
+                for (int64_t i = 0; i < m; ++i) memcpy(tmp.data() + i * words, A + i * ldw, (size_t)words * 8);
+                be->upload(staged, tmp.data(), tmp.size() * 8);
+            }
+            packed = (const uint64_t*)staged;
+            ld = words;
+        } else if (check) {
+            const int64_t bad = be->count_gf2_pad(A, m, n, ldw);
+            if (bad != 0) {
+                be->set_stream(nullptr);
+                return fail(bad > 0 ? GFECH_E_RANGE : GFECH_E_DEVICE,
+                            bad > 0 ? "a pad bit past column n - 1 is set" : "device error");
+            }
+        }
+        bytes = (uint8_t*)be->alloc((size_t)(m * n));
+        if (!bytes) {
+            be->release(staged);
+            be->set_stream(nullptr);
+            return fail(GFECH_E_NOMEM, "device allocation of the unpacked input failed");
+        }
+        be->unpack_gf2(packed, m, n, ld, bytes, n);
+    }
+    std::vector<gfech::Problem> probs(1);
+    probs[0].A = bytes;
+    probs[0].m = m;
+    probs[0].n = n;
+    probs[0].lda = std::max<int64_t>(n, 1);
+    probs[0].p = 2;
+    probs[0].want = variant_of(opts);
+    choose_blocks(m, n, opts, probs[0].row_blocks, probs[0].col_blocks);
+    st = run(be, probs, out, opts);
+    be->release(bytes);
+    be->release(staged);
     be->set_stream(nullptr);
     return st;
 }
@@ -231,10 +315,21 @@ gfech_status gfech_echelonise_u8_dev(const uint8_t* A_dev, int64_t m, int64_t n,
     return echelonise_impl(A_dev, true, m, n, lda, p, opts, stream, out);
 }
 
+gfech_status gfech_echelonise_gf2(const uint64_t* A, int64_t m, int64_t n, int64_t ldw, const gfech_opts* opts,
+                                  gfech_result** out) {
+    return echelonise_gf2_impl(A, false, m, n, ldw, opts, nullptr, out);
+}
+
+gfech_status gfech_echelonise_gf2_dev(const uint64_t* A_dev, int64_t m, int64_t n, int64_t ldw,
+                                      const gfech_opts* opts, void* stream, gfech_result** out) {
+    return echelonise_gf2_impl(A_dev, true, m, n, ldw, opts, stream, out);
+}
+
 gfech_status gfech_echelonise_batch(int64_t count, const gfech_problem* probs, int32_t inputs_on_device,
                                     const gfech_opts* opts, void* stream, gfech_result** outs,
                                     gfech_status* per_problem) {
     if (count < 0 || (count > 0 && (!probs || !outs))) return fail(GFECH_E_ARG, "bad batch arguments");
+    if (check_variant(opts)) return GFECH_E_ARG;
     gfech_status first = GFECH_OK;
     std::vector<int64_t> ok;
     for (int64_t t = 0; t < count; ++t) {
@@ -263,6 +358,7 @@ gfech_status gfech_echelonise_batch(int64_t count, const gfech_problem* probs, i
         const gfech_problem& q = probs[t];
         gfech::Problem pr;
         pr.m = q.m; pr.n = q.n; pr.lda = q.lda; pr.p = (int32_t)q.p; pr.A = q.A;
+        pr.want = variant_of(opts);
         if (inputs_on_device && !(opts && opts->skip_range_check) && q.m > 0 && q.n > 0) {
             int64_t bad = be->count_out_of_range(q.A, q.m, q.n, q.lda, (int32_t)q.p);
             if (bad) {
@@ -329,6 +425,7 @@ gfech_status gfech_nonpivots(const gfech_result* res, int64_t* gamma_bar, int64_
 gfech_status gfech_get_R(const gfech_result* res, uint8_t* R_, int64_t ldr) {
     if (!res) return fail(GFECH_E_ARG, "NULL result");
     const gfech::Result& R = *res->r;
+    if (!has_R(R)) return fail(GFECH_E_STATE, "the result was computed without R");
     if (R.r > 0 && R.n - R.r > 0 && (!R_ || ldr < R.n - R.r)) return fail(GFECH_E_ARG, "bad R buffer");
     std::lock_guard<std::mutex> lk(g_mu);
     return download_matrix(R.be, R.Pfinal + R.offR, R.ldP, R.r, R.n - R.r, R_, ldr);
@@ -337,6 +434,7 @@ gfech_status gfech_get_R(const gfech_result* res, uint8_t* R_, int64_t ldr) {
 gfech_status gfech_get_M(const gfech_result* res, uint8_t* M, int64_t ldm) {
     if (!res) return fail(GFECH_E_ARG, "NULL result");
     const gfech::Result& R = *res->r;
+    if (!has_T(R)) return fail(GFECH_E_STATE, "the result was computed without the transformation");
     if (R.r > 0 && (!M || ldm < R.r)) return fail(GFECH_E_ARG, "bad M buffer");
     std::lock_guard<std::mutex> lk(g_mu);
     return download_matrix(R.be, R.Pfinal + R.offM, R.ldP, R.r, R.r, M, ldm);
@@ -345,6 +443,7 @@ gfech_status gfech_get_M(const gfech_result* res, uint8_t* M, int64_t ldm) {
 gfech_status gfech_get_K(const gfech_result* res, uint8_t* K, int64_t ldk) {
     if (!res) return fail(GFECH_E_ARG, "NULL result");
     const gfech::Result& R = *res->r;
+    if (!has_T(R)) return fail(GFECH_E_STATE, "the result was computed without the transformation");
     if (R.r > 0 && R.m - R.r > 0 && (!K || ldk < R.r)) return fail(GFECH_E_ARG, "bad K buffer");
     std::lock_guard<std::mutex> lk(g_mu);
     return download_matrix(R.be, R.Kfinal, R.ldK, R.m - R.r, R.r, K, ldk);
@@ -353,6 +452,7 @@ gfech_status gfech_get_K(const gfech_result* res, uint8_t* K, int64_t ldk) {
 gfech_status gfech_expand_rref_dev(const gfech_result* res, uint8_t* E, int64_t lde, void* stream) {
     if (!res) return fail(GFECH_E_ARG, "NULL result");
     const gfech::Result& R = *res->r;
+    if (!has_R(R)) return fail(GFECH_E_STATE, "the result was computed without R");
     if (R.r > 0 && R.n > 0 && (!E || lde < R.n)) return fail(GFECH_E_ARG, "bad E buffer");
     std::lock_guard<std::mutex> lk(g_mu);
     R.be->set_stream(stream);
@@ -365,6 +465,7 @@ gfech_status gfech_expand_rref_dev(const gfech_result* res, uint8_t* E, int64_t 
 gfech_status gfech_expand_transform_dev(const gfech_result* res, uint8_t* T, int64_t ldt, void* stream) {
     if (!res) return fail(GFECH_E_ARG, "NULL result");
     const gfech::Result& R = *res->r;
+    if (!has_T(R)) return fail(GFECH_E_STATE, "the result was computed without the transformation");
     if (R.m > 0 && (!T || ldt < R.m)) return fail(GFECH_E_ARG, "bad T buffer");
     std::lock_guard<std::mutex> lk(g_mu);
     R.be->set_stream(stream);
@@ -377,6 +478,7 @@ gfech_status gfech_expand_transform_dev(const gfech_result* res, uint8_t* T, int
 gfech_status gfech_expand_rref(const gfech_result* res, uint8_t* E, int64_t lde) {
     if (!res) return fail(GFECH_E_ARG, "NULL result");
     const gfech::Result& R = *res->r;
+    if (!has_R(R)) return fail(GFECH_E_STATE, "the result was computed without R");
     if (R.r == 0 || R.n == 0) return GFECH_OK;
     if (!E || lde < R.n) return fail(GFECH_E_ARG, "bad E buffer");
     std::lock_guard<std::mutex> lk(g_mu);
@@ -391,6 +493,7 @@ gfech_status gfech_expand_rref(const gfech_result* res, uint8_t* E, int64_t lde)
 gfech_status gfech_expand_transform(const gfech_result* res, uint8_t* T, int64_t ldt) {
     if (!res) return fail(GFECH_E_ARG, "NULL result");
     const gfech::Result& R = *res->r;
+    if (!has_T(R)) return fail(GFECH_E_STATE, "the result was computed without the transformation");
     if (R.m == 0) return GFECH_OK;
     if (!T || ldt < R.m) return fail(GFECH_E_ARG, "bad T buffer");
     std::lock_guard<std::mutex> lk(g_mu);
@@ -405,9 +508,9 @@ gfech_status gfech_expand_transform(const gfech_result* res, uint8_t* T, int64_t
 gfech_status gfech_device_view(const gfech_result* res, gfech_view* v) {
     if (!res || !v) return fail(GFECH_E_ARG, "NULL argument");
     const gfech::Result& R = *res->r;
-    v->R = R.Pfinal + R.offR; v->ldr = R.ldP;
-    v->M = R.Pfinal + R.offM; v->ldm = R.ldP;
-    v->K = R.Kfinal; v->ldk = R.ldK;
+    v->R = has_R(R) ? R.Pfinal + R.offR : nullptr; v->ldr = R.ldP;
+    v->M = has_T(R) ? R.Pfinal + R.offM : nullptr; v->ldm = R.ldP;
+    v->K = has_T(R) ? R.Kfinal : nullptr; v->ldk = R.ldK;
     v->gamma = R.upsilon; v->gamma_bar = R.upsilon_bar;
     v->rho = R.varrho; v->rho_bar = R.varrho_bar;
     return GFECH_OK;
@@ -437,6 +540,7 @@ gfech_status gfech_get_stats(const gfech_result* res, gfech_stats* s) {
     s->launches_small = t.kernel_launches[2];
     s->mad_bytes = t.mad_bytes;
     s->mac_mad_timed = t.kernel_mac[0];
+    s->variant = res->r->want;
     return GFECH_OK;
 }
 

@@ -125,6 +125,12 @@ public:
     virtual void sync() = 0;
     // number of entries >= p in an m x n matrix (waits for the answer)
     virtual int64_t count_out_of_range(const uint8_t* A, int64_t m, int64_t n, int64_t lda, int32_t p) = 0;
+    // GF(2) rows packed in 64-bit words, bit b of word w = column 64 w + b, to
+    // one byte per entry: dst[x][y] = bit (y mod 64) of src[x][y / 64] for
+    // x < m, y < n (ldw words and ldd bytes per row)
+    virtual void unpack_gf2(const uint64_t* src, int64_t m, int64_t n, int64_t ldw, uint8_t* dst, int64_t ldd) = 0;
+    // number of rows whose last word has a set bit past column n - 1 (waits for the answer)
+    virtual int64_t count_gf2_pad(const uint64_t* src, int64_t m, int64_t n, int64_t ldw) = 0;
     // stream for subsequent work (a hipStream_t for the HIP backend)
     virtual void set_stream(void* stream) { (void)stream; }
     // a stream of the library's own (default priority), and its release

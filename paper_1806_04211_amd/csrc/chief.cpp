@@ -152,6 +152,8 @@ public:
         alpha_.assign(pr.row_blocks.begin(), pr.row_blocks.end());
         rankc_.assign(b_, 0);
         sel_.assign(a_, std::vector<int32_t>(b_, 0));
+        trafo_ = pr.want == kWantAll;
+        keepR_ = pr.want != kWantRank;
         amax_ = a_ ? *std::max_element(pr.row_blocks.begin(), pr.row_blocks.end()) : 0;
     }
 
@@ -168,7 +170,7 @@ public:
             int64_t ai = pr_.row_blocks[i];
             // 64-byte aligned rows, so the products take the streamed MAD path
             br.ldC = std::max<int64_t>((n_ + 63) / 64 * 64, 64);
-            br.ldK = (R0_[i] + ai + 63) / 64 * 64;
+            br.ldK = trafo_ ? (R0_[i] + ai + 63) / 64 * 64 : 0;
             for (int s = 0; s < 2; ++s) {
                 br.oC[s] = ar.take(ai * br.ldC);
                 br.oK[s] = ar.take(ai * br.ldK);
@@ -204,7 +206,8 @@ public:
             bc.oQcol = ar.take(sizeof(int32_t) * bj);
         }
         prow_total_ = prow;
-        ldP_ = (n_ + m_ + 63) / 64 * 64;
+        // pivot rows: n data columns, then (with the transformation) m columns of M
+        ldP_ = std::max<int64_t>((n_ + (trafo_ ? m_ : 0) + 63) / 64 * 64, 64);
         oP_ = ar.take(prow_total_ * ldP_);
         arena_bytes_ = ar.size;
         slots_ = ar.slots;
@@ -253,8 +256,10 @@ public:
         for (int i = 0; i < a_; ++i) {
             BR& br = rows_[i];
             int64_t ai = pr_.row_blocks[i];
-            be_.zero(br.K[0], (size_t)(ai * br.ldK));
-            be_.zero(br.K[1], (size_t)(ai * br.ldK));
+            if (trafo_) {
+                be_.zero(br.K[0], (size_t)(ai * br.ldK));
+                be_.zero(br.K[1], (size_t)(ai * br.ldK));
+            }
             if (n_ > 0) {
                 GatherDesc g;
                 g.rows = (int32_t)ai;
@@ -355,7 +360,7 @@ public:
                 g.D = br.C[br.cur] + c0; g.ldd = br.ldC;
                 push_split(pri, bulk, g, t.j, st_.ur_mad);
             }
-            for (int h = 0; h < t.i; ++h) {
+            for (int h = 0; trafo_ && h < t.i; ++h) {
                 int32_t w = sel_[h][t.j];
                 if (w == 0) continue;
                 GemmDesc g;
@@ -539,7 +544,7 @@ public:
                 g.D = X + c0; g.ldd = ldP_;
                 push_split(pri, bulk, g, t.j, st_.ur_mad);
             }
-            for (int h = 0; h <= t.i; ++h) {
+            for (int h = 0; trafo_ && h <= t.i; ++h) {
                 int32_t w = (h < t.i) ? sel_[h][t.j] : (t.j ? sel_[t.i][t.j - 1] : 0);
                 if (w > 0) {
                     GemmDesc g;
@@ -579,7 +584,7 @@ public:
                 g.C = Brow + c0; g.ldc = ldP_; g.D = Brow + c0; g.ldd = ldP_;
                 push_split(pri, bulk, g, t.j, st_.ur_mad);
             }
-            for (int h = 0; h <= t.i; ++h) {
+            for (int h = 0; trafo_ && h <= t.i; ++h) {
                 int32_t w = sel_[h][t.j];
                 if (w == 0) continue;
                 GemmDesc g;
@@ -611,7 +616,7 @@ public:
                 g.D = br.C[1 - br.cur] + c0; g.ldd = br.ldC;
                 push_split(pri, bulk, g, t.j, st_.ur_mad);
             }
-            for (int h = 0; h <= t.i; ++h) {
+            for (int h = 0; trafo_ && h <= t.i; ++h) {
                 int32_t w = (h < t.i) ? sel_[h][t.j] : (t.j ? sel_[t.i][t.j - 1] : 0);
                 if (w > 0) {
                     GemmDesc g;
@@ -653,15 +658,17 @@ public:
     bool assemble_lists(Result& res, Ops& ops) {
         r_ = rank();
         res.m = m_; res.n = n_; res.r = r_; res.p = p_;
+        res.want = pr_.want;
         res.row_blocks = pr_.row_blocks;
         res.col_blocks = pr_.col_blocks;
         res.offR = (r_ + 15) / 16 * 16;
         res.offM = (res.offR + n_ - r_ + 15) / 16 * 16;
-        res.ldP = (res.offM + r_ + 63) / 64 * 64;   // 64-byte aligned rows for the vector loads
+        // 64-byte aligned rows for the vector loads; [X R] only without the transformation
+        res.ldP = ((trafo_ ? res.offM + r_ : res.offR + n_ - r_) + 63) / 64 * 64;
         res.ldK = r_;
         auto ialloc = [&](int64_t cnt) { return (int32_t*)be_.alloc(sizeof(int32_t) * std::max<int64_t>(cnt, 1)); };
-        res.Pfinal = (uint8_t*)be_.alloc((size_t)std::max<int64_t>(r_ * res.ldP, 1));
-        res.Kfinal = (uint8_t*)be_.alloc((size_t)std::max<int64_t>((m_ - r_) * r_, 1));
+        res.Pfinal = (uint8_t*)be_.alloc((size_t)std::max<int64_t>(keepR_ ? r_ * res.ldP : 0, 1));
+        res.Kfinal = (uint8_t*)be_.alloc((size_t)std::max<int64_t>(trafo_ ? (m_ - r_) * r_ : 0, 1));
         res.upsilon = ialloc(r_);
         res.upsilon_bar = ialloc(n_ - r_);
         res.varrho = ialloc(r_);
@@ -716,10 +723,12 @@ public:
             if (sh > 0) {
                 SortDesc s;
                 s.n = sh; s.vals = br.E;
-                s.mode = 1; s.add = (int32_t)(n_ + R0_[h]); s.out = colmap_ + n_ + soff_[h];
-                ops.sort.push_back(s);
-                s.mode = 1; s.add = (int32_t)R0_[h]; s.out = kmap_ + soff_[h];
-                ops.sort.push_back(s);
+                if (trafo_) {
+                    s.mode = 1; s.add = (int32_t)(n_ + R0_[h]); s.out = colmap_ + n_ + soff_[h];
+                    ops.sort.push_back(s);
+                    s.mode = 1; s.add = (int32_t)R0_[h]; s.out = kmap_ + soff_[h];
+                    ops.sort.push_back(s);
+                }
                 s.mode = 0; s.add = (int32_t)R0_[h]; s.out = res.varrho + soff_[h];
                 ops.sort.push_back(s);
             }
@@ -745,9 +754,9 @@ public:
     // the diagonal remnants D_k.R.  RowLengthen (Step 2) is already done:
     // columns of rows selected later were never written and are zero.
     void repack(Result& res, Ops& ops) {
-        if (r_ == 0) return;
+        if (r_ == 0 || !keepR_) return;
         // X, R and M to their column ranges (colmap_ lists the source columns of [X R M])
-        const int64_t part[3][3] = {{0, 0, r_}, {r_, res.offR, n_ - r_}, {n_, res.offM, r_}};
+        const int64_t part[3][3] = {{0, 0, r_}, {r_, res.offR, n_ - r_}, {n_, res.offM, trafo_ ? r_ : 0}};
         for (const auto& q : part) {
             if (q[2] == 0) continue;
             GatherDesc g;
@@ -756,9 +765,9 @@ public:
             g.dst = res.Pfinal + q[1]; g.ldd = res.ldP;
             ops.gather.push_back(g);
         }
-        st_.gather_bytes += 2.0 * r_ * (n_ + r_);
-        // the gaps before R and before M
-        const int64_t gap[2][2] = {{r_, res.offR}, {res.offR + n_ - r_, res.offM}};
+        st_.gather_bytes += 2.0 * r_ * (n_ + (trafo_ ? r_ : 0));
+        // the gaps before R and before M (and after R, up to the leading dimension, without M)
+        const int64_t gap[2][2] = {{r_, res.offR}, {res.offR + n_ - r_, trafo_ ? res.offM : res.ldP}};
         for (const auto& q : gap) {
             if (q[1] == q[0]) continue;
             FillDesc f;
@@ -769,6 +778,7 @@ public:
     }
 
     void repack_diag(Result& res, Ops& ops) {
+        if (!keepR_) return;
         for (int j = 0; j < b_; ++j) {
             BC& bc = cols_[j];
             int32_t rj = rankc_[j], nj = pr_.col_blocks[j] - rj;
@@ -781,7 +791,7 @@ public:
         }
         // K: (m - r) x r, rows = the final non-selected rows of each block row,
         // columns = selected rows in ascending order (zero for block rows h > i)
-        if (m_ - r_ > 0 && r_ > 0) {
+        if (trafo_ && m_ - r_ > 0 && r_ > 0) {
             FillDesc f;
             f.rows = (int32_t)(m_ - r_); f.cols = (int32_t)r_;
             f.dst = res.Kfinal; f.ldd = res.ldK;
@@ -790,7 +800,7 @@ public:
     }
 
     void k_assemble(Result& res, Ops& ops) {
-        if (m_ - r_ == 0 || r_ == 0) return;
+        if (!trafo_ || m_ - r_ == 0 || r_ == 0) return;
         for (int i = 0; i < a_; ++i) {
             BR& br = rows_[i];
             int32_t cols = soff_[i + 1];
@@ -818,6 +828,7 @@ public:
     // which is the same sum the column-by-column order forms.
     void plan_clearup(Result& res, int64_t group_rank) {
         cu_steps_.clear();
+        if (!keepR_) return;                            // the rank alone: no Step 3
         int k1 = b_;                                    // group = block columns [k0, k1)
         while (k1 > 1) {
             int k0 = k1 - 1;
@@ -898,8 +909,9 @@ private:
         // columns added on the left keep their values
         const int64_t c0u = res.offR + noff_[kc];
         const int64_t c0 = std::max<int64_t>(res.offR, c0u & ~(int64_t)15);
-        const int64_t width = res.offM + r_ - c0;
-        if (c0u >= res.offM + r_) return false;
+        const int64_t end = trafo_ ? res.offM + r_ : res.offR + n_ - r_;   // through M, or R alone
+        const int64_t width = end - c0;
+        if (c0u >= end) return false;
         g = GemmDesc();
         g.M = (int32_t)(rhi - rlo); g.N = (int32_t)width; g.K = (int32_t)(phi - plo); g.p = p_;
         g.A = res.Pfinal + rlo * res.ldP + plo; g.lda = res.ldP;
@@ -939,6 +951,8 @@ private:
     int64_t m_ = 0, n_ = 0;
     int32_t p_ = 0;
     int32_t amax_ = 0;
+    bool trafo_ = true;    // the transformation (K panels, M columns of P, UpdateRowTrafo, M in Step 3)
+    bool keepR_ = true;    // the reduced remnant R (Step 3)
     std::vector<int64_t> R0_, C0_;
     std::vector<int32_t> alpha_, rankc_;
     std::vector<std::vector<int32_t>> sel_;   // sel_[h][j] = |E_{h,j}.rho|
@@ -1371,7 +1385,10 @@ size_t Engine::footprint(const Problem& pr) const {
     size_t bytes = plan.plan_memory() + kAlign;
     // the result (at most rank min(m, n)) and the assembly maps
     const size_t r = (size_t)std::min(pr.m, pr.n);
-    bytes += r * (size_t)((pr.n + (int64_t)r + 32 + 63) / 64 * 64) + (size_t)(pr.m - (int64_t)r) * r;
+    if (pr.want == kWantAll)
+        bytes += r * (size_t)((pr.n + (int64_t)r + 32 + 63) / 64 * 64) + (size_t)(pr.m - (int64_t)r) * r;
+    else if (pr.want == kWantRref)
+        bytes += r * (size_t)((pr.n + 16 + 63) / 64 * 64);
     bytes += sizeof(int32_t) * (size_t)(3 * pr.m + 3 * pr.n + 4 * r) + 16 * kAlign;
     return bytes;
 }

@@ -30,17 +30,28 @@ struct Stats {
     double total_mac() const { return cd_mad + ech + ur_mad + urt_mad + cu_mad; }
 };
 
+// What a problem computes (the variants of Section 1): everything (the
+// reduced echelon form and the transformation), the reduced echelon form
+// alone (no UpdateRowTrafo products, no M part of Step 3: M and K are not
+// formed), or the rank with the pivot columns and selected rows (Step 3 is
+// not run either: R is not reduced and not kept).
+enum Want : int32_t { kWantAll = 0, kWantRref = 1, kWantRank = 2 };
+
 // Device-resident result (library-owned).
 struct Result {
     Backend* be = nullptr;
     int64_t m = 0, n = 0, r = 0;
     int32_t p = 0;
+    int32_t want = kWantAll;         // which outputs were computed (Want)
     // Pfinal: r rows, leading dimension ldP.  Columns [0, r) are scratch (the
     // cleared X blocks), [offR, offR + n - r) hold the remnant R (Eq. (3), rows
     // ordered by pivot column, columns = non-pivot columns ascending),
     // [offM, offM + r) hold M (columns ordered by selected row); offR and offM
     // are the first multiples of 16 at or after r and offR + n - r, so the
     // products of Step 3 see 16-byte aligned rows; the gaps are zero.
+    // Without the transformation (kWantRref) there are no M columns (offM is
+    // the end of R) and Kfinal holds nothing; for kWantRank Pfinal holds
+    // nothing either.
     uint8_t* Pfinal = nullptr; int64_t ldP = 0;
     int64_t offR = 0, offM = 0;
     uint8_t* Kfinal = nullptr; int64_t ldK = 0;   // (m - r) x r
@@ -57,6 +68,7 @@ struct Problem {
     const uint8_t* A = nullptr;   // backend address of the m x n input
     int64_t m = 0, n = 0, lda = 0;
     int32_t p = 0;
+    int32_t want = kWantAll;
     std::vector<int32_t> row_blocks, col_blocks;   // a_i and b_j (sums m and n)
 };
 

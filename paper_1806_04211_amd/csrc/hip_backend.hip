@@ -1884,6 +1884,43 @@ k_range(const uint8_t* __restrict__ A, int64_t m, int64_t n, int64_t lda, int p,
     if (cnt) atomicAdd(bad, cnt);
 }
 
+// GF(2) rows packed least significant bit first in 64-bit words, unpacked to
+// one byte per entry.  Thread c of a row writes the 16 entries of bits
+// 16 (c mod 4) .. 16 (c mod 4) + 15 of word c / 4, as one 16-byte store when
+// they lie inside the row and the destination is 16-byte aligned.
+__global__ void __launch_bounds__(SMALL_THREADS)
+k_unpack_gf2(const uint64_t* __restrict__ src, int64_t m, int64_t n, int64_t ldw, uint8_t* __restrict__ dst,
+             int64_t ldd) {
+    const int64_t chunks = (n + 15) / 16;
+    for (int64_t x = blockIdx.x; x < m; x += gridDim.x) {
+        uint8_t* d = dst + x * ldd;
+        for (int64_t c = threadIdx.x; c < chunks; c += SMALL_THREADS) {
+            const uint32_t bits = (uint32_t)(src[x * ldw + c / 4] >> (16 * (c & 3))) & 0xFFFFu;
+            const int64_t y0 = c * 16;
+            if (y0 + 16 <= n && (((uintptr_t)(d + y0)) & 15) == 0) {
+                u32x4 v;
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t b = bits >> (4 * q);
+                    v[q] = (b & 1u) | ((b >> 1) & 1u) << 8 | ((b >> 2) & 1u) << 16 | ((b >> 3) & 1u) << 24;
+                }
+                *(u32x4*)(d + y0) = v;
+            } else {
+                for (int q = 0; q < 16 && y0 + q < n; ++q) d[y0 + q] = (uint8_t)((bits >> q) & 1u);
+            }
+        }
+    }
+}
+
+// rows whose last word has a bit set past column n - 1 (n not a multiple of 64)
+__global__ void __launch_bounds__(SMALL_THREADS)
+k_gf2_pad(const uint64_t* __restrict__ src, int64_t m, int64_t n, int64_t ldw, unsigned long long* bad) {
+    const uint64_t mask = ~((1ull << (n & 63)) - 1);
+    unsigned long long cnt = 0;
+    for (int64_t x = blockIdx.x * SMALL_THREADS + threadIdx.x; x < m; x += (int64_t)gridDim.x * SMALL_THREADS)
+        cnt += (src[x * ldw + n / 64] & mask) != 0;
+    if (cnt) atomicAdd(bad, cnt);
+}
+
 // ============================================================================ host side
 
 constexpr size_t kPad = 256;                 // tail padding of every allocation (vector over-read)
@@ -2230,6 +2267,24 @@ public:
         int64_t bx = std::min<int64_t>(m, 8192);
         hipLaunchKernelGGL(k_range, dim3((unsigned)std::max<int64_t>(bx, 1)), dim3(SMALL_THREADS), 0, stream_, A, m,
                            n, lda, p, (unsigned long long*)counter_);
+        HIP_OK(hipGetLastError());
+        unsigned long long bad = 0;
+        download(&bad, counter_, 8);
+        return err_ ? -1 : (int64_t)bad;
+    }
+
+    void unpack_gf2(const uint64_t* src, int64_t m, int64_t n, int64_t ldw, uint8_t* dst, int64_t ldd) override {
+        if (m <= 0 || n <= 0) return;
+        hipLaunchKernelGGL(k_unpack_gf2, dim3((unsigned)std::min<int64_t>(m, 65535)), dim3(SMALL_THREADS), 0, stream_,
+                           src, m, n, ldw, dst, ldd);
+        HIP_OK(hipGetLastError());
+    }
+    int64_t count_gf2_pad(const uint64_t* src, int64_t m, int64_t n, int64_t ldw) override {
+        if (m <= 0 || n <= 0 || n % 64 == 0) return 0;
+        HIP_OK(hipMemsetAsync(counter_, 0, 8, stream_));
+        const int64_t bx = std::min<int64_t>((m + SMALL_THREADS - 1) / SMALL_THREADS, 4096);
+        hipLaunchKernelGGL(k_gf2_pad, dim3((unsigned)bx), dim3(SMALL_THREADS), 0, stream_, src, m, n, ldw,
+                           (unsigned long long*)counter_);
         HIP_OK(hipGetLastError());
         unsigned long long bad = 0;
         download(&bad, counter_, 8);

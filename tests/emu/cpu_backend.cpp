@@ -307,6 +307,27 @@ public:
         }
     }
 
+    // a lane-0 job, like the memory transfers
+    void unpack_gf2(const uint64_t* src, int64_t m, int64_t n, int64_t ldw, uint8_t* dst, int64_t ldd) override {
+        auto run = [this, src, m, n, ldw, dst, ldd] {
+            for (int64_t x = 0; x < m; ++x) {
+                if (!chk(src + x * ldw, 8 * (size_t)((n + 63) / 64), "unpack src") ||
+                    !chk(dst + x * ldd, (size_t)n, "unpack dst"))
+                    return;
+                for (int64_t y = 0; y < n; ++y) dst[x * ldd + y] = (uint8_t)((src[x * ldw + y / 64] >> (y % 64)) & 1u);
+            }
+        };
+        if (fuzz_) on_lane0(run);
+        else run();
+    }
+    int64_t count_gf2_pad(const uint64_t* src, int64_t m, int64_t n, int64_t ldw) override {
+        if (fuzz_) drain(0, q_[0].size());
+        int64_t bad = 0;
+        if (n % 64 == 0) return 0;
+        for (int64_t x = 0; x < m; ++x)
+            for (int64_t y = n; y < (n + 63) / 64 * 64; ++y) bad += (src[x * ldw + y / 64] >> (y % 64)) & 1u;
+        return bad;
+    }
     int64_t count_out_of_range(const uint8_t* A, int64_t m, int64_t n, int64_t lda, int32_t p) override {
         if (fuzz_) drain(0, q_[0].size());
         int64_t bad = 0;

@@ -24,7 +24,8 @@ def test_header_declares_the_boundary():
     names = declared()
     for must in ("gfech_echelonise_u8", "gfech_echelonise_u8_dev", "gfech_echelonise_batch", "gfech_rank",
                  "gfech_pivots", "gfech_get_R", "gfech_get_M", "gfech_get_K", "gfech_expand_rref",
-                 "gfech_expand_transform", "gfech_result_free", "gfech_mad_dev", "gfech_ech_dev"):
+                 "gfech_expand_transform", "gfech_result_free", "gfech_mad_dev", "gfech_ech_dev",
+                 "gfech_echelonise_gf2", "gfech_echelonise_gf2_dev"):
         assert must in names
 
 

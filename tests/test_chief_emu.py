@@ -286,3 +286,76 @@ def test_random_interleavings_catch_a_missing_wait(lib, fuzz, lane, src):
     finally:
         drop(-1, -1)
     assert bad > 0
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("p", [2, 7, 251])
+def test_variants_without_transformation(lib, variant, p):
+    """The reduced echelon form alone (variant 1) and the rank alone (variant
+    2) give the same outputs as the full result, for every blocking kind;
+    the matrices they leave out are refused with GFECH_E_STATE."""
+    from paper_1806_04211_amd.api import GfechError
+    rng = np.random.default_rng(100 * variant + p)
+    for trial in range(25):
+        m = int(rng.integers(1, 30))
+        n = int(rng.integers(1, 30))
+        A = synth.deficient(trial, p, m, n, p) if m > 1 else synth.uniform(trial, p, m, n, p)
+        if trial % 4 == 0:
+            A[:, int(rng.integers(0, n))] = 0
+        br, bc = int(rng.integers(1, 9)), int(rng.integers(1, 9))
+        e = oracle.echelonize(A, p)
+        res = lib.echelonise(A, p, block_rows=br, block_cols=bc, variant=variant)
+        o = res.outputs()
+        where = f"variant {variant} p={p} {m}x{n} blocks {br}x{bc}"
+        assert o.variant == variant and o.rank == e.rank, where
+        for name in ("gamma", "rho", "gamma_bar", "rho_bar"):
+            assert np.array_equal(getattr(o, name), getattr(e, name)), where
+        assert o.M is None and o.K is None and o.T is None
+        if variant == 1:
+            assert np.array_equal(o.R, e.R) and np.array_equal(o.E, e.E), where
+        else:
+            assert o.R is None and o.E is None
+        for getter in ("get_M", "get_K", "expand_transform") + (("get_R", "expand_rref") if variant == 2 else ()):
+            with pytest.raises(GfechError) as ex:
+                getattr(res, getter)()
+            assert ex.value.status == 8, getter
+        st = res.stats()
+        assert st["mac_trafo"] == 0
+        if variant == 2:
+            assert st["mac_clearup"] == 0
+
+
+def test_variant_out_of_range_is_refused(lib):
+    from paper_1806_04211_amd.api import GfechError
+    with pytest.raises(GfechError) as ex:
+        lib.echelonise(np.zeros((3, 3), np.uint8), 3, variant=3)
+    assert ex.value.status == 1
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 130])
+def test_gf2_packed_input(lib, n):
+    """Bit-packed GF(2) rows give the byte path's result over p = 2 (the
+    oracle's), with row strides above ceil(n / 64) words."""
+    rng = np.random.default_rng(n)
+    for m in (1, 7, 40):
+        A = synth.deficient(n, m, m, n, 2) if m > 1 else synth.uniform(n, m, m, n, 2)
+        W = synth.gf2_pack(A)
+        Wpad = np.concatenate([W, rng.integers(0, 2 ** 63, (m, 2), dtype=np.uint64)], axis=1)  # ldw > words
+        e = oracle.echelonize(A, 2)
+        for Wx in (W, Wpad):
+            o = lib.echelonise_gf2(Wx, n, block_rows=5, block_cols=9).outputs()
+            compare(o, e, f"{m}x{n}")
+
+
+def test_gf2_packed_pad_bits_rejected(lib):
+    from paper_1806_04211_amd.api import GfechError
+    A = synth.uniform(1, 1, 6, 70, 2)
+    W = synth.gf2_pack(A)
+    W[3, 1] |= np.uint64(1) << np.uint64(9)          # column 64 + 9 = 73 >= n
+    with pytest.raises(GfechError) as ex:
+        lib.echelonise_gf2(W, 70)
+    assert ex.value.status == 3
+    # the check can be skipped by a caller who guarantees clean pad bits; here
+    # the set bit lies outside the matrix and changes nothing
+    o = lib.echelonise_gf2(W, 70, skip_range_check=True).outputs()
+    compare(o, oracle.echelonize(A, 2))

@@ -117,3 +117,50 @@ def test_profile_levels_time_the_mad_launches():
     assert s2["mac_mad_timed"] == mad_total
     assert 0 < s3["launches_mad"] < s2["launches_mad"]
     assert 0 < s3["mac_mad_timed"] < mad_total
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_variants_at_default_blocking(variant):
+    """The reduced echelon form alone and the rank alone (several block rows
+    and 2048-wide block columns) equal the oracle's outputs."""
+    lib = gpu_library()
+    m, n, p = 768, 5000, 5
+    A = synth.deficient(9, 1, m, n, p)
+    A[:, 100:2300] = 0
+    say(f"echelonise {m}x{n} GF({p}) variant {variant}")
+    o = lib.echelonise(A, p, variant=variant).outputs()
+    e = oracle.echelonize(A, p)
+    assert o.variant == variant and o.rank == e.rank
+    for name in ("gamma", "rho", "gamma_bar", "rho_bar"):
+        assert np.array_equal(getattr(o, name), getattr(e, name)), name
+    assert o.M is None and o.K is None and o.T is None
+    if variant == 1:
+        assert np.array_equal(o.R, e.R) and np.array_equal(o.E, e.E)
+    else:
+        assert o.R is None and o.E is None
+
+
+@pytest.mark.parametrize("shape", [(300, 200, 96, 80), (700, 1100, 0, 0), (64, 65, 0, 0)])
+def test_gf2_packed_input(shape):
+    """Bit-packed GF(2) input (host and device), unpacked on the device, equals
+    the oracle over p = 2."""
+    torch = torch_cuda()
+    lib = gpu_library()
+    m, n, br, bc = shape
+    A = synth.deficient(2, 77, m, n, 2)
+    W = synth.gf2_pack(A)
+    e = oracle.echelonize(A, 2)
+    say(f"echelonise gf2 packed {m}x{n} (host input)")
+    compare(lib.echelonise_gf2(W, n, block_rows=br, block_cols=bc).outputs(), e, "host")
+    say(f"echelonise gf2 packed {m}x{n} (device input, ldw {W.shape[1] + 1})")
+    Wd = np.concatenate([W, np.zeros((m, 1), np.uint64)], axis=1)
+    t = torch.from_numpy(Wd.view(np.int64).copy()).to("cuda:0")
+    r = lib.echelonise_gf2_dev(t.data_ptr(), m, n, Wd.shape[1], block_rows=br, block_cols=bc)
+    compare(r.outputs(), e, "device")
+    if n % 64:
+        Wd[5, n // 64] |= np.uint64(1) << np.uint64(63)
+        t = torch.from_numpy(Wd.view(np.int64).copy()).to("cuda:0")
+        import paper_1806_04211_amd as gf
+        with pytest.raises(gf.GfechError) as ex:
+            lib.echelonise_gf2_dev(t.data_ptr(), m, n, Wd.shape[1])
+        assert ex.value.status == 3
