@@ -233,6 +233,28 @@ gfech_status gfech_ech_dev(const uint8_t* H, int64_t rows, int64_t cols, int64_t
                            uint8_t* M, int64_t ldm, uint8_t* K, int64_t ldk, uint8_t* R, int64_t ldr,
                            int64_t* rank, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): gfech_ech_dev with
+ * its workspace in a fixed device array of the library's instead of an
+ * allocation.  The array holds GFECH_NOALLOC_SCRATCH_BYTES (16 MiB) on the
+ * device the library was initialised on, allocated when the library's device
+ * code is loaded and held until the process ends.  A block needs
+ * rows * (cols + min(rows, cols)) bytes of it; a larger one gives
+ * GFECH_E_TOO_BIG before any work is queued.  The call allocates nothing and
+ * does not wait: its work is ordered on `stream`, and the rank is written to
+ * device memory, *rank_dev (one int32), instead of being returned.  Every
+ * call shares the one array and it keeps the last call's contents (the ECH
+ * initialises what it reads): calls whose work overlaps on the device (on
+ * different streams, or captured work replayed concurrently) race and give
+ * wrong results.  The library initialises itself on its first call, which
+ * allocates (its streams and descriptor ring): make any other call first,
+ * e.g. gfech_backend_name(). */
+#define GFECH_NOALLOC_SCRATCH_BYTES ((int64_t)16 << 20)
+gfech_status gfech_ech_dev_noalloc(const uint8_t* H, int64_t rows, int64_t cols, int64_t ldh, uint32_t p,
+                                   int32_t* prow, int32_t* qrow, int32_t* pcol, int32_t* qcol,
+                                   uint8_t* M, int64_t ldm, uint8_t* K, int64_t ldk, uint8_t* R, int64_t ldr,
+                                   int32_t* rank_dev, void* stream);
+
 /* ---------------------------------------------------------------- serving
  * A server echelonises requests as they arrive (continuous batching): a
  * worker thread keeps every admitted request's block state in device memory

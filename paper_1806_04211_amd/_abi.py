@@ -82,6 +82,8 @@ SIGNATURES = {
     "gfech_mad_batch_dev": (ctypes.c_int, [c_i64, vp, vp]),
     "gfech_ech_dev": (ctypes.c_int, [vp, c_i64, c_i64, c_i64, c_u32, vp, vp, vp, vp, vp, c_i64, vp, c_i64, vp,
                                      c_i64, i64p, vp]),
+    "gfech_ech_dev_noalloc": (ctypes.c_int, [vp, c_i64, c_i64, c_i64, c_u32, vp, vp, vp, vp, vp, c_i64, vp, c_i64,
+                                             vp, c_i64, vp, vp]),
     "gfech_server_create": (ctypes.c_int, [vp, ctypes.POINTER(vp)]),
     "gfech_server_submit": (ctypes.c_int, [vp, vp, c_i32, ctypes.POINTER(ctypes.c_uint64)]),
     "gfech_server_poll": (ctypes.c_int, [vp, ctypes.c_uint64, ctypes.POINTER(vp)]),

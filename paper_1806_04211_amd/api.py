@@ -234,6 +234,15 @@ class Library:
                                            vp(M), ldm, vp(K), ldk, vp(R), ldr, ctypes.byref(r), vp(stream)))
         return r.value
 
+    def ech_dev_noalloc(self, H, rows, cols, ldh, p, prow, qrow, pcol, qcol, M, ldm, K, ldk, R, ldr, rank_dev,
+                        stream=0):
+        """ECH job on device addresses with the library's fixed workspace; the rank
+        goes to the device int32 at rank_dev; the work is queued on `stream`."""
+        vp = ctypes.c_void_p
+        self._check(self.lib.gfech_ech_dev_noalloc(vp(H), rows, cols, ldh, p, vp(prow), vp(qrow), vp(pcol),
+                                                   vp(qcol), vp(M), ldm, vp(K), ldk, vp(R), ldr, vp(rank_dev),
+                                                   vp(stream)))
+
     def server(self, hbm_budget_bytes: int = 0, max_active: int = 0) -> "Server":
         return Server(self, hbm_budget_bytes, max_active)
 

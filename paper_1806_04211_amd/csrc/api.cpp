@@ -641,6 +641,47 @@ gfech_status gfech_ech_dev(const uint8_t* H, int64_t rows, int64_t cols, int64_t
     return be->error() ? fail(GFECH_E_DEVICE, "device error") : GFECH_OK;
 }
 
+static_assert(GFECH_NOALLOC_SCRATCH_BYTES == (int64_t)gfech::kFixedScratchBytes, "fixed workspace size");
+
+gfech_status gfech_ech_dev_noalloc(const uint8_t* H, int64_t rows, int64_t cols, int64_t ldh, uint32_t p,
+                                   int32_t* prow, int32_t* qrow, int32_t* pcol, int32_t* qcol, uint8_t* M,
+                                   int64_t ldm, uint8_t* K, int64_t ldk, uint8_t* R, int64_t ldr, int32_t* rank_dev,
+                                   void* stream) {
+    if (!rank_dev) return fail(GFECH_E_ARG, "rank_dev is NULL");
+    if (rows < 0 || cols < 0) return fail(GFECH_E_ARG, "negative size");
+    if (rows + cols > 8192) return fail(GFECH_E_TOO_BIG, "block too large for one ECH");
+    if (p > 251 || !is_prime(p)) return fail(GFECH_E_FIELD, "p must be a prime <= 251");
+    const int64_t mr = rows < cols ? rows : cols;
+    const int64_t ldw = cols + mr;
+    if (rows > 0 && cols > 0 &&
+        (!H || ldh < cols || !prow || !qrow || !pcol || !qcol || !M || !K || !R || ldm < mr || ldk < mr || ldr < cols))
+        return fail(GFECH_E_ARG, "bad ECH buffers");
+    if ((size_t)(rows * ldw) > gfech::kFixedScratchBytes)
+        return fail(GFECH_E_TOO_BIG, "the block's workspace exceeds the fixed workspace");
+    std::lock_guard<std::mutex> lk(g_mu);
+    gfech_status st = GFECH_OK;
+    gfech::Backend* be = get_backend(&st);
+    if (!be) return st;
+    uint8_t* ws = be->fixed_scratch();
+    if (!ws) return fail(GFECH_E_DEVICE, "no fixed workspace on this device");
+    be->set_stream(stream);
+    if (rows == 0 || cols == 0) {
+        // rank 0, written by a kernel (no memset, no copy)
+        gfech::FillDesc f;
+        f.rows = 1; f.cols = (int32_t)sizeof(int32_t); f.dst = (uint8_t*)rank_dev; f.ldd = sizeof(int32_t);
+        be->fill({f});
+    } else {
+        gfech::EchDesc e;
+        e.rows = (int32_t)rows; e.cols = (int32_t)cols; e.p = (int32_t)p;
+        e.H = H; e.ldh = ldh; e.work = ws; e.ldw = ldw; e.rcount = rank_dev;
+        e.prow = prow; e.qrow = qrow; e.pcol = pcol; e.qcol = qcol;
+        e.Mo = M; e.ldm = ldm; e.Ko = K; e.ldk = ldk; e.Ro = R; e.ldr = ldr;
+        be->ech({e});
+    }
+    be->set_stream(nullptr);
+    return be->error() ? fail(GFECH_E_DEVICE, "device error") : GFECH_OK;
+}
+
 // ---------------------------------------------------------------- serving
 
 struct gfech_server {

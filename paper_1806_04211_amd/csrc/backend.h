@@ -104,6 +104,10 @@ struct SortDesc {
     int32_t* out = nullptr;
 };
 
+// Size of the fixed device workspace (one per device, held until the process
+// ends) that the allocation-free ECH entry point uses instead of an allocation.
+constexpr size_t kFixedScratchBytes = (size_t)16 << 20;
+
 class Backend {
 public:
     virtual ~Backend() = default;
@@ -152,6 +156,9 @@ public:
         download(host, counts, sizeof(int32_t) * n);
     }
     virtual void release_counts(int32_t* counts) { release(counts); }
+    // The fixed workspace of kFixedScratchBytes (nullptr when unavailable):
+    // device memory that is never allocated or freed after initialisation.
+    virtual uint8_t* fixed_scratch() { return nullptr; }
     // non-zero after a device error; the planner stops and reports it
     virtual int error() const { return 0; }
     // per-launch timing of the grouped jobs (device events on the work stream)

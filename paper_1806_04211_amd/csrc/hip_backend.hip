@@ -1921,6 +1921,12 @@ k_gf2_pad(const uint64_t* __restrict__ src, int64_t m, int64_t n, int64_t ldw, u
     if (cnt) atomicAdd(bad, cnt);
 }
 
+// The fixed workspace of the allocation-free ECH entry point, a plain device
+// array: host code must not pass this name to a kernel (on the host it names a
+// stand-in, not the device address); it uses the address hipGetSymbolAddress
+// returns at initialisation.
+static __device__ __align__(256) uint8_t scratch[kFixedScratchBytes];
+
 // ============================================================================ host side
 
 constexpr size_t kPad = 256;                 // tail padding of every allocation (vector over-read)
@@ -1988,8 +1994,15 @@ public:
             echs_lds_max_ = 64 * 1024;
         }
         no_lds_ech_ = getenv("GFECH_ECH_NO_LDS") != nullptr;
+        // the device address of the fixed workspace on this device (the one
+        // current now, which every later call of this backend uses)
+        if (hipGetSymbolAddress((void**)&fixed_scratch_, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            fixed_scratch_ = nullptr;
+        }
         return true;
     }
+    uint8_t* fixed_scratch() override { return fixed_scratch_; }
 
     const char* name() const override { return "hip-gfx950"; }
 
@@ -2405,6 +2418,7 @@ private:
     void* ring_dev_ = nullptr;
     size_t ring_off_ = 0;
     void* counter_ = nullptr;
+    uint8_t* fixed_scratch_ = nullptr;   // device address of `scratch`
     int err_ = 0;
     int num_cu_ = 0;
     int prof_ = 0;

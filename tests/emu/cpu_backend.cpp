@@ -83,6 +83,11 @@ public:
     // is quarantined until every queue is empty, so a queued job that touches
     // a buffer after its release fails the bounds check instead of landing in
     // a new allocation.
+    // the fixed workspace: one allocation made once and never released
+    uint8_t* fixed_scratch() override {
+        if (!fixed_) fixed_ = (uint8_t*)alloc(kFixedScratchBytes);
+        return fixed_;
+    }
     void set_lane(int lane) override { lane_ = lane; }
     int mark(int lane) override {
         if (lane == 0 && !fuzz_) return 0;
@@ -368,6 +373,7 @@ private:
         size_t wait_upto = 0;
     };
     std::map<uintptr_t, size_t> allocs_;
+    uint8_t* fixed_ = nullptr;
     int err_ = 0;
     int lane_ = 0;
     bool defer_ = !(getenv("GFECH_EMU_EAGER") && getenv("GFECH_EMU_EAGER")[0] == '1');
