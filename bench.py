@@ -136,6 +136,111 @@ def check_result(A_host, res, p, rank_expected, vectors=64, seed=0):
     return out
 
 
+def read_mad_trace(path):
+    """The descriptors of a GFECH_TRACE_MAD file: dicts with the engine
+    iteration, launch number, kind (1 ClearDown, 2 UpdateRow, 3 UpdateRowTrafo,
+    4 ClearUp), shapes, leading dimensions, flags and operand addresses."""
+    keys = ("it", "launch", "kind", "M", "N", "K", "p", "lda", "ldb", "ldc", "ldd", "flags",
+            "A", "B", "C", "D", "brow", "crow")
+    out = []
+    for line in open(path):
+        f = line.split()
+        if len(f) != len(keys):
+            continue
+        d = {}
+        for k, v in zip(keys, f):
+            d[k] = (0 if v == "(nil)" else int(v, 16)) if k in ("A", "B", "C", "D", "brow", "crow") else int(v)
+        out.append(d)
+    return out
+
+
+def replay(torch, lib, descs, reps=10):
+    """The traced descriptors as ONE grouped MAD launch, alone on the stream:
+    operands rebased into one buffer of random residues that keeps their
+    relative addresses (so sharing and alignment are those of the solve),
+    gathered rows replaced by the identity.  Device events bracket each launch
+    (they include the upload of the descriptor array, a few KB).  Returns
+    (multiply-adds, mean ms, operand bytes) of one launch."""
+    p = descs[0]["p"]
+    spans = []
+    for d in descs:
+        M, N, K = d["M"], d["N"], d["K"]
+        spans += [(d["A"], (M - 1) * d["lda"] + K), (d["B"], (K - 1) * d["ldb"] + N + 16),
+                  (d["D"], (M - 1) * d["ldd"] + N)]
+        if d["C"]:
+            spans.append((d["C"], (M - 1) * d["ldc"] + N + 16))
+    lo = min(a for a, _ in spans)
+    hi = max(a + n for a, n in spans)
+    buf = torch.randint(0, p, (hi - lo + 256,), dtype=torch.uint8, device="cuda:0")
+    base = buf.data_ptr()
+    ident = torch.arange(max(max(d["K"], d["M"]) for d in descs), dtype=torch.int32, device="cuda:0")
+    mad = [dict(M=d["M"], N=d["N"], K=d["K"], p=d["p"], A=base + d["A"] - lo, lda=d["lda"],
+                B=base + d["B"] - lo, ldb=d["ldb"], brow=ident.data_ptr() if d["brow"] else 0,
+                C=base + d["C"] - lo if d["C"] else 0, ldc=d["ldc"], crow=ident.data_ptr() if d["crow"] else 0,
+                D=base + d["D"] - lo, ldd=d["ldd"]) for d in descs]
+    stream = torch.cuda.current_stream()
+    lib.mad_batch_dev(mad, stream=stream.cuda_stream)          # warm-up
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lib.mad_batch_dev(mad, stream=stream.cuda_stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del buf
+    mac = sum(float(d["M"]) * d["N"] * d["K"] for d in descs)
+    nbytes = sum(float(d["M"]) * d["K"] + float(d["K"]) * d["N"] + (2.0 if d["C"] else 1.0) * d["M"] * d["N"]
+                 for d in descs)
+    return mac, sum(ms) / len(ms), nbytes
+
+
+def isolated_mad(torch, lib, trace_path):
+    """Section 8(d)(i): the UpdateRow and UpdateRowTrafo products of the
+    middle Step-1 iteration of the traced solve (one layer's worth: the
+    priority products of layer L and the bulk sets of layer L - 1) as one
+    grouped launch, and the largest ClearUp launch, each alone."""
+    tr = read_mad_trace(trace_path)
+    step1 = sorted({d["it"] for d in tr if d["kind"] == 1})
+    mid = step1[len(step1) // 2]
+    ur = [d for d in tr if d["it"] == mid and d["kind"] in (2, 3)]
+    out = {}
+    mac, ms, nb = replay(torch, lib, ur)
+    out["updaterow_layer"] = {"iteration": mid, "descriptors": len(ur), "mac": mac, "ms": ms,
+                              "int8_tops": 2 * mac / (ms * 1e-3) / 1e12, "operand_bytes": nb,
+                              "shapes": sorted({(d["M"], d["N"], d["K"]) for d in ur},
+                                               key=lambda x: -x[0] * x[1] * x[2])[:4]}
+    cu = [d for d in tr if d["kind"] == 4]
+    if cu:
+        launches = {}
+        for d in cu:
+            launches.setdefault(d["launch"], []).append(d)
+        big = max(launches.values(), key=lambda ds: sum(float(d["M"]) * d["N"] * d["K"] for d in ds))
+        mac, ms, nb = replay(torch, lib, big)
+        out["clearup_largest"] = {"descriptors": len(big), "mac": mac, "ms": ms,
+                                  "int8_tops": 2 * mac / (ms * 1e-3) / 1e12, "operand_bytes": nb,
+                                  "shapes": [(d["M"], d["N"], d["K"]) for d in big]}
+    return out
+
+
+def traced_isolated(torch, lib, solve):
+    """One untimed solve with the MAD launch trace on, then isolated_mad."""
+    import tempfile
+    fd, path = tempfile.mkstemp(prefix="gfech_mad_trace_", suffix=".txt")
+    os.close(fd)
+    os.environ["GFECH_TRACE_MAD"] = path
+    try:
+        solve(0).free()
+    finally:
+        del os.environ["GFECH_TRACE_MAD"]
+    try:
+        iso = isolated_mad(torch, lib, path)
+    finally:
+        os.unlink(path)
+    log(f"isolated: {json.dumps(iso)}")
+    return iso
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     return xs[min(len(xs) - 1, int(round(q * (len(xs) - 1))))] if xs else 0.0
@@ -329,6 +434,8 @@ def main():
     ap.add_argument("--block-rows", type=int, default=0, help="block rows a_i (overrides --block)")
     ap.add_argument("--block-cols", type=int, default=0, help="block columns b_j (overrides --block)")
     ap.add_argument("--cpu-sample", type=int, default=2000, help="oracle sample size (0 = skip)")
+    ap.add_argument("--replay-only", action="store_true",
+                    help="only a traced solve and the isolated replays of its launches (for kernel profiles)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the timing of the variants without the transformation")
     ap.add_argument("--no-check", action="store_true",
@@ -382,6 +489,12 @@ def main():
         """profile: 0 no device events, 1 every launch, 2 the MAD launches only,
         3 every fourth MAD launch"""
         return lib.echelonise_dev(A.data_ptr(), n, n, n, p, stream=stream.cuda_stream, profile=profile, **kw)
+
+    if args.replay_only:
+        # for profiling: one traced solve, then the isolated launches alone
+        iso = traced_isolated(torch, lib, solve)
+        print(json.dumps({"isolated": iso}), flush=True)
+        return
 
     rank = None
     for w in range(args.warmup):
@@ -466,6 +579,25 @@ def main():
                                     "avg_ms": mad_ms / max(mad_launches, 1),
                                     "timed_launches": mad_launches, "launches_per_solve": all_mad_launches}},
     }
+    # Section 8(d)(i): one layer's UpdateRow launch and the largest ClearUp
+    # launch replayed alone at their traced shapes.  The isolated layer launch
+    # is the roofline figure; the in-situ one (sampled launches of the timed
+    # solves, which overlap on four streams) and the solve-wide MAD rate stand
+    # beside it.
+    if not args.no_kernel_events:
+        roof = out["roofline"]
+        roof["in_situ"] = {"achieved": roof["achieved"], "frac": roof["frac"], "per_launch": roof.pop("per_launch"),
+                           "note": "sampled MAD launches of the timed solves (contended: four streams overlap)"}
+        roof["solve_wide"] = {"achieved": 2 * mac_mad / mean / 1e12, "frac": 2 * mac_mad / mean / 1e12 / INT8_PEAK_TOPS,
+                              "note": "all MAD multiply-adds of a solve over its wall time"}
+        iso = traced_isolated(torch, lib, solve)
+        u = iso["updaterow_layer"]
+        roof["achieved"] = u["int8_tops"]
+        roof["frac"] = u["int8_tops"] / INT8_PEAK_TOPS
+        roof["measured"] = ("isolated: the UpdateRow / UpdateRowTrafo products of one mid-solve Step-1 iteration "
+                            "as one grouped launch, alone, device events around each of 10 launches")
+        roof["isolated"] = iso
+        roof["traffic"] = profiled_traffic()
     # the variants without the transformation (Section 1), one solve each after
     # a warm-up, beside the full solve's mean
     if not args.no_variants:

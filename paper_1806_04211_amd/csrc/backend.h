@@ -20,13 +20,17 @@ namespace gfech {
 //         (element-wise in place); D never overlaps A or B.
 // Entries are canonical residues in [0, p); K may be 0 (then D = Cin).
 constexpr int32_t kGemmRowsPadded = 1;
+enum GemmKind : int32_t { kGemmOther = 0, kGemmClearDown = 1, kGemmUpdateRow = 2, kGemmUpdateRowTrafo = 3,
+                          kGemmClearUp = 4 };
 
 struct GemmDesc {
     int32_t M = 0, N = 0, K = 0, p = 0;
     // kGemmRowsPadded: every row of B and C may be read up to the next
     // multiple of 16 columns past N (the buffers hold whole rows of their
     // leading dimension); set by the planner for its own buffers
-    int32_t flags = 0, reserved = 0;
+    int32_t flags = 0;
+    int32_t kind = 0;   // what the product is for (GemmKind), for traces only
+
     const uint8_t* A = nullptr; int64_t lda = 0;
     const uint8_t* B = nullptr; int64_t ldb = 0; const int32_t* brow = nullptr;
     const uint8_t* C = nullptr; int64_t ldc = 0; const int32_t* crow = nullptr;

@@ -42,6 +42,7 @@
 #include "chief.h"
 
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -896,6 +897,11 @@ private:
     void push_gemm(Ops& ops, const GemmDesc& g, double& counter) {
         if (g.M <= 0 || g.N <= 0) return;
         ops.gemm.push_back(g);
+        ops.gemm.back().kind = &counter == &st_.cd_mad    ? kGemmClearDown
+                               : &counter == &st_.ur_mad  ? kGemmUpdateRow
+                               : &counter == &st_.urt_mad ? kGemmUpdateRowTrafo
+                               : &counter == &st_.cu_mad  ? kGemmClearUp
+                                                          : kGemmOther;
         counter += (double)g.M * g.N * g.K;
     }
 
@@ -969,6 +975,22 @@ private:
     std::vector<std::vector<GemmDesc>> cu_steps_;
 };
 
+// GFECH_TRACE_MAD=<file>: every MAD launch of the engine is appended to the
+// file, one line per descriptor: engine iteration, launch number, kind
+// (GemmKind), M N K p, leading dimensions, flags and the operand addresses (a
+// measurement aid: the shapes of a layer's launches can be replayed alone).
+FILE* g_trace = nullptr;
+int64_t g_trace_iter = 0, g_trace_launch = 0;
+
+void trace_gemm(const std::vector<GemmDesc>& ds) {
+    for (const GemmDesc& g : ds)
+        fprintf(g_trace, "%lld %lld %d %d %d %d %d %lld %lld %lld %lld %d %p %p %p %p %p %p\n",
+                (long long)g_trace_iter, (long long)g_trace_launch, g.kind, g.M, g.N, g.K, g.p, (long long)g.lda,
+                (long long)g.ldb, (long long)g.ldc, (long long)g.ldd, g.flags, (const void*)g.A, (const void*)g.B,
+                (const void*)g.C, (void*)g.D, (const void*)g.brow, (const void*)g.crow);
+    ++g_trace_launch;
+}
+
 void flush(Backend& be, Ops& ops, Stats& st) {
     if (!ops.gather.empty()) { be.gather(ops.gather); st.launches++; }
     if (!ops.fill.empty()) { be.fill(ops.fill); st.launches++; }
@@ -977,6 +999,7 @@ void flush(Backend& be, Ops& ops, Stats& st) {
     if (!ops.gemm.empty()) {
         // every buffer of the plan holds whole rows of its leading dimension
         for (GemmDesc& g : ops.gemm) g.flags |= kGemmRowsPadded;
+        if (g_trace) trace_gemm(ops.gemm);
         be.gemm(ops.gemm);
         st.launches++;
         st.gemms += (int64_t)ops.gemm.size();
@@ -1018,6 +1041,12 @@ struct Engine::Impl {
     };
 
     Impl(Backend& b, const Engine* e) : be(b), owner(e) {
+        const char* tr = getenv("GFECH_TRACE_MAD");
+        if (tr && tr[0] && !g_trace) {
+            g_trace = fopen(tr, "a");
+            g_trace_iter = g_trace_launch = 0;
+            owns_trace = g_trace != nullptr;
+        }
         const char* gr = getenv("GFECH_CLEARUP_GROUP");
         group_rank = gr ? std::max<int64_t>(1, atoll(gr)) : 2048;
         counts = be.counts_buffer(kCountsCap);
@@ -1028,7 +1057,12 @@ struct Engine::Impl {
         be.sync();
         for (auto& j : jobs) release(*j);
         if (counts) be.release_counts(counts);
+        if (owns_trace) {
+            fclose(g_trace);
+            g_trace = nullptr;
+        }
     }
+    bool owns_trace = false;
 
     Backend& be;
     const Engine* owner;
@@ -1199,6 +1233,7 @@ struct Engine::Impl {
     }
 
     size_t step() {
+        if (owns_trace) ++g_trace_iter;
         if (be.error()) {
             fail_all(be.error());
             return 0;

@@ -70,3 +70,22 @@ def test_exact_matmul_mod_matches_int64():
         Y = rng.integers(0, p, (k, 9)).astype(np.uint8)
         exp = (X.astype(np.int64) @ Y.astype(np.int64)) % p
         assert np.array_equal(bench.exact_matmul_mod(X, Y, p, chunk_rows=16), exp)
+
+
+def test_mad_trace_matches_the_work_counters(tmp_path, monkeypatch):
+    """The opt-in launch trace (read by the benchmark's isolated replay) lists
+    every MAD descriptor once, with its kind: per kind, the traced
+    multiply-adds equal the result's work counters (emulator build)."""
+    from tests import emu
+    lib = emu.library()
+    path = tmp_path / "trace.txt"
+    monkeypatch.setenv("GFECH_TRACE_MAD", str(path))
+    A = synth.deficient(4, 4, 60, 50, 7)
+    res = lib.echelonise(A, 7, block_rows=8, block_cols=12)
+    st = res.stats()
+    tr = bench.read_mad_trace(str(path))
+    assert tr and all(d["A"] and d["D"] and d["p"] == 7 for d in tr)
+    mac = {k: sum(float(d["M"]) * d["N"] * d["K"] for d in tr if d["kind"] == k) for k in (1, 2, 3, 4)}
+    assert mac[1] == st["mac_cleardown"] and mac[2] == st["mac_updaterow"]
+    assert mac[3] == st["mac_trafo"] and mac[4] == st["mac_clearup"]
+    assert len({d["it"] for d in tr if d["kind"] == 1}) > 3
