@@ -46,7 +46,7 @@ typedef enum gfech_status {
     GFECH_E_NOMEM = 4,      /* device or host allocation failed */
     GFECH_E_TOO_BIG = 5,    /* a size exceeds what the kernels index (2^31 - 1 per dimension) */
     GFECH_E_DEVICE = 6,     /* HIP runtime error or no usable gfx950 device */
-    GFECH_E_CANCELLED = 7,
+    GFECH_E_CANCELLED = 7,  /* stopped by the watchdog (opts.timeout_ms) or gfech_server_cancel */
     GFECH_E_STATE = 8       /* call not valid for this object */
 } gfech_status;
 
@@ -74,7 +74,11 @@ typedef struct gfech_opts {
                                (see gfech_stats);
                                0: no events */
     int32_t variant;        /* GFECH_WANT_*; other values give GFECH_E_ARG */
-    int32_t reserved[5];
+    int32_t timeout_ms;     /* > 0: a watchdog.  A call still running after this many
+                               milliseconds stops at its next phase boundary (a layer of
+                               Step 1 or a launch of Step 3), frees what it holds and
+                               returns GFECH_E_CANCELLED; 0: no limit */
+    int32_t reserved[4];
 } gfech_opts;
 
 /* Opaque, library-owned result; immutable once returned.  Its matrices stay
@@ -273,16 +277,33 @@ typedef struct gfech_server_cfg {
 } gfech_server_cfg;
 gfech_status gfech_server_create(const gfech_server_cfg* cfg, gfech_server** out);
 /* Queue one problem.  The input (host or device memory, as the flag says) is
- * checked (entries < p) and copied before the call returns; *ticket names the
- * request.  GFECH_E_TOO_BIG: the request alone exceeds the budget. */
+ * checked (entries < p) and copied before the call returns (a device input on
+ * a stream of the server's own, waited for), so the caller may reuse its
+ * buffer at once; *ticket names the request.  GFECH_E_TOO_BIG: the request
+ * alone exceeds the budget (refused before anything is copied). */
 gfech_status gfech_server_submit(gfech_server* srv, const gfech_problem* prob, int32_t input_on_device,
                                  uint64_t* ticket);
 /* Non-blocking: *out receives the result of a finished request (the caller
  * owns it) or NULL while it is queued or running.  A ticket is answered once;
  * unknown tickets give GFECH_E_ARG, failed requests their error status. */
 gfech_status gfech_server_poll(gfech_server* srv, uint64_t ticket, gfech_result** out);
+/* Cancels a request: a queued one is dropped at once, a running one stops at
+ * its next phase boundary (its device work completes, its memory is freed).
+ * Its ticket then answers GFECH_E_CANCELLED (unless it had already finished,
+ * in which case its result stays available).  Unknown tickets: GFECH_E_ARG. */
+gfech_status gfech_server_cancel(gfech_server* srv, uint64_t ticket);
 /* Blocking form of gfech_server_poll. */
 gfech_status gfech_server_wait(gfech_server* srv, uint64_t ticket, gfech_result** out);
+/* Counters of a server since its creation: the largest device-memory
+ * footprint of the requests in flight at once (the bounds admission uses,
+ * never above the budget), the most requests in flight at once, and the
+ * requests admitted and finished. */
+typedef struct gfech_server_stats {
+    int64_t peak_bytes_in_flight;
+    int64_t peak_active;
+    int64_t admitted, finished;
+} gfech_server_stats;
+gfech_status gfech_server_get_stats(gfech_server* srv, gfech_server_stats* stats);
 /* Drops queued requests, lets running ones finish, frees unclaimed results. */
 void gfech_server_destroy(gfech_server* srv);
 

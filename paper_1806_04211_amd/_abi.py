@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "GFECH_OK", 1: "GFECH_E_ARG", 2: "GFECH_E_FIELD", 3: "GFECH_E
 
 class Opts(ctypes.Structure):
     _fields_ = [("block_rows", c_i64), ("block_cols", c_i64), ("skip_range_check", c_i32),
-                ("profile", c_i32), ("variant", c_i32), ("reserved", c_i32 * 5)]
+                ("profile", c_i32), ("variant", c_i32), ("timeout_ms", c_i32), ("reserved", c_i32 * 4)]
 
 
 class Problem(ctypes.Structure):
@@ -45,6 +45,10 @@ class Stats(ctypes.Structure):
 
 class ServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", c_i64), ("max_active", c_i32), ("reserved", c_i32 * 5)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("peak_bytes_in_flight", c_i64), ("peak_active", c_i64), ("admitted", c_i64), ("finished", c_i64)]
 
 
 class MadDesc(ctypes.Structure):
@@ -87,6 +91,8 @@ SIGNATURES = {
     "gfech_server_create": (ctypes.c_int, [vp, ctypes.POINTER(vp)]),
     "gfech_server_submit": (ctypes.c_int, [vp, vp, c_i32, ctypes.POINTER(ctypes.c_uint64)]),
     "gfech_server_poll": (ctypes.c_int, [vp, ctypes.c_uint64, ctypes.POINTER(vp)]),
+    "gfech_server_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(ServerStats)]),
+    "gfech_server_cancel": (ctypes.c_int, [vp, ctypes.c_uint64]),
     "gfech_server_wait": (ctypes.c_int, [vp, ctypes.c_uint64, ctypes.POINTER(vp)]),
     "gfech_server_destroy": (None, [vp]),
 }

@@ -151,8 +151,9 @@ class Result:
         return o
 
 
-def _opts(block_rows=0, block_cols=0, skip_range_check=False, profile=False, variant=0):
+def _opts(block_rows=0, block_cols=0, skip_range_check=False, profile=False, variant=0, timeout_ms=0):
     o = _abi.Opts()
+    o.timeout_ms = int(timeout_ms)
     o.block_rows = int(block_rows)
     o.block_cols = int(block_cols)
     o.skip_range_check = 1 if skip_range_check else 0
@@ -174,20 +175,21 @@ class Library:
         if st != _abi.GFECH_OK:
             raise GfechError(st, self.lib.gfech_last_error().decode())
 
-    def echelonise(self, A, p: int, block_rows=0, block_cols=0, variant=0) -> Result:
-        """A: host numpy (m x n, uint8).  variant: _abi.WANT_* (what is computed)."""
+    def echelonise(self, A, p: int, block_rows=0, block_cols=0, variant=0, timeout_ms=0) -> Result:
+        """A: host numpy (m x n, uint8).  variant: _abi.WANT_* (what is computed);
+        timeout_ms > 0: the watchdog (GFECH_E_CANCELLED when it fires)."""
         A = np.ascontiguousarray(np.asarray(A, dtype=np.uint8))
         m, n = A.shape
         out = ctypes.c_void_p()
-        o = _opts(block_rows, block_cols, variant=variant)
+        o = _opts(block_rows, block_cols, variant=variant, timeout_ms=timeout_ms)
         self._check(self.lib.gfech_echelonise_u8(_ptr(A), m, n, max(n, 1), p, ctypes.byref(o), ctypes.byref(out)))
         return Result(self.lib, out.value)
 
     def echelonise_dev(self, ptr: int, m: int, n: int, lda: int, p: int, stream: int = 0, block_rows=0,
-                       block_cols=0, skip_range_check=False, profile=False, variant=0) -> Result:
+                       block_cols=0, skip_range_check=False, profile=False, variant=0, timeout_ms=0) -> Result:
         """ptr: device address of an m x n uint8 matrix with leading dimension lda."""
         out = ctypes.c_void_p()
-        o = _opts(block_rows, block_cols, skip_range_check, profile, variant)
+        o = _opts(block_rows, block_cols, skip_range_check, profile, variant, timeout_ms)
         self._check(self.lib.gfech_echelonise_u8_dev(ctypes.c_void_p(ptr), m, n, lda, p, ctypes.byref(o),
                                                      ctypes.c_void_p(stream), ctypes.byref(out)))
         return Result(self.lib, out.value)
@@ -317,6 +319,14 @@ class Server:
         out = ctypes.c_void_p()
         self._check(self._lib.gfech_server_poll(self._h, ticket, ctypes.byref(out)))
         return Result(self._lib, out.value) if out.value else None
+
+    def stats(self) -> dict:
+        s = _abi.ServerStats()
+        self._check(self._lib.gfech_server_get_stats(self._h, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in _abi.ServerStats._fields_}
+
+    def cancel(self, ticket: int):
+        self._check(self._lib.gfech_server_cancel(self._h, ticket))
 
     def wait(self, ticket: int) -> Result:
         out = ctypes.c_void_p()

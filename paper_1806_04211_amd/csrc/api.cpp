@@ -1,6 +1,7 @@
 // C ABI of libgfech (declared in include/gfech.h): argument checks, host /
 // device staging, block-size choice and the result getters.  All arithmetic
 // runs in the backend's kernels through the Chief.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstdio>
@@ -91,6 +92,11 @@ int32_t variant_of(const gfech_opts* o) { return o ? o->variant : GFECH_WANT_RRE
 bool has_R(const gfech::Result& R) { return R.want != gfech::kWantRank; }
 bool has_T(const gfech::Result& R) { return R.want == gfech::kWantAll; }
 
+// the status of a planner / backend error code
+gfech_status status_of(int rc) {
+    return rc == 0 ? GFECH_OK : rc == 4 ? GFECH_E_NOMEM : rc == gfech::kCancelled ? GFECH_E_CANCELLED : GFECH_E_DEVICE;
+}
+
 gfech::Backend* get_backend(gfech_status* st) {
     std::string err;
     gfech::Backend* be = gfech::backend_instance(&err);
@@ -103,8 +109,8 @@ gfech_status run(gfech::Backend* be, std::vector<gfech::Problem>& probs, gfech_r
                  const gfech_opts* opts) {
     std::vector<std::unique_ptr<gfech::Result>> res;
     std::string err;
-    int rc = gfech::run_chief(*be, probs, res, &err, opts ? opts->profile : 0);
-    if (rc) return fail(rc == 4 ? GFECH_E_NOMEM : GFECH_E_DEVICE, err);
+    int rc = gfech::run_chief(*be, probs, res, &err, opts ? opts->profile : 0, opts ? opts->timeout_ms : 0);
+    if (rc) return fail(status_of(rc), err);
     for (size_t q = 0; q < res.size(); ++q) {
         outs[q] = new gfech_result();
         outs[q]->r = std::move(res[q]);
@@ -693,6 +699,7 @@ struct gfech_server {
     };
     gfech::Backend* be = nullptr;
     void* stream = nullptr;
+    void* submit_stream = nullptr;    // the copies of submitted inputs
     size_t budget = 0;
     int32_t max_active = 0;
     std::mutex mu;                    // queue, running, finished, stop
@@ -700,6 +707,8 @@ struct gfech_server {
     std::deque<Req> queue;
     std::map<int64_t, Req> running;   // engine id -> request
     std::map<uint64_t, std::pair<gfech_status, gfech_result*>> finished;
+    std::vector<uint64_t> cancels;    // tickets of running requests to cancel
+    gfech_server_stats counters{};    // under mu
     uint64_t next_ticket = 1;
     bool stop = false;
     std::unique_ptr<gfech::Engine> eng;   // used with g_mu held
@@ -727,7 +736,18 @@ struct gfech_server {
                 }
                 queue.pop_front();
                 running[id] = r;
+                counters.admitted++;
             }
+            counters.peak_bytes_in_flight =
+                std::max<int64_t>(counters.peak_bytes_in_flight, (int64_t)eng->bytes_in_use());
+            counters.peak_active = std::max<int64_t>(counters.peak_active, (int64_t)eng->active());
+        }
+        {
+            std::lock_guard<std::mutex> q(mu);
+            for (uint64_t t : cancels)
+                for (auto& kv : running)
+                    if (kv.second.ticket == t) eng->cancel(kv.first);
+            cancels.clear();
         }
         if (eng->active()) eng->step();
         std::vector<gfech::Engine::Done> fin = eng->take_done();
@@ -742,9 +762,9 @@ struct gfech_server {
                     res = new gfech_result();
                     res->r = std::move(d.result);
                 }
-                finished[it->second.ticket] = {d.status ? (d.status == 4 ? GFECH_E_NOMEM : GFECH_E_DEVICE) : GFECH_OK,
-                                               res};
+                finished[it->second.ticket] = {status_of(d.status), res};
                 running.erase(it);
+                counters.finished++;
             }
             done.notify_all();
         }
@@ -774,6 +794,7 @@ gfech_status gfech_server_create(const gfech_server_cfg* cfg, gfech_server** out
         s->be = get_backend(&st);
         if (!s->be) return st;
         s->stream = s->be->create_stream();
+        s->submit_stream = s->be->create_stream();
         s->eng.reset(new gfech::Engine(*s->be));
     }
     s->budget = (cfg && cfg->hbm_budget_bytes > 0) ? (size_t)cfg->hbm_budget_bytes : ((size_t)200 << 30);
@@ -798,9 +819,21 @@ gfech_status gfech_server_submit(gfech_server* s, const gfech_problem* prob, int
                 if (prob->A[i * lda + j] >= p) return fail(GFECH_E_RANGE, "entry >= p");
     }
     gfech_server::Req r;
+    r.pr.m = m;
+    r.pr.n = n;
+    r.pr.lda = std::max<int64_t>(n, 1);
+    r.pr.p = (int32_t)p;
+    choose_blocks(m, n, nullptr, r.pr.row_blocks, r.pr.col_blocks);
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        s->be->set_stream(s->stream);
+        r.footprint = s->eng->footprint(r.pr);
+    }
+    if (r.footprint > s->budget) return fail(GFECH_E_TOO_BIG, "the problem alone exceeds the memory budget");
+    {
+        // the input is checked and copied on a stream of its own, complete on
+        // return (the caller may reuse its buffer); nothing waits for the engine
+        std::lock_guard<std::mutex> lk(g_mu);
+        s->be->set_stream(s->submit_stream);
         if (input_on_device && m > 0 && n > 0) {
             const int64_t bad = s->be->count_out_of_range(prob->A, m, n, lda, (int32_t)p);
             if (bad != 0) {
@@ -826,20 +859,10 @@ gfech_status gfech_server_submit(gfech_server* s, const gfech_problem* prob, int
                 for (int64_t i = 0; i < m; ++i) memcpy(tmp.data() + i * n, prob->A + i * lda, (size_t)n);
                 s->be->upload(r.input, tmp.data(), (size_t)(m * n));
             }
+            s->be->sync_lane0();
         }
         s->be->set_stream(nullptr);
         r.pr.A = r.input;
-        r.pr.m = m;
-        r.pr.n = n;
-        r.pr.lda = std::max<int64_t>(n, 1);
-        r.pr.p = (int32_t)p;
-        choose_blocks(m, n, nullptr, r.pr.row_blocks, r.pr.col_blocks);
-        r.footprint = s->eng->footprint(r.pr);
-    }
-    if (r.footprint > s->budget) {
-        std::lock_guard<std::mutex> lk(g_mu);
-        s->be->release(r.input);
-        return fail(GFECH_E_TOO_BIG, "the problem alone exceeds the memory budget");
     }
     {
         std::lock_guard<std::mutex> q(s->mu);
@@ -879,6 +902,44 @@ gfech_status gfech_server_poll(gfech_server* s, uint64_t ticket, gfech_result** 
     return st;
 }
 
+gfech_status gfech_server_cancel(gfech_server* s, uint64_t ticket) {
+    if (!s) return fail(GFECH_E_ARG, "null argument");
+    gfech_server::Req dropped;
+    {
+        std::lock_guard<std::mutex> q(s->mu);
+        bool known = s->finished.count(ticket) > 0;
+        for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
+            if (it->ticket != ticket) continue;
+            dropped = *it;
+            s->queue.erase(it);
+            s->finished[ticket] = {GFECH_E_CANCELLED, nullptr};
+            known = true;
+            break;
+        }
+        for (auto& kv : s->running)
+            if (kv.second.ticket == ticket) {
+                s->cancels.push_back(ticket);
+                known = true;
+            }
+        if (!known) return fail(GFECH_E_ARG, "unknown ticket");
+    }
+    if (dropped.input) {
+        // its input was copied completely when it was submitted
+        std::lock_guard<std::mutex> lk(g_mu);
+        s->be->release(dropped.input);
+    }
+    s->done.notify_all();
+    s->work.notify_all();
+    return GFECH_OK;
+}
+
+gfech_status gfech_server_get_stats(gfech_server* s, gfech_server_stats* stats) {
+    if (!s || !stats) return fail(GFECH_E_ARG, "null argument");
+    std::lock_guard<std::mutex> q(s->mu);
+    *stats = s->counters;
+    return GFECH_OK;
+}
+
 gfech_status gfech_server_wait(gfech_server* s, uint64_t ticket, gfech_result** out) {
     if (!s || !out) return fail(GFECH_E_ARG, "null argument");
     *out = nullptr;
@@ -901,7 +962,8 @@ void gfech_server_destroy(gfech_server* s) {
         s->stop = true;
         dropped.swap(s->queue);
     }
-    {
+    if (!dropped.empty()) {
+        // their inputs were copied completely when they were submitted
         std::lock_guard<std::mutex> lk(g_mu);
         for (auto& r : dropped) s->be->release(r.input);
     }
@@ -912,6 +974,7 @@ void gfech_server_destroy(gfech_server* s) {
     s->finished.clear();
     s->eng.reset();
     s->be->destroy_stream(s->stream);
+    s->be->destroy_stream(s->submit_stream);
     delete s;
 }
 

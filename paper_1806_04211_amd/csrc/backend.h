@@ -131,6 +131,8 @@ public:
     virtual void lists(const std::vector<ListDesc>& d) = 0;
     virtual void sort(const std::vector<SortDesc>& d) = 0;
     virtual void sync() = 0;
+    // waits for lane 0's work only (the other lanes may still run)
+    virtual void sync_lane0() { sync(); }
     // number of entries >= p in an m x n matrix (waits for the answer)
     virtual int64_t count_out_of_range(const uint8_t* A, int64_t m, int64_t n, int64_t lda, int32_t p) = 0;
     // GF(2) rows packed in 64-bit words, bit b of word w = column 64 w + b, to

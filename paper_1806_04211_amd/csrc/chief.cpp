@@ -42,6 +42,7 @@
 #include "chief.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -1033,6 +1034,7 @@ struct Engine::Impl {
         std::vector<void*> pieces;
         size_t counts_off = 0, counts_n = 0;
         Phase phase = kStep1;
+        bool cancel = false;
         int layer = 0;
         size_t cu_step = 0;
         std::unique_ptr<Result> res;
@@ -1232,10 +1234,40 @@ struct Engine::Impl {
         jobs.clear();
     }
 
+    // cancelled problems: the bulk part issued last may name their buffers,
+    // so every lane drains before their memory is freed
+    void drop_cancelled() {
+        bool any = false;
+        for (auto& j : jobs) any = any || j->cancel;
+        if (!any) return;
+        issue_bulk(be.mark(0));
+        wait_bulk();
+        be.sync();
+        b1 = Bulk(); b3 = Bulk(); b4 = Bulk(); b6 = Bulk();
+        std::vector<std::unique_ptr<Job>> keep;
+        for (auto& j : jobs) {
+            if (!j->cancel) {
+                keep.push_back(std::move(j));
+                continue;
+            }
+            release(*j);
+            Done d;
+            d.id = j->id;
+            d.status = kCancelled;
+            done.push_back(std::move(d));
+        }
+        jobs.swap(keep);
+    }
+
     size_t step() {
         if (owns_trace) ++g_trace_iter;
         if (be.error()) {
             fail_all(be.error());
+            return 0;
+        }
+        drop_cancelled();
+        if (jobs.empty()) {
+            flush(be, init_ops, shared);
             return 0;
         }
         Ops ops;
@@ -1429,6 +1461,10 @@ size_t Engine::footprint(const Problem& pr) const {
 }
 int64_t Engine::add(const Problem& pr, int* status) { return impl_->add(pr, status); }
 size_t Engine::step() { return impl_->step(); }
+void Engine::cancel(int64_t id) {
+    for (auto& j : impl_->jobs)
+        if (j->id == id) j->cancel = true;
+}
 size_t Engine::active() const { return impl_->jobs.size(); }
 size_t Engine::bytes_in_use() const { return impl_->bytes_in_use; }
 std::vector<Engine::Done> Engine::take_done() {
@@ -1439,7 +1475,8 @@ std::vector<Engine::Done> Engine::take_done() {
 const Stats& Engine::totals() const { return impl_->shared; }
 
 int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::unique_ptr<Result>>& out,
-              std::string* err, int profile) {
+              std::string* err, int profile, int64_t timeout_ms) {
+    const auto t0 = std::chrono::steady_clock::now();
     if (profile) {
         be.take_profile();
         be.set_profile(profile);
@@ -1459,11 +1496,22 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
             }
             ids.push_back(id);
         }
-        while (!rc && eng.active()) eng.step();
+        bool cancelled = false;
+        while (!rc && eng.active()) {
+            if (timeout_ms > 0 && !cancelled &&
+                std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(timeout_ms)) {
+                for (int64_t id : ids) eng.cancel(id);
+                cancelled = true;
+            }
+            eng.step();
+        }
         for (auto& d : eng.take_done()) {
             if (d.status && !rc) {
                 rc = d.status;
-                if (err) *err = rc == 4 ? "device allocation of the result failed" : "device error";
+                if (err)
+                    *err = rc == 4 ? "device allocation of the result failed"
+                           : rc == kCancelled ? "cancelled by the watchdog"
+                                              : "device error";
             }
             if (d.result && d.id < (int64_t)res.size()) res[(size_t)d.id] = std::move(d.result);
         }

@@ -96,6 +96,9 @@ public:
     int64_t add(const Problem& pr, int* status);
     // One iteration; returns the number of problems still active.
     size_t step();
+    // Stops problem `id` at the next iteration: its queued work completes,
+    // its memory is freed and it finishes with status kCancelled (no result).
+    void cancel(int64_t id);
     size_t active() const;
     size_t bytes_in_use() const;
     // Problems finished since the last call: id, status (0 or a backend error
@@ -114,10 +117,15 @@ private:
     std::unique_ptr<Impl> impl_;
 };
 
+// Status of a problem stopped by Engine::cancel (or the watchdog of run_chief).
+constexpr int kCancelled = 7;
+
 // Run the whole method on a set of independent problems in lockstep (their
 // jobs share launches).  Returns 0 or a backend error code; results are
-// appended to `out` in problem order.
+// appended to `out` in problem order.  timeout_ms > 0 is a watchdog: problems
+// still running after that long are cancelled and the call returns kCancelled.
 int run_chief(Backend& be, const std::vector<Problem>& probs,
-              std::vector<std::unique_ptr<Result>>& out, std::string* err, int profile = 0);
+              std::vector<std::unique_ptr<Result>>& out, std::string* err, int profile = 0,
+              int64_t timeout_ms = 0);
 
 }  // namespace gfech

@@ -2062,6 +2062,7 @@ public:
         if (bytes) HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, stream_));
     }
     void sync() override { sync_all(); }
+    void sync_lane0() override { HIP_OK(hipStreamSynchronize(stream_)); }
     // pinned host memory the device writes directly: no copy, only a wait for lane 0
     int32_t* counts_buffer(size_t n) override {
         if (n > counts_cap_) {

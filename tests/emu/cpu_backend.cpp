@@ -88,6 +88,9 @@ public:
         if (!fixed_) fixed_ = (uint8_t*)alloc(kFixedScratchBytes);
         return fixed_;
     }
+    void sync_lane0() override {
+        if (fuzz_) drain(0, q_[0].size());
+    }
     void set_lane(int lane) override { lane_ = lane; }
     int mark(int lane) override {
         if (lane == 0 && !fuzz_) return 0;

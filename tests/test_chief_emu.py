@@ -359,3 +359,23 @@ def test_gf2_packed_pad_bits_rejected(lib):
     # the set bit lies outside the matrix and changes nothing
     o = lib.echelonise_gf2(W, 70, skip_range_check=True).outputs()
     compare(o, oracle.echelonize(A, 2))
+
+
+@pytest.mark.parametrize("seed", [21, 22, 23])
+def test_random_interleavings_with_a_cancelled_neighbour(lib, fuzz, seed):
+    """A request cancelled while others share its launches: under random
+    interleavings (released memory quarantined, so a queued job that still
+    named the cancelled buffers would fail the bounds check) the others
+    still equal the oracle."""
+    from paper_1806_04211_amd.api import GfechError
+    fuzz(seed)
+    srv = lib.server()
+    reqs = [(synth.uniform(seed, t, 700 if t == 1 else 60 + 9 * t, 90, 7), 7) for t in range(4)]
+    tickets = [srv.submit(A, p) for A, p in reqs]
+    srv.cancel(tickets[1])
+    for t, ((A, p), tk) in enumerate(zip(reqs, tickets)):
+        try:
+            compare(srv.wait(tk).outputs(), oracle.echelonize(A, p), f"request {t}")
+        except GfechError as e:
+            assert t == 1 and e.status == 7
+    srv.close()

@@ -51,4 +51,44 @@ def test_server_device_inputs_and_budget():
     with pytest.raises(GfechError) as ex:
         srv.submit(np.zeros((8000, 8000), np.uint8), 3)
     assert ex.value.status == 5
+    st = srv.stats()
+    assert st["admitted"] == st["finished"] == len(reqs)
+    assert 0 < st["peak_bytes_in_flight"] <= 64 << 20 and 1 <= st["peak_active"] <= 3
     srv.close()
+
+
+def test_server_cancel_and_device_inputs_reused_at_once():
+    """Device inputs are copied before submit returns (the caller overwrites
+    its buffer right away); a cancelled request answers GFECH_E_CANCELLED or,
+    if it had already finished, the right result; the rest are unaffected."""
+    torch = torch_cuda()
+    lib = gpu_library()
+    reqs = mixed(9, 8)
+    srv = lib.server()
+    tickets = []
+    buf = torch.empty(max(A.size for A, _ in reqs), dtype=torch.uint8, device="cuda:0")
+    for A, p in reqs:
+        buf[: A.size] = torch.from_numpy(A.ravel().copy()).to("cuda:0")
+        tickets.append(srv.submit_dev(buf.data_ptr(), A.shape[0], A.shape[1], A.shape[1], p))
+        buf.fill_(255)                       # not a residue: a late copy would be refused or wrong
+    torch.cuda.synchronize()
+    srv.cancel(tickets[3])
+    for t, ((A, p), tk) in enumerate(zip(reqs, tickets)):
+        try:
+            compare(srv.wait(tk).outputs(), oracle.echelonize(A, p), f"request {t}")
+        except GfechError as e:
+            assert t == 3 and e.status == 7
+    srv.close()
+
+
+def test_watchdog_cancels_a_long_solve():
+    torch = torch_cuda()
+    lib = gpu_library()
+    from synth import torch_gen
+    say("watchdog: 6000 x 6000 GF(7) with a 1 ms limit")
+    A = torch_gen.uniform(0, 3, 6000, 6000, 7)
+    with pytest.raises(GfechError) as ex:
+        lib.echelonise_dev(A.data_ptr(), 6000, 6000, 6000, 7, timeout_ms=1)
+    assert ex.value.status == 7
+    B = synth.deficient(1, 5, 700, 600, 7)
+    compare(lib.echelonise(B, 7, timeout_ms=60000).outputs(), oracle.echelonize(B, 7), "after the watchdog")

@@ -73,6 +73,9 @@ def test_memory_budget_admission(lib):
     tickets = [srv.submit(A, p) for A, p in reqs]
     for (A, p), t in zip(reqs, tickets):
         compare(srv.wait(t).outputs(), oracle.echelonize(A, p))
+    st = srv.stats()
+    assert st["admitted"] == st["finished"] == len(reqs)
+    assert 0 < st["peak_bytes_in_flight"] <= 16 << 20
     srv.close()
 
 
@@ -93,3 +96,36 @@ def test_errors_and_tickets(lib):
     e = srv.submit(np.zeros((0, 5), np.uint8), 5)
     assert srv.wait(e).rank == 0
     srv.close()
+
+
+def test_cancel_queued_and_running(lib):
+    """A cancelled request answers GFECH_E_CANCELLED unless it had already
+    finished (then its result is right); when it was dropped or stopped, the
+    others are unaffected and the server keeps working afterwards."""
+    srv = lib.server(max_active=1)
+    big = synth.uniform(3, 1, 1500, 300, 7)        # 6 block rows: several iterations
+    small = [(synth.uniform(3, 2 + t, 40, 50, 5), 5) for t in range(3)]
+    tb = srv.submit(big, 7)
+    ts = [srv.submit(A, p) for A, p in small]
+    srv.cancel(ts[1])
+    srv.cancel(tb)
+    for tk, (A, p) in ((tb, (big, 7)), (ts[1], small[1])):
+        try:
+            compare(srv.wait(tk).outputs(), oracle.echelonize(A, p))
+        except GfechError as e:
+            assert e.status == 7
+    for t in (0, 2):
+        compare(srv.wait(ts[t]).outputs(), oracle.echelonize(*small[t]))
+    with pytest.raises(GfechError) as ex:
+        srv.cancel(12345)
+    assert ex.value.status == 1
+    srv.close()
+
+
+def test_watchdog_cancels_and_library_recovers(lib):
+    A = synth.uniform(4, 1, 400, 400, 7)
+    with pytest.raises(GfechError) as ex:
+        lib.echelonise(A, 7, block_rows=8, block_cols=8, timeout_ms=1)
+    assert ex.value.status == 7
+    B = synth.deficient(4, 2, 60, 70, 7)
+    compare(lib.echelonise(B, 7, block_rows=8, block_cols=8, timeout_ms=60000).outputs(), oracle.echelonize(B, 7))
