@@ -69,6 +69,7 @@ def test_server_cancel_and_device_inputs_reused_at_once():
     buf = torch.empty(max(A.size for A, _ in reqs), dtype=torch.uint8, device="cuda:0")
     for A, p in reqs:
         buf[: A.size] = torch.from_numpy(A.ravel().copy()).to("cuda:0")
+        torch.cuda.synchronize()             # the server's streams do not wait for torch's
         tickets.append(srv.submit_dev(buf.data_ptr(), A.shape[0], A.shape[1], A.shape[1], p))
         buf.fill_(255)                       # not a residue: a late copy would be refused or wrong
     torch.cuda.synchronize()
