@@ -220,12 +220,18 @@ class Library:
                                            ctypes.c_void_p(brow), ctypes.c_void_p(C), ldc, ctypes.c_void_p(crow),
                                            ctypes.c_void_p(D), ldd, ctypes.c_void_p(stream)))
 
-    def mad_batch_dev(self, descs, stream=0):
-        """descs: list of dicts with the gfech_mad_desc fields (device addresses)."""
+    @staticmethod
+    def mad_descs(descs):
+        """A gfech_mad_desc array from dicts with its fields (device addresses)."""
         arr = (_abi.MadDesc * max(len(descs), 1))()
         for t, d in enumerate(descs):
             for k, v in d.items():
                 setattr(arr[t], k, v)
+        return arr
+
+    def mad_batch_dev(self, descs, stream=0):
+        """descs: list of dicts with the gfech_mad_desc fields, or an array from mad_descs."""
+        arr = descs if isinstance(descs, ctypes.Array) else self.mad_descs(descs)
         self._check(self.lib.gfech_mad_batch_dev(len(descs), arr, ctypes.c_void_p(stream)))
 
     def ech_dev(self, H, rows, cols, ldh, p, prow, qrow, pcol, qcol, M, ldm, K, ldk, R, ldr, stream=0) -> int:

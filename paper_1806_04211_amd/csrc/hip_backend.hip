@@ -150,6 +150,7 @@ struct GemmTileMap {           // per-descriptor tile grid, device side
 constexpr int GEMM_ARG_CAP = 32;
 struct GemmArgSrc {
     int n;
+    int group;                 // tile rows per group of the tile order (see k_gemm_modp)
     GemmTileMap m[GEMM_ARG_CAP];
     GemmDesc d[GEMM_ARG_CAP];
     __device__ __forceinline__ int count() const { return n; }
@@ -167,6 +168,7 @@ struct GemmArgSrc {
 };
 struct GemmPtrSrc {
     int n;
+    int group;
     const GemmTileMap* m;
     const GemmDesc* d;
     __device__ __forceinline__ int count() const { return n; }
@@ -374,8 +376,19 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
     const GemmTileMap gm = src.map(lo);
     const int local = tile - gm.first_tile;
     const int tn = gm.tiles_n;
-    const int m0 = (local / tn) * TM;
-    const int n0 = (local % tn) * TN;
+    // Tile order inside a descriptor: groups of `group` tile rows, each group
+    // column by column, so consecutive tiles share their B panel (and a group's
+    // A panels) while they are in the XCD's L2; group 1 is row by row.
+    int m0, n0;
+    {
+        const int tm = (g.M + TM - 1) / TM;
+        const int G = src.group;
+        const int grp = local / (G * tn);
+        const int rows = min(G, tm - grp * G);
+        const int idx = local - grp * G * tn;
+        m0 = (grp * G + idx % rows) * TM;
+        n0 = (idx / rows) * TN;
+    }
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -1994,6 +2007,8 @@ public:
             echs_lds_max_ = 64 * 1024;
         }
         no_lds_ech_ = getenv("GFECH_ECH_NO_LDS") != nullptr;
+        const char* gg = getenv("GFECH_GEMM_GROUP");
+        gemm_group_ = gg ? std::max(1, std::min(64, atoi(gg))) : 1;
         // the device address of the fixed workspace on this device (the one
         // current now, which every later call of this backend uses)
         if (hipGetSymbolAddress((void**)&fixed_scratch_, HIP_SYMBOL(scratch)) != hipSuccess) {
@@ -2158,6 +2173,7 @@ public:
         if (d.size() <= (size_t)GEMM_ARG_CAP) {
             GemmArgSrc a;
             a.n = (int)d.size();
+            a.group = gemm_group_;
             for (size_t i = 0; i < d.size(); ++i) { a.m[i] = maps[i]; a.d[i] = d[i]; }
             go(0, k_gemm_modp<GemmArgSrc>, dim3((unsigned)tiles), dim3(GEMM_THREADS), gemm_lds_bytes(), a);
         } else {
@@ -2169,6 +2185,7 @@ public:
             const uint8_t* dev = (const uint8_t*)put(blob.data(), blob.size());
             GemmPtrSrc a;
             a.n = (int)d.size();
+            a.group = gemm_group_;
             a.m = (const GemmTileMap*)dev;
             a.d = (const GemmDesc*)(dev + mb);
             go(0, k_gemm_modp<GemmPtrSrc>, dim3((unsigned)tiles), dim3(GEMM_THREADS), gemm_lds_bytes(), a);
@@ -2415,6 +2432,7 @@ private:
     int mark_base_ = 0;              // id of marks_[0]
     size_t echs_lds_max_ = 0;        // LDS the LDS-resident ECH may use
     bool no_lds_ech_ = false;
+    int gemm_group_ = 1;             // tile rows per group of the MAD tile order
     void* ring_host_ = nullptr;
     void* ring_dev_ = nullptr;
     size_t ring_off_ = 0;
