@@ -335,8 +335,22 @@ def serve_request(rng_seed, t):
 
 
 def run_serve(torch, args):
-    """Poisson arrivals through the server (continuous batching) against a
-    first-come first-served loop of single calls on the same arrivals."""
+    """The serving workload: `requests` requests (n log-uniform in [64, 8192],
+    m = n U[0.75, 1.25], p from {2, 3, 5, 251}, uniform entries from a
+    per-request seed), Poisson arrivals at `load` x the server's capacity,
+    through the server (continuous batching, size classes) and, on the same
+    arrivals, through one plain call at a time (first come, first served).
+
+    Inputs are generated on the device when a request arrives (a few tens of
+    microseconds; all 20000 would take about 140 GB at once).  Three phases:
+    (1) every request alone through one plain call: its service time;
+    (2) the server's capacity mu: all requests through the server with the
+        submitted-but-unfinished inputs kept under `window_gb` (a saturated
+        queue that does not hold every input at once);
+    (3) Poisson arrivals at lambda = load x mu through the server: latency =
+        completion - arrival.  The plain path's latencies on the same arrivals
+        follow from (1): each request starts when it has arrived and the
+        previous one has finished."""
     import numpy as np
 
     import paper_1806_04211_amd as gf
@@ -345,61 +359,75 @@ def run_serve(torch, args):
     nreq = args.requests
     shapes = [serve_request(0, t) for t in range(nreq)]
 
-    # every input is generated before any timing and stays in device memory
-    t0 = time.perf_counter()
-    inputs = [torch_gen.uniform(0, 2000 + t, m, n, p) for t, (m, n, p) in enumerate(shapes)]
-    torch.cuda.synchronize()
-    log(f"{nreq} inputs ready in {time.perf_counter() - t0:.1f} s "
-        f"({sum(m * n for m, n, _ in shapes) / 2**30:.2f} GiB)")
-
-    def submit(srv, t):
+    def make(t):
         m, n, p = shapes[t]
-        return srv.submit_dev(inputs[t].data_ptr(), m, n, n, p)
+        return torch_gen.uniform(0, 2000 + t, m, n, p)
 
-    # service time of every request alone (the plain path), which also
-    # calibrates the capacity of the served path below
+    # (1) the plain path: one call per request, its service time alone
     service = []
+    t0 = time.perf_counter()
     for t in range(nreq):
         m, n, p = shapes[t]
+        A = make(t)
+        torch.cuda.synchronize()
         t1 = time.perf_counter()
-        r = lib.echelonise_dev(inputs[t].data_ptr(), m, n, n, p)
+        r = lib.echelonise_dev(A.data_ptr(), m, n, n, p)
         service.append(time.perf_counter() - t1)
         r.free()
-    log(f"plain path: {sum(service):.2f} s of service for {nreq} requests")
-    # capacity of the server: all requests at once
-    srv = lib.server()
-    t1 = time.perf_counter()
-    tickets = [submit(srv, t) for t in range(nreq)]
-    for tk in tickets:
-        srv.wait(tk).free()
-    burst = time.perf_counter() - t1
+        del A
+        if t % 2000 == 1999:
+            log(f"plain path: {t + 1} requests, {sum(service):.1f} s of service")
+    log(f"plain path: {sum(service):.2f} s of service for {nreq} requests ({time.perf_counter() - t0:.1f} s)")
+
+    srv = lib.server(hbm_budget_bytes=args.budget_gb << 30, size_classes=args.size_classes)
+    cur = torch.cuda.current_stream()
+
+    def collect(pending, done_at, t0):
+        for tk in list(pending):
+            r = srv.poll(tk)
+            if r is not None:
+                done_at[pending.pop(tk)[0]] = time.perf_counter() - t0
+                r.free()
+
+    # (2) capacity: a saturated queue, bounded by the bytes of waiting inputs
+    window = args.window_gb << 30
+    pending, done_at = {}, {}
+    t0 = time.perf_counter()
+    for t in range(nreq):
+        m, n, p = shapes[t]
+        while sum(v[1] for v in pending.values()) + m * n > window and pending:
+            collect(pending, done_at, t0)
+        A = make(t)
+        cur.synchronize()                  # the generation only, not the server's streams
+        pending[srv.submit_dev(A.data_ptr(), m, n, n, p)] = (t, m * n)
+        del A
+        collect(pending, done_at, t0)
+    while pending:
+        collect(pending, done_at, t0)
+    burst = time.perf_counter() - t0
     mu = nreq / burst
-    # the arrival rate is a fraction of what one call at a time sustains, the
-    # path the server is compared with (a burst of every request at once
-    # overstates what the server sustains under staggered arrivals)
-    mu_plain = nreq / sum(service)
-    lam = args.load * mu_plain
-    log(f"server capacity {mu:.1f} solves/s (burst {burst:.2f} s), one call at a time {mu_plain:.1f}/s; "
+    lam = args.load * mu
+    log(f"server capacity {mu:.1f} solves/s ({burst:.1f} s); plain path {nreq / sum(service):.1f} solves/s; "
         f"arrival rate {lam:.1f}/s")
+
+    # (3) Poisson arrivals through the server
     arrivals = np.cumsum(np.random.default_rng(0).exponential(1.0 / lam, nreq))
-    # served: requests arrive at their times; finished ones are collected between arrivals
     pending, done_at = {}, {}
     t0 = time.perf_counter()
     for t in range(nreq):
         while time.perf_counter() - t0 < arrivals[t]:
-            for tk in list(pending):
-                r = srv.poll(tk)
-                if r is not None:
-                    done_at[pending.pop(tk)] = time.perf_counter() - t0
-                    r.free()
-        pending[submit(srv, t)] = t
+            collect(pending, done_at, t0)
+        m, n, p = shapes[t]
+        A = make(t)
+        cur.synchronize()                  # the generation only, not the server's streams
+        pending[srv.submit_dev(A.data_ptr(), m, n, n, p)] = (t, m * n)
+        del A
+        if t % 2000 == 1999:
+            log(f"served: {t + 1} requests submitted, {len(done_at)} finished")
     while pending:
-        for tk in list(pending):
-            r = srv.poll(tk)
-            if r is not None:
-                done_at[pending.pop(tk)] = time.perf_counter() - t0
-                r.free()
+        collect(pending, done_at, t0)
     span = time.perf_counter() - t0
+    st = srv.stats()
     srv.close()
     lat = [done_at[t] - arrivals[t] for t in range(nreq)]
     # the plain path on the same arrivals: one request at a time, first come first served
@@ -407,19 +435,22 @@ def run_serve(torch, args):
     for t in range(nreq):
         fin = max(fin, arrivals[t]) + service[t]
         plain_lat.append(fin - arrivals[t])
+    small = [t for t in range(nreq) if max(shapes[t][:2]) <= 512]
     print(json.dumps({
         "metric": "served solves/s and p50/p99 latency (Poisson arrivals, continuous batching) vs one call at a time",
         "value": nreq / span, "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": span * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u8", "data": "synthetic",
         "config": {"workload": f"{nreq} requests, n log-uniform in [64, 8192], m = n U[0.75, 1.25], p from "
-                               f"{{2, 3, 5, 251}}, Poisson arrivals at {args.load} x the one-call-at-a-time rate ({lam:.1f}/s)",
-                   "requests": nreq, "arrival_rate": lam},
-        "latency_ms": {"p50": percentile(lat, 0.5) * 1e3, "p99": percentile(lat, 0.99) * 1e3},
-        "capacity_solves_per_s": mu,
-        "plain": {"solves_per_s": nreq / fin, "latency_ms": {"p50": percentile(plain_lat, 0.5) * 1e3,
-                                                            "p99": percentile(plain_lat, 0.99) * 1e3},
-                  "service_s": sum(service)},
+                               f"{{2, 3, 5, 251}}, Poisson arrivals at {args.load} x the server's capacity "
+                               f"({lam:.1f}/s), budget {args.budget_gb} GB, {args.size_classes or 3} size classes",
+                   "requests": nreq, "arrival_rate": lam, "capacity": mu, "budget_gb": args.budget_gb},
+        "latency_ms": {"p50": percentile(lat, 0.5) * 1e3, "p99": percentile(lat, 0.99) * 1e3,
+                       "p99_small": percentile([lat[t] for t in small], 0.99) * 1e3},
+        "server": {"peak_gb_in_flight": st["peak_bytes_in_flight"] / 2 ** 30, "peak_active": st["peak_active"]},
+        "plain": {"solves_per_s": nreq / fin, "service_s": sum(service),
+                  "latency_ms": {"p50": percentile(plain_lat, 0.5) * 1e3, "p99": percentile(plain_lat, 0.99) * 1e3,
+                                 "p99_small": percentile([plain_lat[t] for t in small], 0.99) * 1e3}},
     }), flush=True)
 
 
@@ -449,15 +480,23 @@ def main():
                     help="single: the one large matrix (default); batch: many small matrices in one call; "
                          "serve: a Poisson stream of requests through the server")
     ap.add_argument("--count", type=int, default=4096, help="batch: number of matrices")
-    ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
+    ap.add_argument("--requests", type=int, default=20000, help="serve: number of requests")
     ap.add_argument("--load", type=float, default=0.8,
-                    help="serve: arrival rate as a fraction of the one-call-at-a-time rate")
+                    help="serve: arrival rate as a fraction of the server's capacity")
+    ap.add_argument("--budget-gb", type=int, default=200, help="serve: device-memory admission budget")
+    ap.add_argument("--window-gb", type=int, default=32,
+                    help="serve: inputs waiting in the server at most while its capacity is measured")
+    ap.add_argument("--size-classes", type=int, default=0, help="serve: size classes of the server (0 = 3)")
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32; 0 = the environment's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the method here runs on a "
               "single MI355X and has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
 
+    if args.hw_queues > 0:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.hw_queues, 32))     # before the runtime starts
     import torch
 
     if args.copy_mib > 0:

@@ -260,20 +260,28 @@ gfech_status gfech_ech_dev_noalloc(const uint8_t* H, int64_t rows, int64_t cols,
                                    int32_t* rank_dev, void* stream);
 
 /* ---------------------------------------------------------------- serving
- * A server echelonises requests as they arrive (continuous batching): a
- * worker thread keeps every admitted request's block state in device memory
- * and advances all of them together, one phase of the method each per
- * iteration, so requests submitted while others run join at the next
- * iteration and their jobs share launches.  Requests are admitted in arrival
- * order while the device memory they hold (an upper bound per request) fits
- * the budget; a request whose bound alone exceeds the budget is refused.
+ * A server echelonises requests as they arrive (continuous batching).
+ * Requests are sorted into size classes; per class a worker thread keeps
+ * every admitted request's block state in device memory and advances all of
+ * them together, one phase of the method each per iteration, so requests
+ * submitted while others run join at the next iteration and their jobs share
+ * launches, while the classes run side by side on streams of their own.
+ * Requests are admitted in arrival order within their class while the device
+ * memory they hold (an upper bound per request) fits the budget, which the
+ * classes share; a request whose bound alone exceeds the budget is refused.
  * Results are the same as from gfech_echelonise_u8 on the same input (the
  * default blocking).  The functions are thread-safe. */
 typedef struct gfech_server gfech_server;
 typedef struct gfech_server_cfg {
     int64_t hbm_budget_bytes;   /* device memory for admitted requests; 0 = 200 GB */
     int32_t max_active;         /* requests in flight at once; 0 = no limit but the budget */
-    int32_t reserved[5];
+    int32_t size_classes;       /* 1, 2 or 3 (0 = 3): requests are sorted by max(m, n) into
+                                   classes (up to 512, up to 2048, larger; with 2 classes up to
+                                   512 and larger), each with its own engine, streams and worker
+                                   thread, so small requests never wait for the phases of large
+                                   ones; admission is first come first served within a class
+                                   against the one budget */
+    int32_t reserved[4];
 } gfech_server_cfg;
 gfech_status gfech_server_create(const gfech_server_cfg* cfg, gfech_server** out);
 /* Queue one problem.  The input (host or device memory, as the flag says) is

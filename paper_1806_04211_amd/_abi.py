@@ -44,7 +44,7 @@ class Stats(ctypes.Structure):
 
 
 class ServerCfg(ctypes.Structure):
-    _fields_ = [("hbm_budget_bytes", c_i64), ("max_active", c_i32), ("reserved", c_i32 * 5)]
+    _fields_ = [("hbm_budget_bytes", c_i64), ("max_active", c_i32), ("size_classes", c_i32), ("reserved", c_i32 * 4)]
 
 
 class ServerStats(ctypes.Structure):

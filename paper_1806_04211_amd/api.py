@@ -251,8 +251,8 @@ class Library:
                                                    vp(qcol), vp(M), ldm, vp(K), ldk, vp(R), ldr, vp(rank_dev),
                                                    vp(stream)))
 
-    def server(self, hbm_budget_bytes: int = 0, max_active: int = 0) -> "Server":
-        return Server(self, hbm_budget_bytes, max_active)
+    def server(self, hbm_budget_bytes: int = 0, max_active: int = 0, size_classes: int = 0) -> "Server":
+        return Server(self, hbm_budget_bytes, max_active, size_classes)
 
     def echelonise_batch(self, problems, on_device: bool = False, stream: int = 0, block_rows=0, block_cols=0,
                          profile=False, variant=0):
@@ -285,11 +285,12 @@ class Library:
 class Server:
     """Owns one gfech_server* (continuous batching of elimination requests)."""
 
-    def __init__(self, lib: "Library", hbm_budget_bytes: int = 0, max_active: int = 0):
+    def __init__(self, lib: "Library", hbm_budget_bytes: int = 0, max_active: int = 0, size_classes: int = 0):
         self._lib = lib.lib
         cfg = _abi.ServerCfg()
         cfg.hbm_budget_bytes = int(hbm_budget_bytes)
         cfg.max_active = int(max_active)
+        cfg.size_classes = int(size_classes)
         out = ctypes.c_void_p()
         st = self._lib.gfech_server_create(ctypes.byref(cfg), ctypes.byref(out))
         if st != _abi.GFECH_OK:

@@ -19,8 +19,13 @@
 #include "chief.h"
 
 namespace gfech {
-// Provided by the backend translation unit linked into the library.
+// Provided by the backend translation unit linked into the library: the
+// shared instance of the plain calls, and further instances (own streams,
+// memory cache and lock) for the server's size classes.  Instances are
+// never destroyed: results keep pointers to the instance that made them.
 Backend* backend_instance(std::string* err);
+Backend* backend_acquire(std::string* err);
+void backend_release(Backend* be);
 }  // namespace gfech
 
 struct gfech_result {
@@ -29,7 +34,6 @@ struct gfech_result {
 
 namespace {
 
-std::mutex g_mu;
 thread_local std::string g_last_error;
 
 gfech_status fail(gfech_status s, const std::string& msg) {
@@ -131,9 +135,9 @@ gfech_status echelonise_impl(const uint8_t* A, bool on_device, int64_t m, int64_
             for (int64_t j = 0; j < n; ++j)
                 if (A[i * lda + j] >= p) return fail(GFECH_E_RANGE, "entry >= p");
     }
-    std::lock_guard<std::mutex> lk(g_mu);
     gfech::Backend* be = get_backend(&st);
     if (!be) return st;
+    std::lock_guard<std::mutex> lk(be->lock());
     be->set_stream(stream);
     const uint8_t* dA = A;
     void* staged = nullptr;
@@ -189,9 +193,9 @@ gfech_status echelonise_gf2_impl(const uint64_t* A, bool on_device, int64_t m, i
         for (int64_t i = 0; i < m; ++i)
             if (A[i * ldw + n / 64] & mask) return fail(GFECH_E_RANGE, "a pad bit past column n - 1 is set");
     }
-    std::lock_guard<std::mutex> lk(g_mu);
     gfech::Backend* be = get_backend(&st);
     if (!be) return st;
+    std::lock_guard<std::mutex> lk(be->lock());
     be->set_stream(stream);
     const uint64_t* packed = A;
     int64_t ld = ldw;
@@ -352,10 +356,10 @@ gfech_status gfech_echelonise_batch(int64_t count, const gfech_problem* probs, i
         ok.push_back(t);
     }
     if (ok.empty()) return first;
-    std::lock_guard<std::mutex> lk(g_mu);
     gfech_status st = GFECH_OK;
     gfech::Backend* be = get_backend(&st);
     if (!be) return st;
+    std::lock_guard<std::mutex> lk(be->lock());
     be->set_stream(stream);
     std::vector<gfech::Problem> pv;
     std::vector<int64_t> run_idx;
@@ -412,8 +416,8 @@ gfech_status gfech_shape(const gfech_result* res, int64_t* m, int64_t* n, uint32
 
 gfech_status gfech_pivots(const gfech_result* res, int64_t* gamma, int64_t* rho) {
     if (!res) return fail(GFECH_E_ARG, "NULL result");
-    std::lock_guard<std::mutex> lk(g_mu);
     const gfech::Result& R = *res->r;
+    std::lock_guard<std::mutex> lk(R.be->lock());
     if (gamma) download_list(R.be, R.upsilon, R.r, gamma);
     if (rho) download_list(R.be, R.varrho, R.r, rho);
     return GFECH_OK;
@@ -421,8 +425,8 @@ gfech_status gfech_pivots(const gfech_result* res, int64_t* gamma, int64_t* rho)
 
 gfech_status gfech_nonpivots(const gfech_result* res, int64_t* gamma_bar, int64_t* rho_bar) {
     if (!res) return fail(GFECH_E_ARG, "NULL result");
-    std::lock_guard<std::mutex> lk(g_mu);
     const gfech::Result& R = *res->r;
+    std::lock_guard<std::mutex> lk(R.be->lock());
     if (gamma_bar) download_list(R.be, R.upsilon_bar, R.n - R.r, gamma_bar);
     if (rho_bar) download_list(R.be, R.varrho_bar, R.m - R.r, rho_bar);
     return GFECH_OK;
@@ -433,7 +437,7 @@ gfech_status gfech_get_R(const gfech_result* res, uint8_t* R_, int64_t ldr) {
     const gfech::Result& R = *res->r;
     if (!has_R(R)) return fail(GFECH_E_STATE, "the result was computed without R");
     if (R.r > 0 && R.n - R.r > 0 && (!R_ || ldr < R.n - R.r)) return fail(GFECH_E_ARG, "bad R buffer");
-    std::lock_guard<std::mutex> lk(g_mu);
+    std::lock_guard<std::mutex> lk(R.be->lock());
     return download_matrix(R.be, R.Pfinal + R.offR, R.ldP, R.r, R.n - R.r, R_, ldr);
 }
 
@@ -442,7 +446,7 @@ gfech_status gfech_get_M(const gfech_result* res, uint8_t* M, int64_t ldm) {
     const gfech::Result& R = *res->r;
     if (!has_T(R)) return fail(GFECH_E_STATE, "the result was computed without the transformation");
     if (R.r > 0 && (!M || ldm < R.r)) return fail(GFECH_E_ARG, "bad M buffer");
-    std::lock_guard<std::mutex> lk(g_mu);
+    std::lock_guard<std::mutex> lk(R.be->lock());
     return download_matrix(R.be, R.Pfinal + R.offM, R.ldP, R.r, R.r, M, ldm);
 }
 
@@ -451,7 +455,7 @@ gfech_status gfech_get_K(const gfech_result* res, uint8_t* K, int64_t ldk) {
     const gfech::Result& R = *res->r;
     if (!has_T(R)) return fail(GFECH_E_STATE, "the result was computed without the transformation");
     if (R.r > 0 && R.m - R.r > 0 && (!K || ldk < R.r)) return fail(GFECH_E_ARG, "bad K buffer");
-    std::lock_guard<std::mutex> lk(g_mu);
+    std::lock_guard<std::mutex> lk(R.be->lock());
     return download_matrix(R.be, R.Kfinal, R.ldK, R.m - R.r, R.r, K, ldk);
 }
 
@@ -460,7 +464,7 @@ gfech_status gfech_expand_rref_dev(const gfech_result* res, uint8_t* E, int64_t 
     const gfech::Result& R = *res->r;
     if (!has_R(R)) return fail(GFECH_E_STATE, "the result was computed without R");
     if (R.r > 0 && R.n > 0 && (!E || lde < R.n)) return fail(GFECH_E_ARG, "bad E buffer");
-    std::lock_guard<std::mutex> lk(g_mu);
+    std::lock_guard<std::mutex> lk(R.be->lock());
     R.be->set_stream(stream);
     expand_rref_ops(R, E, lde, R.be);
     R.be->sync();
@@ -473,7 +477,7 @@ gfech_status gfech_expand_transform_dev(const gfech_result* res, uint8_t* T, int
     const gfech::Result& R = *res->r;
     if (!has_T(R)) return fail(GFECH_E_STATE, "the result was computed without the transformation");
     if (R.m > 0 && (!T || ldt < R.m)) return fail(GFECH_E_ARG, "bad T buffer");
-    std::lock_guard<std::mutex> lk(g_mu);
+    std::lock_guard<std::mutex> lk(R.be->lock());
     R.be->set_stream(stream);
     expand_transform_ops(R, T, ldt, R.be);
     R.be->sync();
@@ -487,7 +491,7 @@ gfech_status gfech_expand_rref(const gfech_result* res, uint8_t* E, int64_t lde)
     if (!has_R(R)) return fail(GFECH_E_STATE, "the result was computed without R");
     if (R.r == 0 || R.n == 0) return GFECH_OK;
     if (!E || lde < R.n) return fail(GFECH_E_ARG, "bad E buffer");
-    std::lock_guard<std::mutex> lk(g_mu);
+    std::lock_guard<std::mutex> lk(R.be->lock());
     uint8_t* d = (uint8_t*)R.be->alloc((size_t)(R.r * R.n));
     if (!d) return fail(GFECH_E_NOMEM, "device allocation failed");
     expand_rref_ops(R, d, R.n, R.be);
@@ -502,7 +506,7 @@ gfech_status gfech_expand_transform(const gfech_result* res, uint8_t* T, int64_t
     if (!has_T(R)) return fail(GFECH_E_STATE, "the result was computed without the transformation");
     if (R.m == 0) return GFECH_OK;
     if (!T || ldt < R.m) return fail(GFECH_E_ARG, "bad T buffer");
-    std::lock_guard<std::mutex> lk(g_mu);
+    std::lock_guard<std::mutex> lk(R.be->lock());
     uint8_t* d = (uint8_t*)R.be->alloc((size_t)(R.m * R.m));
     if (!d) return fail(GFECH_E_NOMEM, "device allocation failed");
     expand_transform_ops(R, d, R.m, R.be);
@@ -552,7 +556,10 @@ gfech_status gfech_get_stats(const gfech_result* res, gfech_stats* s) {
 
 void gfech_result_free(gfech_result* res) {
     if (!res) return;
-    std::lock_guard<std::mutex> lk(g_mu);
+    if (res->r && res->r->be) {
+        std::lock_guard<std::mutex> lk(res->r->be->lock());
+        res->r.reset();
+    }
     delete res;
 }
 
@@ -583,10 +590,10 @@ gfech_status gfech_mad_batch_dev(int64_t count, const gfech_mad_desc* descs, voi
         if (st) return st;
         if (descs[t].M && descs[t].N) gs.push_back(to_gemm(descs[t]));
     }
-    std::lock_guard<std::mutex> lk(g_mu);
     gfech_status st = GFECH_OK;
     gfech::Backend* be = get_backend(&st);
     if (!be) return st;
+    std::lock_guard<std::mutex> lk(be->lock());
     be->set_stream(stream);
     if (!gs.empty()) be->gemm(gs);
     be->sync();
@@ -618,10 +625,10 @@ gfech_status gfech_ech_dev(const uint8_t* H, int64_t rows, int64_t cols, int64_t
     if (!H || ldh < cols || !prow || !qrow || !pcol || !qcol || !M || !K || !R || ldm < mr || ldk < mr ||
         ldr < cols)
         return fail(GFECH_E_ARG, "bad ECH buffers");
-    std::lock_guard<std::mutex> lk(g_mu);
     gfech_status st = GFECH_OK;
     gfech::Backend* be = get_backend(&st);
     if (!be) return st;
+    std::lock_guard<std::mutex> lk(be->lock());
     be->set_stream(stream);
     int64_t ldw = cols + mr;
     uint8_t* work = (uint8_t*)be->alloc((size_t)(rows * ldw));
@@ -664,10 +671,10 @@ gfech_status gfech_ech_dev_noalloc(const uint8_t* H, int64_t rows, int64_t cols,
         return fail(GFECH_E_ARG, "bad ECH buffers");
     if ((size_t)(rows * ldw) > gfech::kFixedScratchBytes)
         return fail(GFECH_E_TOO_BIG, "the block's workspace exceeds the fixed workspace");
-    std::lock_guard<std::mutex> lk(g_mu);
     gfech_status st = GFECH_OK;
     gfech::Backend* be = get_backend(&st);
     if (!be) return st;
+    std::lock_guard<std::mutex> lk(be->lock());
     uint8_t* ws = be->fixed_scratch();
     if (!ws) return fail(GFECH_E_DEVICE, "no fixed workspace on this device");
     be->set_stream(stream);
@@ -690,96 +697,130 @@ gfech_status gfech_ech_dev_noalloc(const uint8_t* H, int64_t rows, int64_t cols,
 
 // ---------------------------------------------------------------- serving
 
+// Requests are sorted into size classes by max(m, n).  Each class has its own
+// engine, its own backend instance (streams, lanes, memory cache, lock) and
+// its own worker thread: a class's requests share launches (continuous
+// batching), and the phases of a large problem never hold back the small
+// ones, whose iterations are short and whose work runs on other streams.
+// Admission is first come first served within a class, against one
+// device-memory budget shared by the classes.  Lock order: a class backend's
+// lock before the server's mu, never the reverse.
 struct gfech_server {
     struct Req {
         uint64_t ticket = 0;
         gfech::Problem pr;
-        uint8_t* input = nullptr;     // device copy, owned until the request finishes
+        uint8_t* input = nullptr;     // device copy on the class's backend, owned until the request finishes
         size_t footprint = 0;
     };
-    gfech::Backend* be = nullptr;
-    void* stream = nullptr;
-    void* submit_stream = nullptr;    // the copies of submitted inputs
+    struct Class {
+        int64_t max_dim = 0;                  // largest max(m, n) of the class; 0 = no limit
+        gfech::Backend* be = nullptr;
+        void* stream = nullptr;               // lane 0 of the class's engine
+        void* submit_stream = nullptr;        // the copies of submitted inputs
+        std::unique_ptr<gfech::Engine> eng;   // used with be->lock() held
+        std::deque<Req> queue;                // under mu
+        std::map<int64_t, Req> running;       // engine id -> request, under mu
+        std::vector<uint64_t> cancels;        // tickets of running requests to cancel, under mu
+        std::condition_variable work;
+        std::thread worker;
+    };
+    std::vector<std::unique_ptr<Class>> classes;
     size_t budget = 0;
     int32_t max_active = 0;
-    std::mutex mu;                    // queue, running, finished, stop
-    std::condition_variable work, done;
-    std::deque<Req> queue;
-    std::map<int64_t, Req> running;   // engine id -> request
+    std::mutex mu;                    // everything marked "under mu" and the fields below
+    std::condition_variable done;
     std::map<uint64_t, std::pair<gfech_status, gfech_result*>> finished;
-    std::vector<uint64_t> cancels;    // tickets of running requests to cancel
-    gfech_server_stats counters{};    // under mu
     uint64_t next_ticket = 1;
     bool stop = false;
-    std::unique_ptr<gfech::Engine> eng;   // used with g_mu held
-    std::thread worker;
+    size_t bytes_in_flight = 0;       // footprints of the admitted requests of every class
+    int64_t active = 0;
+    gfech_server_stats counters{};
 
-    // admit what fits, advance every active problem by one phase, hand out
-    // the finished ones; the backend is used with g_mu held
-    bool iterate() {
-        std::lock_guard<std::mutex> lk(g_mu);
-        be->set_stream(stream);
+    Class& class_of(int64_t m, int64_t n) {
+        const int64_t d = std::max(m, n);
+        for (auto& k : classes)
+            if (k->max_dim == 0 || d <= k->max_dim) return *k;
+        return *classes.back();
+    }
+    // under mu: the class's next request may be admitted now
+    bool admissible(const Class& k) const {
+        return !k.queue.empty() && (max_active <= 0 || active < max_active) &&
+               (bytes_in_flight == 0 || bytes_in_flight + k.queue.front().footprint <= budget);
+    }
+    bool known(uint64_t ticket) const {
+        if (finished.count(ticket)) return true;
+        for (auto& k : classes) {
+            for (auto& r : k->queue) if (r.ticket == ticket) return true;
+            for (auto& kv : k->running) if (kv.second.ticket == ticket) return true;
+        }
+        return false;
+    }
+
+    // admit what fits, advance the class's active problems by one phase, hand
+    // out the finished ones
+    void iterate(Class& k) {
+        std::lock_guard<std::mutex> lk(k.be->lock());
+        k.be->set_stream(k.stream);
         {
             std::lock_guard<std::mutex> q(mu);
-            while (!queue.empty() && (max_active <= 0 || (int32_t)eng->active() < max_active) &&
-                   (eng->active() == 0 || eng->bytes_in_use() + queue.front().footprint <= budget)) {
-                Req r = queue.front();
+            while (admissible(k)) {
+                Req r = k.queue.front();
                 int st = 0;
-                const int64_t id = eng->add(r.pr, &st);
+                const int64_t id = k.eng->add(r.pr, &st);
                 if (id < 0) {
-                    if (eng->active() > 0) break;            // wait until memory frees up
-                    queue.pop_front();
-                    be->release(r.input);
+                    if (k.eng->active() > 0) break;            // wait until memory frees up
+                    k.queue.pop_front();
+                    k.be->release(r.input);
                     finished[r.ticket] = {GFECH_E_NOMEM, nullptr};
                     done.notify_all();
                     continue;
                 }
-                queue.pop_front();
-                running[id] = r;
+                k.queue.pop_front();
+                k.running[id] = r;
+                bytes_in_flight += r.footprint;
+                active++;
                 counters.admitted++;
             }
-            counters.peak_bytes_in_flight =
-                std::max<int64_t>(counters.peak_bytes_in_flight, (int64_t)eng->bytes_in_use());
-            counters.peak_active = std::max<int64_t>(counters.peak_active, (int64_t)eng->active());
+            counters.peak_bytes_in_flight = std::max<int64_t>(counters.peak_bytes_in_flight, (int64_t)bytes_in_flight);
+            counters.peak_active = std::max<int64_t>(counters.peak_active, active);
+            for (uint64_t t : k.cancels)
+                for (auto& kv : k.running)
+                    if (kv.second.ticket == t) k.eng->cancel(kv.first);
+            k.cancels.clear();
         }
-        {
-            std::lock_guard<std::mutex> q(mu);
-            for (uint64_t t : cancels)
-                for (auto& kv : running)
-                    if (kv.second.ticket == t) eng->cancel(kv.first);
-            cancels.clear();
-        }
-        if (eng->active()) eng->step();
-        std::vector<gfech::Engine::Done> fin = eng->take_done();
+        if (k.eng->active()) k.eng->step();
+        std::vector<gfech::Engine::Done> fin = k.eng->take_done();
         if (!fin.empty()) {
             std::lock_guard<std::mutex> q(mu);
             for (auto& d : fin) {
-                auto it = running.find(d.id);
-                if (it == running.end()) continue;
-                be->release(it->second.input);
+                auto it = k.running.find(d.id);
+                if (it == k.running.end()) continue;
+                k.be->release(it->second.input);
                 gfech_result* res = nullptr;
                 if (d.result) {
                     res = new gfech_result();
                     res->r = std::move(d.result);
                 }
                 finished[it->second.ticket] = {status_of(d.status), res};
-                running.erase(it);
+                bytes_in_flight -= it->second.footprint;
+                active--;
                 counters.finished++;
+                k.running.erase(it);
             }
             done.notify_all();
+            for (auto& o : classes) o->work.notify_all();     // memory freed: other classes may admit
         }
-        be->set_stream(nullptr);
-        return eng->active() > 0;
+        k.be->set_stream(nullptr);
     }
 
-    void loop() {
+    void loop(Class& k) {
         for (;;) {
             {
                 std::unique_lock<std::mutex> q(mu);
-                work.wait(q, [&] { return stop || !queue.empty() || !running.empty(); });
-                if (stop && running.empty()) break;
+                k.work.wait(q, [&] { return stop || admissible(k) || !k.running.empty(); });
+                if (stop && k.running.empty()) break;
             }
-            iterate();
+            iterate(k);
         }
     }
 };
@@ -787,20 +828,33 @@ struct gfech_server {
 gfech_status gfech_server_create(const gfech_server_cfg* cfg, gfech_server** out) {
     if (!out) return fail(GFECH_E_ARG, "out is NULL");
     *out = nullptr;
-    gfech_status st = GFECH_OK;
+    const int32_t nclass = cfg && cfg->size_classes > 0 ? cfg->size_classes : 3;
+    if (nclass > 3) return fail(GFECH_E_ARG, "at most 3 size classes");
+    // class limits on max(m, n): one block; one block column; the rest
+    static const int64_t kLimits[3] = {512, 2048, 0};
     std::unique_ptr<gfech_server> s(new gfech_server());
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        s->be = get_backend(&st);
-        if (!s->be) return st;
-        s->stream = s->be->create_stream();
-        s->submit_stream = s->be->create_stream();
-        s->eng.reset(new gfech::Engine(*s->be));
+    for (int32_t c = 0; c < nclass; ++c) {
+        std::unique_ptr<gfech_server::Class> k(new gfech_server::Class());
+        k->max_dim = c == nclass - 1 ? 0 : kLimits[c];
+        std::string err;
+        k->be = gfech::backend_acquire(&err);
+        if (!k->be) {
+            for (auto& o : s->classes) gfech::backend_release(o->be);
+            return fail(GFECH_E_DEVICE, err.empty() ? "no device backend" : err);
+        }
+        std::lock_guard<std::mutex> lk(k->be->lock());
+        k->stream = k->be->create_stream();
+        k->submit_stream = k->be->create_stream();
+        k->eng.reset(new gfech::Engine(*k->be));
+        s->classes.push_back(std::move(k));
     }
     s->budget = (cfg && cfg->hbm_budget_bytes > 0) ? (size_t)cfg->hbm_budget_bytes : ((size_t)200 << 30);
     s->max_active = cfg ? cfg->max_active : 0;
     gfech_server* raw = s.get();
-    s->worker = std::thread([raw] { raw->loop(); });
+    for (auto& k : s->classes) {
+        gfech_server::Class* kp = k.get();
+        k->worker = std::thread([raw, kp] { raw->loop(*kp); });
+    }
     *out = s.release();
     return GFECH_OK;
 }
@@ -818,59 +872,57 @@ gfech_status gfech_server_submit(gfech_server* s, const gfech_problem* prob, int
             for (int64_t j = 0; j < n; ++j)
                 if (prob->A[i * lda + j] >= p) return fail(GFECH_E_RANGE, "entry >= p");
     }
+    gfech_server::Class& k = s->class_of(m, n);
     gfech_server::Req r;
     r.pr.m = m;
     r.pr.n = n;
     r.pr.lda = std::max<int64_t>(n, 1);
     r.pr.p = (int32_t)p;
     choose_blocks(m, n, nullptr, r.pr.row_blocks, r.pr.col_blocks);
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        r.footprint = s->eng->footprint(r.pr);
-    }
+    r.footprint = k.eng->footprint(r.pr);    // sizes only: no device work
     if (r.footprint > s->budget) return fail(GFECH_E_TOO_BIG, "the problem alone exceeds the memory budget");
     {
         // the input is checked and copied on a stream of its own, complete on
         // return (the caller may reuse its buffer); nothing waits for the engine
-        std::lock_guard<std::mutex> lk(g_mu);
-        s->be->set_stream(s->submit_stream);
+        std::lock_guard<std::mutex> lk(k.be->lock());
+        k.be->set_stream(k.submit_stream);
         if (input_on_device && m > 0 && n > 0) {
-            const int64_t bad = s->be->count_out_of_range(prob->A, m, n, lda, (int32_t)p);
+            const int64_t bad = k.be->count_out_of_range(prob->A, m, n, lda, (int32_t)p);
             if (bad != 0) {
-                s->be->set_stream(nullptr);
+                k.be->set_stream(nullptr);
                 return fail(bad > 0 ? GFECH_E_RANGE : GFECH_E_DEVICE, bad > 0 ? "entry >= p" : "device error");
             }
         }
         // the request owns a packed device copy of its input
         if (m > 0 && n > 0) {
-            r.input = (uint8_t*)s->be->alloc((size_t)(m * n));
+            r.input = (uint8_t*)k.be->alloc((size_t)(m * n));
             if (!r.input) {
-                s->be->set_stream(nullptr);
+                k.be->set_stream(nullptr);
                 return fail(GFECH_E_NOMEM, "device allocation of the input failed");
             }
             if (input_on_device && lda == n) {
-                s->be->copy(r.input, prob->A, (size_t)(m * n));
+                k.be->copy(r.input, prob->A, (size_t)(m * n));
             } else if (input_on_device) {
-                for (int64_t i = 0; i < m; ++i) s->be->copy(r.input + i * n, prob->A + i * lda, (size_t)n);
+                for (int64_t i = 0; i < m; ++i) k.be->copy(r.input + i * n, prob->A + i * lda, (size_t)n);
             } else if (lda == n) {
-                s->be->upload(r.input, prob->A, (size_t)(m * n));
+                k.be->upload(r.input, prob->A, (size_t)(m * n));
             } else {
                 std::vector<uint8_t> tmp((size_t)(m * n));
                 for (int64_t i = 0; i < m; ++i) memcpy(tmp.data() + i * n, prob->A + i * lda, (size_t)n);
-                s->be->upload(r.input, tmp.data(), (size_t)(m * n));
+                k.be->upload(r.input, tmp.data(), (size_t)(m * n));
             }
-            s->be->sync_lane0();
+            k.be->sync_lane0();
         }
-        s->be->set_stream(nullptr);
+        k.be->set_stream(nullptr);
         r.pr.A = r.input;
     }
     {
         std::lock_guard<std::mutex> q(s->mu);
         r.ticket = s->next_ticket++;
         *ticket = r.ticket;
-        s->queue.push_back(r);
+        k.queue.push_back(r);
     }
-    s->work.notify_all();
+    k.work.notify_all();
     return GFECH_OK;
 }
 
@@ -885,9 +937,7 @@ gfech_status take_finished(gfech_server* s, uint64_t ticket, gfech_result** out,
         *known = true;
         return st == GFECH_OK ? GFECH_OK : fail(st, "request failed");
     }
-    *known = false;
-    for (auto& r : s->queue) if (r.ticket == ticket) *known = true;
-    for (auto& kv : s->running) if (kv.second.ticket == ticket) *known = true;
+    *known = s->known(ticket);
     return GFECH_OK;
 }
 }  // namespace
@@ -905,31 +955,30 @@ gfech_status gfech_server_poll(gfech_server* s, uint64_t ticket, gfech_result** 
 gfech_status gfech_server_cancel(gfech_server* s, uint64_t ticket) {
     if (!s) return fail(GFECH_E_ARG, "null argument");
     gfech_server::Req dropped;
+    gfech_server::Class* owner = nullptr;
     {
         std::lock_guard<std::mutex> q(s->mu);
-        bool known = s->finished.count(ticket) > 0;
-        for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
-            if (it->ticket != ticket) continue;
-            dropped = *it;
-            s->queue.erase(it);
-            s->finished[ticket] = {GFECH_E_CANCELLED, nullptr};
-            known = true;
-            break;
-        }
-        for (auto& kv : s->running)
-            if (kv.second.ticket == ticket) {
-                s->cancels.push_back(ticket);
-                known = true;
+        if (!s->known(ticket)) return fail(GFECH_E_ARG, "unknown ticket");
+        for (auto& k : s->classes) {
+            for (auto it = k->queue.begin(); it != k->queue.end(); ++it) {
+                if (it->ticket != ticket) continue;
+                dropped = *it;
+                owner = k.get();
+                k->queue.erase(it);
+                s->finished[ticket] = {GFECH_E_CANCELLED, nullptr};
+                break;
             }
-        if (!known) return fail(GFECH_E_ARG, "unknown ticket");
+            for (auto& kv : k->running)
+                if (kv.second.ticket == ticket) k->cancels.push_back(ticket);
+        }
     }
-    if (dropped.input) {
+    if (owner && dropped.input) {
         // its input was copied completely when it was submitted
-        std::lock_guard<std::mutex> lk(g_mu);
-        s->be->release(dropped.input);
+        std::lock_guard<std::mutex> lk(owner->be->lock());
+        owner->be->release(dropped.input);
     }
     s->done.notify_all();
-    s->work.notify_all();
+    for (auto& k : s->classes) k->work.notify_all();
     return GFECH_OK;
 }
 
@@ -955,26 +1004,39 @@ gfech_status gfech_server_wait(gfech_server* s, uint64_t ticket, gfech_result** 
 
 void gfech_server_destroy(gfech_server* s) {
     if (!s) return;
-    // queued requests are dropped, running ones finish (locks: g_mu before mu, never the reverse)
-    std::deque<gfech_server::Req> dropped;
+    // queued requests are dropped, running ones finish
+    std::vector<std::deque<gfech_server::Req>> dropped(s->classes.size());
     {
         std::lock_guard<std::mutex> q(s->mu);
         s->stop = true;
-        dropped.swap(s->queue);
+        for (size_t c = 0; c < s->classes.size(); ++c) dropped[c].swap(s->classes[c]->queue);
     }
-    if (!dropped.empty()) {
+    for (size_t c = 0; c < s->classes.size(); ++c) {
         // their inputs were copied completely when they were submitted
-        std::lock_guard<std::mutex> lk(g_mu);
-        for (auto& r : dropped) s->be->release(r.input);
+        std::lock_guard<std::mutex> lk(s->classes[c]->be->lock());
+        for (auto& r : dropped[c]) s->classes[c]->be->release(r.input);
     }
-    s->work.notify_all();
-    if (s->worker.joinable()) s->worker.join();
-    std::lock_guard<std::mutex> lk(g_mu);
-    for (auto& kv : s->finished) delete kv.second.second;
-    s->finished.clear();
-    s->eng.reset();
-    s->be->destroy_stream(s->stream);
-    s->be->destroy_stream(s->submit_stream);
+    for (auto& k : s->classes) k->work.notify_all();
+    for (auto& k : s->classes)
+        if (k->worker.joinable()) k->worker.join();
+    std::vector<gfech_result*> unclaimed;
+    {
+        std::lock_guard<std::mutex> q(s->mu);
+        for (auto& kv : s->finished) if (kv.second.second) unclaimed.push_back(kv.second.second);
+        s->finished.clear();
+    }
+    for (gfech_result* r : unclaimed) gfech_result_free(r);
+    for (auto& k : s->classes) {
+        {
+            std::lock_guard<std::mutex> lk(k->be->lock());
+            k->eng.reset();
+            k->be->destroy_stream(k->stream);
+            k->be->destroy_stream(k->submit_stream);
+        }
+        // the backend instance goes back to the pool (results of this server
+        // still refer to it)
+        gfech::backend_release(k->be);
+    }
     delete s;
 }
 

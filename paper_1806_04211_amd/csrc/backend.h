@@ -8,6 +8,7 @@
 #pragma once
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 namespace gfech {
@@ -115,6 +116,9 @@ constexpr size_t kFixedScratchBytes = (size_t)16 << 20;
 class Backend {
 public:
     virtual ~Backend() = default;
+    // Every use of an instance is serialised by its lock (its stream, lanes,
+    // marks and memory cache are per instance).
+    std::mutex& lock() { return mu_; }
     virtual const char* name() const = 0;
     // memory (alloc does not initialise; nullptr on failure)
     virtual void* alloc(size_t bytes) = 0;
@@ -175,6 +179,9 @@ public:
     };
     virtual void set_profile(int level) { (void)level; }   // 0 off, 1 every launch, 2 MAD launches only
     virtual Profile take_profile() { return Profile(); }
+
+private:
+    std::mutex mu_;
 };
 
 }  // namespace gfech

@@ -47,6 +47,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 
 namespace gfech {
@@ -982,8 +983,11 @@ private:
 // measurement aid: the shapes of a layer's launches can be replayed alone).
 FILE* g_trace = nullptr;
 int64_t g_trace_iter = 0, g_trace_launch = 0;
+std::mutex g_trace_mu;     // engines of several threads (a server's size classes) may trace
 
 void trace_gemm(const std::vector<GemmDesc>& ds) {
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    if (!g_trace) return;
     for (const GemmDesc& g : ds)
         fprintf(g_trace, "%lld %lld %d %d %d %d %d %lld %lld %lld %lld %d %p %p %p %p %p %p\n",
                 (long long)g_trace_iter, (long long)g_trace_launch, g.kind, g.M, g.N, g.K, g.p, (long long)g.lda,
@@ -1044,13 +1048,16 @@ struct Engine::Impl {
 
     Impl(Backend& b, const Engine* e) : be(b), owner(e) {
         const char* tr = getenv("GFECH_TRACE_MAD");
-        if (tr && tr[0] && !g_trace) {
-            g_trace = fopen(tr, "a");
-            g_trace_iter = g_trace_launch = 0;
-            owns_trace = g_trace != nullptr;
+        if (tr && tr[0]) {
+            std::lock_guard<std::mutex> lk(g_trace_mu);
+            if (!g_trace) {
+                g_trace = fopen(tr, "a");
+                g_trace_iter = g_trace_launch = 0;
+                owns_trace = g_trace != nullptr;
+            }
         }
         const char* gr = getenv("GFECH_CLEARUP_GROUP");
-        group_rank = gr ? std::max<int64_t>(1, atoll(gr)) : 2048;
+        group_rank = gr ? std::max<int64_t>(1, atoll(gr)) : 4096;
         counts = be.counts_buffer(kCountsCap);
         if (counts) holes.push_back({0, kCountsCap});
         hcounts.resize(kCountsCap);
@@ -1060,6 +1067,7 @@ struct Engine::Impl {
         for (auto& j : jobs) release(*j);
         if (counts) be.release_counts(counts);
         if (owns_trace) {
+            std::lock_guard<std::mutex> lk(g_trace_mu);
             fclose(g_trace);
             g_trace = nullptr;
         }
@@ -1085,7 +1093,7 @@ struct Engine::Impl {
     std::vector<std::pair<size_t, size_t>> holes;   // free ranges of the counts pool
     size_t counts_high = 0;
     std::vector<int32_t> hcounts;
-    int64_t group_rank = 2048;
+    int64_t group_rank = 4096;
 
     bool take_counts(size_t n, size_t* off) {
         n = std::max<size_t>(n, 1);
@@ -1260,7 +1268,10 @@ struct Engine::Impl {
     }
 
     size_t step() {
-        if (owns_trace) ++g_trace_iter;
+        if (owns_trace) {
+            std::lock_guard<std::mutex> lk(g_trace_mu);
+            ++g_trace_iter;
+        }
         if (be.error()) {
             fail_all(be.error());
             return 0;

@@ -2465,4 +2465,38 @@ Backend* backend_instance(std::string* err) {
     return be;
 }
 
+// Further instances for the server's size classes, kept in a pool: an
+// instance is never destroyed (results refer to the instance that made them),
+// a released one is handed out again.
+namespace {
+std::mutex g_pool_mu;
+std::vector<HipBackend*> g_pool;
+}  // namespace
+
+Backend* backend_acquire(std::string* err) {
+    if (!backend_instance(err)) return nullptr;          // the device checks, once
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        if (!g_pool.empty()) {
+            HipBackend* b = g_pool.back();
+            g_pool.pop_back();
+            return b;
+        }
+    }
+    HipBackend* b = new HipBackend();
+    std::string e;
+    if (!b->init(&e)) {
+        delete b;
+        if (err) *err = e;
+        return nullptr;
+    }
+    return b;
+}
+
+void backend_release(Backend* be) {
+    if (!be) return;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_pool.push_back(static_cast<HipBackend*>(be));
+}
+
 }  // namespace gfech

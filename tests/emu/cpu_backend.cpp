@@ -518,6 +518,13 @@ CpuBackend& instance() {
     return be;
 }
 
+// the extra instances (server size classes), pooled and never destroyed;
+// the test hooks below apply to every instance
+std::mutex g_pool_mu;
+std::vector<CpuBackend*> g_all, g_pool;
+uint64_t g_fuzz_seed = 0;
+int g_drop_lane = -1, g_drop_src = -1;
+
 }  // namespace
 
 Backend* backend_instance(std::string* err) {
@@ -525,11 +532,44 @@ Backend* backend_instance(std::string* err) {
     return &instance();
 }
 
+Backend* backend_acquire(std::string* err) {
+    (void)err;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (!g_pool.empty()) {
+        CpuBackend* b = g_pool.back();
+        g_pool.pop_back();
+        return b;
+    }
+    CpuBackend* b = new CpuBackend();
+    // each instance draws its own interleaving from the seed
+    b->set_fuzz(g_fuzz_seed ? g_fuzz_seed + 7919 * (g_all.size() + 1) : 0);
+    b->drop_waits(g_drop_lane, g_drop_src);
+    g_all.push_back(b);
+    return b;
+}
+
+void backend_release(Backend* be) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_pool.push_back(static_cast<CpuBackend*>(be));
+}
+
 }  // namespace gfech
 
 // Test hook of the emulator build only: seed != 0 switches the randomized
-// interleaving of all four lanes on (0 switches it off).
-extern "C" void gfech_emu_set_fuzz(uint64_t seed) { gfech::instance().set_fuzz(seed); }
+// interleaving of all four lanes on (0 switches it off), for every instance.
+extern "C" void gfech_emu_set_fuzz(uint64_t seed) {
+    std::lock_guard<std::mutex> lk(gfech::g_pool_mu);
+    gfech::g_fuzz_seed = seed;
+    gfech::instance().set_fuzz(seed);
+    for (size_t i = 0; i < gfech::g_all.size(); ++i)
+        gfech::g_all[i]->set_fuzz(seed ? seed + 7919 * (i + 1) : 0);
+}
 // Test hook: ignore every wait of `lane` for work of lane `src` (-1: none), a
 // planted ordering mistake that the randomized interleaving must expose.
-extern "C" void gfech_emu_drop_waits(int lane, int src) { gfech::instance().drop_waits(lane, src); }
+extern "C" void gfech_emu_drop_waits(int lane, int src) {
+    std::lock_guard<std::mutex> lk(gfech::g_pool_mu);
+    gfech::g_drop_lane = lane;
+    gfech::g_drop_src = src;
+    gfech::instance().drop_waits(lane, src);
+    for (auto* b : gfech::g_all) b->drop_waits(lane, src);
+}

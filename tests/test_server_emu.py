@@ -129,3 +129,24 @@ def test_watchdog_cancels_and_library_recovers(lib):
     assert ex.value.status == 7
     B = synth.deficient(4, 2, 60, 70, 7)
     compare(lib.echelonise(B, 7, block_rows=8, block_cols=8, timeout_ms=60000).outputs(), oracle.echelonize(B, 7))
+
+
+@pytest.mark.parametrize("classes", [1, 2, 3])
+def test_size_classes_give_the_same_results(lib, classes):
+    """One engine for every size, or one per size class (each with its own
+    backend instance and worker thread): the same results, equal to the
+    oracle's."""
+    rng = np.random.default_rng(classes)
+    reqs = []
+    for t in range(12):
+        n = int(rng.choice([20, 300, 700, 2100]))
+        m = max(1, int(round(n * rng.uniform(0.75, 1.25))))
+        p = int(rng.choice([2, 3, 251]))
+        reqs.append((synth.uniform(classes, t, m, n if n < 2000 else 120, p), p))
+    srv = lib.server(size_classes=classes)
+    tickets = [srv.submit(A, p) for A, p in reqs]
+    for (A, p), t in zip(reqs, tickets):
+        compare(srv.wait(t).outputs(), oracle.echelonize(A, p), f"{A.shape} p={p}")
+    st = srv.stats()
+    assert st["admitted"] == st["finished"] == len(reqs)
+    srv.close()
