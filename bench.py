@@ -242,6 +242,46 @@ def traced_isolated(torch, lib, solve):
     return iso
 
 
+def summarize_replay_profile(prof_dir, pmc_dir, copy_dir, reps=10):
+    """Figures of a `rocprofv3` run of `bench.py --replay-only` (kernel trace in
+    prof_dir, FETCH_SIZE / WRITE_SIZE in pmc_dir, the copy calibration in
+    copy_dir, CSV output).  The replays are the last 2 (reps + 1) MAD
+    dispatches: the UpdateRow layer launch (one warm-up, `reps` timed), then
+    the largest ClearUp launch the same way; the warm-ups are dropped."""
+    import csv
+    import glob
+
+    def rows(d, suffix):
+        path = glob.glob(os.path.join(d, "*" + suffix))[0]
+        return list(csv.DictReader(open(path)))
+
+    def mad(rs):
+        return [r for r in rs if "k_gemm_modp" in r["Kernel_Name"]]
+
+    trace = mad(rows(prof_dir, "kernel_trace.csv"))[-2 * (reps + 1):]
+    fetch = mad(rows(pmc_dir, "fetch_counter_collection.csv") if glob.glob(os.path.join(pmc_dir, "fetch*")) else [])
+    write = mad(rows(pmc_dir, "write_counter_collection.csv") if glob.glob(os.path.join(pmc_dir, "write*")) else [])
+    cf = [float(r["Counter_Value"]) for r in rows(copy_dir, "fetch_counter_collection.csv") if "neg" in r["Kernel_Name"]]
+    cw = [float(r["Counter_Value"]) for r in rows(copy_dir, "write_counter_collection.csv") if "neg" in r["Kernel_Name"]]
+    copy_kib = 1024 * 1024        # bench.py --copy-mib 1024: reads and writes 1 GiB per dispatch
+    f_scale = copy_kib / (sum(cf) / len(cf))
+    w_scale = copy_kib / (sum(cw) / len(cw))
+    out = {"fetch_scale": f_scale, "write_scale": w_scale}
+    for name, lo in (("updaterow_layer", 0), ("clearup_largest", reps + 1)):
+        sel = slice(lo + 1, lo + reps + 1)
+        us = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in trace[sel]]
+        ent = {"dispatches": len(us), "grid": int(trace[lo].get("Grid_Size_X") or trace[lo].get("Grid_Size") or 0),
+               "mean_us": sum(us) / len(us)}
+        if fetch and write:
+            fk = [float(r["Counter_Value"]) for r in fetch[-2 * (reps + 1):][sel]]
+            wk = [float(r["Counter_Value"]) for r in write[-2 * (reps + 1):][sel]]
+            ent["fetch_kib"] = sum(fk) / len(fk)
+            ent["write_kib"] = sum(wk) / len(wk)
+            ent["traffic_bytes"] = 1024 * (ent["fetch_kib"] * f_scale + ent["write_kib"] * w_scale)
+        out[name] = ent
+    return out
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     return xs[min(len(xs) - 1, int(round(q * (len(xs) - 1))))] if xs else 0.0
@@ -466,6 +506,10 @@ def main():
     ap.add_argument("--block-rows", type=int, default=0, help="block rows a_i (overrides --block)")
     ap.add_argument("--block-cols", type=int, default=0, help="block columns b_j (overrides --block)")
     ap.add_argument("--cpu-sample", type=int, default=2000, help="oracle sample size (0 = skip)")
+    ap.add_argument("--summarize-profile", nargs=3, metavar=("TRACE_DIR", "PMC_DIR", "COPY_DIR"),
+                    help="print the figures of a rocprofv3 run of --replay-only (no GPU needed)")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the block-size tuner and write its table to gpurun_out/blocking.json")
     ap.add_argument("--replay-only", action="store_true",
                     help="only a traced solve and the isolated replays of its launches (for kernel profiles)")
     ap.add_argument("--no-variants", action="store_true",
@@ -495,6 +539,9 @@ def main():
               "single MI355X and has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
 
+    if args.summarize_profile:
+        print(json.dumps(summarize_replay_profile(*args.summarize_profile), indent=1))
+        return
     if args.hw_queues > 0:
         os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.hw_queues, 32))     # before the runtime starts
     import torch
@@ -510,7 +557,17 @@ def main():
         return
 
     import paper_1806_04211_amd as gf
+    from paper_1806_04211_amd import tune
     from synth import torch_gen
+
+    if args.tune:
+        # the block-size tuner; the table goes to gpurun_out/ (copied into the package by hand)
+        table = tune.tune(gf.library(), torch, log=log)
+        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+        tune.save(table, os.path.join(ROOT, "gpurun_out", "blocking.json"))
+        print(json.dumps(table), flush=True)
+        return
+    tuned = tune.install_default(gf.library())
 
     n, k, p = args.n, args.inner, args.p
     dev = torch.device("cuda:0")
@@ -601,7 +658,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{n}x{n} over GF({p}), B*C mod {p} with inner dimension {k}, seed 0",
                    "m": n, "n": n, "p": p, "rank": rank, "block_rows": st["block_rows"],
-                   "block_cols": st["block_cols"], "parallelism": "single GPU"},
+                   "block_cols": st["block_cols"],
+                   "blocking": "tuned table" if tuned and not (kw["block_rows"] or kw["block_cols"]) else
+                               "explicit" if (kw["block_rows"] or kw["block_cols"]) else "built-in",
+                   "parallelism": "single GPU"},
         "solves_per_s": 1.0 / mean,
         "latency_ms": {"p50": pct(0.5) * 1e3, "p99": pct(0.99) * 1e3},
         "work": {"mac_total": mac_mad + st["mac_ech"], "mac_mad": mac_mad, "mac_ech": st["mac_ech"],

@@ -81,6 +81,20 @@ typedef struct gfech_opts {
     int32_t reserved[4];
 } gfech_opts;
 
+/* Block sizes (Section 3.1) chosen by measurement: when a call's options
+ * leave block_rows and block_cols at 0, the first entry with
+ * max(m, n) <= max_dim gives them (0 in one of them: the same as the other);
+ * problems above every entry, or with no table installed, get the built-in
+ * choice (one block up to 512 x 512, else blocks of 256 rows and 2048
+ * columns).  Block sizes never change results.  gfech_set_blocking copies
+ * the table (entries with strictly increasing max_dim) and replaces the
+ * previous one; count 0 removes it.  The package's tuner writes such tables. */
+typedef struct gfech_blocking {
+    int64_t max_dim;
+    int64_t block_rows, block_cols;
+} gfech_blocking;
+gfech_status gfech_set_blocking(const gfech_blocking* table, int64_t count);
+
 /* Opaque, library-owned result; immutable once returned.  Its matrices stay
  * in device memory (HBM) until copied out by the getters below. */
 typedef struct gfech_result gfech_result;

@@ -47,6 +47,10 @@ class ServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", c_i64), ("max_active", c_i32), ("size_classes", c_i32), ("reserved", c_i32 * 4)]
 
 
+class Blocking(ctypes.Structure):
+    _fields_ = [("max_dim", c_i64), ("block_rows", c_i64), ("block_cols", c_i64)]
+
+
 class ServerStats(ctypes.Structure):
     _fields_ = [("peak_bytes_in_flight", c_i64), ("peak_active", c_i64), ("admitted", c_i64), ("finished", c_i64)]
 
@@ -61,6 +65,7 @@ class MadDesc(ctypes.Structure):
 SIGNATURES = {
     "gfech_echelonise_u8": (ctypes.c_int, [vp, c_i64, c_i64, c_i64, c_u32, vp, ctypes.POINTER(vp)]),
     "gfech_echelonise_u8_dev": (ctypes.c_int, [vp, c_i64, c_i64, c_i64, c_u32, vp, vp, ctypes.POINTER(vp)]),
+    "gfech_set_blocking": (ctypes.c_int, [vp, c_i64]),
     "gfech_echelonise_gf2": (ctypes.c_int, [vp, c_i64, c_i64, c_i64, vp, ctypes.POINTER(vp)]),
     "gfech_echelonise_gf2_dev": (ctypes.c_int, [vp, c_i64, c_i64, c_i64, vp, vp, ctypes.POINTER(vp)]),
     "gfech_echelonise_batch": (ctypes.c_int, [c_i64, vp, c_i32, vp, vp, ctypes.POINTER(vp), vp]),

@@ -48,17 +48,31 @@ bool is_prime(uint32_t p) {
     return true;
 }
 
-// Blocking (Section 3.1).  Up to 512 x 512 the whole matrix is one block
-// (one ECH job).  Larger matrices get blocks of 256 rows and 2048 columns:
-// the ECH jobs on the critical path stay short (their cost grows with the
-// rows of a block, and a ClearDown whose rows all become pivots in the
-// leading columns finishes the remaining columns with one product), while
-// UpdateRow's products get an inner dimension of up to 2048 pivots per
-// block column, where the MFMA kernel runs several times faster than at 512.
+// Blocking (Section 3.1).  An installed table of tuned block sizes
+// (gfech_set_blocking) takes precedence; without one, up to 512 x 512 the
+// whole matrix is one block (one ECH job), and larger matrices get blocks of
+// 256 rows and 2048 columns: the ECH jobs on the critical path stay short
+// (their cost grows with the rows of a block, and a ClearDown whose rows all
+// become pivots in the leading columns finishes the remaining columns with
+// one product), while UpdateRow's products get an inner dimension of up to
+// 2048 pivots per block column, where the MFMA kernel runs several times
+// faster than at 512.
+std::mutex g_table_mu;
+std::vector<gfech_blocking> g_table;
+
 void choose_blocks(int64_t m, int64_t n, const gfech_opts* o, std::vector<int32_t>& a, std::vector<int32_t>& b) {
     const int64_t single = 512;
     int64_t br = (o && o->block_rows > 0) ? o->block_rows : 0;
     int64_t bc = (o && o->block_cols > 0) ? o->block_cols : 0;
+    if (!br && !bc) {
+        std::lock_guard<std::mutex> lk(g_table_mu);
+        for (const gfech_blocking& t : g_table)
+            if (std::max(m, n) <= t.max_dim) {
+                br = t.block_rows;
+                bc = t.block_cols;
+                break;
+            }
+    }
     if (!br && !bc) {
         if (m <= single && n <= single) {
             br = m;
@@ -325,6 +339,19 @@ gfech_status gfech_echelonise_u8_dev(const uint8_t* A_dev, int64_t m, int64_t n,
     return echelonise_impl(A_dev, true, m, n, lda, p, opts, stream, out);
 }
 
+gfech_status gfech_set_blocking(const gfech_blocking* table, int64_t count) {
+    if (count < 0 || (count > 0 && !table)) return fail(GFECH_E_ARG, "bad blocking table");
+    for (int64_t t = 0; t < count; ++t) {
+        if (table[t].max_dim <= 0 || table[t].block_rows < 0 || table[t].block_cols < 0)
+            return fail(GFECH_E_ARG, "bad blocking table entry");
+        if (t > 0 && table[t].max_dim <= table[t - 1].max_dim)
+            return fail(GFECH_E_ARG, "blocking table entries must have increasing max_dim");
+    }
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    g_table.assign(table, table + count);
+    return GFECH_OK;
+}
+
 gfech_status gfech_echelonise_gf2(const uint64_t* A, int64_t m, int64_t n, int64_t ldw, const gfech_opts* opts,
                                   gfech_result** out) {
     return echelonise_gf2_impl(A, false, m, n, ldw, opts, nullptr, out);
@@ -555,11 +582,8 @@ gfech_status gfech_get_stats(const gfech_result* res, gfech_stats* s) {
 }
 
 void gfech_result_free(gfech_result* res) {
-    if (!res) return;
-    if (res->r && res->r->be) {
-        std::lock_guard<std::mutex> lk(res->r->be->lock());
-        res->r.reset();
-    }
+    // the result's work is complete; releasing its memory takes only the
+    // backend's memory-cache lock, so this never waits for an engine iteration
     delete res;
 }
 
@@ -703,20 +727,22 @@ gfech_status gfech_ech_dev_noalloc(const uint8_t* H, int64_t rows, int64_t cols,
 // batching), and the phases of a large problem never hold back the small
 // ones, whose iterations are short and whose work runs on other streams.
 // Admission is first come first served within a class, against one
-// device-memory budget shared by the classes.  Lock order: a class backend's
-// lock before the server's mu, never the reverse.
+// device-memory budget shared by the classes.  Inputs are copied by a
+// backend instance of their own (its lock is held only for the copy or a
+// release), so a submission never waits for an engine iteration.  Lock
+// order: a class backend's lock, then the input backend's lock, then the
+// server's mu; never the reverse.
 struct gfech_server {
     struct Req {
         uint64_t ticket = 0;
         gfech::Problem pr;
-        uint8_t* input = nullptr;     // device copy on the class's backend, owned until the request finishes
+        uint8_t* input = nullptr;     // device copy (input backend), owned until the request finishes
         size_t footprint = 0;
     };
     struct Class {
         int64_t max_dim = 0;                  // largest max(m, n) of the class; 0 = no limit
         gfech::Backend* be = nullptr;
         void* stream = nullptr;               // lane 0 of the class's engine
-        void* submit_stream = nullptr;        // the copies of submitted inputs
         std::unique_ptr<gfech::Engine> eng;   // used with be->lock() held
         std::deque<Req> queue;                // under mu
         std::map<int64_t, Req> running;       // engine id -> request, under mu
@@ -725,6 +751,8 @@ struct gfech_server {
         std::thread worker;
     };
     std::vector<std::unique_ptr<Class>> classes;
+    gfech::Backend* in_be = nullptr;  // the input copies: allocated, copied and released with its lock
+    void* in_stream = nullptr;
     size_t budget = 0;
     int32_t max_active = 0;
     std::mutex mu;                    // everything marked "under mu" and the fields below
@@ -756,11 +784,20 @@ struct gfech_server {
         return false;
     }
 
+    // the engine's work on the input is complete (it synchronises when a
+    // problem finishes or fails)
+    void release_input(uint8_t* input) {
+        if (!input) return;
+        std::lock_guard<std::mutex> lk(in_be->lock());
+        in_be->release(input);
+    }
+
     // admit what fits, advance the class's active problems by one phase, hand
     // out the finished ones
     void iterate(Class& k) {
         std::lock_guard<std::mutex> lk(k.be->lock());
         k.be->set_stream(k.stream);
+        std::vector<uint8_t*> spent;          // inputs to release (after mu is released)
         {
             std::lock_guard<std::mutex> q(mu);
             while (admissible(k)) {
@@ -770,7 +807,7 @@ struct gfech_server {
                 if (id < 0) {
                     if (k.eng->active() > 0) break;            // wait until memory frees up
                     k.queue.pop_front();
-                    k.be->release(r.input);
+                    spent.push_back(r.input);
                     finished[r.ticket] = {GFECH_E_NOMEM, nullptr};
                     done.notify_all();
                     continue;
@@ -788,6 +825,8 @@ struct gfech_server {
                     if (kv.second.ticket == t) k.eng->cancel(kv.first);
             k.cancels.clear();
         }
+        for (uint8_t* in : spent) release_input(in);
+        spent.clear();
         if (k.eng->active()) k.eng->step();
         std::vector<gfech::Engine::Done> fin = k.eng->take_done();
         if (!fin.empty()) {
@@ -795,7 +834,7 @@ struct gfech_server {
             for (auto& d : fin) {
                 auto it = k.running.find(d.id);
                 if (it == k.running.end()) continue;
-                k.be->release(it->second.input);
+                spent.push_back(it->second.input);
                 gfech_result* res = nullptr;
                 if (d.result) {
                     res = new gfech_result();
@@ -810,6 +849,7 @@ struct gfech_server {
             done.notify_all();
             for (auto& o : classes) o->work.notify_all();     // memory freed: other classes may admit
         }
+        for (uint8_t* in : spent) release_input(in);
         k.be->set_stream(nullptr);
     }
 
@@ -833,6 +873,13 @@ gfech_status gfech_server_create(const gfech_server_cfg* cfg, gfech_server** out
     // class limits on max(m, n): one block; one block column; the rest
     static const int64_t kLimits[3] = {512, 2048, 0};
     std::unique_ptr<gfech_server> s(new gfech_server());
+    {
+        std::string err;
+        s->in_be = gfech::backend_acquire(&err);
+        if (!s->in_be) return fail(GFECH_E_DEVICE, err.empty() ? "no device backend" : err);
+        std::lock_guard<std::mutex> lk(s->in_be->lock());
+        s->in_stream = s->in_be->create_stream();
+    }
     for (int32_t c = 0; c < nclass; ++c) {
         std::unique_ptr<gfech_server::Class> k(new gfech_server::Class());
         k->max_dim = c == nclass - 1 ? 0 : kLimits[c];
@@ -840,11 +887,11 @@ gfech_status gfech_server_create(const gfech_server_cfg* cfg, gfech_server** out
         k->be = gfech::backend_acquire(&err);
         if (!k->be) {
             for (auto& o : s->classes) gfech::backend_release(o->be);
+            gfech::backend_release(s->in_be);
             return fail(GFECH_E_DEVICE, err.empty() ? "no device backend" : err);
         }
         std::lock_guard<std::mutex> lk(k->be->lock());
         k->stream = k->be->create_stream();
-        k->submit_stream = k->be->create_stream();
         k->eng.reset(new gfech::Engine(*k->be));
         s->classes.push_back(std::move(k));
     }
@@ -882,38 +929,40 @@ gfech_status gfech_server_submit(gfech_server* s, const gfech_problem* prob, int
     r.footprint = k.eng->footprint(r.pr);    // sizes only: no device work
     if (r.footprint > s->budget) return fail(GFECH_E_TOO_BIG, "the problem alone exceeds the memory budget");
     {
-        // the input is checked and copied on a stream of its own, complete on
-        // return (the caller may reuse its buffer); nothing waits for the engine
-        std::lock_guard<std::mutex> lk(k.be->lock());
-        k.be->set_stream(k.submit_stream);
+        // the input is checked and copied by the input backend on its stream,
+        // complete on return (the caller may reuse its buffer); nothing waits
+        // for an engine
+        gfech::Backend* be = s->in_be;
+        std::lock_guard<std::mutex> lk(be->lock());
+        be->set_stream(s->in_stream);
         if (input_on_device && m > 0 && n > 0) {
-            const int64_t bad = k.be->count_out_of_range(prob->A, m, n, lda, (int32_t)p);
+            const int64_t bad = be->count_out_of_range(prob->A, m, n, lda, (int32_t)p);
             if (bad != 0) {
-                k.be->set_stream(nullptr);
+                be->set_stream(nullptr);
                 return fail(bad > 0 ? GFECH_E_RANGE : GFECH_E_DEVICE, bad > 0 ? "entry >= p" : "device error");
             }
         }
         // the request owns a packed device copy of its input
         if (m > 0 && n > 0) {
-            r.input = (uint8_t*)k.be->alloc((size_t)(m * n));
+            r.input = (uint8_t*)be->alloc((size_t)(m * n));
             if (!r.input) {
-                k.be->set_stream(nullptr);
+                be->set_stream(nullptr);
                 return fail(GFECH_E_NOMEM, "device allocation of the input failed");
             }
             if (input_on_device && lda == n) {
-                k.be->copy(r.input, prob->A, (size_t)(m * n));
+                be->copy(r.input, prob->A, (size_t)(m * n));
             } else if (input_on_device) {
-                for (int64_t i = 0; i < m; ++i) k.be->copy(r.input + i * n, prob->A + i * lda, (size_t)n);
+                for (int64_t i = 0; i < m; ++i) be->copy(r.input + i * n, prob->A + i * lda, (size_t)n);
             } else if (lda == n) {
-                k.be->upload(r.input, prob->A, (size_t)(m * n));
+                be->upload(r.input, prob->A, (size_t)(m * n));
             } else {
                 std::vector<uint8_t> tmp((size_t)(m * n));
                 for (int64_t i = 0; i < m; ++i) memcpy(tmp.data() + i * n, prob->A + i * lda, (size_t)n);
-                k.be->upload(r.input, tmp.data(), (size_t)(m * n));
+                be->upload(r.input, tmp.data(), (size_t)(m * n));
             }
-            k.be->sync_lane0();
+            be->sync_lane0();
         }
-        k.be->set_stream(nullptr);
+        be->set_stream(nullptr);
         r.pr.A = r.input;
     }
     {
@@ -955,7 +1004,6 @@ gfech_status gfech_server_poll(gfech_server* s, uint64_t ticket, gfech_result** 
 gfech_status gfech_server_cancel(gfech_server* s, uint64_t ticket) {
     if (!s) return fail(GFECH_E_ARG, "null argument");
     gfech_server::Req dropped;
-    gfech_server::Class* owner = nullptr;
     {
         std::lock_guard<std::mutex> q(s->mu);
         if (!s->known(ticket)) return fail(GFECH_E_ARG, "unknown ticket");
@@ -963,7 +1011,6 @@ gfech_status gfech_server_cancel(gfech_server* s, uint64_t ticket) {
             for (auto it = k->queue.begin(); it != k->queue.end(); ++it) {
                 if (it->ticket != ticket) continue;
                 dropped = *it;
-                owner = k.get();
                 k->queue.erase(it);
                 s->finished[ticket] = {GFECH_E_CANCELLED, nullptr};
                 break;
@@ -972,11 +1019,8 @@ gfech_status gfech_server_cancel(gfech_server* s, uint64_t ticket) {
                 if (kv.second.ticket == ticket) k->cancels.push_back(ticket);
         }
     }
-    if (owner && dropped.input) {
-        // its input was copied completely when it was submitted
-        std::lock_guard<std::mutex> lk(owner->be->lock());
-        owner->be->release(dropped.input);
-    }
+    // its input was copied completely when it was submitted
+    s->release_input(dropped.input);
     s->done.notify_all();
     for (auto& k : s->classes) k->work.notify_all();
     return GFECH_OK;
@@ -1011,11 +1055,9 @@ void gfech_server_destroy(gfech_server* s) {
         s->stop = true;
         for (size_t c = 0; c < s->classes.size(); ++c) dropped[c].swap(s->classes[c]->queue);
     }
-    for (size_t c = 0; c < s->classes.size(); ++c) {
-        // their inputs were copied completely when they were submitted
-        std::lock_guard<std::mutex> lk(s->classes[c]->be->lock());
-        for (auto& r : dropped[c]) s->classes[c]->be->release(r.input);
-    }
+    // their inputs were copied completely when they were submitted
+    for (auto& q : dropped)
+        for (auto& r : q) s->release_input(r.input);
     for (auto& k : s->classes) k->work.notify_all();
     for (auto& k : s->classes)
         if (k->worker.joinable()) k->worker.join();
@@ -1031,12 +1073,16 @@ void gfech_server_destroy(gfech_server* s) {
             std::lock_guard<std::mutex> lk(k->be->lock());
             k->eng.reset();
             k->be->destroy_stream(k->stream);
-            k->be->destroy_stream(k->submit_stream);
         }
         // the backend instance goes back to the pool (results of this server
         // still refer to it)
         gfech::backend_release(k->be);
     }
+    {
+        std::lock_guard<std::mutex> lk(s->in_be->lock());
+        s->in_be->destroy_stream(s->in_stream);
+    }
+    gfech::backend_release(s->in_be);
     delete s;
 }
 

@@ -2021,7 +2021,10 @@ public:
 
     const char* name() const override { return "hip-gfx950"; }
 
+    // alloc and release may run outside the instance's lock (a result freed by
+    // another thread); the memory cache has a lock of its own
     void* alloc(size_t bytes) override {
+        std::lock_guard<std::mutex> lk(cache_mu_);
         void* p = nullptr;
         size_t want = bytes + kPad;
         auto it = free_.lower_bound(want);
@@ -2044,6 +2047,7 @@ public:
     }
     void release(void* p) override {
         if (!p) return;
+        std::lock_guard<std::mutex> lk(cache_mu_);
         auto it = sizes_.find(p);
         if (it == sizes_.end()) return;
         free_.insert({it->second, p});
@@ -2443,6 +2447,7 @@ private:
     int prof_ = 0;
     std::vector<Ev> evs_;
     std::vector<hipEvent_t> pool_;
+    std::mutex cache_mu_;               // sizes_ and free_
     std::map<void*, size_t> sizes_;
     std::multimap<size_t, void*> free_;
 };

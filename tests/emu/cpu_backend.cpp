@@ -13,6 +13,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -29,13 +30,18 @@ public:
         void* p = malloc(bytes ? bytes : 1);
         if (p) {
             memset(p, 0xA5, bytes ? bytes : 1);
-            allocs_[(uintptr_t)p] = bytes;
+            std::lock_guard<std::mutex> lk(allocs_mu());
+            allocs()[(uintptr_t)p] = bytes;
         }
         return p;
     }
     void release(void* p) override {
         if (!p) return;
-        allocs_.erase((uintptr_t)p);
+        {
+            std::lock_guard<std::mutex> lk(allocs_mu());
+            allocs().erase((uintptr_t)p);
+        }
+        std::lock_guard<std::mutex> lk(quarantine_mu_);
         if (fuzz_) quarantine_.push_back(p);
         else free(p);
     }
@@ -149,6 +155,7 @@ public:
             drain(2, q_[2].size());
             drain(3, q_[3].size());
         }
+        std::lock_guard<std::mutex> lk(quarantine_mu_);
         for (void* p : quarantine_) free(p);
         quarantine_.clear();
     }
@@ -167,10 +174,13 @@ public:
     bool chk(const void* p, size_t bytes, const char* what) {
         if (bytes == 0) return true;
         uintptr_t a = (uintptr_t)p;
-        auto it = allocs_.upper_bound(a);
-        if (it != allocs_.begin()) {
-            --it;
-            if (a >= it->first && a + bytes <= it->first + it->second) return true;
+        {
+            std::lock_guard<std::mutex> lk(allocs_mu());
+            auto it = allocs().upper_bound(a);
+            if (it != allocs().begin()) {
+                --it;
+                if (a >= it->first && a + bytes <= it->first + it->second) return true;
+            }
         }
         if (!err_) fprintf(stderr, "emulator: out-of-bounds access in %s (%zu bytes at %p)\n", what, bytes, p);
         err_ = 6;
@@ -375,7 +385,16 @@ private:
         int wait_lane = -1;
         size_t wait_upto = 0;
     };
-    std::map<uintptr_t, size_t> allocs_;
+    // live allocations of every instance (device memory is one address space:
+    // a server's instances use each other's buffers)
+    static std::map<uintptr_t, size_t>& allocs() {
+        static std::map<uintptr_t, size_t> m;
+        return m;
+    }
+    static std::mutex& allocs_mu() {
+        static std::mutex mu;
+        return mu;
+    }
     uint8_t* fixed_ = nullptr;
     int err_ = 0;
     int lane_ = 0;
@@ -386,6 +405,7 @@ private:
     std::vector<Job> q_[4];
     size_t done_[4] = {0, 0, 0, 0};
     std::vector<void*> quarantine_;
+    std::mutex quarantine_mu_;      // release() may run on another thread (a result freed there)
     uint64_t steps_ = 0;
     uint32_t weight_[4] = {1, 1, 1, 1};
 

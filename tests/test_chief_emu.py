@@ -379,3 +379,33 @@ def test_random_interleavings_with_a_cancelled_neighbour(lib, fuzz, seed):
         except GfechError as e:
             assert t == 1 and e.status == 7
     srv.close()
+
+
+def test_blocking_table_sets_default_blocks(lib):
+    """An installed blocking table gives the block sizes of calls that leave
+    them to the library (first entry covering max(m, n)); explicit options
+    still win; results never change; count 0 removes the table."""
+    from paper_1806_04211_amd import tune
+    from paper_1806_04211_amd.api import GfechError
+    A = synth.deficient(2, 8, 40, 30, 5)
+    e = oracle.echelonize(A, 5)
+    table = {"entries": [{"max_dim": 20, "block_rows": 3, "block_cols": 4},
+                         {"max_dim": 64, "block_rows": 8, "block_cols": 16}]}
+    try:
+        tune.install(lib, table)
+        r = lib.echelonise(A, 5)
+        st = r.stats()
+        assert (st["block_rows"], st["block_cols"]) == (5, 2)      # 40 rows / 8, 30 columns / 16
+        compare(r.outputs(), e)
+        st = lib.echelonise(A, 5, block_rows=10, block_cols=10).stats()
+        assert (st["block_rows"], st["block_cols"]) == (4, 3)
+        B = synth.uniform(2, 9, 12, 18, 5)
+        st = lib.echelonise(B, 5).stats()
+        assert (st["block_rows"], st["block_cols"]) == (4, 5)      # 12 / 3, 18 / 4
+        with pytest.raises(GfechError):
+            tune.install(lib, {"entries": [{"max_dim": 64, "block_rows": 8, "block_cols": 8},
+                                           {"max_dim": 32, "block_rows": 8, "block_cols": 8}]})
+    finally:
+        lib.lib.gfech_set_blocking(None, 0)
+    st = lib.echelonise(A, 5).stats()
+    assert (st["block_rows"], st["block_cols"]) == (1, 1)           # built-in: one block up to 512
