@@ -494,6 +494,80 @@ def run_serve(torch, args):
     }), flush=True)
 
 
+def run_gf2(torch, args):
+    """The largest single instance: n x n over GF(2), packed in 64-bit words on
+    the device (rows 0 .. n - 1001 i.i.d. Bernoulli(0.5) from seed 4, the last
+    1000 rows sums of 64 distinct earlier rows), through gfech_echelonise_gf2_dev.
+    The solve's result is checked on the host: rank n - 1000 and the first
+    n - 1000 rows selected (pinned by the construction), and Freivalds on Eq. (2)."""
+    import numpy as np
+
+    import paper_1806_04211_amd as gf
+    from paper_1806_04211_amd import tune
+    from synth import torch_gen
+    lib = gf.library()
+    tuned = tune.install_default(lib)
+    n, d = args.gf2_n, 1000
+    words = (n + 63) // 64
+    t0 = time.perf_counter()
+    W = torch_gen.gf2_deficient_packed(4, n, n, d)
+    torch.cuda.synchronize()
+    log(f"{n}x{n} GF(2) packed input ({W.numel() * 8 / 2**30:.1f} GiB) ready in {time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.current_stream()
+
+    def solve(variant=0):
+        return lib.echelonise_gf2_dev(W.data_ptr(), n, n, words, stream=stream.cuda_stream, variant=variant)
+
+    for w in range(args.warmup):
+        t1 = time.perf_counter()
+        r = solve()
+        log(f"warmup {w}: {time.perf_counter() - t1:.2f} s, rank {r.rank}")
+        r.free()
+    times, last, st = [], None, None
+    for s in range(args.steps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = solve()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+        st = r.stats()
+        if last is not None:
+            last.free()
+        last = r
+        log(f"step {s}: {times[-1]:.2f} s, rank {r.rank}")
+    mean = sum(times) / len(times)
+    mac = st["mac_cleardown"] + st["mac_updaterow"] + st["mac_trafo"] + st["mac_clearup"] + st["mac_ech"]
+    out = {
+        "metric": "GF(p) n^3/3 field mul-adds/s vs int8 MFMA peak; solves/s + p50/p99 latency",
+        "value": (n ** 3 / 3) / mean, "unit": "field mul-adds/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": mean * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"{n}x{n} over GF(2), bit-packed in 64-bit words, rank deficiency {d} (rows "
+                               f"{n - d}.. are sums of 64 earlier rows), seed 4", "m": n, "n": n, "p": 2,
+                   "rank": last.rank, "block_rows": st["block_rows"], "block_cols": st["block_cols"],
+                   "blocking": "tuned table" if tuned else "built-in", "parallelism": "single GPU"},
+        "work": {"mac_total": mac, "mac_alg_per_s": mac / mean},
+        "roofline": {"bound": "mfma", "kernel": "k_gemm_modp (MAD mod p, int8 MFMA, unpacked GF(2))",
+                     "solve_wide": {"achieved": 2 * (mac - st["mac_ech"]) / mean / 1e12,
+                                    "frac": 2 * (mac - st["mac_ech"]) / mean / 1e12 / INT8_PEAK_TOPS}},
+    }
+    if not args.no_check:
+        log("checking the last timed solve on the host (pins and Freivalds, 64 vectors)")
+        t1 = time.perf_counter()
+        A_host = np.unpackbits(W.cpu().numpy().view(np.uint8), axis=1, bitorder="little")[:, :n]
+        del W
+        torch.cuda.empty_cache()
+        chk = check_result(A_host, last, 2, n - d)
+        gamma, rho = last.pivots()
+        chk["rho_first_rows_ok"] = bool(np.array_equal(rho, np.arange(n - d)))
+        chk["ok"] = chk["ok"] and chk["rho_first_rows_ok"]
+        chk["seconds"] = time.perf_counter() - t1
+        out["check"] = chk
+        log(f"check: {chk}")
+    last.free()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -520,7 +594,8 @@ def main():
                     help="time the steps without per-launch device events (no roofline / kernel_ms)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates HBM byte counters)")
-    ap.add_argument("--workload", choices=["single", "batch", "serve"], default="single",
+    ap.add_argument("--gf2-n", type=int, default=200000, help="gf2: the matrix size")
+    ap.add_argument("--workload", choices=["single", "batch", "serve", "gf2"], default="single",
                     help="single: the one large matrix (default); batch: many small matrices in one call; "
                          "serve: a Poisson stream of requests through the server")
     ap.add_argument("--count", type=int, default=4096, help="batch: number of matrices")
@@ -554,6 +629,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(torch, args)
+        return
+    if args.workload == "gf2":
+        run_gf2(torch, args)
         return
 
     import paper_1806_04211_amd as gf

@@ -118,8 +118,9 @@ gfech_status gfech_echelonise_u8_dev(const uint8_t* A_dev, int64_t m, int64_t n,
  * gives GFECH_E_RANGE (skip_range_check skips that check).  The result is
  * that of gfech_echelonise_u8 on the unpacked matrix with p = 2 (Eq. (2);
  * over GF(2), -1 = 1, so the paper's negative form and the standard form
- * coincide); the input is unpacked on the device to one byte per entry for
- * the elimination.  Host input, and device input ordered on `stream`. */
+ * coincide); the input is unpacked on the device, one byte per entry,
+ * straight into the working panels of the elimination (no unpacked copy of
+ * the input is made).  Host input, and device input ordered on `stream`. */
 gfech_status gfech_echelonise_gf2(const uint64_t* A, int64_t m, int64_t n, int64_t ldw, const gfech_opts* opts,
                                   gfech_result** out);
 gfech_status gfech_echelonise_gf2_dev(const uint64_t* A_dev, int64_t m, int64_t n, int64_t ldw,

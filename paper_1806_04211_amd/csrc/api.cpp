@@ -189,8 +189,9 @@ gfech_status echelonise_impl(const uint8_t* A, bool on_device, int64_t m, int64_
     return st;
 }
 
-// GF(2) input packed in 64-bit words: unpacked on the device into one byte
-// per entry, then the byte path over p = 2
+// GF(2) input packed in 64-bit words: unpacked on the device straight into
+// the planner's block-row panels (one byte per entry), then the byte path
+// over p = 2
 gfech_status echelonise_gf2_impl(const uint64_t* A, bool on_device, int64_t m, int64_t n, int64_t ldw,
                                  const gfech_opts* opts, void* stream, gfech_result** out) {
     if (!out) return fail(GFECH_E_ARG, "out is NULL");
@@ -214,7 +215,6 @@ gfech_status echelonise_gf2_impl(const uint64_t* A, bool on_device, int64_t m, i
     const uint64_t* packed = A;
     int64_t ld = ldw;
     void* staged = nullptr;
-    uint8_t* bytes = nullptr;
     if (m > 0 && n > 0) {
         if (!on_device) {
             staged = be->alloc((size_t)(m * words) * 8);
@@ -236,16 +236,10 @@ gfech_status echelonise_gf2_impl(const uint64_t* A, bool on_device, int64_t m, i
                             bad > 0 ? "a pad bit past column n - 1 is set" : "device error");
             }
         }
-        bytes = (uint8_t*)be->alloc((size_t)(m * n));
-        if (!bytes) {
-            be->release(staged);
-            be->set_stream(nullptr);
-            return fail(GFECH_E_NOMEM, "device allocation of the unpacked input failed");
-        }
-        be->unpack_gf2(packed, m, n, ld, bytes, n);
     }
     std::vector<gfech::Problem> probs(1);
-    probs[0].A = bytes;
+    probs[0].packed = packed;
+    probs[0].ldw = ld;
     probs[0].m = m;
     probs[0].n = n;
     probs[0].lda = std::max<int64_t>(n, 1);
@@ -253,7 +247,6 @@ gfech_status echelonise_gf2_impl(const uint64_t* A, bool on_device, int64_t m, i
     probs[0].want = variant_of(opts);
     choose_blocks(m, n, opts, probs[0].row_blocks, probs[0].col_blocks);
     st = run(be, probs, out, opts);
-    be->release(bytes);
     be->release(staged);
     be->set_stream(nullptr);
     return st;

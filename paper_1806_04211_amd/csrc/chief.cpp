@@ -164,8 +164,11 @@ public:
     int blockcols() const { return b_; }
 
     // ------------------------------------------------------------ memory
+    // Two arenas: the block-row panels C (needed in Step 1 only, so freed
+    // before the result is assembled) and everything else.  plan_memory
+    // returns the total; panel_bytes() the panels' part.
     size_t plan_memory() {
-        Arena ar;
+        Arena ar, arc;
         rows_.resize(a_);
         cols_.resize(b_);
         for (int i = 0; i < a_; ++i) {
@@ -175,7 +178,7 @@ public:
             br.ldC = std::max<int64_t>((n_ + 63) / 64 * 64, 64);
             br.ldK = trafo_ ? (R0_[i] + ai + 63) / 64 * 64 : 0;
             for (int s = 0; s < 2; ++s) {
-                br.oC[s] = ar.take(ai * br.ldC);
+                br.oC[s] = arc.take(ai * br.ldC);
                 br.oK[s] = ar.take(ai * br.ldK);
                 br.oU[s] = ar.take(sizeof(int32_t) * ai);
             }
@@ -213,19 +216,24 @@ public:
         ldP_ = std::max<int64_t>((n_ + (trafo_ ? m_ : 0) + 63) / 64 * 64, 64);
         oP_ = ar.take(prow_total_ * ldP_);
         arena_bytes_ = ar.size;
+        panel_bytes_ = arc.size;
         slots_ = ar.slots;
-        return ar.size;
+        panel_slots_ = arc.slots;
+        return ar.size + arc.size;
     }
+    size_t panel_bytes() const { return panel_bytes_; }
 
     const std::vector<std::pair<size_t, size_t>>& slots() const { return slots_; }
+    const std::vector<std::pair<size_t, size_t>>& panel_slots() const { return panel_slots_; }
 
-    // at(offset) gives the address of the sub-buffer planned at that offset
-    template <typename At>
-    void bind(At at, int32_t* counts) {
+    // at(offset) gives the address of the sub-buffer planned at that offset of
+    // the main arena, atc(offset) of the panels' arena
+    template <typename At, typename AtC>
+    void bind(At at, AtC atc, int32_t* counts) {
         counts_ = counts;
         for (auto& br : rows_) {
             for (int s = 0; s < 2; ++s) {
-                br.C[s] = at(br.oC[s]);
+                br.C[s] = atc(br.oC[s]);
                 br.K[s] = at(br.oK[s]);
                 br.U[s] = (int32_t*)at(br.oU[s]);
             }
@@ -263,7 +271,10 @@ public:
                 be_.zero(br.K[0], (size_t)(ai * br.ldK));
                 be_.zero(br.K[1], (size_t)(ai * br.ldK));
             }
-            if (n_ > 0) {
+            if (n_ > 0 && pr_.packed) {
+                // GF(2) packed rows straight into the panel (a lane-0 job)
+                be_.unpack_gf2(pr_.packed + R0_[i] * pr_.ldw, ai, n_, pr_.ldw, br.C[0], br.ldC);
+            } else if (n_ > 0) {
                 GatherDesc g;
                 g.rows = (int32_t)ai;
                 g.cols = (int32_t)n_;
@@ -967,7 +978,8 @@ private:
     std::vector<BR> rows_;
     std::vector<BC> cols_;
     std::vector<TaskState> tasks_;
-    std::vector<std::pair<size_t, size_t>> slots_;
+    std::vector<std::pair<size_t, size_t>> slots_, panel_slots_;
+    size_t panel_bytes_ = 0;
     uint8_t* P_ = nullptr;
     int32_t* counts_ = nullptr;
     size_t oP_ = 0, arena_bytes_ = 0;
@@ -1025,6 +1037,9 @@ enum Phase { kStep1, kAssemble, kClearUp, kFinished };
 
 // capacity of the pivot-count pool: one int per block column of each active problem
 constexpr size_t kCountsCap = 1 << 18;
+// C panels at least this large are freed as soon as their problem leaves
+// Step 1 (at the cost of one synchronisation), smaller ones with the rest
+constexpr size_t kEarlyPanelFree = (size_t)1 << 30;
 
 }  // namespace
 
@@ -1035,7 +1050,8 @@ struct Engine::Impl {
         Stats st;
         std::unique_ptr<Plan> plan;
         uint8_t* arena = nullptr;
-        std::vector<void*> pieces;
+        uint8_t* panels = nullptr;           // the C panels (freed when Step 1 ends)
+        std::vector<void*> pieces, panel_pieces;
         size_t counts_off = 0, counts_n = 0;
         Phase phase = kStep1;
         bool cancel = false;
@@ -1120,12 +1136,20 @@ struct Engine::Impl {
         holes.swap(merged);
     }
 
+    void release_panels(Job& j) {
+        be.release(j.panels);
+        for (void* v : j.panel_pieces) be.release(v);
+        j.panels = nullptr;
+        j.panel_pieces.clear();
+    }
+
     void release(Job& j) {
         if (j.plan) j.plan->release_maps();
         be.release(j.arena);
         for (void* v : j.pieces) be.release(v);
         j.arena = nullptr;
         j.pieces.clear();
+        release_panels(j);
         if (j.counts_n) give_counts(j.counts_off, j.counts_n);
         j.counts_n = 0;
         bytes_in_use -= j.bytes;
@@ -1198,27 +1222,34 @@ struct Engine::Impl {
         // bounds-checking backend can tell any overrun of one buffer into the next
         const char* sep_env = getenv("GFECH_SEPARATE_BUFFERS");
         if (sep_env && sep_env[0] == '1') {
-            std::map<size_t, uint8_t*> where;
-            for (auto& sl : j->plan->slots()) {
-                uint8_t* ptr = (uint8_t*)be.alloc(std::max<size_t>(sl.second, 1));
-                if (!ptr) {
-                    release(*j);
-                    if (status) *status = 4;
-                    return -1;
+            std::map<size_t, uint8_t*> where, where_c;
+            for (int arena = 0; arena < 2; ++arena) {
+                for (auto& sl : arena ? j->plan->panel_slots() : j->plan->slots()) {
+                    uint8_t* ptr = (uint8_t*)be.alloc(std::max<size_t>(sl.second, 1));
+                    if (!ptr) {
+                        release(*j);
+                        if (status) *status = 4;
+                        return -1;
+                    }
+                    (arena ? j->panel_pieces : j->pieces).push_back(ptr);
+                    (arena ? where_c : where)[sl.first] = ptr;
                 }
-                j->pieces.push_back(ptr);
-                where[sl.first] = ptr;
             }
-            j->plan->bind([&](size_t off) { return where.at(off); }, counts + j->counts_off);
+            j->plan->bind([&](size_t off) { return where.at(off); }, [&](size_t off) { return where_c.at(off); },
+                          counts + j->counts_off);
         } else {
-            j->arena = (uint8_t*)be.alloc(std::max<size_t>(sz, 1));
-            if (!j->arena) {
+            const size_t pb = j->plan->panel_bytes();
+            j->arena = (uint8_t*)be.alloc(std::max<size_t>(sz - pb, 1));
+            j->panels = (uint8_t*)be.alloc(std::max<size_t>(pb, 1));
+            if (!j->arena || !j->panels) {
                 release(*j);
                 if (status) *status = 4;
                 return -1;
             }
             uint8_t* base = j->arena;
-            j->plan->bind([base](size_t off) { return base + off; }, counts + j->counts_off);
+            uint8_t* cbase = j->panels;
+            j->plan->bind([base](size_t off) { return base + off; }, [cbase](size_t off) { return cbase + off; },
+                          counts + j->counts_off);
         }
         j->bytes = owner->footprint(j->pr);
         bytes_in_use += j->bytes;
@@ -1378,6 +1409,16 @@ struct Engine::Impl {
             if (finished) {
                 issue_bulk(be.mark(0));
                 wait_bulk();
+                // its C panels are not read again: large ones are freed now, so
+                // that the result can take their place (the lanes drain first)
+                bool big = false;
+                for (auto& j : jobs)
+                    if (j->phase == kAssemble && j->plan->panel_bytes() >= kEarlyPanelFree) big = true;
+                if (big) {
+                    be.sync();
+                    for (auto& j : jobs)
+                        if (j->phase == kAssemble) release_panels(*j);
+                }
             }
         } else {
             issue_bulk(be.mark(0));

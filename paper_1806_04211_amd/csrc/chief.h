@@ -67,6 +67,10 @@ struct Result {
 struct Problem {
     const uint8_t* A = nullptr;   // backend address of the m x n input
     int64_t m = 0, n = 0, lda = 0;
+    // or (p = 2) GF(2) rows packed in 64-bit words, ldw words per row, unpacked
+    // straight into the block-row panels (no byte copy of the input is made)
+    const uint64_t* packed = nullptr;
+    int64_t ldw = 0;
     int32_t p = 0;
     int32_t want = kWantAll;
     std::vector<int32_t> row_blocks, col_blocks;   // a_i and b_j (sums m and n)

@@ -108,6 +108,45 @@ def batch_mix(seed: int, count: int, nmin: int = 32, nmax: int = 512,
     return out
 
 
+def gf2_uniform_packed(seed: int, stream: int, m: int, n: int) -> np.ndarray:
+    """m x n GF(2) matrix with i.i.d. Bernoulli(0.5) entries, packed in 64-bit
+    words (bit b of word w = column 64 w + b): word w of row i is the
+    SplitMix64 output of counter i * ceil(n / 64) + w, its bits past column
+    n - 1 cleared."""
+    nw = (n + 63) // 64
+    if m * nw == 0:
+        return np.zeros((m, nw), np.uint64)
+    W = words(seed, stream, 0, m * nw).reshape(m, nw)
+    if n % 64:
+        W[:, -1] &= np.uint64((1 << (n % 64)) - 1)
+    return W
+
+
+def gf2_deficient_packed(seed: int, m: int, n: int, deficiency: int, terms: int = 64) -> np.ndarray:
+    """The large GF(2) workload's construction, packed: rows 0 .. m - deficiency - 1
+    i.i.d. Bernoulli(0.5) (stream 0), and each of the last `deficiency` rows the
+    sum (XOR) of `terms` distinct earlier rows among the first m - deficiency,
+    chosen by a seeded draw.  With probability about 1 - 2^-(n - m + deficiency)
+    the rank is m - deficiency and the selected rows are exactly the first
+    m - deficiency."""
+    top = m - deficiency
+    W = np.zeros((m, (n + 63) // 64), np.uint64)
+    W[:top] = gf2_uniform_packed(seed, 0, top, n)
+    idx = gf2_combination_rows(seed, top, deficiency, terms)
+    for t in range(deficiency):
+        W[top + t] = np.bitwise_xor.reduce(W[idx[t]], axis=0)
+    return W
+
+
+def gf2_combination_rows(seed: int, top: int, deficiency: int, terms: int) -> np.ndarray:
+    """The earlier rows (deficiency x terms, distinct per row) whose sums form
+    the appended rows of gf2_deficient_packed."""
+    rng = np.random.default_rng([seed, 0x6F2])
+    k = min(terms, top)
+    return np.stack([rng.choice(top, size=k, replace=False) for _ in range(deficiency)]) if deficiency else \
+        np.zeros((0, k), np.int64)
+
+
 def gf2_pack(A: np.ndarray) -> np.ndarray:
     """Pack a 0/1 matrix row-wise into uint64 words, bit b of word w = column 64w+b."""
     A = np.asarray(A, np.uint8)

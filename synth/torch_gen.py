@@ -61,3 +61,32 @@ def low_rank_product(seed: int, m: int, n: int, k: int, p: int, device="cuda", c
         del B
     del C
     return out
+
+
+def gf2_uniform_packed(seed: int, stream: int, m: int, n: int, device="cuda", chunk_rows: int = 4096) -> torch.Tensor:
+    """synth.gf2_uniform_packed as an int64 tensor (the same 64 bits per word)."""
+    nw = (n + 63) // 64
+    key = stream_key(seed, stream)
+    out = torch.empty((m, nw), dtype=torch.int64, device=device)
+    for r0 in range(0, m, chunk_rows):
+        r = min(chunk_rows, m - r0)
+        t = torch.arange(r0 * nw + 1, (r0 + r) * nw + 1, dtype=torch.int64, device=device)
+        out[r0:r0 + r] = mix64(t * GAMMA + key).reshape(r, nw)
+    if n % 64:
+        out[:, -1] &= (1 << (n % 64)) - 1
+    return out
+
+
+def gf2_deficient_packed(seed: int, m: int, n: int, deficiency: int, terms: int = 64, device="cuda") -> torch.Tensor:
+    """synth.gf2_deficient_packed as an int64 tensor on `device`."""
+    import synth
+    top = m - deficiency
+    out = torch.empty((m, (n + 63) // 64), dtype=torch.int64, device=device)
+    out[:top] = gf2_uniform_packed(seed, 0, top, n, device)
+    if deficiency:
+        idx = torch.from_numpy(synth.gf2_combination_rows(seed, top, deficiency, terms)).to(device)
+        acc = torch.zeros((deficiency, out.shape[1]), dtype=torch.int64, device=device)
+        for c in range(idx.shape[1]):
+            acc ^= out[idx[:, c]]
+        out[top:] = acc
+    return out

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import gpu_library, say
+from tests.gpu_util import gpu_library, say, torch_cuda
 from tests.test_gpu_parity import compare
 
 pytestmark = pytest.mark.gpu
@@ -72,3 +72,36 @@ def test_batch_sample_of_the_batched_workload():
         compare(r.outputs(), e, f"problem {t} n={A.shape[0]} p={p}")
         r.free()
     assert deficient >= 3
+
+
+def test_gf2_packed_default_blocking_matches_oracle():
+    """Bit-packed GF(2) rows unpacked straight into the block-row panels, at
+    the default blocking (several 2048-wide block columns)."""
+    lib = gpu_library()
+    m, n = 1000, 6500
+    A = synth.uniform(12, 0, m, n, 2)
+    A[:, 300:2500] = 0
+    A[7::9] = A[2::9][: len(A[7::9])]
+    say(f"echelonise gf2 packed {m}x{n} at the default blocking")
+    out = lib.echelonise_gf2(synth.gf2_pack(A), n).outputs()
+    compare(out, oracle.echelonize(A, 2), "gf2 packed")
+
+
+def test_gf2_large_construction_pins_and_freivalds():
+    """The large GF(2) workload's construction at 12000 x 12000 (deficiency
+    100): its pinned rank and selected rows, and Freivalds on Eq. (2) with 64
+    vectors, computed on the host outside the library."""
+    torch = torch_cuda()
+    lib = gpu_library()
+    import bench
+    from synth import torch_gen
+    n, d = 12000, 100
+    W = torch_gen.gf2_deficient_packed(4, n, n, d)
+    say(f"echelonise gf2 packed {n}x{n}, deficiency {d}")
+    res = lib.echelonise_gf2_dev(W.data_ptr(), n, n, W.shape[1])
+    A = np.unpackbits(W.cpu().numpy().view(np.uint8), axis=1, bitorder="little")[:, :n]
+    chk = bench.check_result(A, res, 2, n - d)
+    gamma, rho = res.pivots()
+    res.free()
+    assert chk["ok"], chk
+    assert np.array_equal(rho, np.arange(n - d))

@@ -48,3 +48,15 @@ def test_low_rank_product_float_path_is_exact():
         B = synth.uniform(1, 1, m, k, p).astype(np.int64)
         C = synth.uniform(1, 2, k, n, p).astype(np.int64)
         assert np.array_equal(synth.low_rank_product(1, m, n, k, p), ((B @ C) % p).astype(np.uint8))
+
+
+def test_gf2_deficient_packed_pins():
+    """The large GF(2) construction at a small size: pad bits clear, rank
+    m - deficiency, selected rows the first m - deficiency (the pins its full
+    size is checked by), through the oracle."""
+    m, n, d = 150, 200, 12
+    W = synth.gf2_deficient_packed(4, m, n, d, terms=9)
+    assert not np.any(W[:, -1] >> np.uint64(n % 64))
+    e = oracle.echelonize(synth.gf2_unpack(W, n), 2)
+    assert e.rank == m - d
+    assert np.array_equal(e.rho, np.arange(m - d))
