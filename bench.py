@@ -476,6 +476,13 @@ def run_serve(torch, args):
         fin = max(fin, arrivals[t]) + service[t]
         plain_lat.append(fin - arrivals[t])
     small = [t for t in range(nreq) if max(shapes[t][:2]) <= 512]
+    if args.dump_latencies:
+        with open(args.dump_latencies, "w") as f:
+            f.write("t m n p arrival_s served_ms plain_ms service_ms\n")
+            for t in range(nreq):
+                m, n, p = shapes[t]
+                f.write(f"{t} {m} {n} {p} {arrivals[t]:.6f} {lat[t] * 1e3:.3f} {plain_lat[t] * 1e3:.3f} "
+                        f"{service[t] * 1e3:.3f}\n")
     print(json.dumps({
         "metric": "served solves/s and p50/p99 latency (Poisson arrivals, continuous batching) vs one call at a time",
         "value": nreq / span, "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
@@ -606,6 +613,7 @@ def main():
     ap.add_argument("--window-gb", type=int, default=32,
                     help="serve: inputs waiting in the server at most while its capacity is measured")
     ap.add_argument("--size-classes", type=int, default=0, help="serve: size classes of the server (0 = 3)")
+    ap.add_argument("--dump-latencies", default="", help="serve: write every request's latencies to this file")
     ap.add_argument("--hw-queues", type=int, default=0,
                     help="hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32; 0 = the environment's)")
     args = ap.parse_args()
