@@ -96,8 +96,12 @@ def exact_matmul_mod(X, Y, p, chunk_rows=4096):
     assert k * (p - 1) ** 2 < 2 ** 53
     Yf = Y.astype(dt)
     out = np.empty((X.shape[0], Y.shape[1]), np.int64)
+    t0 = time.perf_counter()
     for r0 in range(0, X.shape[0], chunk_rows):
         out[r0:r0 + chunk_rows] = np.remainder(X[r0:r0 + chunk_rows].astype(dt) @ Yf, p).astype(np.int64)
+        if time.perf_counter() - t0 > 20:         # progress of long host products
+            log(f"  host product: {min(r0 + chunk_rows, X.shape[0])} of {X.shape[0]} rows")
+            t0 = time.perf_counter()
     return out
 
 
@@ -116,6 +120,7 @@ def check_result(A_host, res, p, rank_expected, vectors=64, seed=0):
     r = res.rank
     gamma, rho = res.pivots()
     gbar, rbar = res.nonpivots()
+    log("  check: fetching R, M and K")
     R, M, K = res.get_R(), res.get_M(), res.get_K()
     out = {"rank": r, "rank_expected": rank_expected, "rank_ok": r == rank_expected}
     out["orders_ok"] = bool(np.all(np.diff(gamma) > 0) and np.all(np.diff(rho) > 0)
@@ -124,7 +129,9 @@ def check_result(A_host, res, p, rank_expected, vectors=64, seed=0):
     lead = (gamma - np.arange(r))[:, None]
     out["rref_ok"] = bool(not np.any(R[np.arange(n - r)[None, :] < lead]))
     X = np.random.default_rng([seed, 0xF2E1]).integers(0, p, (n, vectors)).astype(np.uint8)
+    log("  check: A X")
     Y = exact_matmul_mod(A_host, X, p)                      # A X, m x vectors
+    log("  check: M (A X)[rho], R X[gamma_bar], K (A X)[rho]")
     Yr = Y[rho].astype(np.uint8)
     top_l = (-exact_matmul_mod(M, Yr, p)) % p
     top_r = (X[gamma].astype(np.int64) - exact_matmul_mod(R, X[gbar], p)) % p if n > r else X[gamma] % p
