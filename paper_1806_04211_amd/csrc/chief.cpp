@@ -1072,6 +1072,8 @@ struct Engine::Impl {
                 owns_trace = g_trace != nullptr;
             }
         }
+        const char* ht = getenv("GFECH_HOST_TIMING");
+        host_timing = ht && ht[0] == '1';
         const char* gr = getenv("GFECH_CLEARUP_GROUP");
         group_rank = gr ? std::max<int64_t>(1, atoll(gr)) : 4096;
         counts = be.counts_buffer(kCountsCap);
@@ -1079,6 +1081,11 @@ struct Engine::Impl {
         hcounts.resize(kCountsCap);
     }
     ~Impl() {
+        if (host_timing && ht_layers)
+            fprintf(stderr, "gfech host timing: %lld layers, per layer %.1f us issue, %.1f us waiting for the "
+                            "pivot counts, %.1f us after\n",
+                    (long long)ht_layers, 1e6 * ht_pre / ht_layers, 1e6 * ht_wait / ht_layers,
+                    1e6 * ht_post / ht_layers);
         be.sync();
         for (auto& j : jobs) release(*j);
         if (counts) be.release_counts(counts);
@@ -1089,6 +1096,12 @@ struct Engine::Impl {
         }
     }
     bool owns_trace = false;
+    // GFECH_HOST_TIMING=1: host time of Step 1 by phase, printed when the
+    // engine ends (issue before the pivot-count read, the read's wait, the
+    // rest of the layer)
+    bool host_timing = false;
+    double ht_pre = 0, ht_wait = 0, ht_post = 0;
+    int64_t ht_layers = 0;
 
     Backend& be;
     const Engine* owner;
@@ -1319,6 +1332,8 @@ struct Engine::Impl {
             if (j->phase == kStep1) s1.push_back(j->plan.get());
         // ---- Step 1: one layer of every problem in it (see the header comment for the lanes)
         if (!s1.empty()) {
+            const auto h0 = std::chrono::steady_clock::now();
+            auto h1 = h0, h2 = h0;
             // the bulk part issued two layers back reads the scratch copy this
             // layer's ClearDowns write: its mid set is behind the near set lane 0
             // waited for in the previous layer, its far set is waited for here
@@ -1357,6 +1372,7 @@ struct Engine::Impl {
             issue_rest(ready);
             b1 = std::move(b1n);
             for (Plan* pl : s1) pl->clear_counts();
+            h1 = std::chrono::steady_clock::now();
             if (any) {
                 read_counts();
                 if (be.error()) { fail_all(be.error()); return 0; }
@@ -1372,6 +1388,7 @@ struct Engine::Impl {
                         if (j->phase == kStep1) j->plan->absorb_counts(hcounts.data() + j->counts_off, true);
                 }
             }
+            h2 = std::chrono::steady_clock::now();
             // The priority products below read what UpdateRow (1) wrote on lane 2
             // (after the previous bulk part's near set, whose columns they
             // overwrite).  That bulk part's far set (blocks after those) may
@@ -1395,6 +1412,13 @@ struct Engine::Impl {
             for (Plan* pl : s1) pl->ur6(ops, b6);
             flush(be, ops, shared);
             for (Plan* pl : s1) pl->ur_commit();
+            if (host_timing) {
+                const auto h3 = std::chrono::steady_clock::now();
+                ht_pre += std::chrono::duration<double>(h1 - h0).count();
+                ht_wait += std::chrono::duration<double>(h2 - h1).count();
+                ht_post += std::chrono::duration<double>(h3 - h2).count();
+                ht_layers++;
+            }
             shared.layers++;
             bool finished = false;
             for (auto& j : jobs) {
