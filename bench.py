@@ -621,8 +621,10 @@ def main():
                     help="serve: inputs waiting in the server at most while its capacity is measured")
     ap.add_argument("--size-classes", type=int, default=0, help="serve: size classes of the server (0 = 3)")
     ap.add_argument("--dump-latencies", default="", help="serve: write every request's latencies to this file")
-    ap.add_argument("--hw-queues", type=int, default=0,
-                    help="hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32; 0 = the environment's)")
+    ap.add_argument("--hw-queues", type=int, default=-1,
+                    help="hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32; 0 = the environment's; "
+                         "default: 16 for the serving workload, whose size classes each run their own streams, "
+                         "else the environment's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the method here runs on a "
@@ -632,6 +634,8 @@ def main():
     if args.summarize_profile:
         print(json.dumps(summarize_replay_profile(*args.summarize_profile), indent=1))
         return
+    if args.hw_queues < 0:
+        args.hw_queues = 16 if args.workload == "serve" else 0
     if args.hw_queues > 0:
         os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.hw_queues, 32))     # before the runtime starts
     import torch

@@ -1977,15 +1977,10 @@ public:
             if (err) *err = "counter allocation failed";
             return false;
         }
-        // lanes 1, 2 and 3: streams of their own at the default priority;
-        // non-blocking, so they never synchronise implicitly with the legacy
-        // default stream
-        if (hipStreamCreateWithFlags(&lane1_, hipStreamNonBlocking) != hipSuccess ||
-            hipStreamCreateWithFlags(&lane2_, hipStreamNonBlocking) != hipSuccess ||
-            hipStreamCreateWithFlags(&lane3_, hipStreamNonBlocking) != hipSuccess) {
-            if (err) *err = "stream creation failed";
-            return false;
-        }
+        // lanes 1, 2 and 3 are created when first used (lane_stream): a
+        // process's streams share its few hardware queues, and an instance
+        // whose problems never use them (single-block problems, input copies)
+        // should not take a share
         if (hipFuncSetAttribute((const void*)k_ech_panel<DescArg<EchDesc, ECH_ARG_CAP>>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)echp_lds_bytes(ECHP_MAX_ROWS)) != hipSuccess ||
             hipFuncSetAttribute((const void*)k_ech_panel<DescPtr<EchDesc>>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -2118,8 +2113,18 @@ public:
         cur_ = stream_;
     }
     void set_lane(int lane) override { cur_ = lane_stream(lane); }
-    hipStream_t lane_stream(int lane) const {
-        return lane == 1 ? lane1_ : lane == 2 ? lane2_ : lane == 3 ? lane3_ : stream_;
+    // lanes 1, 2 and 3: streams of their own at the default priority,
+    // non-blocking (they never synchronise implicitly with the legacy default
+    // stream), created on first use
+    hipStream_t lane_stream(int lane) {
+        if (lane < 1 || lane > 3) return stream_;
+        hipStream_t& s = lanes_[lane - 1];
+        if (!s && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            note_error(hipErrorOutOfMemory, "stream creation");
+            s = nullptr;
+            return stream_;
+        }
+        return s;
     }
     void* create_stream() override {
         hipStream_t st = nullptr;
@@ -2414,9 +2419,8 @@ private:
     }
     // every lane drained; the marks can be reused
     void sync_all() {
-        HIP_OK(hipStreamSynchronize(lane1_));
-        HIP_OK(hipStreamSynchronize(lane2_));
-        HIP_OK(hipStreamSynchronize(lane3_));
+        for (hipStream_t s : lanes_)
+            if (s) HIP_OK(hipStreamSynchronize(s));
         HIP_OK(hipStreamSynchronize(stream_));
         for (hipEvent_t e : marks_) mark_pool_.push_back(e);
         mark_base_ += (int)marks_.size();
@@ -2425,9 +2429,7 @@ private:
     }
 
     hipStream_t stream_ = nullptr;   // lane 0: the caller's stream
-    hipStream_t lane1_ = nullptr;    // lane 1
-    hipStream_t lane2_ = nullptr;    // lane 2
-    hipStream_t lane3_ = nullptr;    // lane 3
+    hipStream_t lanes_[3] = {nullptr, nullptr, nullptr};   // lanes 1, 2 and 3 (created on first use)
     hipStream_t cur_ = nullptr;      // the lane kernels go to
     std::vector<hipEvent_t> marks_, mark_pool_;
     int32_t* counts_host_ = nullptr;   // counts_buffer(): host view
