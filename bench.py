@@ -343,6 +343,7 @@ def run_batch(torch, args):
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t1)
         ranks = [r.rank for r in res]
+        bst = res[0].stats()                    # launch counts of the whole engine run
         [r.free() for r in res]
         log(f"batched step {s}: {times[-1]:.3f} s")
     # the plain path: one call (one launch sequence) per matrix
@@ -367,6 +368,7 @@ def run_batch(torch, args):
                                                                            "p99": percentile(lat, 0.99) * 1e3}},
         "speedup_vs_per_call": per_call / mean,
         "rank_sum": int(sum(ranks)),
+        "launches_per_batch": bst["launches"], "host_syncs_per_batch": bst["syncs"],
     }), flush=True)
 
 
