@@ -64,7 +64,7 @@ def copy_calibration(torch, mib: int):
     print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_gemm_modp_40000_gf7.md")
+PROFILE = os.path.join(ROOT, "profiles", "k_gemm_modp_replay_40000_gf7.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1806_04211_amd", "csrc", "hip_backend.hip")
 
 
