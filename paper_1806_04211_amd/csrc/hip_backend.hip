@@ -2003,7 +2003,7 @@ public:
         }
         no_lds_ech_ = getenv("GFECH_ECH_NO_LDS") != nullptr;
         const char* gg = getenv("GFECH_GEMM_GROUP");
-        gemm_group_ = gg ? std::max(1, std::min(64, atoi(gg))) : 1;
+        gemm_group_ = gg ? std::max(1, std::min(64, atoi(gg))) : 4;
         // the device address of the fixed workspace on this device (the one
         // current now, which every later call of this backend uses)
         if (hipGetSymbolAddress((void**)&fixed_scratch_, HIP_SYMBOL(scratch)) != hipSuccess) {
@@ -2438,7 +2438,7 @@ private:
     int mark_base_ = 0;              // id of marks_[0]
     size_t echs_lds_max_ = 0;        // LDS the LDS-resident ECH may use
     bool no_lds_ech_ = false;
-    int gemm_group_ = 1;             // tile rows per group of the MAD tile order
+    int gemm_group_ = 4;             // tile rows per group of the MAD tile order (measured: 4)
     void* ring_host_ = nullptr;
     void* ring_dev_ = nullptr;
     size_t ring_off_ = 0;
