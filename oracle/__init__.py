@@ -50,6 +50,13 @@ def load_library(path: str):
     lib.oracle_mad.restype = ctypes.c_int
     lib.oracle_check_field.argtypes = [ctypes.c_uint32]
     lib.oracle_check_field.restype = ctypes.c_int
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.oracle_echelon_gf2.argtypes = [u64p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, i64p, i64p, i64p,
+                                       u64p, u64p]
+    lib.oracle_echelon_gf2.restype = ctypes.c_int
+    lib.oracle_mad_gf2.argtypes = [u64p, u64p, u64p, u64p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                   ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+    lib.oracle_mad_gf2.restype = ctypes.c_int
     return lib
 
 
@@ -165,3 +172,61 @@ def mad_c(A, B, C, p: int):
 
 def is_field(p: int) -> bool:
     return _load().oracle_check_field(p) == 0
+
+
+def _u64(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+@dataclass
+class EchelonGF2:
+    """Result of the packed GF(2) oracle: E (r rows of ceil(n/64) words) and T
+    (m rows of ceil(m/64) words), packed least significant bit first; rows as
+    Echelon's."""
+    m: int
+    n: int
+    rank: int
+    gamma: np.ndarray
+    rho: np.ndarray
+    E: np.ndarray
+    T: np.ndarray
+
+
+def echelonize_gf2(W, n: int, lib=None) -> EchelonGF2:
+    """Whole-matrix echelonisation over GF(2) of packed rows (Section 2.2 with
+    p = 2: the same plain Gauss-Jordan, row operations as word XORs)."""
+    W = np.ascontiguousarray(np.asarray(W, dtype=np.uint64))
+    m = W.shape[0]
+    wn, wm = (n + 63) // 64, (m + 63) // 64
+    lib = lib or _load()
+    k = max(1, min(m, n))
+    piv = np.zeros(k, np.int64)
+    sel = np.zeros(k, np.int64)
+    E = np.zeros((max(m, 1), max(wn, 1)), np.uint64)
+    T = np.zeros((max(m, 1), max(wm, 1)), np.uint64)
+    r = np.zeros(1, np.int64)
+    Wp = W if W.size else np.zeros((1, 1), np.uint64)
+    rc = lib.oracle_echelon_gf2(_u64(Wp), m, n, max(W.shape[1] if W.ndim == 2 else 0, wn, 1), _i64(r), _i64(piv),
+                                _i64(sel), _u64(E), _u64(T))
+    if rc:
+        raise OracleError(_ERRS.get(rc, f"error {rc}"))
+    r = int(r[0])
+    return EchelonGF2(m=m, n=n, rank=r, gamma=piv[:r].copy(), rho=sel[:r].copy(), E=E[:r, :wn].copy(),
+                      T=T[:m, :wm].copy())
+
+
+def mad_gf2(C, A, B, k: int, n: int):
+    """(C + A B) over GF(2) on packed rows (C may be None): A has k columns, B and
+    C n columns."""
+    A = np.ascontiguousarray(A, np.uint64)
+    B = np.ascontiguousarray(B, np.uint64)
+    m = A.shape[0]
+    wn = (n + 63) // 64
+    out = np.zeros((m, wn), np.uint64)
+    Cp = None if C is None else np.ascontiguousarray(C, np.uint64)
+    lib = _load()
+    rc = lib.oracle_mad_gf2(_u64(Cp) if Cp is not None else None, _u64(A), _u64(B), _u64(out), m, k, n,
+                            A.shape[1], B.shape[1], wn)
+    if rc:
+        raise OracleError(_ERRS.get(rc, f"error {rc}"))
+    return out

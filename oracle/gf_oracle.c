@@ -167,3 +167,100 @@ int oracle_mad(const uint8_t* A, const uint8_t* B, const uint8_t* C, uint8_t* ou
         }
     return ORACLE_OK;
 }
+
+/*
+ * GF(2) with rows packed in 64-bit words (bit b of word w = column 64 w + b):
+ * the same plain Gauss-Jordan on [A | I_m] as oracle_echelon with p = 2, where
+ * a row operation is a word-wise XOR and every non-zero pivot is already 1.
+ *   A        : m rows of ldw words (ldw >= ceil(n / 64)); bits past column
+ *              n - 1 must be zero
+ *   pivcols, selrows : as oracle_echelon
+ *   E        : r rows of ceil(n / 64) words (the RREF, packed)
+ *   T        : m rows of ceil(m / 64) words (rows ordered as oracle_echelon's)
+ */
+int oracle_echelon_gf2(const uint64_t* A, int64_t m, int64_t n, int64_t ldw,
+                       int64_t* rank_out, int64_t* pivcols, int64_t* selrows,
+                       uint64_t* E, uint64_t* T) {
+    const int64_t wn = (n + 63) / 64, wm = (m + 63) / 64, w = wn + wm;   /* words of [A | I] */
+    if (m < 0 || n < 0 || (m > 0 && n > 0 && ldw < wn)) return ORACLE_E_ARG;
+    for (int64_t i = 0; i < m && n % 64; ++i)
+        if (A[i * ldw + n / 64] >> (n % 64)) return ORACLE_E_RANGE;
+    uint64_t* W = (uint64_t*)calloc((size_t)(m > 0 ? m : 1) * (size_t)(w > 0 ? w : 1), sizeof(uint64_t));
+    int64_t* piv_col = (int64_t*)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+    int64_t* piv_row = (int64_t*)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+    uint8_t* is_sel = (uint8_t*)calloc((size_t)(m > 0 ? m : 1), 1);
+    if (!W || !piv_col || !piv_row || !is_sel) {
+        free(W); free(piv_col); free(piv_row); free(is_sel);
+        return ORACLE_E_NOMEM;
+    }
+    /* the identity part starts at word wn: bit i of that part is column n + i
+       of [A | I] in the unpacked picture */
+    for (int64_t i = 0; i < m; ++i) {
+        memcpy(W + i * w, A + i * ldw, sizeof(uint64_t) * (size_t)wn);
+        W[i * w + wn + i / 64] |= 1ull << (i % 64);
+    }
+    int64_t r = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        uint64_t* row = W + i * w;
+        /* reduce row i by every existing pivot row */
+        for (int64_t t = 0; t < r; ++t)
+            if ((row[piv_col[t] / 64] >> (piv_col[t] % 64)) & 1u) {
+                const uint64_t* s = W + piv_row[t] * w;
+                for (int64_t k = 0; k < w; ++k) row[k] ^= s[k];
+            }
+        /* first non-zero among the A columns */
+        int64_t c = -1;
+        for (int64_t j = 0; j < n; ++j)
+            if ((row[j / 64] >> (j % 64)) & 1u) { c = j; break; }
+        if (c < 0) continue;                       /* not selected */
+        /* keep earlier pivot rows reduced: clear column c in them */
+        for (int64_t t = 0; t < r; ++t) {
+            uint64_t* s = W + piv_row[t] * w;
+            if ((s[c / 64] >> (c % 64)) & 1u)
+                for (int64_t k = 0; k < w; ++k) s[k] ^= row[k];
+        }
+        piv_col[r] = c;
+        piv_row[r] = i;
+        is_sel[i] = 1;
+        ++r;
+    }
+    for (int64_t a = 1; a < r; ++a) {
+        int64_t c = piv_col[a], rr = piv_row[a], b = a - 1;
+        while (b >= 0 && piv_col[b] > c) { piv_col[b + 1] = piv_col[b]; piv_row[b + 1] = piv_row[b]; --b; }
+        piv_col[b + 1] = c; piv_row[b + 1] = rr;
+    }
+    for (int64_t t = 0; t < r; ++t) {
+        const uint64_t* row = W + piv_row[t] * w;
+        if (E) memcpy(E + t * wn, row, sizeof(uint64_t) * (size_t)wn);
+        if (T) memcpy(T + t * wm, row + wn, sizeof(uint64_t) * (size_t)wm);
+    }
+    int64_t q = r;
+    for (int64_t i = 0; i < m; ++i) {
+        if (is_sel[i]) continue;
+        if (T) memcpy(T + q * wm, W + i * w + wn, sizeof(uint64_t) * (size_t)wm);
+        ++q;
+    }
+    int64_t s = 0;
+    for (int64_t i = 0; i < m; ++i)
+        if (is_sel[i]) selrows[s++] = i;
+    for (int64_t t = 0; t < r; ++t) pivcols[t] = piv_col[t];
+    *rank_out = r;
+    free(W); free(piv_col); free(piv_row); free(is_sel);
+    return ORACLE_OK;
+}
+
+/* plain (C + A * B) over GF(2) on packed rows: A m x k (lda words), B k x n
+   (ldb words), C and out m x n (ldc words); bit j of row i of the product is
+   the parity of the k terms A[i][t] B[t][j] (the MAD job over GF(2)) */
+int oracle_mad_gf2(const uint64_t* C, const uint64_t* A, const uint64_t* B, uint64_t* out,
+                   int64_t m, int64_t k, int64_t n, int64_t lda, int64_t ldb, int64_t ldc) {
+    const int64_t wn = (n + 63) / 64;
+    for (int64_t i = 0; i < m; ++i) {
+        uint64_t* o = out + i * ldc;
+        for (int64_t w = 0; w < wn; ++w) o[w] = C ? C[i * ldc + w] : 0u;
+        for (int64_t t = 0; t < k; ++t)
+            if ((A[i * lda + t / 64] >> (t % 64)) & 1u)
+                for (int64_t w = 0; w < wn; ++w) o[w] ^= B[t * ldb + w];
+    }
+    return ORACLE_OK;
+}

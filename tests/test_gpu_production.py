@@ -105,3 +105,26 @@ def test_gf2_large_construction_pins_and_freivalds():
     res.free()
     assert chk["ok"], chk
     assert np.array_equal(rho, np.arange(n - d))
+
+
+def test_gf2_8192_matches_packed_oracle():
+    """8192 x 8192 over GF(2) (the large construction, deficiency 50) against
+    the packed oracle, element by element: rank, pivots, selected rows, E and
+    T (unpacked from the oracle's words)."""
+    torch = torch_cuda()
+    lib = gpu_library()
+    from synth import torch_gen
+    n, d = 8192, 50
+    W = torch_gen.gf2_deficient_packed(7, n, n, d, terms=9)
+    say(f"echelonise gf2 packed {n}x{n}")
+    res = lib.echelonise_gf2_dev(W.data_ptr(), n, n, W.shape[1])
+    st = res.stats()
+    assert st["block_cols"] >= 2 and st["block_rows"] >= 16
+    out = res.outputs()
+    res.free()
+    say("packed oracle")
+    e = oracle.echelonize_gf2(W.cpu().numpy().view(np.uint64), n)
+    assert out.rank == e.rank == n - d
+    assert np.array_equal(out.gamma, e.gamma) and np.array_equal(out.rho, e.rho)
+    assert np.array_equal(out.E, synth.gf2_unpack(e.E, n))
+    assert np.array_equal(out.T, synth.gf2_unpack(e.T, n))
