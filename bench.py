@@ -584,6 +584,55 @@ def run_gf2(torch, args):
     print(json.dumps(out), flush=True)
 
 
+def run_gf2_mad(torch, args):
+    """GF(2) products two ways on the same logical shapes: the byte path's MAD
+    (int8 MFMA on one byte per entry, p = 2) against the four-Russians MAD on
+    packed rows; device events around 5 launches each after one untimed."""
+    import paper_1806_04211_amd as gf
+    lib = gf.library()
+    stream = torch.cuda.current_stream()
+    rows = []
+    for (M, N, K) in ((256, 32768, 2048), (4096, 20480, 2048), (8192, 8192, 8192), (32768, 40000, 4096)):
+        res = {"shape": [M, N, K]}
+        # bytes: operands of 0/1 entries
+        A8 = torch.randint(0, 2, (M, K), dtype=torch.uint8, device="cuda:0")
+        B8 = torch.randint(0, 2, (K, N), dtype=torch.uint8, device="cuda:0")
+        C8 = torch.randint(0, 2, (M, N), dtype=torch.uint8, device="cuda:0")
+        # packed: random words with the pad bits cleared
+        wk, wn = (K + 63) // 64, (N + 63) // 64
+        Ap = torch.randint(-2 ** 62, 2 ** 62, (M, wk), dtype=torch.int64, device="cuda:0")
+        Bp = torch.randint(-2 ** 62, 2 ** 62, (K, wn), dtype=torch.int64, device="cuda:0")
+        Cp = torch.randint(-2 ** 62, 2 ** 62, (M, wn), dtype=torch.int64, device="cuda:0")
+        if N % 64:
+            Bp[:, -1] &= (1 << (N % 64)) - 1
+            Cp[:, -1] &= (1 << (N % 64)) - 1
+        runs = {
+            "int8_mfma_bytes": lambda: lib.mad_dev(M, N, K, 2, A8.data_ptr(), K, B8.data_ptr(), N, C8.data_ptr(), N,
+                                                    C=C8.data_ptr(), ldc=N, stream=stream.cuda_stream),
+            "four_russians_packed": lambda: lib.mad_gf2_dev(M, N, K, Ap.data_ptr(), wk, Bp.data_ptr(), wn,
+                                                            Cp.data_ptr(), wn, C=Cp.data_ptr(), ldc=wn,
+                                                            stream=stream.cuda_stream)}
+        for name, fn in runs.items():
+            fn()
+            ms = []
+            for _ in range(5):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                e1.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            t = sum(ms) / len(ms)
+            res[name] = {"ms": t, "gf2_mac_per_s": M * N * K / (t * 1e-3)}
+        res["packed_speedup"] = res["int8_mfma_bytes"]["ms"] / res["four_russians_packed"]["ms"]
+        log(f"gf2 mad {M}x{N}x{K}: bytes {res['int8_mfma_bytes']['ms']:.3f} ms, packed "
+            f"{res['four_russians_packed']['ms']:.3f} ms")
+        rows.append(res)
+        del A8, B8, C8, Ap, Bp, Cp
+        torch.cuda.empty_cache()
+    print(json.dumps({"gf2_mad": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -611,7 +660,7 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (calibrates HBM byte counters)")
     ap.add_argument("--gf2-n", type=int, default=200000, help="gf2: the matrix size")
-    ap.add_argument("--workload", choices=["single", "batch", "serve", "gf2"], default="single",
+    ap.add_argument("--workload", choices=["single", "batch", "serve", "gf2", "gf2mad"], default="single",
                     help="single: the one large matrix (default); batch: many small matrices in one call; "
                          "serve: a Poisson stream of requests through the server")
     ap.add_argument("--count", type=int, default=4096, help="batch: number of matrices")
@@ -653,6 +702,9 @@ def main():
         return
     if args.workload == "gf2":
         run_gf2(torch, args)
+        return
+    if args.workload == "gf2mad":
+        run_gf2_mad(torch, args)
         return
 
     import paper_1806_04211_amd as gf

@@ -238,6 +238,17 @@ typedef struct gfech_mad_desc {
 } gfech_mad_desc;
 gfech_status gfech_mad_batch_dev(int64_t count, const gfech_mad_desc* descs, void* stream);
 
+/* MAD over GF(2) on bit-packed rows (bit b of word w of a row = column
+ * 64 w + b): D = (C + A * B) over GF(2), i.e. row i of D is row i of C XOR
+ * the rows of B that row i of A selects.  A: M x K (lda words per row, its
+ * bits past column K - 1 ignored); B: K x N (ldb words); C: M x N (ldc
+ * words) or NULL for zero; D: M x N (ldd words).  Bits of B and C past column
+ * N - 1 must be zero (those of D then are).  D may equal C (same ld); D must
+ * not overlap A or B.  Computed by the method of the four Russians: tables of
+ * the XOR combinations of 8 rows of B in LDS, selected by the bytes of A. */
+gfech_status gfech_mad_gf2_dev(int64_t M, int64_t N, int64_t K, const uint64_t* A, int64_t lda, const uint64_t* B,
+                               int64_t ldb, const uint64_t* C, int64_t ldc, uint64_t* D, int64_t ldd, void* stream);
+
 /* ECH (Remark 2.3) of one block H (rows x cols, ldh) in device memory.  With
  * r = rank(H) (returned in *rank, host memory) the device outputs are
  *   prow[r]        row of the t-th pivot, pivots by increasing column

@@ -224,11 +224,13 @@ int oracle_echelon_gf2(const uint64_t* A, int64_t m, int64_t n, int64_t ldw,
         is_sel[i] = 1;
         ++r;
     }
-    for (int64_t a = 1; a < r; ++a) {
-        int64_t c = piv_col[a], rr = piv_row[a], b = a - 1;
-        while (b >= 0 && piv_col[b] > c) { piv_col[b + 1] = piv_col[b]; piv_row[b + 1] = piv_row[b]; --b; }
-        piv_col[b + 1] = c; piv_row[b + 1] = rr;
-    }
+    /* order the pivots by column: exchange neighbours until sorted */
+    for (int64_t a = 1; a < r; ++a)
+        for (int64_t b = a; b > 0 && piv_col[b - 1] > piv_col[b]; --b) {
+            int64_t tc = piv_col[b], tr = piv_row[b];
+            piv_col[b] = piv_col[b - 1]; piv_row[b] = piv_row[b - 1];
+            piv_col[b - 1] = tc; piv_row[b - 1] = tr;
+        }
     for (int64_t t = 0; t < r; ++t) {
         const uint64_t* row = W + piv_row[t] * w;
         if (E) memcpy(E + t * wn, row, sizeof(uint64_t) * (size_t)wn);

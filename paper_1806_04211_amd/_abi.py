@@ -88,6 +88,7 @@ SIGNATURES = {
     "gfech_backend_name": (ctypes.c_char_p, []),
     "gfech_mad_dev": (ctypes.c_int, [c_i64, c_i64, c_i64, c_u32, vp, c_i64, vp, c_i64, vp, vp, c_i64, vp, vp,
                                      c_i64, vp]),
+    "gfech_mad_gf2_dev": (ctypes.c_int, [c_i64, c_i64, c_i64, vp, c_i64, vp, c_i64, vp, c_i64, vp, c_i64, vp]),
     "gfech_mad_batch_dev": (ctypes.c_int, [c_i64, vp, vp]),
     "gfech_ech_dev": (ctypes.c_int, [vp, c_i64, c_i64, c_i64, c_u32, vp, vp, vp, vp, vp, c_i64, vp, c_i64, vp,
                                      c_i64, i64p, vp]),

@@ -234,6 +234,11 @@ class Library:
         arr = descs if isinstance(descs, ctypes.Array) else self.mad_descs(descs)
         self._check(self.lib.gfech_mad_batch_dev(len(descs), arr, ctypes.c_void_p(stream)))
 
+    def mad_gf2_dev(self, M, N, K, A, lda, B, ldb, D, ldd, C=0, ldc=0, stream=0):
+        """MAD over GF(2) on packed rows (device addresses, leading dimensions in 64-bit words)."""
+        vp = ctypes.c_void_p
+        self._check(self.lib.gfech_mad_gf2_dev(M, N, K, vp(A), lda, vp(B), ldb, vp(C), ldc, vp(D), ldd, vp(stream)))
+
     def ech_dev(self, H, rows, cols, ldh, p, prow, qrow, pcol, qcol, M, ldm, K, ldk, R, ldr, stream=0) -> int:
         """ECH job on device addresses; returns the rank."""
         r = ctypes.c_int64()

@@ -629,6 +629,27 @@ gfech_status gfech_mad_dev(int64_t M, int64_t N, int64_t K, uint32_t p, const ui
     return gfech_mad_batch_dev(1, &d, stream);
 }
 
+gfech_status gfech_mad_gf2_dev(int64_t M, int64_t N, int64_t K, const uint64_t* A, int64_t lda, const uint64_t* B,
+                               int64_t ldb, const uint64_t* C, int64_t ldc, uint64_t* D, int64_t ldd, void* stream) {
+    if (M < 0 || N < 0 || K < 0) return fail(GFECH_E_ARG, "negative size");
+    if (M == 0 || N == 0) return GFECH_OK;
+    const int64_t wn = (N + 63) / 64, wk = (K + 63) / 64;
+    if (!D || ldd < wn || (K > 0 && (!A || !B || lda < wk || ldb < wn)) || (C && ldc < wn))
+        return fail(GFECH_E_ARG, "bad GF(2) MAD buffers");
+    gfech_status st = GFECH_OK;
+    gfech::Backend* be = get_backend(&st);
+    if (!be) return st;
+    std::lock_guard<std::mutex> lk(be->lock());
+    be->set_stream(stream);
+    gfech::Gf2MadDesc d;
+    d.M = M; d.N = N; d.K = K;
+    d.A = A; d.lda = lda; d.B = B; d.ldb = ldb; d.C = C; d.ldc = ldc; d.D = D; d.ldd = ldd;
+    be->mad_gf2(d);
+    be->sync();
+    be->set_stream(nullptr);
+    return be->error() ? fail(GFECH_E_DEVICE, "device error") : GFECH_OK;
+}
+
 gfech_status gfech_ech_dev(const uint8_t* H, int64_t rows, int64_t cols, int64_t ldh, uint32_t p, int32_t* prow,
                            int32_t* qrow, int32_t* pcol, int32_t* qcol, uint8_t* M, int64_t ldm, uint8_t* K,
                            int64_t ldk, uint8_t* R, int64_t ldr, int64_t* rank, void* stream) {

@@ -100,6 +100,20 @@ struct ListDesc {
     const int32_t* keep = nullptr; int32_t* keep_out = nullptr;
 };
 
+// MAD over GF(2) on bit-packed rows (bit b of 64-bit word w = column 64 w + b):
+//   D = C + A * B   (XOR of the rows of B selected by the bits of each row of A)
+//   A: M x K bits, lda words per row (its bits past K - 1 are ignored)
+//   B: K x N bits, ldb words; C (or nullptr = zero) and D: M x N bits, ldc / ldd
+//   words.  Bits of B and C past column N - 1 must be zero (D's then are).
+//   D may equal C (same ld); D never overlaps A or B.
+struct Gf2MadDesc {
+    int64_t M = 0, N = 0, K = 0;
+    const uint64_t* A = nullptr; int64_t lda = 0;
+    const uint64_t* B = nullptr; int64_t ldb = 0;
+    const uint64_t* C = nullptr; int64_t ldc = 0;
+    uint64_t* D = nullptr; int64_t ldd = 0;
+};
+
 // Sorting of small distinct-valued lists (for the final row and column orders):
 //   mode 0: out[k] = add + (k-th smallest value)
 //   mode 1: out[k] = add + (index of the k-th smallest value)
@@ -143,6 +157,8 @@ public:
     // one byte per entry: dst[x][y] = bit (y mod 64) of src[x][y / 64] for
     // x < m, y < n (ldw words and ldd bytes per row)
     virtual void unpack_gf2(const uint64_t* src, int64_t m, int64_t n, int64_t ldw, uint8_t* dst, int64_t ldd) = 0;
+    // one MAD over GF(2) on packed rows (ordered on the current lane)
+    virtual void mad_gf2(const Gf2MadDesc& d) = 0;
     // number of rows whose last word has a set bit past column n - 1 (waits for the answer)
     virtual int64_t count_gf2_pad(const uint64_t* src, int64_t m, int64_t n, int64_t ldw) = 0;
     // stream for subsequent work (a hipStream_t for the HIP backend)

@@ -1924,6 +1924,82 @@ k_unpack_gf2(const uint64_t* __restrict__ src, int64_t m, int64_t n, int64_t ldw
     }
 }
 
+// ---- MAD over GF(2) on bit-packed rows, by the method of the four Russians:
+// for each group of 8 rows of B (8 bits of each row of A), a table of all 256
+// XOR combinations of those rows (restricted to the tile's columns) is built
+// in LDS, and each row of D takes the table entry its byte of A selects.  A
+// workgroup owns 256 rows (one per thread) and 1024 columns (32 dwords); the
+// tables of two groups alternate, so building the next and using the current
+// need one barrier per group.  Table entry e is 8 chunks of 16 bytes, chunk c
+// at position (c + e) mod 8, so the lanes of a wave, which select different
+// entries, spread over the banks.
+constexpr int G2_THREADS = 256;
+constexpr int G2_TW = 32;                      // dwords per row of the tile (1024 columns)
+constexpr int G2_TABLE = 256 * G2_TW * 4;      // bytes of one table
+
+__device__ __forceinline__ int g2_pos(int e, int c) { return e * (G2_TW * 4) + (((c + e) & 7) << 4); }
+
+__global__ void __launch_bounds__(G2_THREADS) k_mad_gf2(Gf2MadDesc d, int tiles_n) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t g2s[];
+    const int tid = threadIdx.x;
+    const int64_t m0 = (int64_t)(blockIdx.x / tiles_n) * G2_THREADS;
+    const int64_t w0 = (int64_t)(blockIdx.x % tiles_n) * G2_TW;   // first dword of the tile
+    const int64_t nw = (d.N + 31) / 32;                            // dwords of a row of D
+    const int64_t row = m0 + tid;
+    const bool live = row < d.M;
+    const uint32_t* A32 = (const uint32_t*)d.A;
+    const uint32_t* B32 = (const uint32_t*)d.B;
+    // builder role: dword w of the tile, entries 32 q .. 32 q + 31
+    const int bw = tid & 31, bq = tid >> 5;
+    const bool bcol = w0 + bw < nw;
+    const int ngroups = (int)((d.K + 7) / 8);
+    const auto build = [&](int g, uint8_t* T) {
+        uint32_t br[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int64_t k = (int64_t)g * 8 + b;
+            br[b] = (k < d.K && bcol) ? gload<uint32_t>(B32 + k * d.ldb * 2 + w0 + bw) : 0u;
+        }
+        uint32_t v = ((bq & 1) ? br[5] : 0u) ^ ((bq & 2) ? br[6] : 0u) ^ ((bq & 4) ? br[7] : 0u);
+        // Gray-code order over the low five bits: one XOR per entry
+#pragma unroll
+        for (int l = 0; l < 32; ++l) {
+            if (l) v ^= br[__builtin_ctz(l)];
+            const int e = 32 * bq + (l ^ (l >> 1));
+            *(uint32_t*)(T + g2_pos(e, bw >> 2) + (bw & 3) * 4) = v;
+        }
+    };
+    uint32_t acc[G2_TW];
+#pragma unroll
+    for (int i = 0; i < G2_TW; ++i) acc[i] = 0;
+    uint64_t aw = 0;
+    if (ngroups > 0) build(0, g2s);
+    __syncthreads();
+    for (int g = 0; g < ngroups; ++g) {
+        uint8_t* T = g2s + (g & 1) * G2_TABLE;
+        if (g + 1 < ngroups) build(g + 1, g2s + ((g + 1) & 1) * G2_TABLE);
+        if ((g & 7) == 0) aw = live ? gload<uint64_t>(d.A + row * d.lda + g / 8) : 0ull;
+        uint32_t a = (uint32_t)(aw >> (8 * (g & 7))) & 0xffu;
+        const int64_t kleft = d.K - (int64_t)g * 8;
+        if (kleft < 8) a &= (1u << kleft) - 1u;            // bits of A past K - 1
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const uint4 t = *(const uint4*)(T + g2_pos((int)a, c));
+            acc[4 * c] ^= t.x; acc[4 * c + 1] ^= t.y; acc[4 * c + 2] ^= t.z; acc[4 * c + 3] ^= t.w;
+        }
+        __syncthreads();
+    }
+    (void)A32;
+    if (!live) return;
+    const uint32_t* C32 = d.C ? (const uint32_t*)(d.C + row * d.ldc) : nullptr;
+    uint32_t* D32 = (uint32_t*)(d.D + row * d.ldd);
+#pragma unroll
+    for (int i = 0; i < G2_TW; ++i) {
+        const int64_t w = w0 + i;
+        if (w < nw) gstore<uint32_t>(D32 + w, acc[i] ^ (C32 ? gload<uint32_t>(C32 + w) : 0u));
+    }
+}
+
 // rows whose last word has a bit set past column n - 1 (n not a multiple of 64)
 __global__ void __launch_bounds__(SMALL_THREADS)
 k_gf2_pad(const uint64_t* __restrict__ src, int64_t m, int64_t n, int64_t ldw, unsigned long long* bad) {
@@ -1990,6 +2066,11 @@ public:
             hipFuncSetAttribute((const void*)k_gemm_modp<GemmPtrSrc>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)gemm_lds_bytes()) != hipSuccess) {
             if (err) *err = "cannot reserve LDS for the kernels";
+            return false;
+        }
+        if (hipFuncSetAttribute((const void*)k_mad_gf2, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * G2_TABLE) !=
+            hipSuccess) {
+            if (err) *err = "cannot reserve LDS for the GF(2) kernel";
             return false;
         }
         // the LDS-resident ECH takes up to 160 KB per workgroup where the device allows it
@@ -2317,6 +2398,15 @@ public:
         if (m <= 0 || n <= 0) return;
         hipLaunchKernelGGL(k_unpack_gf2, dim3((unsigned)std::min<int64_t>(m, 65535)), dim3(SMALL_THREADS), 0, stream_,
                            src, m, n, ldw, dst, ldd);
+        HIP_OK(hipGetLastError());
+    }
+    void mad_gf2(const Gf2MadDesc& d) override {
+        if (d.M <= 0 || d.N <= 0) return;
+        const int64_t nw = (d.N + 31) / 32;
+        const int64_t tn = (nw + G2_TW - 1) / G2_TW, tm = (d.M + G2_THREADS - 1) / G2_THREADS;
+        if (tn * tm > INT32_MAX) { note_error(hipErrorInvalidValue, "gf2 mad too large"); return; }
+        launch_mac_ = (double)d.M * d.N * d.K;
+        go(0, k_mad_gf2, dim3((unsigned)(tn * tm)), dim3(G2_THREADS), (size_t)(2 * G2_TABLE), d, (int)tn);
         HIP_OK(hipGetLastError());
     }
     int64_t count_gf2_pad(const uint64_t* src, int64_t m, int64_t n, int64_t ldw) override {

@@ -325,6 +325,25 @@ public:
         }
     }
 
+    void mad_gf2(const Gf2MadDesc& d) override {
+        enqueue([this, d] {
+            const int64_t wn = (d.N + 63) / 64;
+            for (int64_t i = 0; i < d.M; ++i) {
+                if (!chk(d.D + i * d.ldd, 8 * (size_t)wn, "gf2 mad D") ||
+                    !chk(d.A + i * d.lda, 8 * (size_t)((d.K + 63) / 64), "gf2 mad A") ||
+                    (d.C && !chk(d.C + i * d.ldc, 8 * (size_t)wn, "gf2 mad C")))
+                    return;
+                std::vector<uint64_t> o(wn, 0);
+                if (d.C) for (int64_t w = 0; w < wn; ++w) o[w] = d.C[i * d.ldc + w];
+                for (int64_t k = 0; k < d.K; ++k)
+                    if ((d.A[i * d.lda + k / 64] >> (k % 64)) & 1u) {
+                        if (!chk(d.B + k * d.ldb, 8 * (size_t)wn, "gf2 mad B")) return;
+                        for (int64_t w = 0; w < wn; ++w) o[w] ^= d.B[k * d.ldb + w];
+                    }
+                for (int64_t w = 0; w < wn; ++w) d.D[i * d.ldd + w] = o[w];
+            }
+        });
+    }
     // a lane-0 job, like the memory transfers
     void unpack_gf2(const uint64_t* src, int64_t m, int64_t n, int64_t ldw, uint8_t* dst, int64_t ldd) override {
         auto run = [this, src, m, n, ldw, dst, ldd] {

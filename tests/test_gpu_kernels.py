@@ -273,3 +273,40 @@ def test_mad_extreme_operands(K, p):
         lib.mad_dev(M, N, K, p, dA.data_ptr(), K, dB.data_ptr(), N, dD.data_ptr(), N, C=dC.data_ptr(), ldc=N)
         torch.cuda.synchronize()
         assert np.array_equal(dD.cpu().numpy().reshape(M, N), jobs.mad(C, A, B, p)), name
+
+
+GF2_MAD_SHAPES = [(1, 1, 1), (300, 1000, 77), (256, 1024, 64), (513, 2100, 1030), (1000, 65, 4100), (70, 3000, 9)]
+
+
+@pytest.mark.parametrize("shape", GF2_MAD_SHAPES)
+def test_mad_gf2_packed(shape):
+    """The four-Russians MAD over GF(2) on packed rows against the packed
+    oracle's MAD: with and without C, in place, and with row strides above
+    the words a row needs."""
+    torch = torch_cuda()
+    lib = gpu_library()
+    M, N, K = shape
+    say(f"mad gf2 packed {shape}")
+    rng = np.random.default_rng(M + N + K)
+    A = synth.gf2_pack(rng.integers(0, 2, (M, K)).astype(np.uint8))
+    B = synth.gf2_pack(rng.integers(0, 2, (K, N)).astype(np.uint8))
+    C = synth.gf2_pack(rng.integers(0, 2, (M, N)).astype(np.uint8))
+    exp = oracle.mad_gf2(C, A, B, K, N)
+    # bits of A past K - 1 are ignored: set them
+    Ax = A.copy()
+    if K % 64:
+        Ax[:, -1] |= ~((np.uint64(1) << np.uint64(K % 64)) - np.uint64(1))
+    pad = lambda X, k: np.concatenate([X, np.zeros((X.shape[0], k), np.uint64)], axis=1)
+    t = lambda X: torch.from_numpy(np.ascontiguousarray(X).view(np.int64)).to("cuda:0")
+    dA, dB, dC = t(pad(Ax, 1)), t(pad(B, 2)), t(C)
+    dD = torch.zeros_like(dC)
+    wa, wb, wn = Ax.shape[1] + 1, B.shape[1] + 2, C.shape[1]
+    lib.mad_gf2_dev(M, N, K, dA.data_ptr(), wa, dB.data_ptr(), wb, dD.data_ptr(), wn, C=dC.data_ptr(), ldc=wn)
+    torch.cuda.synchronize()
+    assert np.array_equal(dD.cpu().numpy().view(np.uint64), exp)
+    lib.mad_gf2_dev(M, N, K, dA.data_ptr(), wa, dB.data_ptr(), wb, dD.data_ptr(), wn)
+    torch.cuda.synchronize()
+    assert np.array_equal(dD.cpu().numpy().view(np.uint64), oracle.mad_gf2(None, A, B, K, N))
+    lib.mad_gf2_dev(M, N, K, dA.data_ptr(), wa, dB.data_ptr(), wb, dC.data_ptr(), wn, C=dC.data_ptr(), ldc=wn)
+    torch.cuda.synchronize()
+    assert np.array_equal(dC.cpu().numpy().view(np.uint64), exp)

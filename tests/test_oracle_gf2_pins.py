@@ -87,6 +87,7 @@ MUTANTS = {
     "last_nonzero_pivot": ("if ((row[j / 64] >> (j % 64)) & 1u) { c = j; break; }",
                            "if ((row[j / 64] >> (j % 64)) & 1u) { c = j; }"),
     "identity_not_augmented": ("W[i * w + wn + i / 64] |= 1ull << (i % 64);", ";"),
+    "unsorted_pivots": ("b > 0 && piv_col[b - 1] > piv_col[b]", "0"),
     "identity_bit_off_by_one": ("W[i * w + wn + i / 64] |= 1ull << (i % 64);",
                                 "W[i * w + wn + (i + 1) / 64] |= 1ull << ((i + 1) % 64);"),
 }
