@@ -384,18 +384,32 @@ gfech_status gfech_echelonise_batch(int64_t count, const gfech_problem* probs, i
     std::vector<gfech::Problem> pv;
     std::vector<int64_t> run_idx;
     std::vector<void*> staged;
+    // device inputs: one range check for all of them (one wait)
+    std::vector<int64_t> bad(probs ? (size_t)count : 0, 0);
+    if (inputs_on_device && !(opts && opts->skip_range_check)) {
+        std::vector<gfech::Backend::RangeDesc> rd;
+        std::vector<int64_t> who;
+        for (int64_t t : ok) {
+            const gfech_problem& q = probs[t];
+            if (q.m <= 0 || q.n <= 0) continue;
+            gfech::Backend::RangeDesc d;
+            d.A = q.A; d.m = q.m; d.n = q.n; d.lda = q.lda; d.p = (int32_t)q.p;
+            rd.push_back(d);
+            who.push_back(t);
+        }
+        std::vector<int64_t> b;
+        be->count_out_of_range_many(rd, b);
+        for (size_t k = 0; k < who.size(); ++k) bad[(size_t)who[k]] = b[k];
+    }
     for (int64_t t : ok) {
         const gfech_problem& q = probs[t];
         gfech::Problem pr;
         pr.m = q.m; pr.n = q.n; pr.lda = q.lda; pr.p = (int32_t)q.p; pr.A = q.A;
         pr.want = variant_of(opts);
-        if (inputs_on_device && !(opts && opts->skip_range_check) && q.m > 0 && q.n > 0) {
-            int64_t bad = be->count_out_of_range(q.A, q.m, q.n, q.lda, (int32_t)q.p);
-            if (bad) {
-                if (per_problem) per_problem[t] = GFECH_E_RANGE;
-                if (!first) first = fail(GFECH_E_RANGE, "entry >= p");
-                continue;
-            }
+        if (bad[(size_t)t]) {
+            if (per_problem) per_problem[t] = bad[(size_t)t] > 0 ? GFECH_E_RANGE : GFECH_E_DEVICE;
+            if (!first) first = fail(bad[(size_t)t] > 0 ? GFECH_E_RANGE : GFECH_E_DEVICE, "entry >= p");
+            continue;
         }
         if (!inputs_on_device && q.m > 0 && q.n > 0) {
             void* d = be->alloc((size_t)(q.m * q.n));

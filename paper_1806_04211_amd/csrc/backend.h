@@ -153,6 +153,16 @@ public:
     virtual void sync_lane0() { sync(); }
     // number of entries >= p in an m x n matrix (waits for the answer)
     virtual int64_t count_out_of_range(const uint8_t* A, int64_t m, int64_t n, int64_t lda, int32_t p) = 0;
+    // the same for many matrices at once, one answer per matrix (one wait in all)
+    struct RangeDesc {
+        const uint8_t* A = nullptr;
+        int64_t m = 0, n = 0, lda = 0;
+        int32_t p = 0;
+    };
+    virtual void count_out_of_range_many(const std::vector<RangeDesc>& ds, std::vector<int64_t>& bad) {
+        bad.assign(ds.size(), 0);
+        for (size_t t = 0; t < ds.size(); ++t) bad[t] = count_out_of_range(ds[t].A, ds[t].m, ds[t].n, ds[t].lda, ds[t].p);
+    }
     // GF(2) rows packed in 64-bit words, bit b of word w = column 64 w + b, to
     // one byte per entry: dst[x][y] = bit (y mod 64) of src[x][y / 64] for
     // x < m, y < n (ldw words and ldd bytes per row)

@@ -1897,6 +1897,22 @@ k_range(const uint8_t* __restrict__ A, int64_t m, int64_t n, int64_t lda, int p,
     if (cnt) atomicAdd(bad, cnt);
 }
 
+// entries >= p of many matrices: workgroup (x, y) scans rows x, x + gridDim.x,
+// ... of matrix y and adds its count to bad[y]
+struct RangeArg {
+    const uint8_t* A;
+    int64_t m, n, lda;
+    int32_t p;
+};
+__global__ void __launch_bounds__(SMALL_THREADS)
+k_range_many(const RangeArg* __restrict__ ds, unsigned long long* bad) {
+    const RangeArg d = ds[blockIdx.y];
+    unsigned long long cnt = 0;
+    for (int64_t x = blockIdx.x; x < d.m; x += gridDim.x)
+        for (int64_t y = threadIdx.x; y < d.n; y += SMALL_THREADS) cnt += gload<uint8_t>(d.A + x * d.lda + y) >= d.p;
+    if (cnt) atomicAdd(bad + blockIdx.y, cnt);
+}
+
 // GF(2) rows packed least significant bit first in 64-bit words, unpacked to
 // one byte per entry.  Thread c of a row writes the 16 entries of bits
 // 16 (c mod 4) .. 16 (c mod 4) + 15 of word c / 4, as one 16-byte store when
@@ -2394,6 +2410,37 @@ public:
         return err_ ? -1 : (int64_t)bad;
     }
 
+    void count_out_of_range_many(const std::vector<RangeDesc>& ds, std::vector<int64_t>& bad) override {
+        bad.assign(ds.size(), 0);
+        if (ds.empty()) return;
+        // descriptors and counters in one device buffer: the descriptors are
+        // uploaded, the counters zeroed by the same copy
+        const size_t nd = ds.size();
+        std::vector<uint8_t> blob(nd * sizeof(RangeArg) + nd * 8, 0);
+        int64_t mmax = 1;
+        for (size_t t = 0; t < nd; ++t) {
+            RangeArg a{ds[t].A, ds[t].m, ds[t].n, ds[t].lda, ds[t].p};
+            memcpy(blob.data() + t * sizeof(RangeArg), &a, sizeof(a));
+            mmax = std::max(mmax, ds[t].m);
+        }
+        uint8_t* dev = (uint8_t*)alloc(blob.size());
+        if (!dev) {
+            Backend::count_out_of_range_many(ds, bad);
+            return;
+        }
+        upload(dev, blob.data(), blob.size());
+        unsigned long long* cnt = (unsigned long long*)(dev + nd * sizeof(RangeArg));
+        for (size_t off = 0; off < nd; off += 65535) {
+            const size_t c = std::min<size_t>(65535, nd - off);
+            hipLaunchKernelGGL(k_range_many, dim3((unsigned)std::min<int64_t>(mmax, 64), (unsigned)c),
+                               dim3(SMALL_THREADS), 0, stream_, (const RangeArg*)dev + off, cnt + off);
+        }
+        HIP_OK(hipGetLastError());
+        std::vector<unsigned long long> h(nd);
+        download(h.data(), cnt, nd * 8);
+        release(dev);
+        for (size_t t = 0; t < nd; ++t) bad[t] = err_ ? -1 : (int64_t)h[t];
+    }
     void unpack_gf2(const uint64_t* src, int64_t m, int64_t n, int64_t ldw, uint8_t* dst, int64_t ldd) override {
         if (m <= 0 || n <= 0) return;
         hipLaunchKernelGGL(k_unpack_gf2, dim3((unsigned)std::min<int64_t>(m, 65535)), dim3(SMALL_THREADS), 0, stream_,

@@ -164,3 +164,26 @@ def test_gf2_packed_input(shape):
         with pytest.raises(gf.GfechError) as ex:
             lib.echelonise_gf2_dev(t.data_ptr(), m, n, Wd.shape[1])
         assert ex.value.status == 3
+
+
+def test_batch_device_inputs_range_checked_together():
+    """Device inputs of a batch are range-checked in one pass: the problem with
+    an entry >= p is refused, the others are solved."""
+    torch = torch_cuda()
+    lib = gpu_library()
+    mix = synth.batch_mix(21, 12, nmin=8, nmax=120)
+    bufs = [dev(torch, A) for A, _ in mix]
+    bad_t = 5
+    A5, p5 = mix[bad_t]
+    A5 = A5.copy()
+    A5[A5.shape[0] // 2, 1] = p5          # not a residue
+    bufs[bad_t] = dev(torch, A5)
+    probs = [(b.data_ptr(), A.shape[0], A.shape[1], A.shape[1], p) for b, (A, p) in zip(bufs, mix)]
+    say("batch of 12 device inputs, one out of range")
+    res, sts = lib.echelonise_batch(probs, on_device=True)
+    for t, ((A, p), r, s) in enumerate(zip(mix, res, sts)):
+        if t == bad_t:
+            assert s == 3 and r is None
+        else:
+            assert s == 0
+            compare(r.outputs(), oracle.echelonize(A, p), f"problem {t}")
