@@ -54,12 +54,8 @@ namespace gfech {
 
 Result::~Result() {
     if (!be) return;
-    be->release(Pfinal);
-    be->release(Kfinal);
-    be->release(upsilon);
-    be->release(upsilon_bar);
-    be->release(varrho);
-    be->release(varrho_bar);
+    be->release(block);
+    for (void* v : pieces) be->release(v);
 }
 
 std::vector<int32_t> even_blocks(int64_t total, int64_t target) {
@@ -680,20 +676,44 @@ public:
         // 64-byte aligned rows for the vector loads; [X R] only without the transformation
         res.ldP = ((trafo_ ? res.offM + r_ : res.offR + n_ - r_) + 63) / 64 * 64;
         res.ldK = r_;
-        auto ialloc = [&](int64_t cnt) { return (int32_t*)be_.alloc(sizeof(int32_t) * std::max<int64_t>(cnt, 1)); };
-        res.Pfinal = (uint8_t*)be_.alloc((size_t)std::max<int64_t>(keepR_ ? r_ * res.ldP : 0, 1));
-        res.Kfinal = (uint8_t*)be_.alloc((size_t)std::max<int64_t>(trafo_ ? (m_ - r_) * r_ : 0, 1));
-        res.upsilon = ialloc(r_);
-        res.upsilon_bar = ialloc(n_ - r_);
-        res.varrho = ialloc(r_);
-        res.varrho_bar = ialloc(m_ - r_);
-        rowmap_ = ialloc(r_);
-        colmap_ = ialloc(n_ + r_);
-        kmap_ = ialloc(r_);
-        ordj_ = ialloc(r_);
-        if (!res.Pfinal || !res.Kfinal || !res.upsilon || !res.upsilon_bar || !res.varrho || !res.varrho_bar ||
-            !rowmap_ || !colmap_ || !kmap_ || !ordj_)
-            return false;
+        // the result in one allocation, the assembly maps in another (freed
+        // with the plan): two allocations per problem, not ten
+        Arena rb, mb;
+        const size_t oPf = rb.take((size_t)std::max<int64_t>(keepR_ ? r_ * res.ldP : 0, 1));
+        const size_t oKf = rb.take((size_t)std::max<int64_t>(trafo_ ? (m_ - r_) * r_ : 0, 1));
+        const auto ilist = [](Arena& a, int64_t cnt) { return a.take(sizeof(int32_t) * std::max<int64_t>(cnt, 1)); };
+        const size_t oU = ilist(rb, r_), oUb = ilist(rb, n_ - r_), oV = ilist(rb, r_), oVb = ilist(rb, m_ - r_);
+        const size_t oRm = ilist(mb, r_), oCm = ilist(mb, n_ + r_), oKm = ilist(mb, r_), oOj = ilist(mb, r_);
+        // GFECH_SEPARATE_BUFFERS=1: every piece its own allocation, so a
+        // bounds-checking backend can tell an overrun of one into the next
+        const char* sep_env = getenv("GFECH_SEPARATE_BUFFERS");
+        const bool sep = sep_env && sep_env[0] == '1';
+        std::map<size_t, uint8_t*> rp, mp;
+        if (sep) {
+            for (int a = 0; a < 2; ++a)
+                for (auto& sl : (a ? mb : rb).slots) {
+                    uint8_t* ptr = (uint8_t*)be_.alloc(std::max<size_t>(sl.second, 1));
+                    if (!ptr) return false;
+                    (a ? map_pieces_ : res.pieces).push_back(ptr);
+                    (a ? mp : rp)[sl.first] = ptr;
+                }
+        } else {
+            res.block = be_.alloc(rb.size);
+            maps_ = be_.alloc(mb.size);
+            if (!res.block || !maps_) return false;
+        }
+        const auto at = [&](size_t off) { return sep ? rp.at(off) : (uint8_t*)res.block + off; };
+        const auto atm = [&](size_t off) { return sep ? mp.at(off) : (uint8_t*)maps_ + off; };
+        res.Pfinal = at(oPf);
+        res.Kfinal = at(oKf);
+        res.upsilon = (int32_t*)at(oU);
+        res.upsilon_bar = (int32_t*)at(oUb);
+        res.varrho = (int32_t*)at(oV);
+        res.varrho_bar = (int32_t*)at(oVb);
+        rowmap_ = (int32_t*)atm(oRm);
+        colmap_ = (int32_t*)atm(oCm);
+        kmap_ = (int32_t*)atm(oKm);
+        ordj_ = (int32_t*)atm(oOj);
         // block column offsets in the final orders
         rowoff_.assign(b_ + 1, 0);
         noff_.assign(b_ + 1, 0);
@@ -867,10 +887,10 @@ public:
     }
 
     void release_maps() {
-        be_.release(rowmap_);
-        be_.release(colmap_);
-        be_.release(kmap_);
-        be_.release(ordj_);
+        be_.release(maps_);
+        for (void* v : map_pieces_) be_.release(v);
+        map_pieces_.clear();
+        maps_ = nullptr;
         rowmap_ = colmap_ = kmap_ = ordj_ = nullptr;
     }
 
@@ -984,6 +1004,8 @@ private:
     int32_t* counts_ = nullptr;
     size_t oP_ = 0, arena_bytes_ = 0;
     int64_t prow_total_ = 0, ldP_ = 0, r_ = 0;
+    void* maps_ = nullptr;   // the block the four maps below are carved from
+    std::vector<void*> map_pieces_;   // or their separate allocations
     int32_t *rowmap_ = nullptr, *colmap_ = nullptr, *kmap_ = nullptr, *ordj_ = nullptr;
     std::vector<int64_t> rowoff_, noff_, soff_, uoff_;
     std::vector<std::vector<GemmDesc>> cu_steps_;

@@ -59,6 +59,8 @@ struct Result {
     int32_t* upsilon_bar = nullptr;  // n - r
     int32_t* varrho = nullptr;       // r selected rows, ascending
     int32_t* varrho_bar = nullptr;   // m - r
+    void* block = nullptr;           // the one allocation all of the above are carved from
+    std::vector<void*> pieces;       // or separate allocations (bounds-checking test builds)
     Stats stats;
     std::vector<int32_t> row_blocks, col_blocks;
     ~Result();
