@@ -1159,41 +1159,59 @@ __global__ void __launch_bounds__(512) k_ech_panel(Src src) {
 // scaled to -1 and kept reduced against each other; outputs as in EchDesc),
 // for blocks of at most 256 rows over GF(p), p <= 46, with the whole working
 // matrix W = [H | T] held in LDS (row length LW: the columns of H, padded to
-// 16, then the transformation columns, one per pivot).
+// 16, then the transformation columns, one per pivot).  Eight waves.
 //
-// Panels of 32 columns: thread x holds row x's 32 panel entries as 16 words
-// of two 16-bit entries, and its row of the panel's transformation F (one
-// column per pivot of the panel) the same way.  Sums stay unreduced inside a
-// panel: an entry receives at most 32 products, each at most (p - 1)^2 <=
-// 45^2, so it stays below 2^16 and one packed 16-bit multiply-add updates two
-// entries.  A pivot step takes two barriers: each wave posts the ballot of
-// its candidate rows, every thread picks the first candidate from the four
-// ballots (the paper's pivot rule); the pivot row's thread publishes its
-// words in LDS, the lanes of its wave reduce the 64 entries, one each, and
-// after the second barrier every thread reads them and updates its row.
-// That is the fallback; the usual panel is eliminated by wave 0 alone (see
-// the pivot search below).  After a panel, F is applied to the remaining
-// columns and to the transformation columns of earlier pivots with MFMA, in
-// place in LDS, one wave per chunk of 32 columns:
+// Columns go in panels of 32.  A panel's pivots are found by wave 0 alone
+// over the first (up to) 64 unselected rows, one row per lane (no row after
+// them can be a pivot while one of them is a candidate): a lane holds its
+// row's 32 panel entries and its row of the panel transformation F as 16-bit
+// pairs, unreduced (an entry receives at most 32 products, each at most
+// (p - 1)^2 <= 45^2, so it stays below 2^16).  A pivot step: a ballot picks
+// the first candidate with a non-zero entry (the paper's pivot rule), the
+// pivot's lane publishes its words in LDS, every lane reduces one of the 64
+// published entries, and every lane reads the reduced row back and updates
+// its own with one packed 16-bit multiply-add per word; -1/pivot comes from a
+// register table (lane v holds -1/v) read across lanes.  The search runs at
+// raised wave priority.  The panel's pivot rows are then known as
+// combinations G of the original rows, every other row is cleared by them
+// with its own entries at the pivot columns as coefficients, and one MFMA
+// pass (F = W G per block of 16 rows) applies it all:
 //     W[x][y] := (x a pivot of this panel ? 0 : W[x][y]) + sum_t F[x][t] W[pivot row t][y]
-// while wave 0, once the next panel's columns are done, searches that panel.
+// over the later columns and the transformation columns of earlier pivots,
+// in units of 16 columns, the B operand read from the pivot rows themselves
+// with ds_read_b64_tr_b8.  The next panel's two units go first, split by
+// rows over all eight waves (every wave reads its B operand before any of
+// them writes: pivot rows are written too); then wave 0 searches the next
+// panel while waves 1 to 7 update the remaining units, each unit by one wave
+// over every row.  When a column of the search has no candidate while later
+// unselected rows exist, the panel goes to the four-wave elimination
+// instead: threads 0..255 own rows 0..255, each pivot step takes two
+// barriers (each wave posts the ballot of its candidate rows, every thread
+// picks the first candidate; the pivot row's thread publishes its words, the
+// lanes of its wave reduce the 64 entries, one each, and after the second
+// barrier every thread reads them and updates its row).
 constexpr int ECHS_MAX_ROWS = 256;
 constexpr int ECHS_MAX_P = 46;
-constexpr int ECHS_THREADS = 256;
+constexpr int ECHS_THREADS = 512;
 constexpr int ECHS_PW = 32;        // panel width
-constexpr int ECHS_CH = 32;        // columns per trailing-update chunk
+// LDS layout: the fixed part first (every offset a multiple of 16)
+//   pb      96 dwords: [0, 32) published words, [32, 64) reduced, [64] -1/pivot
+//           (four-wave elimination), [65] the search's pivot count, [72, 88)
+//           two sets of four wave ballots
+//   prl, pcl, qrl   256 ints each: pivot rows, pivot columns, non-pivot rows
+//   invt    64 dwords: -1/v mod p
+//   sel, inpanels   256 bytes, 2 x 256 bytes
+//   Gt      32 x 32 bytes: G^T of the panel found by the search
+// then F (rows16 x 32 bytes) and W (rows16 x LW bytes).
+constexpr int ECHS_OFF_PRL = 384, ECHS_OFF_PCL = 1408, ECHS_OFF_QRL = 2432, ECHS_OFF_INVT = 3456;
+constexpr int ECHS_OFF_SEL = 3712, ECHS_OFF_INP = 3968, ECHS_OFF_GT = 4480, ECHS_FIXED = 5504;
 
 __host__ __device__ inline int echs_tc(int cols) { return (cols + 15) & ~15; }
 __host__ __device__ inline int echs_lw(int cols, int maxr) { return echs_tc(cols) + ((maxr + 15) & ~15); }
-// LDS: W, the panel transformation F (rows x 32), G^T of the panel found
-// by one wave (32 x 32), the published pivot row (64 dwords, -1/pivot and
-// two sets of four wave ballots: 88 dwords), prl, pcl, qrow (256 ints each),
-// the inverse table (64), sel and two inpanel arrays (256 bytes each)
 __host__ __device__ inline size_t echs_lds_bytes(int rows, int cols) {
     const int maxr = rows < cols ? rows : cols;
     const size_t rows16 = (size_t)((rows + 15) & ~15);
-    return rows16 * (size_t)echs_lw(cols, maxr) + rows16 * ECHS_PW + (size_t)ECHS_PW * ECHS_PW + 88 * 4 +
-           3 * 256 * 4 + 64 * 4 + 3 * 256;
+    return (size_t)ECHS_FIXED + rows16 * ECHS_PW + rows16 * (size_t)echs_lw(cols, maxr);
 }
 
 // f(std::integral_constant<int, K>) for K = K0 .. N - 1, unrolled at compile time
@@ -1219,41 +1237,95 @@ __device__ __forceinline__ void pkmad_words(uint32_t* acc, const uint32_t* v, ui
     for (int w = 0; w < NW; ++w) acc[w] = pkmad16(f2, v[w], acc[w]);
 }
 
+// Orders the LDS accesses of one wave around it (the wave's LDS operations
+// complete in order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// v mod p for 0 <= v < 2^17, given inv17 = fl(fl(1/p) (1 + 2^-18)) (fl(1/p)
+// within an ulp or two): fl(v inv17) = (v / p)(1 + e) with 0 < e < 2^-17, so it
+// is at least v / p and below floor(v / p) + 1 (v e < 1 <= p - v mod p), and
+// its integer part is floor(v / p) exactly.  For every p <= 251 and v < 2^17
+// this is checked exhaustively on the host in float32 arithmetic.
+__device__ __forceinline__ uint32_t mod17(uint32_t v, float inv17, uint32_t p) {
+    const int q = (int)((float)v * inv17);
+    return (uint32_t)(__mul24(q, -(int)p) + (int)v);
+}
+
+// byte u (when 0 <= u < 4) of w, a residue, less one mod p
+__device__ __forceinline__ uint32_t echs_dec_byte(uint32_t w, int u, uint32_t p) {
+    if (u < 0 || u >= 4) return w;
+    const uint32_t sh = 8u * (uint32_t)u, b = (w >> sh) & 0xffu;
+    return (w & ~(0xffu << sh)) | ((b ? b - 1u : p - 1u) << sh);
+}
+
+// 32 panel entries of a row (bytes at p, `wc` of them valid) as 16 words of
+// 16-bit pairs: column k in half (k & 1) of word k / 2
+__device__ __forceinline__ void echs_unpack_panel(const uint8_t* p, bool ok, int wc, uint32_t* D) {
+    uint4 a = make_uint4(0, 0, 0, 0), b = make_uint4(0, 0, 0, 0);
+    if (ok) {
+        a = *(const uint4*)p;
+        b = *(const uint4*)(p + 16);
+    }
+    const uint32_t d[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        uint32_t lo = __builtin_amdgcn_perm(0u, d[i], 0x0c010c00u);
+        uint32_t hi = __builtin_amdgcn_perm(0u, d[i], 0x0c030c02u);
+        if (wc < ECHS_PW) {   // columns past the block hold other data: clear them
+            if (4 * i >= wc) lo &= 0u; else if (4 * i + 1 >= wc) lo &= 0xffffu;
+            if (4 * i + 2 >= wc) hi &= 0u; else if (4 * i + 3 >= wc) hi &= 0xffffu;
+        }
+        D[2 * i] = lo;
+        D[2 * i + 1] = hi;
+    }
+}
+
 template <class Src>
 __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    constexpr int NW = ECHS_THREADS / 64;
     const EchDesc e = src.get(blockIdx.x);
     const int rows = e.rows, cols = e.cols;
     const int maxr = rows < cols ? rows : cols;
     const int TC = echs_tc(cols), LW = echs_lw(cols, maxr);
-    const int rows16 = (rows + 15) & ~15;
+    const int rows16 = (rows + 15) & ~15, nrb = rows16 >> 4;
     const uint32_t p = (uint32_t)e.p;
     const float inv = 1.0f / (float)p;
-    const int x = threadIdx.x, lane = x & 63, wave = x >> 6;
+    const float inv17 = inv * (1.0f + 0x1p-18f);
+    // the wave index is uniform: reading it through the first lane lets the
+    // compiler keep what depends on it in scalar registers
+    const int x = threadIdx.x, lane = x & 63, wave = __builtin_amdgcn_readfirstlane(x >> 6);
 
-    uint8_t* W = smem;                                       // [rows16][LW]
-    uint8_t* Fl = W + (size_t)rows16 * LW;                   // [rows16][32]
-    uint8_t* Gt = Fl + rows16 * ECHS_PW;                     // [32][32] Gt[s][t]: coefficient of original pivot row s in the panel's pivot row t
-    uint32_t* pb = (uint32_t*)(Gt + ECHS_PW * ECHS_PW);      // [32] published words, [32] reduced, -1/pivot
-    unsigned long long* mskb = (unsigned long long*)(pb + 72); // [2][4] candidate rows of each wave, by column parity
-    int* prl = (int*)(pb + 88);                              // pivot rows, pivot order
-    int* pcl = prl + 256;                                    // pivot columns
-    int* qrl = pcl + 256;                                    // non-pivot rows (outputs)
-    uint32_t* invt = (uint32_t*)(qrl + 256);                 // -1/v mod p
-    uint8_t* sel = (uint8_t*)(invt + 64);                    // row selected
-    uint8_t* inpanels = sel + 256;                           // [2][256] row a pivot of the panel, by panel parity
+    uint32_t* const pb = (uint32_t*)smem;
+    unsigned long long* const mskb = (unsigned long long*)(pb + 72);
+    int* const prl = (int*)(smem + ECHS_OFF_PRL);
+    int* const pcl = (int*)(smem + ECHS_OFF_PCL);
+    int* const qrl = (int*)(smem + ECHS_OFF_QRL);
+    uint32_t* const invt = (uint32_t*)(smem + ECHS_OFF_INVT);
+    uint8_t* const sel = smem + ECHS_OFF_SEL;
+    uint8_t* const inpanels = smem + ECHS_OFF_INP;
+    uint8_t* const Gt = smem + ECHS_OFF_GT;      // Gt[s][t]: coefficient of original pivot row s in the panel's pivot row t
+    uint8_t* const Fl = smem + ECHS_FIXED;       // [rows16][32]
+    uint8_t* const W = Fl + rows16 * ECHS_PW;    // [rows16][LW]
 
-    // invt[v] = -1/v mod p, by search (p <= 46)
-    if (x < 64) {
-        uint32_t iv = 0;
-        if (x > 0 && (uint32_t)x < p)
-            for (uint32_t j = 1; j < p; ++j)
-                if (mod22(__umul24((uint32_t)x, j), inv, p) == 1u) iv = p - j;
-        invt[x] = iv;
+    // -1/v mod p for v = lane (0 for v = 0 and v >= p): v^(p - 2) = 1/v (Fermat)
+    uint32_t ninv = 0;
+    {
+        uint32_t b = (uint32_t)lane < p ? (uint32_t)lane : 0u, a = 1u;
+        for (uint32_t ex = p - 2; ex; ex >>= 1) {
+            if (ex & 1u) a = mod22(a * b, inv, p);
+            b = mod22(b * b, inv, p);
+        }
+        ninv = (lane > 0 && (uint32_t)lane < p) ? p - a : 0u;
     }
+    if (x < 64) invt[x] = ninv;
     for (int i = x; i < 256; i += ECHS_THREADS) { sel[i] = 0; inpanels[i] = 0; inpanels[256 + i] = 0; }
     // W = [H | 0], rows beyond `rows` zero.  Thread x covers 16-byte chunks
-    // x, x + 256, ...; the loads of 8 chunks are in flight together.
+    // x, x + 512, ...; the loads of 8 chunks are in flight together.
     {
         const int cpr = LW >> 4;                     // chunks per row
         const int nch = rows16 * cpr;
@@ -1282,22 +1354,13 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
     __syncthreads();
 
     int r = 0;
-    bool my_sel = x >= rows;     // thread x owns row x for the whole elimination
-    int* const act = qrl;        // the panel's active rows (scratch until the outputs)
-    // ---- Pivot search by wave 0 alone, over the first (up to) 64 unselected
-    // rows, one per lane: no row after them can be a pivot while one of them
-    // is a candidate.  A column where none is, while later unselected rows
-    // exist, sends the panel to the four-wave elimination below.  Otherwise
-    // the panel's pivot rows are known as combinations G of the original
-    // rows, every other row x is cleared by the pivot rows with its own
-    // entries at the pivot columns as coefficients (the pivot rows are -1
-    // at their own pivot column and 0 at the others), and one MFMA pass
-    // applies it all, the panel's columns included.
-    // Panel c0's pivot search (wave 0) runs in the iteration of the panel
-    // before it, beside that panel's trailing update; the iteration at
-    // c0 = -32 only searches panel 0.  The two inpanel arrays alternate by
-    // panel, so the search can mark the next panel's pivots while the update
-    // still reads the current panel's.
+    bool my_sel = x >= rows;     // thread x < 256 owns row x in the four-wave elimination
+    int* const act = qrl;        // the search's candidate rows (scratch until the outputs)
+    // Panel c0's search (wave 0) runs in the iteration of the panel before
+    // it, beside that panel's trailing update; the iteration at c0 = -32 only
+    // searches panel 0.  The two inpanel arrays alternate by panel, so the
+    // search can mark the next panel's pivots while the update still reads
+    // the current panel's.
     for (int c0 = -ECHS_PW; c0 < cols && r < maxr; c0 += ECHS_PW) {
         const int pi = (c0 + ECHS_PW) / ECHS_PW;
         uint8_t* const inpanel = inpanels + 256 * (pi & 1);          // the current panel's pivots
@@ -1306,7 +1369,7 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
         int rp = 0, fast_rp = -1;
         if (c0 >= 0) {
             const int wc = min(ECHS_PW, cols - c0);
-            fast_rp = (int)pb[65];
+            fast_rp = __builtin_amdgcn_readfirstlane((int)pb[65]);
             my_sel = x >= rows || sel[x];
             if (fast_rp >= 0) {
                 rp = fast_rp;
@@ -1329,11 +1392,11 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
                     }
                     const long bv0 = *(const long*)(Gt + (lane & 15) * ECHS_PW + kq);
                     const long bv1 = *(const long*)(Gt + (16 + (lane & 15)) * ECHS_PW + kq);
-                    for (int rb = wave; rb < (rows16 >> 4); rb += ECHS_THREADS / 64) {
+                    for (int rb = wave; rb < nrb; rb += NW) {
                         const int row = rb * 16 + (lane & 15);
+                        const int ip = row < rows ? (int)inpanel[row] : 0;
                         uint64_t av = 0;
                         if (row < rows) {
-                            const int ip = inpanel[row];
                             const uint8_t* wr = W + (size_t)row * LW;
                             if (ip) {
                                 const int u = ip - 1 - kq;
@@ -1351,12 +1414,10 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
                         uint32_t w0 = 0, w1 = 0;
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
-                            w0 |= mod22((uint32_t)f0[j], inv, p) << (8 * j);
-                            w1 |= mod22((uint32_t)f1[j], inv, p) << (8 * j);
+                            w0 |= mod17((uint32_t)f0[j], inv17, p) << (8 * j);
+                            w1 |= mod17((uint32_t)f1[j], inv17, p) << (8 * j);
                         }
                         const int s0 = (lane >> 4) * 4;
-                        *(uint32_t*)(Fl + row * ECHS_PW + s0) = w0;
-                        *(uint32_t*)(Fl + row * ECHS_PW + 16 + s0) = w1;
                         if (row < rows) {
                             uint8_t* wt = W + (size_t)row * LW + TC + r;
 #pragma unroll
@@ -1365,35 +1426,26 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
                                 if (16 + s0 + j < rp) wt[16 + s0 + j] = (uint8_t)(w1 >> (8 * j));
                             }
                         }
+                        // the update adds F W[pivot rows] to every row: a pivot row's F is
+                        // G's row less its own unit vector
+                        if (ip) {
+                            w0 = echs_dec_byte(w0, ip - 1 - s0, p);
+                            w1 = echs_dec_byte(w1, ip - 1 - 16 - s0, p);
+                        }
+                        *(uint32_t*)(Fl + row * ECHS_PW + s0) = w0;
+                        *(uint32_t*)(Fl + row * ECHS_PW + 16 + s0) = w1;
                     }
                 }
             } else {
+                // Four-wave elimination of the panel (threads 0..255; the other
+                // waves take part in the barriers only)
                 const bool ok = x < rows;
-                // the row's panel entries: column k in half (k & 1) of word k / 2
                 uint32_t D[16], F[16];
                 uint32_t scale = 1;
                 int pidx = -1;
-                {
-                    uint4 a = make_uint4(0, 0, 0, 0), b = make_uint4(0, 0, 0, 0);
-                    if (ok) {
-                        a = *(const uint4*)(W + (size_t)x * LW + c0);
-                        b = *(const uint4*)(W + (size_t)x * LW + c0 + 16);
-                    }
-                    const uint32_t d[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+                echs_unpack_panel(W + (size_t)x * LW + c0, ok, wc, D);
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        uint32_t lo = __builtin_amdgcn_perm(0u, d[i], 0x0c010c00u);
-                        uint32_t hi = __builtin_amdgcn_perm(0u, d[i], 0x0c030c02u);
-                        if (wc < ECHS_PW) {   // columns past the block hold other data: clear them
-                            if (4 * i >= wc) lo &= 0u; else if (4 * i + 1 >= wc) lo &= 0xffffu;
-                            if (4 * i + 2 >= wc) hi &= 0u; else if (4 * i + 3 >= wc) hi &= 0xffffu;
-                        }
-                        D[2 * i] = lo;
-                        D[2 * i + 1] = hi;
-                    }
-#pragma unroll
-                    for (int w = 0; w < 16; ++w) F[w] = 0;
-                }
+                for (int w = 0; w < 16; ++w) F[w] = 0;
                 // Column k of the panel (k static, so every register index is).  Every
                 // decision below is taken from LDS values all threads read alike, so
                 // rp stays uniform.
@@ -1405,7 +1457,7 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
                     const unsigned long long bm = __ballot(!my_sel && red != 0u);
                     // by column parity: a column without a pivot has no second barrier
                     unsigned long long* msk = mskb + 4 * (k & 1);
-                    if (lane == 0) msk[wave] = bm;
+                    if (lane == 0 && wave < 4) msk[wave] = bm;
                     __syncthreads();
                     const unsigned long long m0w = msk[0], m1w = msk[1], m2w = msk[2], m3w = msk[3];
                     const int Q = m0w ? 0 : m1w ? 1 : m2w ? 2 : m3w ? 3 : -1;
@@ -1429,9 +1481,7 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
                     }
                     if (wave == Q) {
                         // the pivot's wave reduces the 64 published entries, one per lane
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        wave_sync();
                         ((uint16_t*)(pb + 32))[lane] = (uint16_t)mod22(((const uint16_t*)pb)[lane], inv, p);
                     }
                     __syncthreads();
@@ -1461,6 +1511,7 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
                     }
                     ++rp;
                 });
+                rp = __builtin_amdgcn_readfirstlane(rp);
                 // reduce, give the pivot row its own transformation entry 1 and scale
                 // it to pivot -1, then write the panel, F (for the MFMA) and the new
                 // transformation columns (F itself) back to LDS
@@ -1491,11 +1542,15 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
                         for (int j = 0; j < ECHS_PW; ++j)
                             if (j < wc) wr[c0 + j] = (uint8_t)(pk[j >> 2] >> (8 * (j & 3)));
                     }
-                    *(uint4*)(Fl + x * ECHS_PW) = make_uint4(fk[0], fk[1], fk[2], fk[3]);
-                    *(uint4*)(Fl + x * ECHS_PW + 16) = make_uint4(fk[4], fk[5], fk[6], fk[7]);
 #pragma unroll
                     for (int t = 0; t < ECHS_PW; ++t)
                         if (t < rp) wr[TC + r + t] = (uint8_t)(fk[t >> 2] >> (8 * (t & 3)));
+                    if (pidx >= 0) {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) fk[i] = echs_dec_byte(fk[i], pidx - 4 * i, p);
+                    }
+                    *(uint4*)(Fl + x * ECHS_PW) = make_uint4(fk[0], fk[1], fk[2], fk[3]);
+                    *(uint4*)(Fl + x * ECHS_PW + 16) = make_uint4(fk[4], fk[5], fk[6], fk[7]);
                 } else if (x < rows16) {   // rows past `rows` (padding of the MFMA tiles)
                     *(uint4*)(Fl + x * ECHS_PW) = make_uint4(0, 0, 0, 0);
                     *(uint4*)(Fl + x * ECHS_PW + 16) = make_uint4(0, 0, 0, 0);
@@ -1505,80 +1560,84 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
         }
         const bool next = nc0 < cols && r + rp < maxr;
         if (rp > 0) {
-            // Trailing update, in chunks of 32 columns, each chunk by one wave over
-            // all rows: segment 0 the data columns from the panel on (from the
-            // next panel when the four-wave elimination has written this one),
-            // segment 1 the transformation columns of earlier pivots.  The MFMA's
-            // B operand (16 columns x 8 pivots per group of 16 lanes) is read
-            // from the pivot rows themselves with ds_read_b64_tr_b8 before the
-            // wave writes any of its columns; no other wave touches them.  When
-            // there is a next panel, wave 0 updates its columns first and then
-            // searches it while waves 1 to 3 update the rest.
+            // Trailing update in units of 16 columns: units [0, n0u) the data
+            // columns from ybeg on (from the next panel when the four-wave
+            // elimination has written this one), units [n0u, nu) the
+            // transformation columns of earlier pivots.  Lane l's B operand is
+            // 8 bytes of pivot row kk at column y0 + 8 (l & 1); the MFMA gives
+            // lane l the row rb * 16 + (l & 15) at columns 4 (l / 16) .. + 3.
             const int ybeg = fast_rp >= 0 ? c0 : nc0;
-            const int n0c = ybeg < cols ? (cols - ybeg + ECHS_CH - 1) / ECHS_CH : 0;
-            const int nch = n0c + (r + ECHS_CH - 1) / ECHS_CH;
-            const int qn = (nc0 - ybeg) / ECHS_CH;     // the next panel's chunk
+            const int n0u = ybeg < cols ? (cols - ybeg + 15) >> 4 : 0;
+            const int nu = n0u + ((r + 15) >> 4);
             const int kk = (lane >> 4) * 8 + ((lane & 15) >> 1);
             const int po = (kk < rp ? prl[r + kk] : prl[r]) * LW + ((lane & 1) << 3);
-            const auto chunk = [&](int q) {
-                int y0, nc;
-                if (q < n0c) {
-                    y0 = ybeg + q * ECHS_CH;
-                    nc = min(ECHS_CH, cols - y0);
+            const int cc = (lane >> 4) * 4;
+            const auto ucol = [&](int u, int& y0, int& nc) {
+                if (u < n0u) {
+                    y0 = ybeg + 16 * u;
+                    nc = min(16, cols - y0);
                 } else {
-                    y0 = TC + (q - n0c) * ECHS_CH;
-                    nc = min(ECHS_CH, TC + r - y0);
-                }
-                const long b0 = __builtin_bit_cast(long, lds_read_tr8(W + po + y0));
-                const long b1 = __builtin_bit_cast(long, lds_read_tr8(W + po + y0 + 16));
-                for (int rb = 0; rb < (rows16 >> 4); ++rb) {
-                    const int row = rb * 16 + (lane & 15);
-                    const long av = *(const long*)(Fl + row * ECHS_PW + (lane >> 4) * 8);
-                    v4i acc[2];
-                    acc[0] = __builtin_amdgcn_mfma_i32_16x16x32_i8(b0, av, v4i{0, 0, 0, 0}, 0, 0, 0);
-                    acc[1] = nc > 16 ? __builtin_amdgcn_mfma_i32_16x16x32_i8(b1, av, v4i{0, 0, 0, 0}, 0, 0, 0)
-                                     : v4i{0, 0, 0, 0};
-                    if (row < rows) {
-                        const bool keep = !inpanel[row];
-                        uint32_t* wrow = (uint32_t*)(W + (size_t)row * LW + y0);
-#pragma unroll
-                        for (int cb = 0; cb < 2; ++cb) {
-                            const int cc = cb * 16 + (lane >> 4) * 4;
-                            if (cc < nc) {
-                                const uint32_t old = wrow[cc >> 2];
-                                uint32_t out = 0;
-#pragma unroll
-                                for (int j = 0; j < 4; ++j) {
-                                    const uint32_t ob = (old >> (8 * j)) & 0xffu;
-                                    const uint32_t nv = mod22((keep ? ob : 0u) + (uint32_t)acc[cb][j], inv, p);
-                                    out |= (cc + j < nc ? nv : ob) << (8 * j);
-                                }
-                                wrow[cc >> 2] = out;
-                            }
-                        }
-                    }
+                    y0 = TC + 16 * (u - n0u);
+                    nc = min(16, TC + r - y0);
                 }
             };
-            if (next) {
-                if (wave == 0) {
-                    chunk(qn);
-                } else {
-                    for (int j = wave - 1;; j += 3) {
-                        const int q = j + (j >= qn ? 1 : 0);
-                        if (q >= nch) break;
-                        chunk(q);
-                    }
+            const auto bfrag = [&](int y0) { return __builtin_bit_cast(long, lds_read_tr8(W + po + y0)); };
+            // W[row][y0 + cc + j] += sum_t F[row][t] W[pivot row t][y0 + cc + j]: the
+            // old bytes enter as the MFMA's accumulator; bytes past the unit's nc
+            // columns are kept
+            const auto apply = [&](int y0, int nc, long b, int rb) {
+                const int row = rb * 16 + (lane & 15);
+                const long av = *(const long*)(Fl + row * ECHS_PW + (lane >> 4) * 8);
+                uint32_t* wp = (uint32_t*)(W + (size_t)row * LW + y0 + cc);
+                const uint32_t old = *wp;
+                const v4i c = {(int)(old & 0xffu), (int)((old >> 8) & 0xffu), (int)((old >> 16) & 0xffu),
+                               (int)(old >> 24)};
+                const v4i acc = __builtin_amdgcn_mfma_i32_16x16x32_i8(b, av, c, 0, 0, 0);
+                if (row < rows && cc < nc) {
+                    uint32_t out = 0;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) out |= mod17((uint32_t)acc[j], inv17, p) << (8 * j);
+                    const uint32_t keep = nc - cc >= 4 ? 0u : 0xffffffffu << (8 * (nc - cc));
+                    *wp = (out & ~keep) | (old & keep);
                 }
+            };
+            const auto unit = [&](int u) {      // one unit, every row, by one wave
+                int y0, nc;
+                ucol(u, y0, nc);
+                const long b = bfrag(y0);
+#pragma unroll 2
+                for (int rb = 0; rb < nrb; ++rb) apply(y0, nc, b, rb);
+            };
+            if (next) {
+                // the next panel's columns (units qa and qa + 1) first, by rows over
+                // all waves; every wave reads its B operands before any wave writes
+                const int qa = (nc0 - ybeg) >> 4;
+                const bool two = qa + 1 < n0u;
+                int ya, na, yb = 0, nb = 0;
+                ucol(qa, ya, na);
+                if (two) ucol(qa + 1, yb, nb);
+                const long ba = bfrag(ya);
+                const long bb = two ? bfrag(yb) : 0;
+                __syncthreads();
+                for (int rb = wave; rb < nrb; rb += NW) {
+                    apply(ya, na, ba, rb);
+                    if (two) apply(yb, nb, bb, rb);
+                }
+                __syncthreads();
+                // the other units, one wave each, beside the search
+                const int skip = two ? 2 : 1;
+                for (int i = wave - 1; wave > 0 && i < nu - skip; i += NW - 1) unit(i < qa ? i : i + skip);
             } else {
-                for (int q = wave; q < nch; q += 4) chunk(q);
+                for (int u = wave; u < nu; u += NW) unit(u);
             }
         }
         if (next && wave == 0) {
             // the next panel's columns are final: search it
+            __builtin_amdgcn_s_setprio(3);
             const int c0 = nc0, r_nx = r + rp;
             const int r = r_nx;
             uint8_t* const inpanel = inpanel_nx;
-            const int wc = min(ECHS_PW, cols - c0);
+            const int wc = __builtin_amdgcn_readfirstlane(min(ECHS_PW, cols - c0));
             int total = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -1589,90 +1648,72 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
                 if (un && pos < 64) act[pos] = row;
                 total += __popcll(bq);
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            wave_sync();
             const int arow = lane < total ? act[lane] : -1;
             const bool spill = total > 64;
             uint32_t D[16], F[16];
-            {
-                uint4 a = make_uint4(0, 0, 0, 0), b = make_uint4(0, 0, 0, 0);
-                if (arow >= 0) {
-                    a = *(const uint4*)(W + (size_t)arow * LW + c0);
-                    b = *(const uint4*)(W + (size_t)arow * LW + c0 + 16);
-                }
-                const uint32_t d[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+            echs_unpack_panel(W + (size_t)(arow >= 0 ? arow : 0) * LW + c0, arow >= 0, wc, D);
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    uint32_t lo = __builtin_amdgcn_perm(0u, d[i], 0x0c010c00u);
-                    uint32_t hi = __builtin_amdgcn_perm(0u, d[i], 0x0c030c02u);
-                    if (wc < ECHS_PW) {
-                        if (4 * i >= wc) lo &= 0u; else if (4 * i + 1 >= wc) lo &= 0xffffu;
-                        if (4 * i + 2 >= wc) hi &= 0u; else if (4 * i + 3 >= wc) hi &= 0xffffu;
-                    }
-                    D[2 * i] = lo;
-                    D[2 * i + 1] = hi;
-                }
-#pragma unroll
-                for (int w = 0; w < 16; ++w) F[w] = 0;
-            }
-            bool asel = arow < 0, fb = false;
+            for (int w = 0; w < 16; ++w) F[w] = 0;
+            // selected lanes (a lane without a candidate row counts as one), as a mask
+            unsigned long long selm = __ballot(arow < 0);
+            bool nocand = false;   // a column of the block where no candidate is non-zero
             uint32_t scale = 1;
-            int pidx = -1, pcolk = 0, rpa = 0;
-            static_for<0, ECHS_PW>([&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                if (fb || k >= wc || r + rpa >= maxr) return;
-                constexpr int wk = k >> 1, hk = 16 * (k & 1);
-                const uint32_t red = mod22((D[wk] >> hk) & 0xffffu, inv, p);
-                const unsigned long long bm = __ballot(!asel && red != 0u);
-                if (!bm) {
-                    if (spill) fb = true;
-                    return;
-                }
-                const bool me = lane == __ffsll((long long)bm) - 1;
-                if (me) {
-                    const uint32_t sv = invt[red];
-                    const uint32_t one = 1u << (16 * (rpa & 1));
+            int pidx = -1, rpa = 0;
+            // Steps in groups of 8; a group runs while the panel has columns left
+            // and some candidate is unselected.  Within a group every step runs,
+            // branch-free: past the panel's columns (zeroed by the unpacking) no
+            // lane is a candidate and the step changes nothing.
+            static_for<0, ECHS_PW / 8>([&](auto gc) {
+                constexpr int g = decltype(gc)::value;
+                if (__builtin_amdgcn_readfirstlane((int)(8 * g >= wc || selm == ~0ull))) return;
+                static_for<8 * g, 8 * g + 8>([&](auto kc) {
+                    constexpr int k = decltype(kc)::value;
+                    constexpr int wk = k >> 1, hk = 16 * (k & 1);
+                    const uint32_t red = mod17((D[wk] >> hk) & 0xffffu, inv17, p);
+                    const unsigned long long bm = __ballot(red != 0u) & ~selm;
+                    nocand = nocand | ((bm == 0) & (k < wc));
+                    const int P = bm ? __ffsll((long long)bm) - 1 : 0;
+                    const bool me = bm != 0 && lane == P;
+                    const uint32_t sv = __builtin_amdgcn_readlane(ninv, __builtin_amdgcn_readlane(red, P));
+                    if (me) {
 #pragma unroll
-                    for (int w = 0; w < 16; w += 4) {
-                        *(uint4*)(pb + w) = make_uint4(D[w], D[w + 1], D[w + 2], D[w + 3]);
-                        *(uint4*)(pb + 16 + w) = make_uint4(
-                            F[w] + (w == (rpa >> 1) ? one : 0u), F[w + 1] + (w + 1 == (rpa >> 1) ? one : 0u),
-                            F[w + 2] + (w + 2 == (rpa >> 1) ? one : 0u), F[w + 3] + (w + 3 == (rpa >> 1) ? one : 0u));
+                        for (int w = 0; w < 16; w += 4) {
+                            *(uint4*)(pb + w) = make_uint4(D[w], D[w + 1], D[w + 2], D[w + 3]);
+                            *(uint4*)(pb + 16 + w) = make_uint4(F[w], F[w + 1], F[w + 2], F[w + 3]);
+                        }
+                        prl[r + rpa] = arow;
+                        pcl[r + rpa] = c0 + k;
                     }
-                    pb[64] = sv;
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                ((uint16_t*)(pb + 32))[lane] = (uint16_t)mod22(((const uint16_t*)pb)[lane], inv, p);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                uint32_t pv[32];
+                    wave_sync();
+                    // lane j reduces published entry j; the pivot's own transformation
+                    // entry (index 32 + rpa, zero so far) becomes 1
+                    ((uint16_t*)(pb + 32))[lane] =
+                        (uint16_t)(mod17(((const uint16_t*)pb)[lane], inv17, p) + (lane == 32 + rpa ? 1u : 0u));
+                    wave_sync();
+                    uint32_t pv[32];
 #pragma unroll
-                for (int w = 0; w < 32; w += 4) {
-                    const uint4 t4 = *(const uint4*)(pb + 32 + w);
-                    pv[w] = t4.x; pv[w + 1] = t4.y; pv[w + 2] = t4.z; pv[w + 3] = t4.w;
-                }
-                const uint32_t sv = pb[64];
-                const uint32_t f2 = (me ? 0u : mod22(__umul24(red, sv), inv, p)) * 0x10001u;
+                    for (int w = 0; w < 32; w += 4) {
+                        const uint4 t4 = *(const uint4*)(pb + 32 + w);
+                        pv[w] = t4.x; pv[w + 1] = t4.y; pv[w + 2] = t4.z; pv[w + 3] = t4.w;
+                    }
+                    const uint32_t f = mod17(__umul24(red, sv), inv17, p);
+                    const uint32_t f2 = (bm != 0 && !me) ? f * 0x10001u : 0u;
 #pragma unroll
-                for (int w = wk; w < 16; ++w) D[w] = pkmad16(f2, pv[w], D[w]);
+                    for (int w = wk; w < 16; ++w) D[w] = pkmad16(f2, pv[w], D[w]);
 #pragma unroll
-                for (int w = 0; w <= wk; ++w) F[w] = pkmad16(f2, pv[16 + w], F[w]);
-                if (me) {
-                    asel = true;
-                    scale = sv;
-                    pidx = rpa;
-                    pcolk = k;
-                }
-                ++rpa;
-                // the next step publishes into pb again: every lane has read it
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    for (int w = 0; w <= wk; ++w) F[w] = pkmad16(f2, pv[16 + w], F[w]);
+                    scale = me ? sv : scale;
+                    pidx = me ? rpa : pidx;
+                    selm |= bm & (~bm + 1ull);
+                    rpa = __builtin_amdgcn_readfirstlane(rpa + (bm != 0 ? 1 : 0));
+                    wave_sync();
+                });
             });
+            __builtin_amdgcn_s_setprio(0);
+            // no candidate in a column of the block while later unselected rows
+            // exist: the four-wave elimination takes the panel
+            const bool fb = spill && nocand;
             if (!fb && pidx >= 0) {
                 // G row pidx = scale (F + e_pidx), reduced, as 16 words of 16-bit pairs
 #pragma unroll
@@ -1681,15 +1722,13 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
                     uint32_t lo = fw & 0xffffu, hi = fw >> 16;
                     if (2 * w == pidx) lo += 1;
                     if (2 * w + 1 == pidx) hi += 1;
-                    F[w] = mod22(__umul24(lo, scale), inv, p) | (mod22(__umul24(hi, scale), inv, p) << 16);
+                    F[w] = mod22(__umul24(lo, scale), inv, p) | (mod22(__umul24(hi, scale), inv, p) << 16);   // lo, hi < 2^16
                 }
 #pragma unroll
                 for (int w = 0; w < 16; ++w) {
                     Gt[(2 * w) * ECHS_PW + pidx] = (uint8_t)F[w];
                     Gt[(2 * w + 1) * ECHS_PW + pidx] = (uint8_t)(F[w] >> 16);
                 }
-                prl[r + pidx] = arow;
-                pcl[r + pidx] = c0 + pcolk;
                 sel[arow] = 1;
                 inpanel[arow] = (uint8_t)(pidx + 1);
             }
@@ -1700,6 +1739,9 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
         r += rp;
     }
     // ---- outputs
+    const int nq = cols - r;
+    int* const qcl = (int*)Fl;                       // the non-pivot columns, when they fit
+    const bool qin = nq <= rows16 * (ECHS_PW / 4);
     if (x == 0) *e.rcount = r;
     for (int t = x; t < r; t += ECHS_THREADS) {
         e.prow[t] = prl[t];
@@ -1719,33 +1761,58 @@ __global__ void __launch_bounds__(ECHS_THREADS) k_ech_lds(Src src) {
             base += __popcll(bq);
         }
     }
-    if (wave == 1) {
-        int base = 0;
-        for (int y0 = 0; y0 < cols; y0 += 64) {
-            const int y = y0 + lane;
-            int lo = 0, hi = r;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (pcl[mid] < y) lo = mid + 1; else hi = mid;
-            }
-            const bool np = y < cols && !(lo < r && pcl[lo] == y);
-            const unsigned long long bq = __ballot(np);
-            if (np) e.qcol[base + __popcll(bq & ((1ull << lane) - 1))] = y;
-            base += __popcll(bq);
+    // the non-pivot columns: column y, not a pivot, goes to position y less the
+    // number of pivot columns before it (pcl is increasing)
+    for (int y = x; y < cols; y += ECHS_THREADS) {
+        int lo = 0, hi = r;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (pcl[mid] < y) lo = mid + 1; else hi = mid;
         }
-        for (int y = lane; y < e.qtail; y += 64) e.qcol[base + y] = cols + y;
+        if (!(lo < r && pcl[lo] == y)) {
+            e.qcol[y - lo] = y;
+            if (qin) qcl[y - lo] = y;
+        }
     }
+    for (int y = x; y < e.qtail; y += ECHS_THREADS) e.qcol[nq + y] = cols + y;
     __syncthreads();
-    // M (rows of the pivots), K (non-pivot rows), R (pivot rows at the non-pivot columns)
-    for (int t = wave; t < r; t += ECHS_THREADS / 64) {
-        const uint8_t* wr = W + (size_t)prl[t] * LW;
-        for (int u = lane; u < r; u += 64) gstore<uint8_t>(e.Mo + (int64_t)t * e.ldm + u, wr[TC + u]);
-        for (int k2 = lane; k2 < cols - r; k2 += 64)
-            gstore<uint8_t>(e.Ro + (int64_t)t * e.ldr + k2, wr[gload<int32_t>(e.qcol + k2)]);
+    // M (rows of the pivots) and K (non-pivot rows) at the transformation
+    // columns, 16 bytes per thread; R (pivot rows at the non-pivot columns),
+    // 4 bytes per thread
+    const int mch = (r + 15) >> 4;
+    const bool mal = ((((uintptr_t)e.Mo) | (uintptr_t)e.ldm) & 15) == 0;
+    const bool kal = ((((uintptr_t)e.Ko) | (uintptr_t)e.ldk) & 15) == 0;
+    for (int i = x; i < rows * mch; i += ECHS_THREADS) {
+        const int t = i / mch, c = i - t * mch;
+        const bool piv = t < r;
+        const int src_row = piv ? prl[t] : qrl[t - r];
+        uint8_t* dst = piv ? e.Mo + (int64_t)t * e.ldm : e.Ko + (int64_t)(t - r) * e.ldk;
+        const uint4 v = *(const uint4*)(W + (size_t)src_row * LW + TC + 16 * c);
+        const int nb = min(16, r - 16 * c);
+        if (nb == 16 && (piv ? mal : kal)) {
+            gstore<uint4>(dst + 16 * c, v);
+        } else {
+            const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+            for (int j = 0; j < nb; ++j) gstore<uint8_t>(dst + 16 * c + j, (uint8_t)(wv[j >> 2] >> (8 * (j & 3))));
+        }
     }
-    for (int s2 = wave; s2 < rows - r; s2 += ECHS_THREADS / 64) {
-        const uint8_t* wr = W + (size_t)qrl[s2] * LW + TC;
-        for (int u = lane; u < r; u += 64) gstore<uint8_t>(e.Ko + (int64_t)s2 * e.ldk + u, wr[u]);
+    const int rch = (nq + 3) >> 2;
+    const bool ral = ((((uintptr_t)e.Ro) | (uintptr_t)e.ldr) & 3) == 0;
+    for (int i = x; i < r * rch; i += ECHS_THREADS) {
+        const int t = i / rch, k2 = 4 * (i - t * rch);
+        const uint8_t* wr = W + (size_t)prl[t] * LW;
+        const int nb = min(4, nq - k2);
+        uint32_t v = 0;
+        for (int j = 0; j < nb; ++j) {
+            const int qc = qin ? qcl[k2 + j] : gload<int32_t>(e.qcol + k2 + j);
+            v |= (uint32_t)wr[qc] << (8 * j);
+        }
+        uint8_t* dst = e.Ro + (int64_t)t * e.ldr + k2;
+        if (nb == 4 && ral) {
+            gstore<uint32_t>(dst, v);
+        } else {
+            for (int j = 0; j < nb; ++j) gstore<uint8_t>(dst + j, (uint8_t)(v >> (8 * j)));
+        }
     }
 }
 
