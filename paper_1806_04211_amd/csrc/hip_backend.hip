@@ -2245,6 +2245,7 @@ public:
     int32_t* counts_buffer(size_t n) override {
         if (n > counts_cap_) {
             sync_all();
+            pending_.clear();
             if (counts_host_) (void)hipHostFree(counts_host_);
             counts_host_ = nullptr;
             counts_dev_ = nullptr;
@@ -2266,10 +2267,45 @@ public:
         }
         return counts_dev_;
     }
+    // The ECH kernels write each pivot count straight into the pinned counts
+    // buffer, once, with its final value.  ech() sets the slots it launches for
+    // to -1 first; read_counts then polls those slots instead of sleeping in a
+    // stream synchronisation (whose wake-up came tens of microseconds after
+    // the kernel on this chain), asking the stream every 64 polls, so that a
+    // failed launch or a finished stream ends the wait.  The work queued after
+    // the ECH stays ordered behind it on its stream.
     void read_counts(int32_t* host, const int32_t* counts, size_t n) override {
+        if (counts == counts_dev_ && n <= counts_cap_) {
+            if (pending_.empty()) HIP_OK(hipStreamSynchronize(stream_));
+            else wait_pending();
+            for (size_t k = 0; k < n; ++k) host[k] = __atomic_load_n(counts_host_ + k, __ATOMIC_ACQUIRE);
+            return;
+        }
         HIP_OK(hipStreamSynchronize(stream_));
-        if (counts == counts_dev_ && n <= counts_cap_) memcpy(host, counts_host_, sizeof(int32_t) * n);
-        else download(host, counts, sizeof(int32_t) * n);
+        download(host, counts, sizeof(int32_t) * n);
+    }
+    void wait_pending() {
+        for (uint64_t spin = 1;; ++spin) {
+            bool ready = true;
+            for (size_t k : pending_)
+                if (__atomic_load_n(counts_host_ + k, __ATOMIC_ACQUIRE) < 0) {
+                    ready = false;
+                    break;
+                }
+            if (ready) break;
+            if ((spin & 63) == 0) {
+                const hipError_t q = hipStreamQuery(stream_);
+                if (q == hipErrorNotReady) continue;
+                HIP_OK(q);
+                // the stream is idle: every count it was going to write is there
+                for (size_t k : pending_)
+                    if (__atomic_load_n(counts_host_ + k, __ATOMIC_ACQUIRE) < 0)
+                        note_error(hipErrorUnknown, "pivot count missing");
+                break;
+            }
+            __builtin_ia32_pause();
+        }
+        pending_.clear();
     }
     void release_counts(int32_t*) override {}
     void set_stream(void* s) override {
@@ -2383,6 +2419,14 @@ public:
 
     void ech(const std::vector<EchDesc>& ds) override {
         if (ds.empty()) return;
+        // the slots these ECHs write in the pinned counts buffer: -1 until written
+        for (const EchDesc& e : ds) {
+            if (e.rcount >= counts_dev_ && e.rcount < counts_dev_ + counts_cap_) {
+                const size_t k = (size_t)(e.rcount - counts_dev_);
+                __atomic_store_n(counts_host_ + k, -1, __ATOMIC_RELEASE);
+                pending_.push_back(k);
+            }
+        }
         // blocks of at most 256 rows over p <= 46 whose working matrix fits in
         // LDS: k_ech_lds; the others below
         std::vector<EchDesc> lds, rest;
@@ -2638,6 +2682,7 @@ private:
     std::vector<hipEvent_t> marks_, mark_pool_;
     int32_t* counts_host_ = nullptr;   // counts_buffer(): host view
     int32_t* counts_dev_ = nullptr;    // and device view
+    std::vector<size_t> pending_;      // slots of counts_host_ an ECH queued since the last read will write
     size_t counts_cap_ = 0;
     int mark_base_ = 0;              // id of marks_[0]
     size_t echs_lds_max_ = 0;        // LDS the LDS-resident ECH may use
