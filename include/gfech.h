@@ -204,6 +204,12 @@ typedef struct gfech_stats {
      * (all of them at level 2, about a quarter at level 3) */
     double mac_mad_timed;
     int64_t variant;        /* the GFECH_WANT_* the result was computed for */
+    /* ClearDowns whose ECH of the leading columns of a wide block left rows
+     * unselected: tail_checks of them found those rows reduced to zero on the
+     * remaining columns (the result stands, no second ECH); ech_reruns ran
+     * the ECH again on the whole block (Section 2.3.2 splits ech by columns
+     * the same way) */
+    int64_t tail_checks, ech_reruns;
 } gfech_stats;
 gfech_status gfech_get_stats(const gfech_result* res, gfech_stats* stats);
 

@@ -40,7 +40,8 @@ class Stats(ctypes.Structure):
                 ("block_rows", c_i64), ("block_cols", c_i64),
                 ("ms_mad", ctypes.c_double), ("ms_ech", ctypes.c_double), ("ms_small", ctypes.c_double),
                 ("launches_mad", c_i64), ("launches_ech", c_i64), ("launches_small", c_i64),
-                ("mad_bytes", ctypes.c_double), ("mac_mad_timed", ctypes.c_double), ("variant", c_i64)]
+                ("mad_bytes", ctypes.c_double), ("mac_mad_timed", ctypes.c_double), ("variant", c_i64),
+                ("tail_checks", c_i64), ("ech_reruns", c_i64)]
 
 
 class ServerCfg(ctypes.Structure):

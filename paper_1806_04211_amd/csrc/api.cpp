@@ -585,6 +585,8 @@ gfech_status gfech_get_stats(const gfech_result* res, gfech_stats* s) {
     s->mad_bytes = t.mad_bytes;
     s->mac_mad_timed = t.kernel_mac[0];
     s->variant = res->r->want;
+    s->tail_checks = t.tail_checks;
+    s->ech_reruns = t.ech_reruns;
     return GFECH_OK;
 }
 

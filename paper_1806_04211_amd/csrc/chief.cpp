@@ -440,6 +440,7 @@ public:
             st_.ech += (double)t.alpha * t.w * t.rp;
             if (rerun_pass) {
                 t.rerun = false;
+                st_.ech_reruns += 1;
             } else {
                 st_.echs += 1;
                 t.rerun = t.split && t.rp < t.alpha;
@@ -451,6 +452,65 @@ public:
 
     void clear_counts() {
         for (auto& t : tasks_) t.rp = 0;
+    }
+
+    // A task whose ECH of the leading t.w columns left rows unselected (t.rerun):
+    // by the identity of Remark 2.3 on the leading columns, K H[rho'] + H[rho'-bar]
+    // vanishes there, and the rows rho'-bar reduced by the pivot rows found are
+    // Z = K H[rho', tail] + H[rho'-bar, tail] on the columns after them.  When
+    // Z is zero no column after the leading ones holds a pivot (Section 2.3.2's
+    // splitting of ech by columns, with an empty second half): the result of the
+    // leading columns stands as for a full selection (its K already reduces
+    // rho'-bar to zero on every column; the remnant product of cd_post gives R's
+    // columns after them), and the ECH need not run again on all of H.  Z goes
+    // to the ECH workspace (no ECH reads it now).
+    void cd_tail(Ops& ops) {
+        for (auto& t : tasks_) {
+            if (!t.rerun || t.rp == 0) continue;
+            BC& bc = cols_[t.j];
+            const int32_t bj = pr_.col_blocks[t.j];
+            GemmDesc g;
+            g.M = t.alpha - t.rp; g.N = bj - t.r - t.w; g.K = t.rp; g.p = p_;
+            g.A = bc.AK[t.par]; g.lda = bj;
+            g.B = t.H + t.w; g.ldb = t.ldh; g.brow = bc.Prow[t.par];
+            g.C = t.H + t.w; g.ldc = t.ldh; g.crow = bc.Qrow[t.par];
+            g.D = bc.W; g.ldd = bc.ldW;
+            push_gemm(ops, g, st_.cd_mad);
+        }
+    }
+    // one range check per task of cd_tail (p = 1 counts the non-zero entries of
+    // Z; with no pivot among the leading columns Z is the tail of H itself)
+    void tail_ranges(std::vector<Backend::RangeDesc>& rd) const {
+        for (auto& t : tasks_) {
+            if (!t.rerun) continue;
+            const BC& bc = cols_[t.j];
+            Backend::RangeDesc d;
+            if (t.rp > 0) {
+                d.A = bc.W; d.m = t.alpha - t.rp; d.lda = bc.ldW;
+            } else {
+                d.A = t.H + t.w; d.m = t.alpha; d.lda = t.ldh;
+            }
+            d.n = pr_.col_blocks[t.j] - t.r - t.w;
+            d.p = 1;
+            rd.push_back(d);
+        }
+    }
+    // the counts in the order of tail_ranges, from nz[pos] on; returns true
+    // when some task still needs the ECH on all of H
+    bool absorb_tail(const std::vector<int64_t>& nz, size_t& pos) {
+        bool again = false;
+        for (auto& t : tasks_) {
+            if (!t.rerun) continue;
+            const int64_t c = pos < nz.size() ? nz[pos] : -1;
+            ++pos;
+            if (c == 0) {
+                t.rerun = false;
+                st_.tail_checks += 1;
+            } else {
+                again = true;
+            }
+        }
+        return again;
     }
 
     // ClearDown after ECH: CEX of D.R by gamma' (A.E and R'), UNH on D.gamma, Extend on E.rho
@@ -1401,6 +1461,22 @@ struct Engine::Impl {
                 bool again = false;
                 for (auto& j : jobs)
                     if (j->phase == kStep1) again = j->plan->absorb_counts(hcounts.data() + j->counts_off, false) || again;
+                if (again) {
+                    // the rows left unselected: reduced by the pivots found, are
+                    // they zero after the leading columns?  Only where not, the
+                    // ECH runs again on all of H
+                    for (Plan* pl : s1) pl->cd_tail(ops);
+                    flush(be, ops, shared);
+                    std::vector<Backend::RangeDesc> rd;
+                    for (Plan* pl : s1) pl->tail_ranges(rd);
+                    std::vector<int64_t> nz;
+                    be.count_out_of_range_many(rd, nz);
+                    shared.syncs++;
+                    if (be.error()) { fail_all(be.error()); return 0; }
+                    size_t pos = 0;
+                    again = false;
+                    for (Plan* pl : s1) again = pl->absorb_tail(nz, pos) || again;
+                }
                 if (again) {
                     for (Plan* pl : s1) pl->cd_ech(ops, true);
                     flush(be, ops, shared);

@@ -23,6 +23,10 @@ struct Stats {
     double gather_bytes = 0;   // bytes moved by extracts / riffles / copies
     double mad_bytes = 0;      // operand bytes of the MAD launches: A, B, C read once, D written once
     int64_t layers = 0, echs = 0, gemms = 0, launches = 0, syncs = 0;
+    // ClearDowns whose ECH of the leading columns left rows unselected: those
+    // whose remnant after them was zero (no second ECH), and those whose ECH
+    // ran again on the whole block
+    int64_t tail_checks = 0, ech_reruns = 0;
     // kernel time by kind when profiling was requested (device events): gemm, ech, small jobs
     double kernel_ms[3] = {0, 0, 0};
     int64_t kernel_launches[3] = {0, 0, 0};

@@ -1833,6 +1833,7 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_gather(Src src) {
     // a column map onto 16-byte aligned destination rows: by chunks (below)
     const bool runs = !g.dcol && !g.neg_p && g.scol && ((((uintptr_t)g.dst) | (uintptr_t)g.ldd) & 15) == 0 &&
                       ((((uintptr_t)g.src) | (uintptr_t)g.lds) & 3) == 0;
+    const bool sal = (((uintptr_t)g.scol) & 15) == 0;
     for (int x = blockIdx.x; x < g.rows; x += gridDim.x) {
         const int64_t sr = g.srow ? gload<int32_t>(g.srow + x) : x;
         const int64_t dr = g.drow ? gload<int32_t>(g.drow + x) : x;
@@ -1872,8 +1873,16 @@ __global__ void __launch_bounds__(SMALL_THREADS) k_gather(Src src) {
             for (int y = threadIdx.x * 16; y < g.cols; y += SMALL_THREADS * 16) {
                 if (y + 16 <= g.cols) {
                     int32_t ix[16];
+                    if (sal) {     // the 16 column numbers as four 16-byte loads
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) ix[i] = gload<int32_t>(g.scol + y + i);
+                        for (int i = 0; i < 16; i += 4) {
+                            const uint4 q = gload<uint4>(g.scol + y + i);
+                            ix[i] = (int32_t)q.x; ix[i + 1] = (int32_t)q.y; ix[i + 2] = (int32_t)q.z; ix[i + 3] = (int32_t)q.w;
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) ix[i] = gload<int32_t>(g.scol + y + i);
+                    }
                     // the realigned load reads the dwords around the 16 bytes: up
                     // to 3 bytes past them, which must stay inside the source row
                     bool run = (int64_t)ix[0] + 20 <= g.lds;

@@ -203,10 +203,18 @@ def test_wide_block_columns(lib, p):
     Z = synth.uniform(p, 9, 20, 160, p)
     Z[:, 3:60] = 0                                                # pivots far to the right
     cases.append(Z)
+    checked = reruns = 0
     for A in cases:
         e = oracle.echelonize(A, p)
         for br, bc in ((4, 80), (5, 120), (3, 45), (8, 160)):
-            compare(lib.echelonise(A, p, block_rows=br, block_cols=bc).outputs(), e, f"{A.shape} {br}x{bc}")
+            res = lib.echelonise(A, p, block_rows=br, block_cols=bc)
+            compare(res.outputs(), e, f"{A.shape} {br}x{bc}")
+            st = res.stats()
+            checked += st["tail_checks"]
+            reruns += st["ech_reruns"]
+    # dependent rows: their remnant after the leading columns is zero, checked
+    # without a second ECH; pivots far to the right: the ECH runs again
+    assert checked > 0 and reruns > 0
     del rng
 
 
