@@ -752,17 +752,14 @@ def main():
         r.free()
         log(f"warmup {w}: {time.perf_counter() - t1:.3f} s, rank {rank}")
 
-    # timed steps: device events around a pseudo-random quarter of the MAD
-    # launches (the roofline kernel; an event pair costs host time on the
-    # issuing thread, which the solve waits for); every other launch runs
-    # without events
+    # timed steps: no device events at all
     times, stats = [], []
     last = None
     torch.cuda.synchronize()
     for s in range(args.steps):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        r = solve(0 if args.no_kernel_events else 3)
+        r = solve(0)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         times.append(dt)
@@ -772,9 +769,15 @@ def main():
             last.free()
         last = r                      # the last timed solve's result is checked below
         log(f"step {s}: {dt:.3f} s, rank {rank}")
-    # one more (untimed) solve with every launch timed, for the per-kind breakdown
-    breakdown = None
+    # two more (untimed) solves: one with device events around a pseudo-random
+    # quarter of the MAD launches (the in-situ figure: an event pair costs host
+    # time on the issuing thread, so the timed steps carry none), one with
+    # every launch timed, for the per-kind breakdown
+    breakdown, sampled = None, None
     if not args.no_kernel_events:
+        r = solve(3)
+        sampled = r.stats()
+        r.free()
         r = solve(1)
         breakdown = r.stats()
         r.free()
@@ -782,10 +785,10 @@ def main():
     mean = sum(times) / len(times)
     st = stats[-1]
     mac_mad = st["mac_cleardown"] + st["mac_updaterow"] + st["mac_trafo"] + st["mac_clearup"]
-    # the timed (sampled) MAD launches of every timed step
-    mad_ms = sum(x["ms_mad"] for x in stats)
-    mad_launches = sum(x["launches_mad"] for x in stats)
-    mac_timed = sum(x["mac_mad_timed"] for x in stats)
+    # the timed (sampled) MAD launches of the sampled solve
+    mad_ms = sampled["ms_mad"] if sampled else 0.0
+    mad_launches = sampled["launches_mad"] if sampled else 0
+    mac_timed = sampled["mac_mad_timed"] if sampled else 0.0
     achieved = (2.0 * mac_timed) / (mad_ms * 1e-3) / 1e12 if mad_ms > 0 else 0.0
     # MAD launches of one solve (the solve with every launch timed counts them)
     all_mad_launches = breakdown["launches_mad"] if breakdown else 0
@@ -832,13 +835,13 @@ def main():
     }
     # Section 8(d)(i): one layer's UpdateRow launch and the largest ClearUp
     # launch replayed alone at their traced shapes.  The isolated layer launch
-    # is the roofline figure; the in-situ one (sampled launches of the timed
-    # solves, which overlap on four streams) and the solve-wide MAD rate stand
+    # is the roofline figure; the in-situ one (sampled launches of an untimed
+    # solve, which overlap on four streams) and the solve-wide MAD rate stand
     # beside it.
     if not args.no_kernel_events:
         roof = out["roofline"]
         roof["in_situ"] = {"achieved": roof["achieved"], "frac": roof["frac"], "per_launch": roof.pop("per_launch"),
-                           "note": "sampled MAD launches of the timed solves (contended: four streams overlap)"}
+                           "note": "sampled MAD launches of one untimed solve (contended: four streams overlap)"}
         roof["solve_wide"] = {"achieved": 2 * mac_mad / mean / 1e12, "frac": 2 * mac_mad / mean / 1e12 / INT8_PEAK_TOPS,
                               "note": "all MAD multiply-adds of a solve over its wall time"}
         iso = traced_isolated(torch, lib, solve)
