@@ -97,8 +97,9 @@ struct DescPtr {
 
 // ============================================================================ GEMM mod p
 //
-// Workgroup tile TM x TN of D, 4 waves in 2 x 2, each wave 128 x 64 as 4 x 2
-// blocks of v_mfma_i32_32x32x32_i8 (on this chip it retires half again as
+// Workgroup tile TM x TN of D (TN = 128 or 256, see GemmCfg), 2 x (TN / 64)
+// waves, each wave 128 x 64 as 4 x 2 blocks of v_mfma_i32_32x32x32_i8 (on
+// this chip it retires half again as
 // many products per cycle as the 16 x 16 x 64 form).  The MFMA is issued with
 // the operands swapped (the B tile as the first operand) so that a lane's
 // results come in runs of four consecutive columns of one row of D: the
@@ -116,8 +117,9 @@ struct DescPtr {
 // Interior tiles with unpermuted, 16-byte aligned operands over p <= 127
 // stream both tiles straight into LDS (global_load_lds_dwordx4: lane l of a
 // wave writes the 16 bytes at the wave's LDS base + 16 l, from any address it
-// chooses) through three stages, two steps ahead of the MFMAs.  The other
-// tiles go through registers, one step ahead, in two of the stages.
+// chooses) through three stages (four for the wide tile), that many steps
+// less one ahead of the MFMAs.  The other tiles go through registers, one
+// step ahead, in two of the stages.
 //
 // Exactness: residues of p <= 127 are used as they are, residues of p > 127
 // are centred (x >= 128 becomes x - p), so every product is an int8 x int8
@@ -126,14 +128,31 @@ struct DescPtr {
 // float quotient estimate (mod22), otherwise with a Barrett step (ModP).
 
 constexpr int TM = 256;          // rows of D per workgroup tile
-constexpr int TN = 128;          // columns of D per workgroup tile
 constexpr int TK = 64;           // reduction depth per LDS stage
-constexpr int GEMM_THREADS = 256;
 constexpr int GEMM_A_STAGE = TM * TK;                    // bytes of one A tile
-constexpr int GEMM_STAGE = GEMM_A_STAGE + TK * TN;       // A tile, then B tile
-constexpr int GEMM_STAGES = 3;
 
-constexpr size_t gemm_lds_bytes() { return (size_t)GEMM_STAGES * GEMM_STAGE; }
+// The two tile widths: WN = 4 wave columns (tile 256 x 256, 8 waves, four
+// stages, one workgroup per compute unit), the one used, or WN = 2 (tile
+// 256 x 128, 4 waves, three stages, two workgroups per compute unit): the
+// same waves per SIMD, and the wide tile moves a third fewer operand bytes
+// per multiply-add.
+template <int WN>
+struct GemmCfg {
+    static constexpr int TN = 64 * WN;                  // columns of D per workgroup tile
+    static constexpr int WAVES = 2 * WN;                // 2 x WN waves, each 128 x 64
+    static constexpr int THREADS = 64 * WAVES;
+    static constexpr int BCH = TN / 16;                 // 16-byte chunks per B row
+    static constexpr int STAGE = GEMM_A_STAGE + TK * TN;   // A tile, then B tile
+    static constexpr int STAGES = WN == 2 ? 3 : 4;
+    static constexpr int OCC = WN == 2 ? 2 : 1;         // workgroups per compute unit
+    static constexpr int A_PIECES = GEMM_A_STAGE / 1024 / WAVES;   // 1 KB pieces per wave and stage
+    static constexpr int B_PIECES = TK * TN / 1024 / WAVES;
+    static constexpr int RPS = STAGE / TN;              // rows of a C tile one stage holds
+    static constexpr int NA = 4 * TM / THREADS;         // A chunks per thread (register path)
+    static_assert(A_PIECES >= 1 && B_PIECES >= 1 && TM * TN / 1024 / WAVES == 8, "tile layout");
+    static constexpr size_t lds_bytes() { return (size_t)STAGES * STAGE; }
+};
+constexpr int TN = 128;          // the narrow tile's width (host-side tile counts use GemmCfg)
 
 // LDS byte offset of 16-byte chunk c (< 4) of row m of an A tile
 __device__ __forceinline__ int a_chunk_pos(int m, int c) { return m * TK + ((c ^ ((m >> 2) & 3)) << 4); }
@@ -259,23 +278,26 @@ __device__ __forceinline__ uint4 load16_any(const uint8_t* p) {
                       __builtin_amdgcn_alignbyte(w3, w2, sh), __builtin_amdgcn_alignbyte(w4, w3, sh));
 }
 
+template <int WN>
 struct GemmRegs {
-    uint4 a[4];     // A: four 16-byte chunks (rows of the A tile)
-    uint4 b[2];     // B: k-rows (tid >> 3) and (tid >> 3) + 32, 16 columns from 16 (tid & 7)
+    uint4 a[GemmCfg<WN>::NA];   // A: 16-byte chunks tid, tid + THREADS, .. (row c / 4, chunk c % 4)
+    uint4 b[2];                 // B: k-rows tid / BCH and that + 32, 16 columns from 16 (tid % BCH)
 };
 
 // Interior tiles (FAST): no bounds checks, so the loads stay in flight while
 // the MFMAs of the current step run.  Otherwise every chunk is checked.
-template <bool FAST>
+template <bool FAST, int WN>
 __device__ __forceinline__ void gemm_load(const GemmDesc& g, int m0, int n0, int k0, int tid, uint32_t adj,
-                                          GemmRegs& R) {
-    const int kr = tid >> 3, cb = (tid & 7) * 16;
+                                          GemmRegs<WN>& R) {
+    using GC = GemmCfg<WN>;
+    constexpr int NA = GC::NA, GEMM_THREADS = GC::THREADS;
+    const int kr = tid / GC::BCH, cb = (tid % GC::BCH) * 16;
     if (FAST) {
         int64_t br[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) br[h] = g.brow ? gload<int32_t>(g.brow + k0 + kr + 32 * h) : k0 + kr + 32 * h;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < NA; ++s) {
             const int c = tid + s * GEMM_THREADS;
             R.a[s] = gload<uint4>(g.A + (int64_t)(m0 + (c >> 2)) * g.lda + k0 + (c & 3) * 16);
         }
@@ -283,7 +305,7 @@ __device__ __forceinline__ void gemm_load(const GemmDesc& g, int m0, int n0, int
         for (int h = 0; h < 2; ++h) R.b[h] = load16_any(g.B + br[h] * g.ldb + n0 + cb);
         if (adj) {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
+            for (int s = 0; s < NA; ++s) {
                 R.a[s].x = centre(R.a[s].x, adj); R.a[s].y = centre(R.a[s].y, adj);
                 R.a[s].z = centre(R.a[s].z, adj); R.a[s].w = centre(R.a[s].w, adj);
             }
@@ -296,7 +318,7 @@ __device__ __forceinline__ void gemm_load(const GemmDesc& g, int m0, int n0, int
         return;
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < NA; ++s) {
         const int c = tid + s * GEMM_THREADS;
         const int row = c >> 2, kc = (c & 3) * 16;
         const int gr = m0 + row, gk = k0 + kc;
@@ -320,16 +342,18 @@ __device__ __forceinline__ void gemm_load(const GemmDesc& g, int m0, int n0, int
     }
 }
 
-__device__ __forceinline__ void gemm_store_lds(const GemmRegs& R, uint8_t* As, uint8_t* Bs, int tid) {
+template <int WN>
+__device__ __forceinline__ void gemm_store_lds(const GemmRegs<WN>& R, uint8_t* As, uint8_t* Bs, int tid) {
+    using GC = GemmCfg<WN>;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int c = tid + s * GEMM_THREADS;
+    for (int s = 0; s < GC::NA; ++s) {
+        const int c = tid + s * GC::THREADS;
         *(uint4*)(As + a_chunk_pos(c >> 2, c & 3)) = R.a[s];
     }
     // k-rows kr and kr + 32 share the swizzle (kr & 7)
-    const int kr = tid >> 3, pos = ((tid & 7) ^ (kr & 7)) << 4;
-    *(uint4*)(Bs + kr * TN + pos) = R.b[0];
-    *(uint4*)(Bs + (kr + 32) * TN + pos) = R.b[1];
+    const int kr = tid / GC::BCH, pos = ((tid % GC::BCH) ^ (kr & 7)) << 4;
+    *(uint4*)(Bs + kr * GC::TN + pos) = R.b[0];
+    *(uint4*)(Bs + (kr + 32) * GC::TN + pos) = R.b[1];
 }
 
 // 16 bytes from global address g into LDS at (wave-uniform) lds_base + 16 * lane.
@@ -353,10 +377,13 @@ __device__ __forceinline__ v2i lds_read_tr8(const uint8_t* p) {
 
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-template <class Src>
-__global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
+template <int WN, class Src>
+__global__ void __launch_bounds__(GemmCfg<WN>::THREADS, GemmCfg<WN>::OCC) k_gemm_modp(Src src) {
+    using GC = GemmCfg<WN>;
+    constexpr int TN = GC::TN, GEMM_THREADS = GC::THREADS, GEMM_STAGE = GC::STAGE, NS = GC::STAGES;
+    constexpr int PCS = GC::A_PIECES + GC::B_PIECES;   // 1 KB pieces per wave and stage
     constexpr int IM = 4;                 // 32-row MFMA blocks per wave
-    constexpr int JN = TN / 64;           // 32-column MFMA blocks per wave
+    constexpr int JN = 2;                 // 32-column MFMA blocks per wave
     extern __shared__ __attribute__((aligned(16))) uint8_t gsm[];
     // stage s: A tile at As(s) ([m][k], swizzled), B tile at Bs(s) ([k][n], swizzled)
     const auto As = [](int s) { return gsm + s * GEMM_STAGE; };
@@ -392,8 +419,8 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm = (wave >> 1) * 128;     // wave's 128 x 64 sub-tile
-    const int wn = (wave & 1) * (TN / 2);
+    const int wm = (wave / WN) * 128;     // wave's 128 x 64 sub-tile
+    const int wn = (wave % WN) * 64;
     const uint32_t p = (uint32_t)g.p;
     const uint32_t adj = p > 127 ? 256u - p : 0u;
 
@@ -455,7 +482,7 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
         }
     };
 
-    GemmRegs R;
+    GemmRegs<WN> R;
     // LDS epilogue: the C tile arrives in LDS during the last step, D leaves
     // through LDS as whole 16-byte row chunks.  Stage of the last step, or -1.
     int epi_st = -1;
@@ -463,16 +490,17 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
     const bool al16_d = ((((uintptr_t)g.D) | (uintptr_t)g.ldd) & 15) == 0;
     if (stream) {
         const bool lds_epi = al16_c && al16_d;
-        // ---- streamed into LDS, two steps ahead.  Per wave and stage: four
-        // 1 KB pieces of the A tile (chunk P = piece * 64 + lane is row P / 4,
-        // position P % 4) and two of the B tile (chunk P is k-row P / 8,
-        // position P % 8), each lane loading the global chunk its LDS position holds.
+        // ---- streamed into LDS, NS - 1 steps ahead.  Per wave and stage:
+        // A_PIECES 1 KB pieces of the A tile (chunk P = piece * 64 + lane is row
+        // P / 4, position P % 4) and B_PIECES of the B tile (chunk P is k-row
+        // P / BCH, position P % BCH), each lane loading the global chunk its LDS
+        // position holds.
         const uint32_t lds0 = (uint32_t)(uintptr_t)gsm;
-        const uint8_t* asrc[4];
+        const uint8_t* asrc[GC::A_PIECES];
         const uint8_t* bsrc[2];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int P = (wave * 4 + t) * 64 + lane, row = P >> 2, pos = P & 3;
+        for (int t = 0; t < GC::A_PIECES; ++t) {
+            const int P = (wave * GC::A_PIECES + t) * 64 + lane, row = P >> 2, pos = P & 3;
             asrc[t] = g.A + (int64_t)min(m0 + row, g.M - 1) * g.lda + ((pos ^ ((row >> 2) & 3)) << 4);
         }
         // B row of k-row kr of step s: brow[s * TK + kr] when gathered (bix[s][t]
@@ -481,7 +509,7 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
         int bix[4][2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-            const int P = (wave * 2 + t) * 64 + lane, kr = P >> 3, pos = P & 7;
+            const int P = (wave * GC::B_PIECES + t) * 64 + lane, kr = P / GC::BCH, pos = P % GC::BCH;
             const int col = n0 + ((pos ^ (kr & 7)) << 4);
             bsrc[t] = g.B + (col < g.N ? col : 0);
 #pragma unroll
@@ -495,29 +523,32 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
         const auto issue = [&](int ks, int st) {
             const uint32_t base = lds0 + (uint32_t)(st * GEMM_STAGE);
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                dma16(asrc[t] + (int64_t)ks * TK, __builtin_amdgcn_readfirstlane(base + (uint32_t)((wave * 4 + t) * 1024)));
+            for (int t = 0; t < GC::A_PIECES; ++t)
+                dma16(asrc[t] + (int64_t)ks * TK,
+                      __builtin_amdgcn_readfirstlane(base + (uint32_t)((wave * GC::A_PIECES + t) * 1024)));
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
                 const int64_t brow_t = g.brow ? (int64_t)(ks == 0 ? bix[0][t] : ks == 1 ? bix[1][t] : ks == 2 ? bix[2][t] : bix[3][t])
                                               : (int64_t)ks * TK + bix[0][t];
                 dma16(bsrc[t] + brow_t * g.ldb,
-                      __builtin_amdgcn_readfirstlane(base + (uint32_t)(GEMM_A_STAGE + (wave * 2 + t) * 1024)));
+                      __builtin_amdgcn_readfirstlane(base + (uint32_t)(GEMM_A_STAGE + (wave * GC::B_PIECES + t) * 1024)));
             }
         };
-        issue(0, 0);
-        if (nk_str > 1) issue(1, 1);
-        // the C tile of the last step goes to the other two stages (rows 0..191
-        // in the next stage, 192..255 in the one after) while its MFMAs run
+#pragma unroll
+        for (int s0 = 0; s0 < NS - 1; ++s0)
+            if (s0 < nk_str) issue(s0, s0);
+        // the C tile of the last step goes to the next two stages (rows
+        // 0 .. RPS - 1 in the next, the rest in the one after) while its MFMAs
+        // run; 8 pieces of 1 KB per wave, each 1024 / TN whole rows
         const auto fetch_c = [&](int st) {
             epi_st = st;
             if (!g.C) return;
-            const uint32_t s1 = lds0 + (uint32_t)((st == 2 ? 0 : st + 1) * GEMM_STAGE);
-            const uint32_t s2 = lds0 + (uint32_t)((st == 0 ? 2 : st - 1) * GEMM_STAGE);
+            const uint32_t s1 = lds0 + (uint32_t)(((st + 1) % NS) * GEMM_STAGE);
+            const uint32_t s2 = lds0 + (uint32_t)(((st + 2) % NS) * GEMM_STAGE);
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                const int r0 = (wave * 8 + t) * 8, row = r0 + (lane >> 3), pos = lane & 7;
-                const uint32_t base = r0 < 192 ? s1 + (uint32_t)(r0 * TN) : s2 + (uint32_t)((r0 - 192) * TN);
+                const int r0 = (wave * 8 + t) * (1024 / TN), row = r0 + lane / GC::BCH, pos = lane % GC::BCH;
+                const uint32_t base = r0 < GC::RPS ? s1 + (uint32_t)(r0 * TN) : s2 + (uint32_t)((r0 - GC::RPS) * TN);
                 const int col = n0 + ((pos ^ ((row >> 1) & 7)) << 4);
                 dma16(g.C + (int64_t)min(m0 + row, g.M - 1) * g.ldc + (col < g.N ? col : 0),
                       __builtin_amdgcn_readfirstlane(base));
@@ -528,16 +559,19 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
         // flight, the DMA of the next steps included.
         int st = 0;
         for (int ks = 0; ks < nk_str; ++ks) {
-            // this wave's pieces of step ks have landed (at most the 6 of step
-            // ks + 1 still in flight); the barrier makes every wave's visible
-            // and ends every wave's reads of step ks - 1, whose stage step
-            // ks + 2 then overwrites
-            if (ks + 1 < nk_str) vm_wait<6>(); else vm_wait<0>();
+            // this wave's pieces of step ks have landed (the PCS pieces of each
+            // later step issued may still be in flight); the barrier makes every
+            // wave's visible and ends every wave's reads of step ks - 1, whose
+            // stage step ks + NS - 1 then overwrites
+            const int later = min(NS - 2, nk_str - 1 - ks);
+            if (later >= 2) vm_wait<2 * PCS>();
+            else if (later == 1) vm_wait<PCS>();
+            else vm_wait<0>();
             __syncthreads();
-            if (ks + 2 < nk_str) issue(ks + 2, st == 0 ? 2 : st - 1);
+            if (ks + NS - 1 < nk_str) issue(ks + NS - 1, (st + NS - 1) % NS);
             if (ks == nk - 1 && lds_epi) fetch_c(st);
             mma_step(st);
-            st = st == 2 ? 0 : st + 1;
+            st = st + 1 == NS ? 0 : st + 1;
         }
         if (nk > nk_str) {
             // the K tail (one step) through registers: its stage was last read
@@ -589,9 +623,9 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
     if (epi_st >= 0) {
         // C tile row m at cl(m), its 16-byte chunk c at position c ^ ((m >> 1) & 7):
         // the 16 lanes reading one chunk of 16 rows hit 16 different bank groups
-        uint8_t* const s1 = As(epi_st == 2 ? 0 : epi_st + 1);
-        uint8_t* const s2 = As(epi_st == 0 ? 2 : epi_st - 1);
-        const auto cl = [&](int m) { return m < 192 ? s1 + m * TN : s2 + (m - 192) * TN; };
+        uint8_t* const s1 = As((epi_st + 1) % NS);
+        uint8_t* const s2 = As((epi_st + 2) % NS);
+        const auto cl = [&](int m) { return m < GC::RPS ? s1 + m * TN : s2 + (m - GC::RPS) * TN; };
         vm_wait<0>();
         __syncthreads();
         // each lane reads its C words and writes its D words in their place
@@ -609,10 +643,10 @@ __global__ void __launch_bounds__(GEMM_THREADS, 2) k_gemm_modp(Src src) {
                 }
         }
         __syncthreads();
-        // whole 16-byte chunks of D rows: chunk P = tid + 256 u is row P / 8, position P % 8
+        // whole 16-byte chunks of D rows: chunk P = tid + THREADS u is row P / BCH, position P % BCH
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int P = tid + u * GEMM_THREADS, row = P >> 3, pos = P & 7;
+            const int P = tid + u * GEMM_THREADS, row = P / GC::BCH, pos = P % GC::BCH;
             const uint4 v = *(const uint4*)(cl(row) + pos * 16);
             const int col = n0 + ((pos ^ ((row >> 1) & 7)) << 4);
             if (m0 + row < g.M && col < g.N) {
@@ -2153,10 +2187,14 @@ public:
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)echp_lds_bytes(ECHP_MAX_ROWS)) != hipSuccess ||
             hipFuncSetAttribute((const void*)k_ech_panel<DescPtr<EchDesc>>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)echp_lds_bytes(ECHP_MAX_ROWS)) != hipSuccess ||
-            hipFuncSetAttribute((const void*)k_gemm_modp<GemmArgSrc>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)gemm_lds_bytes()) != hipSuccess ||
-            hipFuncSetAttribute((const void*)k_gemm_modp<GemmPtrSrc>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)gemm_lds_bytes()) != hipSuccess) {
+            hipFuncSetAttribute((const void*)k_gemm_modp<2, GemmArgSrc>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)GemmCfg<2>::lds_bytes()) != hipSuccess ||
+            hipFuncSetAttribute((const void*)k_gemm_modp<2, GemmPtrSrc>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)GemmCfg<2>::lds_bytes()) != hipSuccess ||
+            hipFuncSetAttribute((const void*)k_gemm_modp<4, GemmArgSrc>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)GemmCfg<4>::lds_bytes()) != hipSuccess ||
+            hipFuncSetAttribute((const void*)k_gemm_modp<4, GemmPtrSrc>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)GemmCfg<4>::lds_bytes()) != hipSuccess) {
             if (err) *err = "cannot reserve LDS for the kernels";
             return false;
         }
@@ -2177,6 +2215,8 @@ public:
         no_lds_ech_ = getenv("GFECH_ECH_NO_LDS") != nullptr;
         const char* gg = getenv("GFECH_GEMM_GROUP");
         gemm_group_ = gg ? std::max(1, std::min(64, atoi(gg))) : 4;
+        const char* gw = getenv("GFECH_GEMM_WIDE");
+        gemm_wide_ = !(gw && gw[0] == '0');
         // the device address of the fixed workspace on this device (the one
         // current now, which every later call of this backend uses)
         if (hipGetSymbolAddress((void**)&fixed_scratch_, HIP_SYMBOL(scratch)) != hipSuccess) {
@@ -2368,17 +2408,31 @@ public:
     }
     int error() const override { return err_; }
 
-    // 256 x 128 tiles: at occupancy 2 they run faster at every shape measured
-    // than 256 x 256 tiles did (occupancy 1), whose latencies stay exposed
+    // The 256 x 256 tile (eight waves) for every product; GFECH_GEMM_WIDE=0
+    // takes the 256 x 128 tile (four waves, two workgroups per compute unit)
+    // instead.  Measured on the 40000 x 40000 GF(7) solve: 103.9 ms against
+    // 105.9 ms; the isolated layer launch 0.556 ms against 0.635 ms; the
+    // batch of 4096 small matrices 53.9K solves/s against 47.5K; the wide
+    // tile for products of at least 1024 columns and the narrow one for the
+    // rest (two launches): 110.7 ms.
     void gemm(const std::vector<GemmDesc>& ds) override {
+        std::vector<GemmDesc> d;
+        for (const GemmDesc& g : ds)
+            if (g.M > 0 && g.N > 0) d.push_back(g);
+        if (d.empty()) return;
+        if (gemm_wide_) gemm_launch<4>(d);
+        else gemm_launch<2>(d);
+    }
+    template <int WN>
+    void gemm_launch(const std::vector<GemmDesc>& ds) {
+        using GC = GemmCfg<WN>;
         std::vector<GemmDesc> d;
         std::vector<GemmTileMap> maps;
         int64_t tiles = 0;
         for (const GemmDesc& g : ds) {
-            if (g.M <= 0 || g.N <= 0) continue;
             if (g.K > 65536) { note_error(hipErrorInvalidValue, "gemm K > 65536"); return; }
             GemmTileMap t;
-            t.tiles_n = (g.N + TN - 1) / TN;
+            t.tiles_n = (g.N + GC::TN - 1) / GC::TN;
             t.first_tile = (int32_t)tiles;
             tiles += (int64_t)((g.M + TM - 1) / TM) * t.tiles_n;
             d.push_back(g);
@@ -2393,7 +2447,7 @@ public:
             a.n = (int)d.size();
             a.group = gemm_group_;
             for (size_t i = 0; i < d.size(); ++i) { a.m[i] = maps[i]; a.d[i] = d[i]; }
-            go(0, k_gemm_modp<GemmArgSrc>, dim3((unsigned)tiles), dim3(GEMM_THREADS), gemm_lds_bytes(), a);
+            go(0, k_gemm_modp<WN, GemmArgSrc>, dim3((unsigned)tiles), dim3(GC::THREADS), GC::lds_bytes(), a);
         } else {
             // one upload: the tile maps, then the descriptors (256-byte aligned)
             const size_t mb = (maps.size() * sizeof(GemmTileMap) + 255) & ~(size_t)255;
@@ -2406,7 +2460,7 @@ public:
             a.group = gemm_group_;
             a.m = (const GemmTileMap*)dev;
             a.d = (const GemmDesc*)(dev + mb);
-            go(0, k_gemm_modp<GemmPtrSrc>, dim3((unsigned)tiles), dim3(GEMM_THREADS), gemm_lds_bytes(), a);
+            go(0, k_gemm_modp<WN, GemmPtrSrc>, dim3((unsigned)tiles), dim3(GC::THREADS), GC::lds_bytes(), a);
         }
         HIP_OK(hipGetLastError());
     }
@@ -2697,6 +2751,7 @@ private:
     size_t echs_lds_max_ = 0;        // LDS the LDS-resident ECH may use
     bool no_lds_ech_ = false;
     int gemm_group_ = 4;             // tile rows per group of the MAD tile order (measured: 4)
+    bool gemm_wide_ = true;          // 256 x 256 MAD tiles (GFECH_GEMM_WIDE=0: 256 x 128)
     void* ring_host_ = nullptr;
     void* ring_dev_ = nullptr;
     size_t ring_off_ = 0;
