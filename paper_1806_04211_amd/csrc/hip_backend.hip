@@ -143,7 +143,7 @@ struct GemmCfg {
     static constexpr int THREADS = 64 * WAVES;
     static constexpr int BCH = TN / 16;                 // 16-byte chunks per B row
     static constexpr int STAGE = GEMM_A_STAGE + TK * TN;   // A tile, then B tile
-    static constexpr int STAGES = WN == 2 ? 3 : 4;
+    static constexpr int STAGES = WN == 2 ? 3 : 4;   // five for the wide tile measured no faster
     static constexpr int OCC = WN == 2 ? 2 : 1;         // workgroups per compute unit
     static constexpr int A_PIECES = GEMM_A_STAGE / 1024 / WAVES;   // 1 KB pieces per wave and stage
     static constexpr int B_PIECES = TK * TN / 1024 / WAVES;
@@ -564,7 +564,8 @@ __global__ void __launch_bounds__(GemmCfg<WN>::THREADS, GemmCfg<WN>::OCC) k_gemm
             // wave's visible and ends every wave's reads of step ks - 1, whose
             // stage step ks + NS - 1 then overwrites
             const int later = min(NS - 2, nk_str - 1 - ks);
-            if (later >= 2) vm_wait<2 * PCS>();
+            if (later >= 3) vm_wait<3 * PCS>();
+            else if (later == 2) vm_wait<2 * PCS>();
             else if (later == 1) vm_wait<PCS>();
             else vm_wait<0>();
             __syncthreads();
