@@ -244,6 +244,14 @@ typedef struct gfech_mad_desc {
 } gfech_mad_desc;
 gfech_status gfech_mad_batch_dev(int64_t count, const gfech_mad_desc* descs, void* stream);
 
+/* gfech_mad_batch_dev, and *kernel_ms (host memory) receives the summed
+ * execution time of its MAD kernel launches, taken from each dispatch's own
+ * begin and end timestamps (the upload of the descriptor array and launch
+ * gaps excluded).  Returns once the launches have finished.  For measuring
+ * the product kernel in isolation. */
+gfech_status gfech_mad_batch_dev_timed(int64_t count, const gfech_mad_desc* descs, void* stream,
+                                       double* kernel_ms);
+
 /* MAD over GF(2) on bit-packed rows (bit b of word w of a row = column
  * 64 w + b): D = (C + A * B) over GF(2), i.e. row i of D is row i of C XOR
  * the rows of B that row i of A selects.  A: M x K (lda words per row, its

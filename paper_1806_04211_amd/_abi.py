@@ -91,6 +91,7 @@ SIGNATURES = {
                                      c_i64, vp]),
     "gfech_mad_gf2_dev": (ctypes.c_int, [c_i64, c_i64, c_i64, vp, c_i64, vp, c_i64, vp, c_i64, vp, c_i64, vp]),
     "gfech_mad_batch_dev": (ctypes.c_int, [c_i64, vp, vp]),
+    "gfech_mad_batch_dev_timed": (ctypes.c_int, [c_i64, vp, vp, ctypes.POINTER(ctypes.c_double)]),
     "gfech_ech_dev": (ctypes.c_int, [vp, c_i64, c_i64, c_i64, c_u32, vp, vp, vp, vp, vp, c_i64, vp, c_i64, vp,
                                      c_i64, i64p, vp]),
     "gfech_ech_dev_noalloc": (ctypes.c_int, [vp, c_i64, c_i64, c_i64, c_u32, vp, vp, vp, vp, vp, c_i64, vp, c_i64,

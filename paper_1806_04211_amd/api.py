@@ -234,6 +234,13 @@ class Library:
         arr = descs if isinstance(descs, ctypes.Array) else self.mad_descs(descs)
         self._check(self.lib.gfech_mad_batch_dev(len(descs), arr, ctypes.c_void_p(stream)))
 
+    def mad_batch_dev_timed(self, descs, stream=0) -> float:
+        """mad_batch_dev, returning the summed execution time (ms) of its MAD kernel launches."""
+        arr = descs if isinstance(descs, ctypes.Array) else self.mad_descs(descs)
+        ms = ctypes.c_double()
+        self._check(self.lib.gfech_mad_batch_dev_timed(len(descs), arr, ctypes.c_void_p(stream), ctypes.byref(ms)))
+        return ms.value
+
     def mad_gf2_dev(self, M, N, K, A, lda, B, ldb, D, ldd, C=0, ldc=0, stream=0):
         """MAD over GF(2) on packed rows (device addresses, leading dimensions in 64-bit words)."""
         vp = ctypes.c_void_p

@@ -615,7 +615,7 @@ static gfech::GemmDesc to_gemm(const gfech_mad_desc& d) {
     return g;
 }
 
-gfech_status gfech_mad_batch_dev(int64_t count, const gfech_mad_desc* descs, void* stream) {
+static gfech_status mad_batch(int64_t count, const gfech_mad_desc* descs, void* stream, double* kernel_ms) {
     if (count < 0 || (count > 0 && !descs)) return fail(GFECH_E_ARG, "bad MAD batch");
     std::vector<gfech::GemmDesc> gs;
     for (int64_t t = 0; t < count; ++t) {
@@ -628,10 +628,29 @@ gfech_status gfech_mad_batch_dev(int64_t count, const gfech_mad_desc* descs, voi
     if (!be) return st;
     std::lock_guard<std::mutex> lk(be->lock());
     be->set_stream(stream);
+    if (kernel_ms) {
+        be->take_profile();                 // drop events of earlier work
+        be->set_profile(2);                 // MAD launches carry start and stop events
+    }
     if (!gs.empty()) be->gemm(gs);
     be->sync();
+    if (kernel_ms) {
+        *kernel_ms = be->take_profile().ms[0];
+        be->set_profile(0);
+    }
     be->set_stream(nullptr);
     return be->error() ? fail(GFECH_E_DEVICE, "device error") : GFECH_OK;
+}
+
+gfech_status gfech_mad_batch_dev(int64_t count, const gfech_mad_desc* descs, void* stream) {
+    return mad_batch(count, descs, stream, nullptr);
+}
+
+gfech_status gfech_mad_batch_dev_timed(int64_t count, const gfech_mad_desc* descs, void* stream,
+                                       double* kernel_ms) {
+    if (!kernel_ms) return fail(GFECH_E_ARG, "kernel_ms is NULL");
+    *kernel_ms = 0;
+    return mad_batch(count, descs, stream, kernel_ms);
 }
 
 gfech_status gfech_mad_dev(int64_t M, int64_t N, int64_t K, uint32_t p, const uint8_t* A, int64_t lda,

@@ -1168,6 +1168,12 @@ struct Engine::Impl {
                             "pivot counts, %.1f us after\n",
                     (long long)ht_layers, 1e6 * ht_pre / ht_layers, 1e6 * ht_wait / ht_layers,
                     1e6 * ht_post / ht_layers);
+        if (host_timing && ht_layers)
+            fprintf(stderr, "gfech host timing: issue by part (us per layer): wait and begin %.1f, extract %.1f, "
+                            "ClearDown MADs %.1f, ECH %.1f, near set %.1f, UpdateRow (1) %.1f, rest %.1f\n",
+                    1e6 * ht_seg[0] / ht_layers, 1e6 * ht_seg[1] / ht_layers, 1e6 * ht_seg[2] / ht_layers,
+                    1e6 * ht_seg[3] / ht_layers, 1e6 * ht_seg[4] / ht_layers, 1e6 * ht_seg[5] / ht_layers,
+                    1e6 * ht_seg[6] / ht_layers);
         be.sync();
         for (auto& j : jobs) release(*j);
         if (counts) be.release_counts(counts);
@@ -1183,6 +1189,7 @@ struct Engine::Impl {
     // rest of the layer)
     bool host_timing = false;
     double ht_pre = 0, ht_wait = 0, ht_post = 0;
+    double ht_seg[7] = {0, 0, 0, 0, 0, 0, 0};   // the issue phase by part (see step())
     int64_t ht_layers = 0;
 
     Backend& be;
@@ -1415,7 +1422,14 @@ struct Engine::Impl {
         // ---- Step 1: one layer of every problem in it (see the header comment for the lanes)
         if (!s1.empty()) {
             const auto h0 = std::chrono::steady_clock::now();
-            auto h1 = h0, h2 = h0;
+            auto h1 = h0, h2 = h0, hp = h0;
+            int seg = 0;
+            const auto tick = [&] {
+                if (!host_timing) return;
+                const auto t = std::chrono::steady_clock::now();
+                ht_seg[seg++] += std::chrono::duration<double>(t - hp).count();
+                hp = t;
+            };
             // the bulk part issued two layers back reads the scratch copy this
             // layer's ClearDowns write: its mid set is behind the near set lane 0
             // waited for in the previous layer, its far set is waited for here
@@ -1423,10 +1437,13 @@ struct Engine::Impl {
             far_wait = far_done;
             for (size_t q = 0; q < jobs.size(); ++q)
                 if (jobs[q]->phase == kStep1) jobs[q]->plan->begin_layer(jobs[q]->layer);
+            tick();
             for (Plan* pl : s1) pl->cd_extract(ops);
             flush(be, ops, shared);
+            tick();
             for (Plan* pl : s1) pl->cd_mad(ops);
             flush(be, ops, shared);
+            tick();
             // the previous layer's bulk part starts after this layer's ClearDown
             // MADs and is issued after this layer's ECHs, so the ECHs (one
             // workgroup each) reach the device first: issued behind a large
@@ -1435,7 +1452,9 @@ struct Engine::Impl {
             bool any = false;
             for (Plan* pl : s1) { pl->cd_ech(ops, false); any = any || pl->any_ech(); }
             flush(be, ops, shared);
+            tick();
             issue_near(ready);
+            tick();
             // UpdateRow (1)'s priority products overwrite the near set's columns
             // and need nothing this layer's ECH computes: lane 2 runs them beside
             // the ECH, issued before the mid and far sets so that they reach the
@@ -1451,7 +1470,9 @@ struct Engine::Impl {
                 u1_done = be.mark(2);
                 be.set_lane(0);
             }
+            tick();
             issue_rest(ready);
+            tick();
             b1 = std::move(b1n);
             for (Plan* pl : s1) pl->clear_counts();
             h1 = std::chrono::steady_clock::now();

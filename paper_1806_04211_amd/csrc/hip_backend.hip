@@ -95,6 +95,15 @@ struct DescPtr {
     __device__ __forceinline__ D get(int i) const { return p[i]; }
 };
 
+// f(std::integral_constant<int, K>) for K = K0 .. N - 1, unrolled at compile time
+template <int K0, int N, class Fn>
+__device__ __forceinline__ void static_for(Fn&& f) {
+    if constexpr (K0 < N) {
+        f(std::integral_constant<int, K0>{});
+        static_for<K0 + 1, N>(f);
+    }
+}
+
 // ============================================================================ GEMM mod p
 //
 // Workgroup tile TM x TN of D (TN = 128 or 256, see GemmCfg), 2 x (TN / 64)
@@ -108,7 +117,10 @@ struct DescPtr {
 // in LDS, 64-byte rows, the 16-byte chunk c of row m at position
 // c ^ ((m >> 2) & 3), so the 16 lanes reading one chunk of 16 rows hit 16
 // different bank groups.  B is kept as it is stored, [k][n], the 16-byte
-// chunk c of row k at position c ^ (k & 7); the MFMA wants 16 consecutive k
+// chunk c of row k at position c ^ s(k) (GemmCfg::bswz: s(k) = 2 (k & 7) in
+// the 256-column tile, whose rows span all 64 banks, so that the two groups
+// of 16 lanes reading chunks 2m and 2m + 1 of the same 8 rows use disjoint
+// banks; k & 7 in the 128-column tile); the MFMA wants 16 consecutive k
 // of one column per lane, which ds_read_b64_tr_b8 delivers: within each group
 // of 16 lanes, lane pairs (2t, 2t + 1) address the two halves of a 16-byte
 // row t (t < 8), and lane c of the group receives byte c of each of the 8
@@ -151,6 +163,8 @@ struct GemmCfg {
     static constexpr int NA = 4 * TM / THREADS;         // A chunks per thread (register path)
     static_assert(A_PIECES >= 1 && B_PIECES >= 1 && TM * TN / 1024 / WAVES == 8, "tile layout");
     static constexpr size_t lds_bytes() { return (size_t)STAGES * STAGE; }
+    // position offset of the 16-byte chunks of B row k (chunk c at c ^ bswz(k))
+    static __device__ __forceinline__ int bswz(int k) { return BCH == 16 ? (k & 7) << 1 : k & 7; }
 };
 constexpr int TN = 128;          // the narrow tile's width (host-side tile counts use GemmCfg)
 
@@ -216,8 +230,8 @@ struct GemmPtrSrc {
 // less, and r = v - q p lies in [0, 2p): one conditional subtraction (as an
 // unsigned min: r - p wraps around when r < p) finishes.
 __device__ __forceinline__ uint32_t mod22(uint32_t v, float inv, uint32_t p) {
-    const uint32_t q = (uint32_t)((float)v * inv);
-    const uint32_t r = v - __umul24(q, p);
+    const int q = (int)((float)v * inv);
+    const uint32_t r = (uint32_t)(__mul24(q, -(int)p) + (int)v);   // one 24-bit multiply-add
     return min(r, r - p);
 }
 
@@ -350,8 +364,8 @@ __device__ __forceinline__ void gemm_store_lds(const GemmRegs<WN>& R, uint8_t* A
         const int c = tid + s * GC::THREADS;
         *(uint4*)(As + a_chunk_pos(c >> 2, c & 3)) = R.a[s];
     }
-    // k-rows kr and kr + 32 share the swizzle (kr & 7)
-    const int kr = tid / GC::BCH, pos = ((tid % GC::BCH) ^ (kr & 7)) << 4;
+    // k-rows kr and kr + 32 share the swizzle
+    const int kr = tid / GC::BCH, pos = ((tid % GC::BCH) ^ GC::bswz(kr)) << 4;
     *(uint4*)(Bs + kr * GC::TN + pos) = R.b[0];
     *(uint4*)(Bs + (kr + 32) * GC::TN + pos) = R.b[1];
 }
@@ -418,7 +432,7 @@ __global__ void __launch_bounds__(GemmCfg<WN>::THREADS, GemmCfg<WN>::OCC) k_gemm
     }
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = (wave / WN) * 128;     // wave's 128 x 64 sub-tile
     const int wn = (wave % WN) * 64;
     const uint32_t p = (uint32_t)g.p;
@@ -454,31 +468,50 @@ __global__ void __launch_bounds__(GemmCfg<WN>::THREADS, GemmCfg<WN>::OCC) k_gemm
     const int r32 = lane & 31;
     const int kh = lane >> 5;
 
-    // one K step on LDS stage st: two halves of 32, each 4 x 2 MFMAs 32 x 32 x 32
+    // The operands of one half of a K step (32 of its 64 k) on LDS stage st:
+    // B operand of block j: lane 32 kh + c gets column wn + 32 j + c and
+    // k = 32 h + 16 kh .. + 15; its group of 16 lanes reads rows k0 + t and
+    // k0 + 8 + t (t = r16 / 2, whose swizzle is bswz(t)) of the 16-column chunk
+    // (wn + 32 j) / 16 + (c >= 16) at half r16 & 1.  A operand of block i:
+    // row wm + 32 i + r32, the same 16 k (chunk 2 h + kh).
+    struct Half { v4i a[IM]; v4i b[JN]; };
+    const auto read_half = [&](int st, int h, Half& f) {
+        const int k0 = 32 * h + 16 * kh, t = r16 >> 1;
+#pragma unroll
+        for (int j = 0; j < JN; ++j) {
+            const int ch = (wn >> 4) + 2 * j + ((lane >> 4) & 1);
+            const uint8_t* rp = Bs(st) + (k0 + t) * TN + ((ch ^ GC::bswz(t)) << 4) + ((r16 & 1) << 3);
+            const v2i lo2 = lds_read_tr8(rp), hi2 = lds_read_tr8(rp + 8 * TN);
+            f.b[j] = v4i{lo2.x, lo2.y, hi2.x, hi2.y};
+        }
+#pragma unroll
+        for (int i = 0; i < IM; ++i) f.a[i] = *(const v4i*)(As(st) + a_chunk_pos(wm + i * 32 + r32, 2 * h + kh));
+    };
+    // the 4 x 2 MFMAs 32 x 32 x 32 of one half
+    const auto mma_half = [&](const Half& f) {
+#pragma unroll
+        for (int i = 0; i < IM; ++i)
+#pragma unroll
+            for (int j = 0; j < JN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.b[j], f.a[i], acc[i][j], 0, 0, 0);
+    };
+    // the same, with `between(m)` called after MFMA m (m < 8)
+    const auto mma_half_with = [&](const Half& f, auto between) {
+#pragma unroll
+        for (int i = 0; i < IM; ++i)
+#pragma unroll
+            for (int j = 0; j < JN; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.b[j], f.a[i], acc[i][j], 0, 0, 0);
+                between(i * JN + j);
+            }
+    };
+    // one K step on LDS stage st, operands read as it goes
     const auto mma_step = [&](int st) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            // B operand of block j: lane 32 kh + c gets column wn + 32 j + c and
-            // k = 32 h + 16 kh .. + 15; its group of 16 lanes reads rows k0 + t and
-            // k0 + 8 + t (t = r16 / 2, whose swizzle is t) of the 16-column chunk
-            // (wn + 32 j) / 16 + (c >= 16) at half r16 & 1
-            v4i bf[JN];
-            const int k0 = 32 * h + 16 * kh, t = r16 >> 1;
-#pragma unroll
-            for (int j = 0; j < JN; ++j) {
-                const int ch = (wn >> 4) + 2 * j + ((lane >> 4) & 1);
-                const uint8_t* rp = Bs(st) + (k0 + t) * TN + ((ch ^ t) << 4) + ((r16 & 1) << 3);
-                const v2i lo2 = lds_read_tr8(rp), hi2 = lds_read_tr8(rp + 8 * TN);
-                bf[j] = v4i{lo2.x, lo2.y, hi2.x, hi2.y};
-            }
-            // A operand of block i: row wm + 32 i + r32, the same 16 k (chunk 2 h + kh)
-#pragma unroll
-            for (int i = 0; i < IM; ++i) {
-                const v4i af = *(const v4i*)(As(st) + a_chunk_pos(wm + i * 32 + r32, 2 * h + kh));
-#pragma unroll
-                for (int j = 0; j < JN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(bf[j], af, acc[i][j], 0, 0, 0);
-            }
+            Half f;
+            read_half(st, h, f);
+            mma_half(f);
         }
     };
 
@@ -510,7 +543,7 @@ __global__ void __launch_bounds__(GemmCfg<WN>::THREADS, GemmCfg<WN>::OCC) k_gemm
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             const int P = (wave * GC::B_PIECES + t) * 64 + lane, kr = P / GC::BCH, pos = P % GC::BCH;
-            const int col = n0 + ((pos ^ (kr & 7)) << 4);
+            const int col = n0 + ((pos ^ GC::bswz(kr)) << 4);
             bsrc[t] = g.B + (col < g.N ? col : 0);
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4)
@@ -520,22 +553,27 @@ __global__ void __launch_bounds__(GemmCfg<WN>::THREADS, GemmCfg<WN>::OCC) k_gemm
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4) asm volatile("" ::"v"(bix[s4][0]), "v"(bix[s4][1]));
         }
-        const auto issue = [&](int ks, int st) {
+        // ungathered B: piece t of step ks reads from bbase[t] + ks TK ldb
+        const uint8_t* bbase[2] = {bsrc[0] + (int64_t)bix[0][0] * g.ldb, bsrc[1] + (int64_t)bix[0][1] * g.ldb};
+        const int64_t bstep = (int64_t)TK * g.ldb;
+        // piece q (< PCS) of step ks into stage st: the A pieces, then the B pieces
+        const auto piece = [&](int ks, int st, int q) {
             const uint32_t base = lds0 + (uint32_t)(st * GEMM_STAGE);
-#pragma unroll
-            for (int t = 0; t < GC::A_PIECES; ++t)
-                dma16(asrc[t] + (int64_t)ks * TK,
-                      __builtin_amdgcn_readfirstlane(base + (uint32_t)((wave * GC::A_PIECES + t) * 1024)));
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const int64_t brow_t = g.brow ? (int64_t)(ks == 0 ? bix[0][t] : ks == 1 ? bix[1][t] : ks == 2 ? bix[2][t] : bix[3][t])
-                                              : (int64_t)ks * TK + bix[0][t];
-                dma16(bsrc[t] + brow_t * g.ldb,
-                      __builtin_amdgcn_readfirstlane(base + (uint32_t)(GEMM_A_STAGE + (wave * GC::B_PIECES + t) * 1024)));
+            if (q < GC::A_PIECES) {
+                dma16(asrc[q] + (int64_t)ks * TK, base + (uint32_t)((wave * GC::A_PIECES + q) * 1024));
+            } else {
+                const int t = q - GC::A_PIECES;
+                const uint8_t* src = g.brow ? bsrc[t] + (int64_t)(ks == 0 ? bix[0][t] : ks == 1 ? bix[1][t] : ks == 2 ? bix[2][t] : bix[3][t]) * g.ldb
+                                            : bbase[t] + ks * bstep;
+                dma16(src, base + (uint32_t)(GEMM_A_STAGE + (wave * GC::B_PIECES + t) * 1024));
             }
         };
+        const auto issue = [&](int ks, int st) {
 #pragma unroll
-        for (int s0 = 0; s0 < NS - 1; ++s0)
+            for (int q = 0; q < PCS; ++q) piece(ks, st, q);
+        };
+#pragma unroll
+        for (int s0 = 0; s0 < NS; ++s0)
             if (s0 < nk_str) issue(s0, s0);
         // the C tile of the last step goes to the next two stages (rows
         // 0 .. RPS - 1 in the next, the rest in the one after) while its MFMAs
@@ -554,29 +592,70 @@ __global__ void __launch_bounds__(GemmCfg<WN>::THREADS, GemmCfg<WN>::OCC) k_gemm
                       __builtin_amdgcn_readfirstlane(base));
             }
         };
-        // No load into registers may sit inside this loop: the compiler would
-        // guard every use of a register it writes with a wait for all loads in
-        // flight, the DMA of the next steps included.
-        int st = 0;
-        for (int ks = 0; ks < nk_str; ++ks) {
-            // this wave's pieces of step ks have landed (the PCS pieces of each
-            // later step issued may still be in flight); the barrier makes every
-            // wave's visible and ends every wave's reads of step ks - 1, whose
-            // stage step ks + NS - 1 then overwrites
-            const int later = min(NS - 2, nk_str - 1 - ks);
+        // this wave's pieces of step `next` have landed, `later` steps after it
+        // being in flight (PCS pieces each)
+        const auto wait_step = [&](int later) {
             if (later >= 3) vm_wait<3 * PCS>();
             else if (later == 2) vm_wait<2 * PCS>();
             else if (later == 1) vm_wait<PCS>();
             else vm_wait<0>();
+        };
+        // No load into registers may sit inside this loop: the compiler would
+        // guard every use of a register it writes with a wait for all loads in
+        // flight, the DMA of the next steps included.
+        //
+        // Step ks runs its first half's MFMAs on operands read before, then
+        // waits for step ks + 1 and meets the other waves at the barrier: by
+        // then every wave has read all of step ks into registers, so its stage
+        // takes step ks + NS, and step ks + 1 is visible.  The first half of
+        // step ks + 1 is read while the second half's MFMAs of step ks run,
+        // and its second half after them: the reads' latency stays off the
+        // matrix cores' path, and the barrier falls between two groups of
+        // MFMAs rather than before a group's operands are read.
+        wait_step(min(NS - 1, nk_str - 1));
+        __syncthreads();
+        Half f0, f1;
+        read_half(0, 0, f0);
+        read_half(0, 1, f1);
+        // The transfers of step ks + NS go out one or two at a time between
+        // the second half's MFMAs: a wave whose transfer waits for the
+        // memory pipeline's queue cannot issue anything after it.  (The last
+        // step is peeled off, and the steps that issue no transfer get a loop
+        // of their own, so that the loops' reads are unconditional and the
+        // compiler's waits count them exactly.)
+        int st = 0;
+        const auto body = [&](int ks, auto dma) {
+            const int nst = st + 1 == NS ? 0 : st + 1;
+            mma_half(f0);
+            wait_step(min(NS - 2, nk_str - 2 - ks));
             __syncthreads();
-            if (ks + NS - 1 < nk_str) issue(ks + NS - 1, (st + NS - 1) % NS);
-            if (ks == nk - 1 && lds_epi) fetch_c(st);
-            mma_step(st);
-            st = st + 1 == NS ? 0 : st + 1;
-        }
+            read_half(nst, 0, f0);
+            if constexpr (decltype(dma)::value) {
+                mma_half_with(f1, [&](int m) {
+                    static_for<0, PCS>([&](auto q) {
+                        if (q * 8 / PCS == m) {
+                            __builtin_amdgcn_sched_barrier(0);
+                            piece(ks + NS, st, q);
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
+                    });
+                });
+            } else {
+                mma_half(f1);
+            }
+            read_half(nst, 1, f1);
+            st = nst;
+        };
+        int ks = 0;
+        for (; ks + NS < nk_str; ++ks) body(ks, std::true_type{});
+        for (; ks + 1 < nk_str; ++ks) body(ks, std::false_type{});
+        mma_half(f0);
+        if (nk == nk_str && lds_epi) fetch_c(st);
+        mma_half(f1);
+        st = st + 1 == NS ? 0 : st + 1;
         if (nk > nk_str) {
             // the K tail (one step) through registers: its stage was last read
-            // two steps ago
+            // by step nk_str - NS, which every wave has passed
             gemm_load<false>(g, m0, n0, nk_str * TK, tid, adj, R);
             gemm_store_lds(R, As(st), Bs(st), tid);
             __syncthreads();
@@ -629,19 +708,58 @@ __global__ void __launch_bounds__(GemmCfg<WN>::THREADS, GemmCfg<WN>::OCC) k_gemm
         const auto cl = [&](int m) { return m < GC::RPS ? s1 + m * TN : s2 + (m - GC::RPS) * TN; };
         vm_wait<0>();
         __syncthreads();
-        // each lane reads its C words and writes its D words in their place
-#pragma unroll
-        for (int i = 0; i < IM; ++i) {
+        // each lane reads all its C words, then writes its D words in their
+        // place: the reads are in flight together and no write precedes a read
+        // it might alias; the uniform choices (C present, reduction) are taken
+        // once for the whole tile, not per word
+        const auto wp = [&](int i, int j, int q) {
             const int row = wm + i * 32 + r32;
-            uint8_t* rp = cl(row);
+            const int ch = (wn >> 4) + 2 * j + (q >> 1);
+            return (uint32_t*)(cl(row) + ((ch ^ ((row >> 1) & 7)) << 4) + (q & 1) * 8 + kh * 4);
+        };
+        uint32_t cw[IM][JN][4];
+        if (g.C) {
 #pragma unroll
-            for (int j = 0; j < JN; ++j)
+            for (int i = 0; i < IM; ++i)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int ch = (wn >> 4) + 2 * j + (q >> 1);
-                    uint32_t* w = (uint32_t*)(rp + ((ch ^ ((row >> 1) & 7)) << 4) + (q & 1) * 8 + kh * 4);
-                    *w = reduce4(acc4(i, j, q), g.C ? *w : 0u);
-                }
+                for (int j = 0; j < JN; ++j)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) cw[i][j][q] = *wp(i, j, q);
+        } else {
+#pragma unroll
+            for (int i = 0; i < IM; ++i)
+#pragma unroll
+                for (int j = 0; j < JN; ++j)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) cw[i][j][q] = 0;
+        }
+        if (small) {
+#pragma unroll
+            for (int i = 0; i < IM; ++i)
+#pragma unroll
+                for (int j = 0; j < JN; ++j)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const v4i a = acc4(i, j, q);
+                        uint32_t out = 0;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            out |= mod22((uint32_t)a[e] + ((cw[i][j][q] >> (8 * e)) & 0xffu), inv, p) << (8 * e);
+                        *wp(i, j, q) = out;
+                    }
+        } else {
+#pragma unroll
+            for (int i = 0; i < IM; ++i)
+#pragma unroll
+                for (int j = 0; j < JN; ++j)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const v4i a = acc4(i, j, q);
+                        uint32_t out = 0;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) out |= mod(a[e] + (int)((cw[i][j][q] >> (8 * e)) & 0xffu)) << (8 * e);
+                        *wp(i, j, q) = out;
+                    }
         }
         __syncthreads();
         // whole 16-byte chunks of D rows: chunk P = tid + THREADS u is row P / BCH, position P % BCH
@@ -1247,15 +1365,6 @@ __host__ __device__ inline size_t echs_lds_bytes(int rows, int cols) {
     const int maxr = rows < cols ? rows : cols;
     const size_t rows16 = (size_t)((rows + 15) & ~15);
     return (size_t)ECHS_FIXED + rows16 * ECHS_PW + rows16 * (size_t)echs_lw(cols, maxr);
-}
-
-// f(std::integral_constant<int, K>) for K = K0 .. N - 1, unrolled at compile time
-template <int K0, int N, class Fn>
-__device__ __forceinline__ void static_for(Fn&& f) {
-    if constexpr (K0 < N) {
-        f(std::integral_constant<int, K0>{});
-        static_for<K0 + 1, N>(f);
-    }
 }
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
@@ -2398,14 +2507,34 @@ public:
         } else {
             HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         }
-        HIP_OK(hipEventRecord(e, lane_stream(lane)));
+        hipStream_t s = lane_stream(lane);
+        HIP_OK(hipEventRecord(e, s));
         marks_.push_back(e);
+        mark_streams_.push_back(s);
         return mark_base_ + (int)marks_.size() - 1;
     }
+    // A stream-wait costs the host about ten microseconds, so the waits that
+    // order nothing are left out: on a mark of the waiting stream itself, on a
+    // mark at or before one of the same stream this stream already waited for
+    // (marks of one stream complete in order), and on a mark already reached.
     void wait_mark(int lane, int m) override {
         // marks below mark_base_ were passed by a full synchronisation already
         if (m < mark_base_ || m - mark_base_ >= (int)marks_.size()) return;
-        HIP_OK(hipStreamWaitEvent(lane_stream(lane), marks_[m - mark_base_], 0));
+        const hipStream_t w = lane_stream(lane), src = mark_streams_[m - mark_base_];
+        if (w == src) return;
+        Waited* slot = nullptr;
+        for (Waited& x : waited_)
+            if (x.waiter == w && x.source == src) slot = &x;
+        if (slot && slot->mark >= m) return;
+        if (!slot) {
+            waited_.push_back({w, src, -1});
+            slot = &waited_.back();
+        }
+        slot->mark = m;
+        const hipError_t q = hipEventQuery(marks_[m - mark_base_]);
+        if (q == hipSuccess) return;
+        if (q != hipErrorNotReady) note_error(q, "hipEventQuery");
+        HIP_OK(hipStreamWaitEvent(w, marks_[m - mark_base_], 0));
     }
     int error() const override { return err_; }
 
@@ -2443,12 +2572,13 @@ public:
         if (tiles > INT32_MAX) { note_error(hipErrorInvalidValue, "too many gemm tiles"); return; }
         launch_mac_ = 0;
         for (const GemmDesc& g : d) launch_mac_ += (double)g.M * g.N * g.K;
+        const unsigned grid = (unsigned)tiles;
         if (d.size() <= (size_t)GEMM_ARG_CAP) {
             GemmArgSrc a;
             a.n = (int)d.size();
             a.group = gemm_group_;
             for (size_t i = 0; i < d.size(); ++i) { a.m[i] = maps[i]; a.d[i] = d[i]; }
-            go(0, k_gemm_modp<WN, GemmArgSrc>, dim3((unsigned)tiles), dim3(GC::THREADS), GC::lds_bytes(), a);
+            go(0, k_gemm_modp<WN, GemmArgSrc>, dim3(grid), dim3(GC::THREADS), GC::lds_bytes(), a);
         } else {
             // one upload: the tile maps, then the descriptors (256-byte aligned)
             const size_t mb = (maps.size() * sizeof(GemmTileMap) + 255) & ~(size_t)255;
@@ -2461,7 +2591,7 @@ public:
             a.group = gemm_group_;
             a.m = (const GemmTileMap*)dev;
             a.d = (const GemmDesc*)(dev + mb);
-            go(0, k_gemm_modp<WN, GemmPtrSrc>, dim3((unsigned)tiles), dim3(GC::THREADS), GC::lds_bytes(), a);
+            go(0, k_gemm_modp<WN, GemmPtrSrc>, dim3(grid), dim3(GC::THREADS), GC::lds_bytes(), a);
         }
         HIP_OK(hipGetLastError());
     }
@@ -2738,12 +2868,18 @@ private:
         mark_base_ += (int)marks_.size();
         if (mark_base_ > (1 << 30)) mark_base_ = 0;
         marks_.clear();
+        mark_streams_.clear();
+        waited_.clear();
     }
 
     hipStream_t stream_ = nullptr;   // lane 0: the caller's stream
     hipStream_t lanes_[3] = {nullptr, nullptr, nullptr};   // lanes 1, 2 and 3 (created on first use)
     hipStream_t cur_ = nullptr;      // the lane kernels go to
     std::vector<hipEvent_t> marks_, mark_pool_;
+    std::vector<hipStream_t> mark_streams_;   // the stream each of marks_ was recorded on
+    struct Waited { hipStream_t waiter, source; int mark; };
+    std::vector<Waited> waited_;     // since the last full synchronisation: the latest mark of
+                                     // `source` that `waiter` waits for
     int32_t* counts_host_ = nullptr;   // counts_buffer(): host view
     int32_t* counts_dev_ = nullptr;    // and device view
     std::vector<size_t> pending_;      // slots of counts_host_ an ECH queued since the last read will write

@@ -92,6 +92,14 @@ def test_mad_batch_grouped():
     torch.cuda.synchronize()
     for dD, exp, M, N in exps:
         assert np.array_equal(dD.cpu().numpy().reshape(M, N), exp)
+    say("mad batch of 40, timed")
+    for dD, _, _, _ in exps:
+        dD.zero_()
+    torch.cuda.synchronize()
+    ms = lib.mad_batch_dev_timed(descs)
+    assert 0 < ms < 1000
+    for dD, exp, M, N in exps:
+        assert np.array_equal(dD.cpu().numpy().reshape(M, N), exp)
 
 
 ECH_SHAPES = [(1, 1), (5, 9), (9, 5), (64, 64), (100, 37), (37, 100), (300, 300), (513, 200), (200, 700),
