@@ -226,8 +226,11 @@ def test_mad_batch_streamed():
 
 
 # inner dimensions of the large solves' products (2048-wide block columns) and beyond,
-# on 16-byte aligned rows so interior tiles take the streamed path
-LONG_K_SHAPES = [(256, 512, 2048), (512, 384, 4096), (300, 272, 2048)]
+# on 16-byte aligned rows so interior tiles take the streamed path; even step
+# counts from 4 up move A two steps at a time (6 and 10 steps: the transfer
+# schedule's first and last steps overlap), an odd count (5) one step at a time
+LONG_K_SHAPES = [(256, 512, 2048), (512, 384, 4096), (300, 272, 2048), (512, 256, 384), (256, 512, 640),
+                 (512, 512, 320)]
 
 
 @pytest.mark.parametrize("p", [2, 7, 127, 131, 251])
