@@ -66,19 +66,25 @@ def copy_calibration(torch, mib: int):
 
 PROFILE = os.path.join(ROOT, "profiles", "k_gemm_modp_replay_40000_gf7.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1806_04211_amd", "csrc", "hip_backend.hip")
+BLOCKING_TABLE = os.path.join(ROOT, "paper_1806_04211_amd", "blocking.json")
 
 
 def profiled_traffic():
     """HBM bytes per MAD launch from the committed counter summary, when it was
-    taken on the current kernel source (same sha256); otherwise None."""
+    taken on the current kernel source and, if it names one, the current
+    blocking table (which decides the replayed launch); otherwise None."""
     import hashlib
+    keys = ("source_sha256", "blocking_sha256", "traffic_bytes_per_launch")
     try:
         fields = {}
         for line in open(PROFILE):
-            if ":" in line and line.split(":", 1)[0].strip() in ("source_sha256", "traffic_bytes_per_launch"):
+            if ":" in line and line.split(":", 1)[0].strip() in keys:
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip().strip("`")
         sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        if "blocking_sha256" in fields:
+            if fields["blocking_sha256"] != hashlib.sha256(open(BLOCKING_TABLE, "rb").read()).hexdigest():
+                return None
         if fields.get("source_sha256") == sha and "traffic_bytes_per_launch" in fields:
             return float(fields["traffic_bytes_per_launch"])
     except OSError:

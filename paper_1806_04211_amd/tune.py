@@ -24,7 +24,7 @@ from . import _abi
 
 DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "blocking.json")
 ROWS = (128, 256, 512)
-COLS = (512, 1024, 2048, 4096)
+COLS = (512, 1024, 1536, 2048, 3072, 4096)
 
 
 def candidates(n: int):

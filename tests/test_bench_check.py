@@ -89,3 +89,11 @@ def test_mad_trace_matches_the_work_counters(tmp_path, monkeypatch):
     assert mac[1] == st["mac_cleardown"] and mac[2] == st["mac_updaterow"]
     assert mac[3] == st["mac_trafo"] and mac[4] == st["mac_clearup"]
     assert len({d["it"] for d in tr if d["kind"] == 1}) > 3
+
+
+def test_committed_profile_matches_the_sources():
+    """The committed rocprofv3 summary of the isolated MAD launches was taken on
+    the current kernel source and blocking table, so the benchmark reports its
+    traffic figure (a kernel or table change needs a new profile)."""
+    import bench
+    assert bench.profiled_traffic() is not None
