@@ -1157,7 +1157,7 @@ struct Engine::Impl {
         const char* ht = getenv("GFECH_HOST_TIMING");
         host_timing = ht && ht[0] == '1';
         const char* gr = getenv("GFECH_CLEARUP_GROUP");
-        group_rank = gr ? std::max<int64_t>(1, atoll(gr)) : 4096;
+        group_rank = gr ? std::max<int64_t>(1, atoll(gr)) : kClearUpGroup;
         counts = be.counts_buffer(kCountsCap);
         if (counts) holes.push_back({0, kCountsCap});
         hcounts.resize(kCountsCap);
@@ -1211,7 +1211,8 @@ struct Engine::Impl {
     std::vector<std::pair<size_t, size_t>> holes;   // free ranges of the counts pool
     size_t counts_high = 0;
     std::vector<int32_t> hcounts;
-    int64_t group_rank = 4096;
+    static constexpr int64_t kClearUpGroup = 16384;   // pivots per ClearUp group (GFECH_CLEARUP_GROUP)
+    int64_t group_rank = kClearUpGroup;
 
     bool take_counts(size_t n, size_t* off) {
         n = std::max<size_t>(n, 1);

@@ -417,3 +417,16 @@ def test_blocking_table_sets_default_blocks(lib):
         lib.lib.gfech_set_blocking(None, 0)
     st = lib.echelonise(A, 5).stats()
     assert (st["block_rows"], st["block_cols"]) == (1, 1)           # built-in: one block up to 512
+
+
+@pytest.mark.parametrize("group", [1, 3, 7])
+def test_grouped_clearup(lib, monkeypatch, group):
+    """ClearUp in groups of a few pivots (GFECH_CLEARUP_GROUP): the clearing
+    inside each group, then one product for every row above it (Section 3,
+    Step 3, grouped); the same outputs as the oracle for several blockings."""
+    monkeypatch.setenv("GFECH_CLEARUP_GROUP", str(group))
+    for p in (2, 7, 251):
+        A = synth.low_rank_product(p, 40, 64, 30, p)
+        e = oracle.echelonize(A, p)
+        for br, bc in ((4, 8), (5, 6), (8, 16)):
+            compare(lib.echelonise(A, p, block_rows=br, block_cols=bc).outputs(), e, f"group {group} {br}x{bc} p={p}")

@@ -128,3 +128,15 @@ def test_gf2_8192_matches_packed_oracle():
     assert np.array_equal(out.gamma, e.gamma) and np.array_equal(out.rho, e.rho)
     assert np.array_equal(out.E, synth.gf2_unpack(e.E, n))
     assert np.array_equal(out.T, synth.gf2_unpack(e.T, n))
+
+
+def test_grouped_clearup_matches_oracle(monkeypatch):
+    """ClearUp groups of about 300 pivots (GFECH_CLEARUP_GROUP) at the default
+    blocking: several groups, each cleared inside and then applied to every
+    row above it in one product, compared with the oracle."""
+    monkeypatch.setenv("GFECH_CLEARUP_GROUP", "300")
+    lib = gpu_library()
+    A = synth.low_rank_product(7, 1024, 6200, 1000, 7)
+    say("echelonise 1024x6200 GF(7), ClearUp groups of 300 pivots")
+    out = lib.echelonise(A, 7).outputs()
+    compare(out, oracle.echelonize(A, 7), "grouped ClearUp")
