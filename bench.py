@@ -69,6 +69,20 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1806_04211_amd", "csrc", "hip_backend.
 BLOCKING_TABLE = os.path.join(ROOT, "paper_1806_04211_amd", "blocking.json")
 
 
+def block_size(n, tuned, rows=0, cols=0):
+    """[block rows, block columns] a square n x n solve runs with: explicit
+    sizes, else the tuned table's entry (when installed), else the library's
+    built-in choice (256 x 2048 above 512 x 512, one block below)."""
+    if rows or cols:
+        return [rows or cols, cols or rows]
+    if tuned:
+        with open(BLOCKING_TABLE) as f:
+            for e in json.load(f)["entries"]:
+                if n <= e["max_dim"]:
+                    return [e["block_rows"], e["block_cols"]]
+    return [256, 2048] if n > 512 else [n, n]
+
+
 def profiled_traffic():
     """HBM bytes per MAD launch from the committed counter summary, when it was
     taken on the current kernel source and, if it names one, the current
@@ -560,7 +574,8 @@ def run_gf2(torch, args):
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": f"{n}x{n} over GF(2), bit-packed in 64-bit words, rank deficiency {d} (rows "
                                f"{n - d}.. are sums of 64 earlier rows), seed 4", "m": n, "n": n, "p": 2,
-                   "rank": last.rank, "block_rows": st["block_rows"], "block_cols": st["block_cols"],
+                   "rank": last.rank, "block_grid": [st["block_rows"], st["block_cols"]],
+                   "block_size": block_size(n, tuned),
                    "blocking": "tuned table" if tuned else "built-in", "parallelism": "single GPU"},
         "work": {"mac_total": mac, "mac_alg_per_s": mac / mean},
         "roofline": {"bound": "mfma", "kernel": "k_gemm_modp (MAD mod p, int8 MFMA, unpacked GF(2))",
@@ -811,8 +826,8 @@ def main():
         "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": f"{n}x{n} over GF({p}), B*C mod {p} with inner dimension {k}, seed 0",
-                   "m": n, "n": n, "p": p, "rank": rank, "block_rows": st["block_rows"],
-                   "block_cols": st["block_cols"],
+                   "m": n, "n": n, "p": p, "rank": rank, "block_grid": [st["block_rows"], st["block_cols"]],
+                   "block_size": block_size(n, tuned, kw["block_rows"], kw["block_cols"]),
                    "blocking": "tuned table" if tuned and not (kw["block_rows"] or kw["block_cols"]) else
                                "explicit" if (kw["block_rows"] or kw["block_cols"]) else "built-in",
                    "parallelism": "single GPU"},
