@@ -117,6 +117,9 @@ struct Bulk {
 // bulk part of layer L reads copy L mod kScratchCopies while layers L + 1 and
 // L + 2 write the other copies
 constexpr int kScratchCopies = 3;
+// regions up to this size are zeroed by the fill job (one launch for all of
+// them), larger ones by a memset
+constexpr int64_t kFillZeroMax = 4 << 20;
 
 struct TaskState {      // one (i, j) of the current layer
     int i = 0, j = 0;
@@ -257,15 +260,31 @@ public:
         P_ = at(oP_);
     }
 
-    // zero what must start at zero, load the input, initialise the index lists
+    // zero what must start at zero, load the input, initialise the index lists.
+    // Small regions are zeroed by the fill job, which takes every region of a
+    // batch in one launch (a memset costs the host a few microseconds each:
+    // three per matrix made a third of a batch of 4096 small matrices).
     void init(Ops& ops) {
-        be_.zero(P_, (size_t)(prow_total_ * ldP_));
+        const auto zero = [&](uint8_t* p, int64_t rows, int64_t ld) {
+            if (rows <= 0 || ld <= 0) return;
+            if (rows * ld <= kFillZeroMax) {
+                FillDesc f;
+                f.rows = (int32_t)rows;
+                f.cols = (int32_t)ld;
+                f.dst = p;
+                f.ldd = ld;
+                ops.fill.push_back(f);
+            } else {
+                be_.zero(p, (size_t)(rows * ld));
+            }
+        };
+        zero(P_, prow_total_, ldP_);
         for (int i = 0; i < a_; ++i) {
             BR& br = rows_[i];
             int64_t ai = pr_.row_blocks[i];
             if (trafo_) {
-                be_.zero(br.K[0], (size_t)(ai * br.ldK));
-                be_.zero(br.K[1], (size_t)(ai * br.ldK));
+                zero(br.K[0], ai, br.ldK);
+                zero(br.K[1], ai, br.ldK);
             }
             if (n_ > 0 && pr_.packed) {
                 // GF(2) packed rows straight into the panel (a lane-0 job)
@@ -1693,6 +1712,13 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
             ids.push_back(id);
         }
         bool cancelled = false;
+        // GFECH_HOST_TIMING=1: host time of the call by part (planning, each
+        // engine iteration, the end), printed when the call ends
+        const char* ht = getenv("GFECH_HOST_TIMING");
+        const bool timing = ht && ht[0] == '1';
+        auto tp = std::chrono::steady_clock::now();
+        std::vector<double> parts;
+        if (timing) parts.push_back(std::chrono::duration<double>(tp - t0).count());
         while (!rc && eng.active()) {
             if (timeout_ms > 0 && !cancelled &&
                 std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(timeout_ms)) {
@@ -1700,6 +1726,18 @@ int run_chief(Backend& be, const std::vector<Problem>& probs, std::vector<std::u
                 cancelled = true;
             }
             eng.step();
+            if (timing) {
+                const auto t = std::chrono::steady_clock::now();
+                parts.push_back(std::chrono::duration<double>(t - tp).count());
+                tp = t;
+            }
+        }
+        if (timing) {
+            fprintf(stderr, "gfech call timing (ms): %zu problems, planning %.2f, iterations", probs.size(),
+                    1e3 * parts[0]);
+            for (size_t k = 1; k < parts.size() && k <= 12; ++k) fprintf(stderr, " %.2f", 1e3 * parts[k]);
+            if (parts.size() > 13) fprintf(stderr, " ... (%zu)", parts.size() - 1);
+            fprintf(stderr, "\n");
         }
         for (auto& d : eng.take_done()) {
             if (d.status && !rc) {
