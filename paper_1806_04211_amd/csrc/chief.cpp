@@ -1193,6 +1193,9 @@ struct Engine::Impl {
                     1e6 * ht_seg[0] / ht_layers, 1e6 * ht_seg[1] / ht_layers, 1e6 * ht_seg[2] / ht_layers,
                     1e6 * ht_seg[3] / ht_layers, 1e6 * ht_seg[4] / ht_layers, 1e6 * ht_seg[5] / ht_layers,
                     1e6 * ht_seg[6] / ht_layers);
+        if (host_timing)
+            fprintf(stderr, "gfech host timing: after Step 1 (ms): assembly %.2f, ClearUp issue %.2f, finishing %.2f\n",
+                    1e3 * ht_tail[0], 1e3 * ht_tail[1], 1e3 * ht_tail[2]);
         be.sync();
         for (auto& j : jobs) release(*j);
         if (counts) be.release_counts(counts);
@@ -1209,6 +1212,7 @@ struct Engine::Impl {
     bool host_timing = false;
     double ht_pre = 0, ht_wait = 0, ht_post = 0;
     double ht_seg[7] = {0, 0, 0, 0, 0, 0, 0};   // the issue phase by part (see step())
+    double ht_tail[3] = {0, 0, 0};              // assembly, ClearUp issue, finishing (with its wait)
     int64_t ht_layers = 0;
 
     Backend& be;
@@ -1590,6 +1594,7 @@ struct Engine::Impl {
         if (be.error()) { fail_all(be.error()); return 0; }
 
         // ---- assembly of the result (and Step 2, implicit), then Step 3's plan
+        const auto ha = std::chrono::steady_clock::now();
         std::vector<Job*> asmj;
         for (auto& j : jobs)
             if (j->phase == kAssemble) asmj.push_back(j.get());
@@ -1613,6 +1618,7 @@ struct Engine::Impl {
             }
         }
         // ---- Step 3: the next ClearUp launch of every problem in it
+        const auto hc = std::chrono::steady_clock::now();
         bool cu = false;
         for (auto& j : jobs) {
             if (j->phase != kClearUp) continue;
@@ -1626,6 +1632,7 @@ struct Engine::Impl {
             if (j->phase == kClearUp && j->cu_step >= j->plan->clearup_steps()) j->phase = kFinished;
 
         // ---- finished problems: their work must be complete before their memory is reused
+        const auto hf = std::chrono::steady_clock::now();
         bool fin = false;
         for (auto& j : jobs) fin = fin || j->phase == kFinished;
         if (fin) {
@@ -1653,6 +1660,12 @@ struct Engine::Impl {
                 done.push_back(std::move(d));
             }
             jobs.swap(keep);
+        }
+        if (host_timing) {
+            const auto he = std::chrono::steady_clock::now();
+            ht_tail[0] += std::chrono::duration<double>(hc - ha).count();
+            ht_tail[1] += std::chrono::duration<double>(hf - hc).count();
+            ht_tail[2] += std::chrono::duration<double>(he - hf).count();
         }
         return jobs.size();
     }
