@@ -2648,6 +2648,13 @@ public:
                 rest.push_back(e);
             }
         }
+        // largest blocks first: the hardware hands out workgroups in order, so
+        // the longest ones start first and the launch ends with short ones
+        const auto larger = [](const EchDesc& a, const EchDesc& b) {
+            return (int64_t)a.rows * a.cols > (int64_t)b.rows * b.cols;
+        };
+        std::stable_sort(lds.begin(), lds.end(), larger);
+        std::stable_sort(rest.begin(), rest.end(), larger);
         for (size_t off = 0; off < lds.size(); off += 65535) {
             const size_t cnt = std::min<size_t>(65535, lds.size() - off);
             launch_descs<ECH_ARG_CAP>(lds.data() + off, cnt, k_ech_lds<DescArg<EchDesc, ECH_ARG_CAP>>,
